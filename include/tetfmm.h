@@ -1,0 +1,193 @@
+/*
+ * tetfmm.h -- C ABI of the MI355X (gfx950) tetrahedral Fast Multipole library.
+ *
+ * The library evaluates the magnetic scalar potential of a tetrahedral mesh
+ * whose magnetisation is affine on every tetrahedron (Palmesi et al., "Highly
+ * Parallel Demagnetization Field Calculation Using the Fast Multipole Method
+ * on Tetrahedral Meshes with Continuous Sources", eq. approx1):
+ *
+ *     u(x) = 1/(4 pi) sum_T int_T M_T(r') . grad' (1 / |x - r'|) dr'
+ *
+ * at a set of target points (by default the mesh nodes), either by the Fast
+ * Multipole Method of Secs. 2-3 (octree, MAC, dual tree traversal, Cartesian
+ * Taylor expansions of order p, exact near-field integrals) or by the O(N^2)
+ * direct sum of the exact tet-to-target integrals (Sec. 2.1).
+ *
+ * Conventions
+ *  - Every function returns 0 on success or a negative TFMM_E* code; the
+ *    message of the last failure on the calling thread is tfmm_last_error().
+ *    No C++ exception crosses this interface.
+ *  - The caller owns every buffer it passes.  tfmm_plan_create copies the
+ *    mesh; the caller may free its arrays when it returns.
+ *  - Device pointers are HIP device allocations on the plan's device (for
+ *    example torch tensors on that device).  Work is queued on the HIP stream
+ *    passed in (NULL = the default stream) and is asynchronous: the caller
+ *    synchronises that stream before reading the output.
+ *  - A plan is not thread-safe: one evaluation at a time per plan.
+ *  - Units: u carries the 1/(4 pi) of eq. approx1; u has the units of
+ *    M times length.
+ */
+#ifndef TETFMM_H
+#define TETFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define TFMM_OK 0
+#define TFMM_EINVAL (-1)     /* bad sizes or parameters */
+#define TFMM_EINDEX (-2)     /* tet node index out of range */
+#define TFMM_EDEGEN (-3)     /* tetrahedron of (near) zero volume */
+#define TFMM_ENONFINITE (-4) /* NaN or Inf in the inputs */
+#define TFMM_ENOMEM (-5)     /* host or device allocation failed */
+#define TFMM_EDEVICE (-6)    /* HIP error, or no usable device */
+#define TFMM_ENOTSUP (-7)    /* valid request this build does not support */
+
+/* largest expansion order p accepted */
+#define TFMM_PMAX 10
+
+/* M2L arithmetic */
+#define TFMM_M2L_FP64 0 /* plain FP64 */
+
+typedef struct tfmm_plan_s *tfmm_plan; /* opaque, owned by the library */
+
+/*
+ * Parameters of the method.
+ *  p          expansion order: multipole and local expansions hold every
+ *             Taylor term with |n| <= p (Sec. 2.2), (p+1)(p+2)(p+3)/6
+ *             coefficients; M2L keeps |n| + |m| <= p.  1 <= p <= TFMM_PMAX.
+ *  leaf_size  an octree cell is split while it holds more than leaf_size
+ *             tets (by centroid) or targets (Sec. 3.1).  >= 1.
+ *  theta      multipole acceptance parameter (Sec. 3.2): cells A (target)
+ *             and B (source) interact through M2L iff
+ *             r_tgt(A) + r_src(B) < theta |c_A - c_B|.  0 < theta < 1.
+ *  m2l_precision  TFMM_M2L_FP64.
+ *  device     HIP device ordinal; -1 builds a host-only plan (tree and lists
+ *             without any device allocation: only tfmm_plan_stats,
+ *             tfmm_plan_lists and tfmm_plan_cells work on it).
+ */
+typedef struct {
+    int32_t p;
+    int32_t leaf_size;
+    double theta;
+    int32_t m2l_precision;
+    int32_t device;
+} tfmm_params;
+
+/* Sizes of a plan. */
+typedef struct {
+    int64_t n_nodes, n_tets, n_targets;
+    int64_t n_cells, n_leaves, depth;
+    int64_t n_m2l;       /* M2L cell pairs */
+    int64_t n_p2p;       /* P2P leaf pairs */
+    int64_t n_p2p_pairs; /* target x tet pairs integrated directly */
+    int64_t ncoef;       /* (p+1)(p+2)(p+3)/6 */
+    int64_t device_bytes; /* device memory held by the plan */
+    double setup_seconds; /* wall time of tfmm_plan_create */
+} tfmm_stats;
+
+/*
+ * Build a plan: validate the mesh, orient every tet to positive volume,
+ * build the octree (Sec. 3.1), the cell radii (Sec. 3.2) and the M2L and
+ * P2P interaction lists by the dual tree traversal (Sec. 3.3), then upload
+ * everything the evaluation needs to the device.
+ *
+ *  nodes    host, [n_nodes][3] double, node coordinates
+ *  tets     host, [n_tets][4] int32, 0-based node indices, either orientation
+ *  targets  host, [n_targets][3] double, or NULL to use the nodes as targets
+ *  prm      parameters (see tfmm_params)
+ *  out      receives the plan; NULL on failure
+ * Errors: TFMM_EINVAL (sizes, p, leaf_size, theta), TFMM_EINDEX,
+ *         TFMM_EDEGEN (|det| <= 1e-12 * mean edge^3 for some tet),
+ *         TFMM_ENONFINITE, TFMM_ENOMEM, TFMM_EDEVICE.
+ */
+int tfmm_plan_create(const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
+                     const double *targets, int64_t n_targets, const tfmm_params *prm, tfmm_plan *out);
+
+/*
+ * FMM evaluation (Secs. 2-3: P2M, M2M, M2L, L2L, L2P plus the exact
+ * near-field P2P of Sec. 2.1) of F fields.
+ *  M  device, [F][n_nodes][3] double: nodal magnetisation, affine per tet
+ *  u  device, [F][n_targets] double: potential at the targets (overwritten)
+ * Asynchronous on `hip_stream` (a hipStream_t, NULL = default stream).
+ * Errors: TFMM_EINVAL (F < 1, NULL pointers, host-only plan), TFMM_EDEVICE.
+ */
+int tfmm_evaluate(tfmm_plan plan, const double *M, int32_t F, double *u, void *hip_stream);
+
+/*
+ * O(N^2) direct sum of the exact tet-to-target integrals (Sec. 2.1) over all
+ * targets and all tets, in FP64.  Same arguments and errors as tfmm_evaluate.
+ */
+int tfmm_direct(tfmm_plan plan, const double *M, int32_t F, double *u, void *hip_stream);
+
+/* Synchronous convenience forms with host arrays (copies in and out). */
+int tfmm_evaluate_host(tfmm_plan plan, const double *M, int32_t F, double *u);
+int tfmm_direct_host(tfmm_plan plan, const double *M, int32_t F, double *u);
+
+/* Sizes of the plan. */
+int tfmm_plan_stats(tfmm_plan plan, tfmm_stats *out);
+
+/*
+ * Interaction lists as integer cell coordinates, for verification.
+ *  kind 0 = M2L pairs, 1 = P2P pairs.
+ *  out  host, [n][8] int32: levelA, ixA, iyA, izA, levelB, ixB, iyB, izB
+ *       (A target cell, B source cell; a cell at level L covers
+ *       [origin + i s, origin + (i+1) s) per axis with s = side / 2^L), or
+ *       NULL to query the count.
+ * Returns the number of pairs (>= 0) or a negative error code.
+ */
+int64_t tfmm_plan_lists(tfmm_plan plan, int32_t kind, int32_t *out);
+
+/*
+ * Cells, for verification.
+ *  cells  host, [n_cells][6] int32: level, ix, iy, iz, n_tets, n_targets (or NULL)
+ *  radii  host, [n_cells][2] double: r_src, r_tgt of Sec. 3.2 (or NULL)
+ * Returns n_cells or a negative error code.
+ */
+int64_t tfmm_plan_cells(tfmm_plan plan, int32_t *cells, double *radii);
+
+/*
+ * Expansion coefficients left by the last tfmm_evaluate (field F-1), for
+ * verification: which 0 = multipole Q_n, 1 = local l_m (Taylor coefficients,
+ * u = sum_m l_m (x - c)^m), in cell order of tfmm_plan_cells and the graded
+ * multi-index order (degree ascending; within a degree n_x descending, then
+ * n_y descending).  out: host, [n_cells][ncoef] double.  Synchronises the
+ * device.
+ */
+int tfmm_plan_expansions(tfmm_plan plan, int32_t which, double *out);
+
+/*
+ * The quadrature rule P2M uses to integrate the polynomial expansion
+ * integrands of eq. expCoeffs exactly (Sec. 2.2): a collapsed Gauss-Jacobi
+ * (conical product) rule on the unit simplex, exact to total degree
+ * `degree` (0 <= degree <= 2 TFMM_PMAX).  out: host, [npts][4] double rows
+ * (lambda1, lambda2, lambda3, weight), weights summing to 1/6, or NULL to
+ * query npts.  Host-only; needs no device.
+ */
+int tfmm_simplex_rule(int32_t degree, double *out, int32_t *npts);
+
+/* Release the plan and its device memory.  NULL is ignored. */
+int tfmm_plan_destroy(tfmm_plan plan);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *tfmm_last_error(void);
+
+/*
+ * Per-phase GPU time of the evaluations run since timing was switched on.
+ * tfmm_set_timing(plan, 1) clears the record and makes every tfmm_evaluate
+ * record a HIP event pair around each phase on its stream (no extra
+ * synchronisation); tfmm_kernel_times synchronises on those events and
+ * returns, per phase, the average milliseconds per evaluation and the
+ * number of evaluations recorded.  Phases: 0 p2m, 1 m2m (all levels),
+ * 2 m2l, 3 l2l (all levels), 4 l2p, 5 p2p.
+ */
+int tfmm_set_timing(tfmm_plan plan, int32_t on);
+int tfmm_kernel_times(tfmm_plan plan, double *ms /* [6] */, int64_t *launches /* [6] */);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,258 @@
+"""Python binding of libtetfmm.so, the MI355X (gfx950) tetrahedral FMM.
+
+Argument marshalling only: every step of the evaluation runs in the HIP
+kernels of the library.  The names mirror the C ABI of include/tetfmm.h.
+There is no fallback: if the library is not built, loading fails loudly.
+
+Device arrays are torch tensors on the plan's GPU (float64, contiguous);
+work is queued on torch's current stream of that device unless a stream is
+given.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = [
+    "TetFMMError", "Plan", "tfmm_plan_create", "tfmm_evaluate", "tfmm_direct", "tfmm_evaluate_host",
+    "tfmm_direct_host", "tfmm_plan_stats", "tfmm_plan_lists", "tfmm_plan_cells", "tfmm_plan_expansions",
+    "tfmm_plan_destroy", "tfmm_last_error", "tfmm_simplex_rule", "tfmm_set_timing", "tfmm_kernel_times",
+    "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libtetfmm.so")
+_lib = None
+
+TFMM_PMAX = 10
+KERNEL_NAMES = ("p2m", "m2m", "m2l", "l2l", "l2p", "p2p")
+ERRORS = {-1: "EINVAL", -2: "EINDEX", -3: "EDEGEN", -4: "ENONFINITE", -5: "ENOMEM", -6: "EDEVICE", -7: "ENOTSUP"}
+
+_dp = C.POINTER(C.c_double)
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+
+
+class _Params(C.Structure):
+    _fields_ = [("p", C.c_int32), ("leaf_size", C.c_int32), ("theta", C.c_double), ("m2l_precision", C.c_int32),
+                ("device", C.c_int32)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("n_nodes", "n_tets", "n_targets", "n_cells", "n_leaves", "depth", "n_m2l",
+                                        "n_p2p", "n_p2p_pairs", "ncoef", "device_bytes")] + [("setup_seconds",
+                                                                                               C.c_double)]
+
+
+class TetFMMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def library_path():
+    return _LIBPATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        raise RuntimeError(f"libtetfmm.so is not built ({_LIBPATH}); run __graft_entry__.build() "
+                           "or python -m paper_1606_00247_amd.build")
+    lib = C.CDLL(_LIBPATH)
+    sig = {
+        "tfmm_plan_create": (C.c_int, [_dp, C.c_int64, _i32p, C.c_int64, _dp, C.c_int64, C.POINTER(_Params),
+                                       C.POINTER(C.c_void_p)]),
+        "tfmm_evaluate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+        "tfmm_direct": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+        "tfmm_evaluate_host": (C.c_int, [C.c_void_p, _dp, C.c_int32, _dp]),
+        "tfmm_direct_host": (C.c_int, [C.c_void_p, _dp, C.c_int32, _dp]),
+        "tfmm_plan_stats": (C.c_int, [C.c_void_p, C.POINTER(_Stats)]),
+        "tfmm_plan_lists": (C.c_int64, [C.c_void_p, C.c_int32, _i32p]),
+        "tfmm_plan_cells": (C.c_int64, [C.c_void_p, _i32p, _dp]),
+        "tfmm_plan_expansions": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
+        "tfmm_plan_destroy": (C.c_int, [C.c_void_p]),
+        "tfmm_last_error": (C.c_char_p, []),
+        "tfmm_simplex_rule": (C.c_int, [C.c_int32, _dp, _i32p]),
+        "tfmm_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+        "tfmm_kernel_times": (C.c_int, [C.c_void_p, _dp, _i64p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def tfmm_last_error():
+    return _load().tfmm_last_error().decode()
+
+
+def _check(rc):
+    if rc < 0:
+        raise TetFMMError(int(rc), tfmm_last_error())
+    return rc
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t)
+
+
+class Plan:
+    """Owns a tfmm_plan handle (destroyed with the object or tfmm_plan_destroy)."""
+
+    def __init__(self, handle, device, n_nodes, n_targets, params):
+        self._h = C.c_void_p(handle)
+        self.device = device
+        self.n_nodes = n_nodes
+        self.n_targets = n_targets
+        self.params = params
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("plan already destroyed")
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.tfmm_plan_destroy(h)
+            self._h = None
+
+
+def tfmm_plan_create(nodes, tets, targets=None, p=8, leaf_size=64, theta=0.5, m2l_precision=0, device=0):
+    """Build the octree, lists and device data of a mesh (copies the host arrays)."""
+    lib = _load()
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    if nodes.ndim != 2 or nodes.shape[1] != 3 or tets.ndim != 2 or tets.shape[1] != 4:
+        raise ValueError("nodes must be [N,3] and tets [T,4]")
+    tp, nt = None, 0
+    if targets is not None:
+        targets = np.ascontiguousarray(targets, dtype=np.float64)
+        if targets.ndim != 2 or targets.shape[1] != 3:
+            raise ValueError("targets must be [n,3]")
+        tp, nt = _ptr(targets, _dp), targets.shape[0]
+    prm = _Params(int(p), int(leaf_size), float(theta), int(m2l_precision), int(device))
+    h = C.c_void_p()
+    _check(lib.tfmm_plan_create(_ptr(nodes, _dp), nodes.shape[0], _ptr(tets, _i32p), tets.shape[0], tp, nt,
+                                C.byref(prm), C.byref(h)))
+    return Plan(h.value, int(device), nodes.shape[0], nt if targets is not None else nodes.shape[0],
+                dict(p=int(p), leaf_size=int(leaf_size), theta=float(theta), m2l_precision=int(m2l_precision)))
+
+
+def _stream_handle(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_call(fn, plan, M, u, stream):
+    import torch
+    if not (isinstance(M, torch.Tensor) and M.is_cuda and M.dtype == torch.float64 and M.is_contiguous()):
+        raise ValueError("M must be a contiguous float64 CUDA tensor [F, n_nodes, 3] or [n_nodes, 3]")
+    squeeze = M.dim() == 2
+    F = 1 if squeeze else M.shape[0]
+    if tuple(M.shape[-2:]) != (plan.n_nodes, 3):
+        raise ValueError(f"M must end in [{plan.n_nodes}, 3]")
+    if M.device.index != plan.device:
+        raise ValueError("M is not on the plan's device")
+    if u is None:
+        u = torch.empty((plan.n_targets,) if squeeze else (F, plan.n_targets), dtype=torch.float64, device=M.device)
+    elif not (u.is_cuda and u.dtype == torch.float64 and u.is_contiguous() and u.numel() == F * plan.n_targets):
+        raise ValueError("u must be a contiguous float64 CUDA tensor with F * n_targets elements")
+    _check(fn(plan.handle, C.c_void_p(M.data_ptr()), F, C.c_void_p(u.data_ptr()), _stream_handle(stream, M.device)))
+    return u
+
+
+def tfmm_evaluate(plan, M, u=None, stream=None):
+    """FMM potential at the targets (asynchronous on `stream`)."""
+    return _dev_call(_load().tfmm_evaluate, plan, M, u, stream)
+
+
+def tfmm_direct(plan, M, u=None, stream=None):
+    """O(N^2) direct sum of the exact tet integrals (asynchronous on `stream`)."""
+    return _dev_call(_load().tfmm_direct, plan, M, u, stream)
+
+
+def _host_call(fn, plan, M):
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    squeeze = M.ndim == 2
+    if squeeze:
+        M = M[None]
+    if M.shape[1:] != (plan.n_nodes, 3):
+        raise ValueError(f"M must be [F, {plan.n_nodes}, 3]")
+    u = np.zeros((M.shape[0], plan.n_targets))
+    _check(fn(plan.handle, _ptr(M, _dp), M.shape[0], _ptr(u, _dp)))
+    return u[0] if squeeze else u
+
+
+def tfmm_evaluate_host(plan, M):
+    return _host_call(_load().tfmm_evaluate_host, plan, M)
+
+
+def tfmm_direct_host(plan, M):
+    return _host_call(_load().tfmm_direct_host, plan, M)
+
+
+def tfmm_plan_stats(plan):
+    st = _Stats()
+    _check(_load().tfmm_plan_stats(plan.handle, C.byref(st)))
+    return {n: getattr(st, n) for n, _ in _Stats._fields_}
+
+
+def tfmm_plan_lists(plan, kind):
+    """kind 'm2l' or 'p2p' -> int32 [n, 8] (levA, ixA, iyA, izA, levB, ixB, iyB, izB)."""
+    k = {"m2l": 0, "p2p": 1}[kind]
+    n = _check(_load().tfmm_plan_lists(plan.handle, k, None))
+    out = np.zeros((n, 8), dtype=np.int32)
+    _check(_load().tfmm_plan_lists(plan.handle, k, _ptr(out, _i32p)))
+    return out
+
+
+def tfmm_plan_cells(plan):
+    n = _check(_load().tfmm_plan_cells(plan.handle, None, None))
+    cells = np.zeros((n, 6), dtype=np.int32)
+    radii = np.zeros((n, 2))
+    _check(_load().tfmm_plan_cells(plan.handle, _ptr(cells, _i32p), _ptr(radii, _dp)))
+    return cells, radii
+
+
+def tfmm_plan_expansions(plan, which):
+    """'Q' (multipole) or 'L' (local) of the last evaluation's last field: [n_cells, ncoef]."""
+    st = tfmm_plan_stats(plan)
+    out = np.zeros((st["n_cells"], st["ncoef"]))
+    _check(_load().tfmm_plan_expansions(plan.handle, {"Q": 0, "L": 1}[which], _ptr(out, _dp)))
+    return out
+
+
+def tfmm_plan_destroy(plan):
+    if plan._h is not None:
+        _check(_load().tfmm_plan_destroy(plan._h))
+        plan._h = None
+
+
+def tfmm_simplex_rule(degree):
+    """[npts, 4] rows (lambda1, lambda2, lambda3, weight) of the P2M quadrature."""
+    n = C.c_int32()
+    _check(_load().tfmm_simplex_rule(int(degree), None, C.byref(n)))
+    out = np.zeros((n.value, 4))
+    _check(_load().tfmm_simplex_rule(int(degree), _ptr(out, _dp), C.byref(n)))
+    return out
+
+
+def tfmm_set_timing(plan, on=True):
+    _check(_load().tfmm_set_timing(plan.handle, 1 if on else 0))
+
+
+def tfmm_kernel_times(plan):
+    """{kernel: (average ms per evaluation, number of evaluations timed)} of the timed evaluations."""
+    ms = np.zeros(len(KERNEL_NAMES))
+    n = np.zeros(len(KERNEL_NAMES), dtype=np.int64)
+    _check(_load().tfmm_kernel_times(plan.handle, _ptr(ms, _dp), _ptr(n, _i64p)))
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_NAMES)}

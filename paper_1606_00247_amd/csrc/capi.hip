@@ -1,0 +1,468 @@
+// C ABI of the tetrahedral FMM library (declared in include/tetfmm.h).
+// Every entry point converts failures into a TFMM_E* code plus a thread-local
+// message; no exception crosses the interface.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tetfmm.h"
+#include "device.h"
+#include "plan.h"
+
+struct tfmm_plan_s {
+    tfmm::DevicePlan dp;
+    bool on_device = false;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int set_error(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+// Runs f with the plan's device current, restoring the caller's device.
+template <class Fn>
+int guarded(Fn &&f)
+{
+    try {
+        return f();
+    } catch (const tfmm::PlanError &e) {
+        return set_error(e.code, e.msg);
+    } catch (const tfmm::DeviceError &e) {
+        return set_error(TFMM_EDEVICE, e.msg);
+    } catch (const std::bad_alloc &) {
+        return set_error(TFMM_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return set_error(TFMM_EINVAL, e.what());
+    } catch (...) {
+        return set_error(TFMM_EINVAL, "unknown failure");
+    }
+}
+
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev)
+    {
+        tfmm::hip_check(hipGetDevice(&prev), "hipGetDevice");
+        if (prev != dev) tfmm::hip_check(hipSetDevice(dev), "hipSetDevice");
+    }
+    ~DeviceScope()
+    {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+template <class T>
+T *dev_upload(const std::vector<T> &h, int64_t &bytes)
+{
+    T *d = nullptr;
+    size_t n = std::max<size_t>(h.size(), 1);
+    tfmm::hip_check(hipMalloc(&d, n * sizeof(T)), "hipMalloc");
+    bytes += (int64_t)(n * sizeof(T));
+    if (!h.empty()) tfmm::hip_check(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy H2D");
+    return d;
+}
+
+}  // namespace
+
+namespace tfmm {
+
+void upload_plan(DevicePlan &dp)
+{
+    const HostPlan &hp = dp.hp;
+    const int64_t T = hp.n_tets, N = hp.n_targets, C = (int64_t)hp.cells.size();
+    dp.ncoef = (hp.p + 1) * (hp.p + 2) * (hp.p + 3) / 6;
+    int64_t &B = dp.device_bytes;
+    B = 0;
+    {
+        std::vector<double> xyz(12 * T);
+        std::vector<int32_t> nd(4 * T);
+        for (int64_t s = 0; s < T; ++s)
+            for (int c = 0; c < 4; ++c) {
+                int32_t n = hp.tet_nodes[4 * s + c];
+                nd[c * T + s] = n;
+                for (int k = 0; k < 3; ++k) xyz[(3 * c + k) * T + s] = hp.nodes[3 * (int64_t)n + k];
+            }
+        dp.tet_xyz = dev_upload(xyz, B);
+        dp.tet_node = dev_upload(nd, B);
+    }
+    {
+        std::vector<double> xyz(3 * N);
+        std::vector<int32_t> leaf(N, -1);
+        for (int64_t s = 0; s < N; ++s)
+            for (int k = 0; k < 3; ++k) xyz[k * N + s] = hp.tgt_xyz[3 * s + k];
+        for (int64_t c = 0; c < C; ++c) {
+            const Cell &K = hp.cells[c];
+            if (K.nchild == 0)
+                for (int32_t s = K.xbeg; s < K.xend; ++s) leaf[s] = (int32_t)c;
+        }
+        dp.tgt_xyz = dev_upload(xyz, B);
+        dp.tgt_perm = dev_upload(hp.tgt_perm, B);
+        dp.tgt_leaf = dev_upload(leaf, B);
+    }
+    {
+        std::vector<double> cc(3 * C);
+        std::vector<int32_t> ci(8 * C);
+        for (int64_t c = 0; c < C; ++c) {
+            const Cell &K = hp.cells[c];
+            for (int k = 0; k < 3; ++k) cc[k * C + c] = K.c[k];
+            int32_t *o = &ci[8 * c];
+            o[0] = K.tbeg;
+            o[1] = K.tend;
+            o[2] = K.xbeg;
+            o[3] = K.xend;
+            o[4] = K.cbeg;
+            o[5] = K.nchild;
+            o[6] = K.parent;
+            o[7] = K.level;
+        }
+        dp.cell_c = dev_upload(cc, B);
+        dp.cell_i = dev_upload(ci, B);
+    }
+    {
+        std::vector<int32_t> p2m, m2m, l2l, m2lc;
+        dp.m2m_level_ptr.assign(hp.depth + 2, 0);
+        dp.l2l_level_ptr.assign(hp.depth + 2, 0);
+        for (int64_t c = 0; c < C; ++c) {
+            const Cell &K = hp.cells[c];
+            if (K.nchild == 0 && K.tend > K.tbeg) p2m.push_back((int32_t)c);
+            if (hp.m2l_ptr[c + 1] > hp.m2l_ptr[c]) m2lc.push_back((int32_t)c);
+        }
+        for (int Lv = 0; Lv <= hp.depth; ++Lv) {
+            dp.m2m_level_ptr[Lv] = (int32_t)m2m.size();
+            dp.l2l_level_ptr[Lv] = (int32_t)l2l.size();
+            for (int32_t c = hp.level_begin[Lv]; c < hp.level_begin[Lv + 1]; ++c) {
+                const Cell &K = hp.cells[c];
+                if (K.nchild > 0 && K.tend > K.tbeg) m2m.push_back(c);
+                if (Lv > 0 && K.xend > K.xbeg) l2l.push_back(c);
+            }
+        }
+        dp.m2m_level_ptr[hp.depth + 1] = (int32_t)m2m.size();
+        dp.l2l_level_ptr[hp.depth + 1] = (int32_t)l2l.size();
+        dp.n_p2m_cells = (int32_t)p2m.size();
+        dp.n_m2l_cells = (int32_t)m2lc.size();
+        dp.p2m_cells = dev_upload(p2m, B);
+        dp.m2m_cells = dev_upload(m2m, B);
+        dp.l2l_cells = dev_upload(l2l, B);
+        dp.m2l_cells = dev_upload(m2lc, B);
+        dp.m2l_ptr = dev_upload(hp.m2l_ptr, B);
+        dp.m2l_src = dev_upload(hp.m2l_src, B);
+    }
+    {
+        // P2P: source leaves with their target-leaf lists, cut into blocks of <= 64 tets
+        std::vector<int32_t> cnt(C + 1, 0);
+        for (size_t i = 0; i < hp.p2p_b.size(); ++i) cnt[hp.p2p_b[i] + 1]++;
+        for (int64_t c = 0; c < C; ++c) cnt[c + 1] += cnt[c];
+        std::vector<int32_t> tl(hp.p2p_a.size());
+        {
+            std::vector<int32_t> fillp(cnt.begin(), cnt.end() - 1);
+            for (size_t i = 0; i < hp.p2p_b.size(); ++i) tl[fillp[hp.p2p_b[i]]++] = hp.p2p_a[i];
+        }
+        std::vector<int32_t> blk, idx;
+        for (int64_t b = 0; b < C; ++b) {
+            if (cnt[b + 1] == cnt[b]) continue;
+            const int64_t ib = (int64_t)idx.size();
+            for (int32_t j = cnt[b]; j < cnt[b + 1]; ++j) {
+                const Cell &A = hp.cells[tl[j]];
+                for (int32_t s = A.xbeg; s < A.xend; ++s) idx.push_back(s);
+            }
+            const int64_t ie = (int64_t)idx.size();
+            if (ie > INT32_MAX) throw PlanError{TFMM_ENOTSUP, "near-field target list exceeds 2^31 entries"};
+            const Cell &Bc = hp.cells[b];
+            for (int32_t t = Bc.tbeg; t < Bc.tend; t += 64) {
+                blk.push_back(t);
+                blk.push_back(std::min(Bc.tend, t + 64));
+                blk.push_back((int32_t)ib);
+                blk.push_back((int32_t)ie);
+            }
+        }
+        dp.n_p2p_blk = (int32_t)(blk.size() / 4);
+        dp.n_p2p_idx = (int64_t)idx.size();
+        dp.p2p_blk = dev_upload(blk, B);
+        dp.p2p_idx = dev_upload(idx, B);
+    }
+    {
+        int np = 0;
+        std::vector<double> q = simplex_rule(hp.p, &np);
+        dp.nq = np;
+        dp.quad = dev_upload(q, B);
+    }
+}
+
+void free_plan(DevicePlan &dp)
+{
+    collect_timing(dp);
+    for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
+    dp.event_pool.clear();
+    void *ptrs[] = {dp.tet_xyz, dp.tet_node, dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, dp.cell_c, dp.cell_i,
+                    dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.m2l_cells, dp.m2l_ptr, dp.m2l_src, dp.p2p_blk,
+                    dp.p2p_idx, dp.quad, dp.Q, dp.L};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+}  // namespace tfmm
+
+extern "C" {
+
+const char *tfmm_last_error(void) { return g_last_error.c_str(); }
+
+int tfmm_plan_create(const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
+                     const double *targets, int64_t n_targets, const tfmm_params *prm, tfmm_plan *out)
+{
+    if (out) *out = nullptr;
+    if (!prm || !out) return set_error(TFMM_EINVAL, "prm and out must not be NULL");
+    if (prm->m2l_precision != TFMM_M2L_FP64) return set_error(TFMM_ENOTSUP, "unsupported m2l_precision");
+    return guarded([&]() -> int {
+        auto t0 = std::chrono::steady_clock::now();
+        std::unique_ptr<tfmm_plan_s> P(new tfmm_plan_s());
+        tfmm::build_host_plan(P->dp.hp, nodes, n_nodes, tets, n_tets, targets, n_targets, prm->p, prm->leaf_size,
+                              prm->theta);
+        P->dp.ncoef = (prm->p + 1) * (prm->p + 2) * (prm->p + 3) / 6;
+        if (prm->device >= 0) {
+            int ndev = 0;
+            if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+                return set_error(TFMM_EDEVICE, "no HIP device available");
+            if (prm->device >= ndev) return set_error(TFMM_EDEVICE, "device ordinal out of range");
+            P->dp.device = prm->device;
+            DeviceScope ds(prm->device);
+            try {
+                tfmm::upload_plan(P->dp);
+            } catch (...) {
+                tfmm::free_plan(P->dp);
+                throw;
+            }
+            P->on_device = true;
+        }
+        P->dp.hp.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *out = P.release();
+        return TFMM_OK;
+    });
+}
+
+int tfmm_plan_destroy(tfmm_plan plan)
+{
+    if (!plan) return TFMM_OK;
+    return guarded([&]() -> int {
+        if (plan->on_device) {
+            DeviceScope ds(plan->dp.device);
+            tfmm::free_plan(plan->dp);
+        }
+        delete plan;
+        return TFMM_OK;
+    });
+}
+
+static int check_eval_args(tfmm_plan plan, const double *M, int32_t F, double *u)
+{
+    if (!plan) return set_error(TFMM_EINVAL, "NULL plan");
+    if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan cannot evaluate");
+    if (F < 1 || !M || !u) return set_error(TFMM_EINVAL, "F must be >= 1 and M, u non-NULL");
+    return TFMM_OK;
+}
+
+int tfmm_evaluate(tfmm_plan plan, const double *M, int32_t F, double *u, void *hip_stream)
+{
+    int rc = check_eval_args(plan, M, F, u);
+    if (rc) return rc;
+    return guarded([&]() -> int {
+        DeviceScope ds(plan->dp.device);
+        tfmm::run_evaluate(plan->dp, M, F, u, (hipStream_t)hip_stream);
+        return TFMM_OK;
+    });
+}
+
+int tfmm_direct(tfmm_plan plan, const double *M, int32_t F, double *u, void *hip_stream)
+{
+    int rc = check_eval_args(plan, M, F, u);
+    if (rc) return rc;
+    return guarded([&]() -> int {
+        DeviceScope ds(plan->dp.device);
+        tfmm::run_direct(plan->dp, M, F, u, (hipStream_t)hip_stream);
+        return TFMM_OK;
+    });
+}
+
+static int host_eval(tfmm_plan plan, const double *M, int32_t F, double *u, bool direct)
+{
+    int rc = check_eval_args(plan, M, F, u);
+    if (rc) return rc;
+    return guarded([&]() -> int {
+        DeviceScope ds(plan->dp.device);
+        const size_t mb = sizeof(double) * (size_t)F * plan->dp.hp.n_nodes * 3;
+        const size_t ub = sizeof(double) * (size_t)F * plan->dp.hp.n_targets;
+        double *dM = nullptr, *du = nullptr;
+        tfmm::hip_check(hipMalloc(&dM, mb), "hipMalloc M");
+        if (hipMalloc(&du, ub) != hipSuccess) {
+            (void)hipFree(dM);
+            throw tfmm::DeviceError{"hipMalloc u failed"};
+        }
+        try {
+            tfmm::hip_check(hipMemcpy(dM, M, mb, hipMemcpyHostToDevice), "hipMemcpy M");
+            if (direct)
+                tfmm::run_direct(plan->dp, dM, F, du, nullptr);
+            else
+                tfmm::run_evaluate(plan->dp, dM, F, du, nullptr);
+            tfmm::hip_check(hipMemcpy(u, du, ub, hipMemcpyDeviceToHost), "hipMemcpy u");
+        } catch (...) {
+            (void)hipFree(dM);
+            (void)hipFree(du);
+            throw;
+        }
+        (void)hipFree(dM);
+        (void)hipFree(du);
+        return TFMM_OK;
+    });
+}
+
+int tfmm_evaluate_host(tfmm_plan plan, const double *M, int32_t F, double *u) { return host_eval(plan, M, F, u, false); }
+int tfmm_direct_host(tfmm_plan plan, const double *M, int32_t F, double *u) { return host_eval(plan, M, F, u, true); }
+
+int tfmm_plan_stats(tfmm_plan plan, tfmm_stats *out)
+{
+    if (!plan || !out) return set_error(TFMM_EINVAL, "NULL argument");
+    const tfmm::HostPlan &hp = plan->dp.hp;
+    std::memset(out, 0, sizeof(*out));
+    out->n_nodes = hp.n_nodes;
+    out->n_tets = hp.n_tets;
+    out->n_targets = hp.n_targets;
+    out->n_cells = (int64_t)hp.cells.size();
+    for (const auto &c : hp.cells) out->n_leaves += c.nchild == 0;
+    out->depth = hp.depth;
+    out->n_m2l = (int64_t)hp.m2l_src.size();
+    out->n_p2p = (int64_t)hp.p2p_a.size();
+    out->n_p2p_pairs = hp.n_p2p_pairs;
+    out->ncoef = plan->dp.ncoef;
+    out->device_bytes = plan->dp.device_bytes +
+                        (int64_t)(2 * sizeof(double) * (size_t)plan->dp.Fcap * hp.cells.size() * plan->dp.ncoef);
+    out->setup_seconds = hp.setup_seconds;
+    return TFMM_OK;
+}
+
+int64_t tfmm_plan_lists(tfmm_plan plan, int32_t kind, int32_t *out)
+{
+    if (!plan) return set_error(TFMM_EINVAL, "NULL plan");
+    if (kind != 0 && kind != 1) return set_error(TFMM_EINVAL, "kind must be 0 (M2L) or 1 (P2P)");
+    const tfmm::HostPlan &hp = plan->dp.hp;
+    auto put = [&](int64_t k, int32_t a, int32_t b) {
+        const tfmm::Cell &A = hp.cells[a], &B = hp.cells[b];
+        int32_t *o = out + 8 * k;
+        o[0] = A.level;
+        o[1] = A.ix;
+        o[2] = A.iy;
+        o[3] = A.iz;
+        o[4] = B.level;
+        o[5] = B.ix;
+        o[6] = B.iy;
+        o[7] = B.iz;
+    };
+    if (kind == 0) {
+        int64_t n = (int64_t)hp.m2l_src.size();
+        if (out) {
+            int64_t k = 0;
+            for (int64_t a = 0; a + 1 < (int64_t)hp.m2l_ptr.size(); ++a)
+                for (int32_t j = hp.m2l_ptr[a]; j < hp.m2l_ptr[a + 1]; ++j) put(k++, (int32_t)a, hp.m2l_src[j]);
+        }
+        return n;
+    }
+    int64_t n = (int64_t)hp.p2p_a.size();
+    if (out)
+        for (int64_t k = 0; k < n; ++k) put(k, hp.p2p_a[k], hp.p2p_b[k]);
+    return n;
+}
+
+int64_t tfmm_plan_cells(tfmm_plan plan, int32_t *cells, double *radii)
+{
+    if (!plan) return set_error(TFMM_EINVAL, "NULL plan");
+    const tfmm::HostPlan &hp = plan->dp.hp;
+    const int64_t n = (int64_t)hp.cells.size();
+    for (int64_t i = 0; i < n; ++i) {
+        const tfmm::Cell &c = hp.cells[i];
+        if (cells) {
+            int32_t *o = cells + 6 * i;
+            o[0] = c.level;
+            o[1] = c.ix;
+            o[2] = c.iy;
+            o[3] = c.iz;
+            o[4] = c.tend - c.tbeg;
+            o[5] = c.xend - c.xbeg;
+        }
+        if (radii) {
+            radii[2 * i] = c.rsrc;
+            radii[2 * i + 1] = c.rtgt;
+        }
+    }
+    return n;
+}
+
+int tfmm_plan_expansions(tfmm_plan plan, int32_t which, double *out)
+{
+    if (!plan || !out) return set_error(TFMM_EINVAL, "NULL argument");
+    if (!plan->on_device || plan->dp.last_F < 1) return set_error(TFMM_EINVAL, "no evaluation on this plan yet");
+    if (which != 0 && which != 1) return set_error(TFMM_EINVAL, "which must be 0 (Q) or 1 (L)");
+    return guarded([&]() -> int {
+        DeviceScope ds(plan->dp.device);
+        tfmm::hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        const size_t per = (size_t)plan->dp.hp.cells.size() * plan->dp.ncoef;
+        const double *src = (which == 0 ? plan->dp.Q : plan->dp.L) + per * (size_t)(plan->dp.last_F - 1);
+        tfmm::hip_check(hipMemcpy(out, src, per * sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy expansions");
+        return TFMM_OK;
+    });
+}
+
+int tfmm_simplex_rule(int32_t degree, double *out, int32_t *npts)
+{
+    if (!npts || degree < 0 || degree > 2 * TFMM_PMAX) return set_error(TFMM_EINVAL, "bad degree");
+    return guarded([&]() -> int {
+        int n = 0;
+        std::vector<double> r = tfmm::simplex_rule(degree, &n);
+        if (out) std::memcpy(out, r.data(), r.size() * sizeof(double));
+        *npts = n;
+        return TFMM_OK;
+    });
+}
+
+int tfmm_set_timing(tfmm_plan plan, int32_t on)
+{
+    if (!plan) return set_error(TFMM_EINVAL, "NULL plan");
+    return guarded([&]() -> int {
+        if (plan->on_device) {
+            DeviceScope ds(plan->dp.device);
+            tfmm::collect_timing(plan->dp);
+        }
+        tfmm::reset_timing(plan->dp);
+        plan->dp.timing = on != 0;
+        return TFMM_OK;
+    });
+}
+
+int tfmm_kernel_times(tfmm_plan plan, double *ms, int64_t *launches)
+{
+    if (!plan || !ms || !launches) return set_error(TFMM_EINVAL, "NULL argument");
+    if (plan->on_device) {
+        int rc = guarded([&]() -> int {
+            DeviceScope ds(plan->dp.device);
+            tfmm::collect_timing(plan->dp);
+            return TFMM_OK;
+        });
+        if (rc) return rc;
+    }
+    for (int i = 0; i < tfmm::KT_COUNT; ++i) {
+        ms[i] = plan->dp.kt_n[i] ? plan->dp.kt_ms[i] / (double)plan->dp.kt_n[i] : 0.0;
+        launches[i] = plan->dp.kt_n[i];
+    }
+    return TFMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Device-side plan and kernel launchers of the tetrahedral FMM (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "plan.h"
+
+namespace tfmm {
+
+// Thrown by launchers on HIP failures (converted to TFMM_EDEVICE at the ABI).
+struct DeviceError {
+    std::string msg;
+};
+
+void hip_check(hipError_t e, const char *what);
+
+// Kernel timing slots
+enum { KT_P2M = 0, KT_M2M, KT_M2L, KT_L2L, KT_L2P, KT_P2P, KT_COUNT };
+
+struct DevicePlan {
+    HostPlan hp;
+    int device = -1;
+    int ncoef = 0;  // (p+1)(p+2)(p+3)/6
+
+    // tets in octree order: corner coordinates [12][T] (row 3*c + axis) and
+    // corner node ids [4][T]
+    double *tet_xyz = nullptr;
+    int32_t *tet_node = nullptr;
+    // targets in octree order: [3][N], original index, leaf cell
+    double *tgt_xyz = nullptr;
+    int32_t *tgt_perm = nullptr;
+    int32_t *tgt_leaf = nullptr;
+    // cells: centres [3][C]; ints [C][8]: tbeg, tend, xbeg, xend, cbeg, nchild, parent, level
+    double *cell_c = nullptr;
+    int32_t *cell_i = nullptr;
+    // work lists
+    int32_t *p2m_cells = nullptr;  // leaves holding tets
+    int32_t n_p2m_cells = 0;
+    int32_t *m2m_cells = nullptr;  // per level: parents holding tets (host ranges below)
+    std::vector<int32_t> m2m_level_ptr;
+    int32_t *l2l_cells = nullptr;  // per level: non-root cells holding targets
+    std::vector<int32_t> l2l_level_ptr;
+    int32_t *m2l_cells = nullptr;  // target cells with a non-empty M2L list
+    int32_t n_m2l_cells = 0;
+    int32_t *m2l_ptr = nullptr, *m2l_src = nullptr;
+    // P2P: blocks of <= 64 tets of one source leaf with their target list
+    int32_t *p2p_blk = nullptr;  // [nblk][4]: tbeg, tend, ibeg, iend into p2p_idx
+    int32_t n_p2p_blk = 0;
+    int32_t *p2p_idx = nullptr;  // sorted-target indices
+    int64_t n_p2p_idx = 0;
+    // quadrature rule for P2M: [nq][4] = lambda1, lambda2, lambda3, weight
+    double *quad = nullptr;
+    int32_t nq = 0;
+    // expansions [Fcap][C][ncoef]
+    double *Q = nullptr, *L = nullptr;
+    int32_t Fcap = 0;
+    int32_t last_F = 0;
+
+    int64_t device_bytes = 0;
+
+    // timing: event pairs recorded on the evaluation stream around each phase,
+    // read back (and the device synchronised) only when the times are queried
+    bool timing = false;
+    struct Span {
+        int slot;
+        hipEvent_t a, b;
+    };
+    std::vector<Span> spans;
+    std::vector<hipEvent_t> event_pool;
+    size_t events_used = 0;
+    double kt_ms[KT_COUNT] = {0};
+    int64_t kt_n[KT_COUNT] = {0};
+};
+
+// Fold recorded spans into kt_ms / kt_n (synchronises on the recorded events).
+void collect_timing(DevicePlan &dp);
+void reset_timing(DevicePlan &dp);
+
+// Allocate and upload; hp must be built.  Throws DeviceError.
+void upload_plan(DevicePlan &dp);
+void free_plan(DevicePlan &dp);
+void ensure_expansions(DevicePlan &dp, int32_t F);
+
+// Queue the FMM evaluation of F fields on `stream`.
+void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t stream);
+// Queue the O(N^2) direct sum of F fields on `stream`.
+void run_direct(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t stream);
+
+// Collapsed Gauss-Jacobi rule on the unit simplex exact to total degree `deg`:
+// rows lambda1, lambda2, lambda3, weight (weights sum to 1/6).
+std::vector<double> simplex_rule(int deg, int *npts);
+
+}  // namespace tfmm

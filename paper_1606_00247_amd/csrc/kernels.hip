@@ -1,0 +1,968 @@
+// HIP kernels of the tetrahedral FMM for CDNA4 (gfx950), FP64.
+//
+//   p2m   multipole coefficients of the tets of a leaf (eq. expCoeffs) by an
+//         exact collapsed Gauss-Jacobi rule, reduced per leaf in LDS
+//   m2m   binomial shift of child multipoles to the parent centre
+//   m2l   multipole -> local translation of the Cartesian Taylor expansion
+//   l2l   binomial shift of a local expansion to the child centres
+//   l2p   evaluation of the local expansion at the targets (writes u)
+//   p2p   exact near-field tet-to-target potential (Sec. 2.1), source-major:
+//         one workgroup per block of <= 64 tets of a source leaf, the tets'
+//         geometry and field coefficients staged in LDS, every lane a target,
+//         atomically accumulated into u
+//
+// Multi-indices |n| <= p are stored in graded order: degree ascending, within
+// a degree n_x descending, then n_y descending.  idx(n) = d(d+1)(d+2)/6 +
+// r(r+1)/2 + n_z with d = |n| and r = n_y + n_z.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/tetfmm.h"
+#include "device.h"
+
+namespace tfmm {
+
+// ---------------------------------------------------------------------------
+// constant tables
+// ---------------------------------------------------------------------------
+constexpr int kPmax = TFMM_PMAX;
+constexpr int kNcoefMax = (kPmax + 1) * (kPmax + 2) * (kPmax + 3) / 6;
+
+struct MiTable {
+    int8_t v[kNcoefMax][4];  // nx, ny, nz, |n|
+};
+constexpr MiTable make_mi()
+{
+    MiTable t{};
+    int k = 0;
+    for (int d = 0; d <= kPmax; ++d)
+        for (int nx = d; nx >= 0; --nx)
+            for (int ny = d - nx; ny >= 0; --ny) {
+                t.v[k][0] = (int8_t)nx;
+                t.v[k][1] = (int8_t)ny;
+                t.v[k][2] = (int8_t)(d - nx - ny);
+                t.v[k][3] = (int8_t)d;
+                ++k;
+            }
+    return t;
+}
+struct BinomTable {
+    double c[2 * kPmax + 1][2 * kPmax + 1];
+    double invfact[2 * kPmax + 1];
+};
+constexpr BinomTable make_binom()
+{
+    BinomTable t{};
+    for (int n = 0; n <= 2 * kPmax; ++n)
+        for (int r = 0; r <= 2 * kPmax; ++r) t.c[n][r] = 0.0;
+    for (int n = 0; n <= 2 * kPmax; ++n) {
+        t.c[n][0] = 1.0;
+        for (int r = 1; r <= n; ++r) t.c[n][r] = t.c[n - 1][r - 1] + (r <= n - 1 ? t.c[n - 1][r] : 0.0);
+    }
+    double f = 1.0;
+    for (int n = 0; n <= 2 * kPmax; ++n) {
+        if (n > 0) f *= n;
+        t.invfact[n] = 1.0 / f;
+    }
+    return t;
+}
+__constant__ MiTable c_mi = make_mi();
+__constant__ BinomTable c_bin = make_binom();
+
+__device__ __forceinline__ int mi_index(int nx, int ny, int nz)
+{
+    int d = nx + ny + nz, r = ny + nz;
+    return d * (d + 1) * (d + 2) / 6 + r * (r + 1) / 2 + nz;
+}
+__host__ __device__ constexpr int ncoef_of(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+constexpr double kInv4Pi = 0.07957747154594767;  // 1/(4 pi)
+
+// cell int fields
+enum { CI_TBEG = 0, CI_TEND, CI_XBEG, CI_XEND, CI_CBEG, CI_NCHILD, CI_PARENT, CI_LEVEL, CI_N };
+
+// ---------------------------------------------------------------------------
+// fill
+// ---------------------------------------------------------------------------
+__global__ void k_fill(double *__restrict__ a, int64_t n, double v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) a[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// P2M.  One workgroup per leaf with tets (blockIdx.x), field blockIdx.y.
+//   W_{k,m} = sum_points w M_k(y) (y - c)^m,  |m| <= p-1
+//   Q_n     = sum_k n_k W_{k, n - e_k},  Q_0 = 0
+// Points are (tet, quadrature node) pairs, CH at a time: every thread builds
+// one point's powers of (y - c) and w M(y) in LDS, then thread j accumulates
+// monomial j over the chunk.
+// ---------------------------------------------------------------------------
+constexpr int kP2MThreads = 256;
+constexpr int kP2MChunk = 256;
+
+__global__ __launch_bounds__(kP2MThreads) void k_p2m(const int32_t *__restrict__ cells, const int32_t *__restrict__ cell_i,
+                                                     const double *__restrict__ cell_c, int64_t C,
+                                                     const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node,
+                                                     int64_t T, const double *__restrict__ quad, int nq,
+                                                     const double *__restrict__ M, int64_t n_nodes, int p,
+                                                     double *__restrict__ Q)
+{
+    __shared__ double s_pw[kP2MChunk][3][kPmax];  // powers 0..p-1 of (y - c)
+    __shared__ double s_wm[kP2MChunk][3];
+    __shared__ double s_W[3][ncoef_of(kPmax - 1)];
+    const int cell = cells[blockIdx.x];
+    const int f = blockIdx.y;
+    const double *Mf = M + (int64_t)f * n_nodes * 3;
+    const int tbeg = cell_i[CI_N * cell + CI_TBEG], tend = cell_i[CI_N * cell + CI_TEND];
+    const double cx = cell_c[cell], cy = cell_c[C + cell], cz = cell_c[2 * C + cell];
+    const int nmono = ncoef_of(p - 1);
+    const int ncoef = ncoef_of(p);
+    const int tid = threadIdx.x;
+    int ma = 0, mb = 0, mc = 0;
+    if (tid < nmono) {
+        ma = c_mi.v[tid][0];
+        mb = c_mi.v[tid][1];
+        mc = c_mi.v[tid][2];
+    }
+    double W0 = 0.0, W1 = 0.0, W2 = 0.0;
+    const int npts = (tend - tbeg) * nq;
+    for (int base = 0; base < npts; base += kP2MChunk) {
+        const int g = base + tid;
+        if (g < npts) {
+            const int t = tbeg + g / nq, q = g % nq;
+            const double l1 = quad[4 * q], l2 = quad[4 * q + 1], l3 = quad[4 * q + 2], w = quad[4 * q + 3];
+            const double l0 = 1.0 - (l1 + l2 + l3);
+            double v[4][3], m[4][3];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int nd = tet_node[(int64_t)c * T + t];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    v[c][k] = tet_xyz[(int64_t)(3 * c + k) * T + t];
+                    m[c][k] = Mf[3 * (int64_t)nd + k];
+                }
+            }
+            double e[3][3];
+#pragma unroll
+            for (int c = 1; c < 4; ++c)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) e[c - 1][k] = v[c][k] - v[0][k];
+            const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                               e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                               e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+            const double wv = w * fabs(det);  // 6 |V| w
+            const double cc[3] = {cx, cy, cz};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double y = l0 * v[0][k] + l1 * v[1][k] + l2 * v[2][k] + l3 * v[3][k] - cc[k];
+                s_wm[tid][k] = wv * (l0 * m[0][k] + l1 * m[1][k] + l2 * m[2][k] + l3 * m[3][k]);
+                double pw = 1.0;
+                for (int j = 0; j < p; ++j) {
+                    s_pw[tid][k][j] = pw;
+                    pw *= y;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < nmono) {
+            const int n = min(kP2MChunk, npts - base);
+            for (int i = 0; i < n; ++i) {
+                const double mono = s_pw[i][0][ma] * s_pw[i][1][mb] * s_pw[i][2][mc];
+                W0 += s_wm[i][0] * mono;
+                W1 += s_wm[i][1] * mono;
+                W2 += s_wm[i][2] * mono;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid < nmono) {
+        s_W[0][tid] = W0;
+        s_W[1][tid] = W1;
+        s_W[2][tid] = W2;
+    }
+    __syncthreads();
+    double *Qc = Q + ((int64_t)f * C + cell) * ncoef;
+    for (int n = tid; n < ncoef; n += blockDim.x) {
+        const int nx = c_mi.v[n][0], ny = c_mi.v[n][1], nz = c_mi.v[n][2];
+        double s = 0.0;
+        if (nx > 0) s += nx * s_W[0][mi_index(nx - 1, ny, nz)];
+        if (ny > 0) s += ny * s_W[1][mi_index(nx, ny - 1, nz)];
+        if (nz > 0) s += nz * s_W[2][mi_index(nx, ny, nz - 1)];
+        Qc[n] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// M2M.  One workgroup per parent cell of a level (blockIdx.x), field blockIdx.y.
+//   Q_n(P) = sum_children sum_{k <= n} C(n,k) (c_C - c_P)^{n-k} Q_k(C)
+// ---------------------------------------------------------------------------
+constexpr int kShiftThreads = 256;
+
+__global__ __launch_bounds__(kShiftThreads) void k_m2m(const int32_t *__restrict__ cells, const int32_t *__restrict__ cell_i,
+                                                       const double *__restrict__ cell_c, int64_t C, int p,
+                                                       double *__restrict__ Q)
+{
+    __shared__ double s_q[kNcoefMax];
+    __shared__ double s_pw[3][kPmax + 1];
+    const int cell = cells[blockIdx.x];
+    const int f = blockIdx.y;
+    const int ncoef = ncoef_of(p);
+    const int cbeg = cell_i[CI_N * cell + CI_CBEG], nch = cell_i[CI_N * cell + CI_NCHILD];
+    double acc[2] = {0.0, 0.0};
+    for (int ch = cbeg; ch < cbeg + nch; ++ch) {
+        if (cell_i[CI_N * ch + CI_TEND] == cell_i[CI_N * ch + CI_TBEG]) continue;  // no tets
+        __syncthreads();
+        const double *Qc = Q + ((int64_t)f * C + ch) * ncoef;
+        for (int n = threadIdx.x; n < ncoef; n += blockDim.x) s_q[n] = Qc[n];
+        if (threadIdx.x < 3) {
+            const int k = threadIdx.x;
+            const double dlt = cell_c[k * C + ch] - cell_c[k * C + cell];
+            double pw = 1.0;
+            for (int j = 0; j <= p; ++j) {
+                s_pw[k][j] = pw;
+                pw *= dlt;
+            }
+        }
+        __syncthreads();
+        for (int r = 0; r < 2; ++r) {
+            const int n = threadIdx.x + r * blockDim.x;
+            if (n >= ncoef) break;
+            const int nx = c_mi.v[n][0], ny = c_mi.v[n][1], nz = c_mi.v[n][2];
+            double s = 0.0;
+            for (int kx = 0; kx <= nx; ++kx) {
+                const double ax = c_bin.c[nx][kx] * s_pw[0][nx - kx];
+                for (int ky = 0; ky <= ny; ++ky) {
+                    const double axy = ax * c_bin.c[ny][ky] * s_pw[1][ny - ky];
+                    for (int kz = 0; kz <= nz; ++kz)
+                        s += axy * c_bin.c[nz][kz] * s_pw[2][nz - kz] * s_q[mi_index(kx, ky, kz)];
+                }
+            }
+            acc[r] += s;
+        }
+    }
+    double *Qp = Q + ((int64_t)f * C + cell) * ncoef;
+    for (int r = 0; r < 2; ++r) {
+        const int n = threadIdx.x + r * blockDim.x;
+        if (n < ncoef) Qp[n] = acc[r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// L2L.  One workgroup per child cell of a level (blockIdx.x), field blockIdx.y.
+//   l_m(C) += sum_{k >= m, |k| <= p} C(k,m) (c_C - c_P)^{k-m} l_k(P)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kShiftThreads) void k_l2l(const int32_t *__restrict__ cells, const int32_t *__restrict__ cell_i,
+                                                       const double *__restrict__ cell_c, int64_t C, int p,
+                                                       double *__restrict__ L)
+{
+    __shared__ double s_l[kNcoefMax];
+    __shared__ double s_pw[3][kPmax + 1];
+    const int cell = cells[blockIdx.x];
+    const int f = blockIdx.y;
+    const int ncoef = ncoef_of(p);
+    const int par = cell_i[CI_N * cell + CI_PARENT];
+    const double *Lp = L + ((int64_t)f * C + par) * ncoef;
+    for (int n = threadIdx.x; n < ncoef; n += blockDim.x) s_l[n] = Lp[n];
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        const double dlt = cell_c[k * C + cell] - cell_c[k * C + par];
+        double pw = 1.0;
+        for (int j = 0; j <= p; ++j) {
+            s_pw[k][j] = pw;
+            pw *= dlt;
+        }
+    }
+    __syncthreads();
+    double *Lc = L + ((int64_t)f * C + cell) * ncoef;
+    for (int m = threadIdx.x; m < ncoef; m += blockDim.x) {
+        const int mx = c_mi.v[m][0], my = c_mi.v[m][1], mz = c_mi.v[m][2], dm = c_mi.v[m][3];
+        double s = 0.0;
+        for (int kx = mx; kx <= p - (my + mz); ++kx) {
+            const double ax = c_bin.c[kx][mx] * s_pw[0][kx - mx];
+            for (int ky = my; ky <= p - kx - mz; ++ky) {
+                const double axy = ax * c_bin.c[ky][my] * s_pw[1][ky - my];
+                for (int kz = mz; kz <= p - kx - ky; ++kz)
+                    s += axy * c_bin.c[kz][mz] * s_pw[2][kz - mz] * s_l[mi_index(kx, ky, kz)];
+            }
+        }
+        (void)dm;
+        Lc[m] += s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// M2L.  One wavefront per target cell (blockIdx.x), field blockIdx.y.
+// With D_k(R) = d^k/dR^k (1/|R|) and Qh_n = (-1)^|n| Q_n / n!:
+//   l_m(A) = 1/(4 pi m!) sum_B sum_{|n|>=1, |n|+|m|<=p} D_{n+m}(c_A - c_B) Qh_n(B)
+// D is generated degree by degree by
+//   |k| r^2 D_k = -(2|k|-1) sum_i k_i R_i D_{k-e_i} - (|k|-1) sum_i k_i (k_i-1) D_{k-2e_i}
+// ---------------------------------------------------------------------------
+constexpr int kM2LThreads = 64;
+constexpr int kM2LPerLane = (kNcoefMax + kM2LThreads - 1) / kM2LThreads;
+
+__global__ __launch_bounds__(kM2LThreads) void k_m2l(const int32_t *__restrict__ tcells, const int32_t *__restrict__ ptr,
+                                                     const int32_t *__restrict__ src, const double *__restrict__ cell_c,
+                                                     int64_t C, int p, const double *__restrict__ Q,
+                                                     double *__restrict__ L)
+{
+    __shared__ double s_D[kNcoefMax];
+    __shared__ double s_q[kNcoefMax];
+    const int A = tcells[blockIdx.x];
+    const int f = blockIdx.y;
+    const int ncoef = ncoef_of(p);
+    const int lane = threadIdx.x;
+    const double ax = cell_c[A], ay = cell_c[C + A], az = cell_c[2 * C + A];
+    double acc[kM2LPerLane];
+#pragma unroll
+    for (int r = 0; r < kM2LPerLane; ++r) acc[r] = 0.0;
+    for (int j = ptr[A]; j < ptr[A + 1]; ++j) {
+        const int B = src[j];
+        const double Rx = ax - cell_c[B], Ry = ay - cell_c[C + B], Rz = az - cell_c[2 * C + B];
+        const double r2 = (Rx * Rx + Ry * Ry) + Rz * Rz;
+        const double *Qb = Q + ((int64_t)f * C + B) * ncoef;
+        __syncthreads();
+        for (int n = lane; n < ncoef; n += kM2LThreads) {
+            const int dn = c_mi.v[n][3];
+            const double sg = (dn & 1) ? -1.0 : 1.0;
+            s_q[n] = sg * Qb[n] * c_bin.invfact[c_mi.v[n][0]] * c_bin.invfact[c_mi.v[n][1]] * c_bin.invfact[c_mi.v[n][2]];
+        }
+        if (lane == 0) s_D[0] = 1.0 / sqrt(r2);
+        __syncthreads();
+        for (int d = 1; d <= p; ++d) {
+            const int b = d * (d + 1) * (d + 2) / 6, cnt = (d + 1) * (d + 2) / 2;
+            for (int e = lane; e < cnt; e += kM2LThreads) {
+                const int k = b + e;
+                const int kx = c_mi.v[k][0], ky = c_mi.v[k][1], kz = c_mi.v[k][2];
+                double s1 = 0.0, s2 = 0.0;
+                if (kx > 0) s1 += kx * Rx * s_D[mi_index(kx - 1, ky, kz)];
+                if (ky > 0) s1 += ky * Ry * s_D[mi_index(kx, ky - 1, kz)];
+                if (kz > 0) s1 += kz * Rz * s_D[mi_index(kx, ky, kz - 1)];
+                if (kx > 1) s2 += kx * (kx - 1) * s_D[mi_index(kx - 2, ky, kz)];
+                if (ky > 1) s2 += ky * (ky - 1) * s_D[mi_index(kx, ky - 2, kz)];
+                if (kz > 1) s2 += kz * (kz - 1) * s_D[mi_index(kx, ky, kz - 2)];
+                s_D[k] = -((2.0 * d - 1.0) * s1 + (d - 1.0) * s2) / (d * r2);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < kM2LPerLane; ++r) {
+            const int m = lane + r * kM2LThreads;
+            if (m >= ncoef) break;
+            const int mx = c_mi.v[m][0], my = c_mi.v[m][1], mz = c_mi.v[m][2], dm = c_mi.v[m][3];
+            double s = 0.0;
+            for (int dn = 1; dn <= p - dm; ++dn)
+                for (int nx = dn; nx >= 0; --nx)
+                    for (int ny = dn - nx; ny >= 0; --ny) {
+                        const int nz = dn - nx - ny;
+                        s += s_D[mi_index(nx + mx, ny + my, nz + mz)] * s_q[mi_index(nx, ny, nz)];
+                    }
+            acc[r] += s;
+        }
+    }
+    double *La = L + ((int64_t)f * C + A) * ncoef;
+#pragma unroll
+    for (int r = 0; r < kM2LPerLane; ++r) {
+        const int m = lane + r * kM2LThreads;
+        if (m < ncoef)
+            La[m] = acc[r] * kInv4Pi * c_bin.invfact[c_mi.v[m][0]] * c_bin.invfact[c_mi.v[m][1]] *
+                    c_bin.invfact[c_mi.v[m][2]];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// L2P.  One thread per target (octree order); writes u[f][perm[i]].
+//   u(x) = sum_m l_m (x - c)^m
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_l2p(const double *__restrict__ tgt_xyz, const int32_t *__restrict__ tgt_perm,
+                                             const int32_t *__restrict__ tgt_leaf, int64_t N,
+                                             const double *__restrict__ cell_c, int64_t C, int p,
+                                             const double *__restrict__ L, double *__restrict__ u)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int f = blockIdx.y;
+    if (i >= N) return;
+    const int leaf = tgt_leaf[i];
+    const int ncoef = ncoef_of(p);
+    const double y[3] = {tgt_xyz[i] - cell_c[leaf], tgt_xyz[N + i] - cell_c[C + leaf],
+                         tgt_xyz[2 * N + i] - cell_c[2 * C + leaf]};
+    double pw[3][kPmax + 1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        pw[k][0] = 1.0;
+#pragma unroll
+        for (int j = 1; j <= kPmax; ++j) pw[k][j] = pw[k][j - 1] * y[k];
+    }
+    const double *Ll = L + ((int64_t)f * C + leaf) * ncoef;
+    double s = 0.0;
+    for (int m = 0; m < ncoef; ++m) {
+        const int a = c_mi.v[m][0], b = c_mi.v[m][1], c = c_mi.v[m][2];
+        double px = 1.0, py = 1.0, pz = 1.0;
+#pragma unroll
+        for (int j = 1; j <= kPmax; ++j) {
+            px = (j == a) ? pw[0][j] : px;
+            py = (j == b) ? pw[1][j] : py;
+            pz = (j == c) ? pw[2][j] : pz;
+        }
+        s += Ll[m] * (px * py * pz);
+    }
+    u[(int64_t)f * N + tgt_perm[i]] = s;
+}
+
+// ---------------------------------------------------------------------------
+// P2P / direct sum: exact potential of linearly magnetised tets (Sec. 2.1).
+//
+// For a tet with outward face normals n_k (face k opposite corner k), target
+// x, d_i = v_i - x, the potential is (integration by parts into the faces)
+//   4 pi u_T(x) = sum_k alpha_k(x) I0_k(x) + sum_e gamma_e g_e(x)
+// with the face single-layer integral of a constant density
+//   I0_k = sum_{e in k} t0_{k,e} f_e - h_k Omega_k,
+// the edge terms  f_e = ln((R_b + l_b)/(R_a + l_a)),
+//                 g_e = R0_e^2 f_e + l_b R_b - l_a R_a  (edge e = (a, b)),
+// h_k = n_k . d (signed height), Omega_k the signed solid angle of face k,
+// t0_{k,e} the in-plane distance of x's projection to edge e, and the field
+// coefficients (G = dM/dr, M_0 the value at corner 0)
+//   alpha_k = M(x).n_k + h_k (n_k.G n_k - div M / 2),  M(x) = M_0 - G d_0,
+//   gamma_e = 1/2 sum_{faces k of e} (G^T n_k) . u_{k,e},
+// u_{k,e} the outward in-plane normal of edge e in face k.
+//
+// Corner order after orientation (positive volume) fixes the faces, counter-
+// clockwise about the outward normal:
+//   F0 = (1,2,3), F1 = (0,3,2), F2 = (0,1,3), F3 = (0,2,1)
+// and edges e0..e5 = (0,1),(0,2),(0,3),(1,2),(1,3),(2,3).
+// ---------------------------------------------------------------------------
+constexpr int kP2PThreads = 256;
+constexpr int kP2PTets = 64;  // tets per block
+constexpr int kEa[6] = {0, 0, 0, 1, 1, 2};
+constexpr int kEb[6] = {1, 2, 3, 2, 3, 3};
+// face k: its three edges and the orientation sign of each
+constexpr int kFe[4][3] = {{3, 5, 4}, {2, 5, 1}, {0, 4, 2}, {1, 3, 0}};
+constexpr double kFs[4][3] = {{1, 1, -1}, {1, -1, -1}, {1, 1, -1}, {1, -1, -1}};
+// face k: counter-clockwise corners
+constexpr int kFv[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
+
+struct TetGeom {
+    double v[4][3];
+    double n[4][3];
+    double il[6];  // 1 / edge length
+};
+struct TetField {
+    double a[4];     // M_0 . n_k
+    double b[4][3];  // G^T n_k
+    double c[4];     // n_k . G n_k - div M / 2
+    double g[6];     // gamma_e
+};
+
+__device__ inline void tet_prepare(const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node, int64_t T,
+                                   int64_t t, const double *__restrict__ M, int64_t n_nodes, int F, TetGeom &G,
+                                   TetField *fld)
+{
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) G.v[c][k] = tet_xyz[(int64_t)(3 * c + k) * T + t];
+    double N[4][3];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const int a = kFv[f][0], b = kFv[f][1], c = kFv[f][2];
+        double u[3], w[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            u[k] = G.v[b][k] - G.v[a][k];
+            w[k] = G.v[c][k] - G.v[a][k];
+        }
+        N[f][0] = u[1] * w[2] - u[2] * w[1];
+        N[f][1] = u[2] * w[0] - u[0] * w[2];
+        N[f][2] = u[0] * w[1] - u[1] * w[0];
+        const double inv = 1.0 / sqrt(N[f][0] * N[f][0] + N[f][1] * N[f][1] + N[f][2] * N[f][2]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) G.n[f][k] = N[f][k] * inv;
+    }
+    double eh[6][3];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        double d[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = G.v[kEb[e]][k] - G.v[kEa[e]][k];
+        const double il = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        G.il[e] = il;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) eh[e][k] = d[k] * il;
+    }
+    // gradients of the barycentric coordinates
+    double e1[3], e2[3], e3[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = G.v[1][k] - G.v[0][k];
+        e2[k] = G.v[2][k] - G.v[0][k];
+        e3[k] = G.v[3][k] - G.v[0][k];
+    }
+    double gl[4][3];
+    gl[1][0] = e2[1] * e3[2] - e2[2] * e3[1];
+    gl[1][1] = e2[2] * e3[0] - e2[0] * e3[2];
+    gl[1][2] = e2[0] * e3[1] - e2[1] * e3[0];
+    gl[2][0] = e3[1] * e1[2] - e3[2] * e1[1];
+    gl[2][1] = e3[2] * e1[0] - e3[0] * e1[2];
+    gl[2][2] = e3[0] * e1[1] - e3[1] * e1[0];
+    gl[3][0] = e1[1] * e2[2] - e1[2] * e2[1];
+    gl[3][1] = e1[2] * e2[0] - e1[0] * e2[2];
+    gl[3][2] = e1[0] * e2[1] - e1[1] * e2[0];
+    const double idet = 1.0 / (e1[0] * gl[1][0] + e1[1] * gl[1][1] + e1[2] * gl[1][2]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        gl[1][k] *= idet;
+        gl[2][k] *= idet;
+        gl[3][k] *= idet;
+        gl[0][k] = -(gl[1][k] + gl[2][k] + gl[3][k]);
+    }
+    int nd[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) nd[c] = tet_node[(int64_t)c * T + t];
+    for (int f = 0; f < F; ++f) {
+        const double *Mf = M + (int64_t)f * n_nodes * 3;
+        double m[4][3];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) m[c][k] = Mf[3 * (int64_t)nd[c] + k];
+        // div M = sum_i M_i . grad lambda_i
+        double divM = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) divM += m[c][0] * gl[c][0] + m[c][1] * gl[c][1] + m[c][2] * gl[c][2];
+        TetField &F1 = fld[f];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            // G^T n = sum_i (M_i . n) grad lambda_i
+            double b[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double mn = m[c][0] * G.n[k][0] + m[c][1] * G.n[k][1] + m[c][2] * G.n[k][2];
+                b[0] += mn * gl[c][0];
+                b[1] += mn * gl[c][1];
+                b[2] += mn * gl[c][2];
+            }
+            F1.a[k] = m[0][0] * G.n[k][0] + m[0][1] * G.n[k][1] + m[0][2] * G.n[k][2];
+            F1.b[k][0] = b[0];
+            F1.b[k][1] = b[1];
+            F1.b[k][2] = b[2];
+            F1.c[k] = (b[0] * G.n[k][0] + b[1] * G.n[k][1] + b[2] * G.n[k][2]) - 0.5 * divM;
+        }
+#pragma unroll
+        for (int e = 0; e < 6; ++e) F1.g[e] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int e = kFe[k][j];
+                const double s = kFs[k][j];
+                // u_{k,e} = (s e_hat) x n_k
+                const double ux = s * (eh[e][1] * G.n[k][2] - eh[e][2] * G.n[k][1]);
+                const double uy = s * (eh[e][2] * G.n[k][0] - eh[e][0] * G.n[k][2]);
+                const double uz = s * (eh[e][0] * G.n[k][1] - eh[e][1] * G.n[k][0]);
+                F1.g[e] += 0.5 * (F1.b[k][0] * ux + F1.b[k][1] * uy + F1.b[k][2] * uz);
+            }
+    }
+}
+
+// Geometric part of one pair: I0_k, g_e, h_k and d_0.
+__device__ __forceinline__ void pair_geometry(const double x[3], const TetGeom &G, double I0[4], double ge[6],
+                                              double h[4], double d0[3])
+{
+    double d[4][3], R2[4], R[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[c][k] = G.v[c][k] - x[k];
+        R2[c] = d[c][0] * d[c][0] + d[c][1] * d[c][1] + d[c][2] * d[c][2];
+        R[c] = sqrt(R2[c]);
+    }
+    d0[0] = d[0][0];
+    d0[1] = d[0][1];
+    d0[2] = d[0][2];
+    double D[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a + 1; b < 4; ++b) D[a][b] = D[b][a] = d[a][0] * d[b][0] + d[a][1] * d[b][1] + d[a][2] * d[b][2];
+    double cx[6][3], fl[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        const int a = kEa[e], b = kEb[e];
+        const double il = G.il[e];
+        cx[e][0] = d[a][1] * d[b][2] - d[a][2] * d[b][1];
+        cx[e][1] = d[a][2] * d[b][0] - d[a][0] * d[b][2];
+        cx[e][2] = d[a][0] * d[b][1] - d[a][1] * d[b][0];
+        const double r0sq = (cx[e][0] * cx[e][0] + cx[e][1] * cx[e][1] + cx[e][2] * cx[e][2]) * (il * il);
+        const double la = (D[a][b] - R2[a]) * il;  // (v_a - x) . e_hat
+        const double lb = (R2[b] - D[a][b]) * il;  // (v_b - x) . e_hat
+        // f = ln((R_b + l_b)/(R_a + l_a)) in a form free of cancellation
+        const bool fwd = la >= 0.0, bwd = lb <= 0.0;
+        const double num = fwd ? (R[b] + lb) : (bwd ? (R[a] - la) : (R[b] + lb) * (R[a] - la));
+        const double den = fwd ? (R[a] + la) : (bwd ? (R[b] - lb) : r0sq);
+        const bool ok = (R[a] > 0.0) && (R[b] > 0.0) && (den > 0.0);
+        const double f = ok ? log(num / den) : 0.0;  // factors t0 and R0^2 vanish otherwise
+        fl[e] = f * il;
+        ge[e] = r0sq * f + lb * R[b] - la * R[a];
+    }
+    // faces
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int a = kFv[k][0], b = kFv[k][1], c = kFv[k][2];
+        const double hk = G.n[k][0] * d[a][0] + G.n[k][1] * d[a][1] + G.n[k][2] * d[a][2];
+        h[k] = hk;
+        // det[d_a, d_b, d_c] = d_c . (d_a x d_b); edge (a,b) of face k is kFe[k][0]
+        const int e0 = kFe[k][0];
+        const double det = kFs[k][0] * (d[c][0] * cx[e0][0] + d[c][1] * cx[e0][1] + d[c][2] * cx[e0][2]);
+        const double den = R[a] * R[b] * R[c] + D[a][b] * R[c] + D[a][c] * R[b] + D[b][c] * R[a];
+        const double omega = 2.0 * atan2(det, den);
+        double s = -hk * omega;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int e = kFe[k][j];
+            const double t0l = kFs[k][j] * (G.n[k][0] * cx[e][0] + G.n[k][1] * cx[e][1] + G.n[k][2] * cx[e][2]);
+            s += t0l * fl[e];
+        }
+        I0[k] = s;
+    }
+}
+
+template <int FCH>
+__global__ __launch_bounds__(kP2PThreads) void k_p2p(const int32_t *__restrict__ blk, int direct_tets, int64_t T,
+                                                     const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node,
+                                                     const int32_t *__restrict__ idx, const double *__restrict__ tgt_xyz,
+                                                     const int32_t *__restrict__ tgt_perm, int64_t N,
+                                                     const double *__restrict__ M, int64_t n_nodes, int f0,
+                                                     double *__restrict__ u)
+{
+    __shared__ TetGeom s_g[kP2PTets];
+    __shared__ TetField s_f[kP2PTets][FCH];
+    int tb, te, ib, ie;
+    if (direct_tets) {  // direct sum: consecutive tets, all targets
+        tb = blockIdx.x * kP2PTets;
+        te = min<int64_t>(T, tb + kP2PTets);
+        ib = 0;
+        ie = (int)N;
+    } else {
+        tb = blk[4 * blockIdx.x];
+        te = blk[4 * blockIdx.x + 1];
+        ib = blk[4 * blockIdx.x + 2];
+        ie = blk[4 * blockIdx.x + 3];
+    }
+    const int nt = te - tb;
+    const double *Mf0 = M + (int64_t)f0 * n_nodes * 3;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x)
+        tet_prepare(tet_xyz, tet_node, T, tb + t, Mf0, n_nodes, FCH, s_g[t], s_f[t]);
+    __syncthreads();
+    for (int i = ib + threadIdx.x; i < ie; i += blockDim.x) {
+        const int s = direct_tets ? i : idx[i];
+        const double x[3] = {tgt_xyz[s], tgt_xyz[N + s], tgt_xyz[2 * N + s]};
+        double acc[FCH];
+#pragma unroll
+        for (int f = 0; f < FCH; ++f) acc[f] = 0.0;
+        for (int t = 0; t < nt; ++t) {
+            double I0[4], ge[6], h[4], d0[3];
+            pair_geometry(x, s_g[t], I0, ge, h, d0);
+#pragma unroll
+            for (int f = 0; f < FCH; ++f) {
+                const TetField &F1 = s_f[t][f];
+                double v = 0.0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const double alpha =
+                        F1.a[k] - (d0[0] * F1.b[k][0] + d0[1] * F1.b[k][1] + d0[2] * F1.b[k][2]) + F1.c[k] * h[k];
+                    v += alpha * I0[k];
+                }
+#pragma unroll
+                for (int e = 0; e < 6; ++e) v += F1.g[e] * ge[e];
+                acc[f] += v;
+            }
+        }
+        const int64_t o = tgt_perm[s];
+#pragma unroll
+        for (int f = 0; f < FCH; ++f) atomicAdd(&u[(int64_t)(f0 + f) * N + o], acc[f] * kInv4Pi);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) throw DeviceError{std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+namespace {
+
+hipEvent_t pool_event(DevicePlan &dp)
+{
+    if (dp.events_used == dp.event_pool.size()) {
+        hipEvent_t e;
+        hip_check(hipEventCreate(&e), "hipEventCreate");
+        dp.event_pool.push_back(e);
+    }
+    return dp.event_pool[dp.events_used++];
+}
+
+// Records an event pair around one phase on the evaluation stream; nothing is
+// synchronised here.
+struct KTimer {
+    DevicePlan &dp;
+    int slot;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    KTimer(DevicePlan &d, int s, hipStream_t stream) : dp(d), slot(s), st(stream)
+    {
+        if (!dp.timing) return;
+        if (dp.spans.size() >= 4096) collect_timing(dp);
+        a = pool_event(dp);
+        hip_check(hipEventRecord(a, st), "hipEventRecord");
+    }
+    ~KTimer() noexcept(false)
+    {
+        if (!dp.timing) return;
+        hipEvent_t b = pool_event(dp);
+        hip_check(hipEventRecord(b, st), "hipEventRecord");
+        dp.spans.push_back({slot, a, b});
+    }
+};
+
+void fill(double *a, int64_t n, double v, hipStream_t st)
+{
+    if (n <= 0) return;
+    int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    k_fill<<<dim3((unsigned)blocks), dim3(256), 0, st>>>(a, n, v);
+    hip_check(hipGetLastError(), "k_fill launch");
+}
+
+template <int FCH>
+void launch_p2p(DevicePlan &dp, bool direct, int f0, const double *M, double *u, hipStream_t st)
+{
+    const HostPlan &hp = dp.hp;
+    unsigned nblk = direct ? (unsigned)((hp.n_tets + kP2PTets - 1) / kP2PTets) : (unsigned)dp.n_p2p_blk;
+    if (nblk == 0) return;
+    k_p2p<FCH><<<dim3(nblk), dim3(kP2PThreads), 0, st>>>(dp.p2p_blk, direct ? 1 : 0, hp.n_tets, dp.tet_xyz,
+                                                         dp.tet_node, dp.p2p_idx, dp.tgt_xyz, dp.tgt_perm,
+                                                         hp.n_targets, M, hp.n_nodes, f0, u);
+    hip_check(hipGetLastError(), "k_p2p launch");
+}
+
+void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u, hipStream_t st)
+{
+    int f = 0;
+    while (f < F) {
+        int left = F - f;
+        if (left >= 4) {
+            launch_p2p<4>(dp, direct, f, M, u, st);
+            f += 4;
+        } else if (left >= 2) {
+            launch_p2p<2>(dp, direct, f, M, u, st);
+            f += 2;
+        } else {
+            launch_p2p<1>(dp, direct, f, M, u, st);
+            f += 1;
+        }
+    }
+}
+
+}  // namespace
+
+void collect_timing(DevicePlan &dp)
+{
+    for (const auto &sp : dp.spans) {
+        hip_check(hipEventSynchronize(sp.b), "hipEventSynchronize");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, sp.a, sp.b), "hipEventElapsedTime");
+        dp.kt_ms[sp.slot] += ms;
+        dp.kt_n[sp.slot] += 1;
+    }
+    dp.spans.clear();
+    dp.events_used = 0;
+}
+
+void reset_timing(DevicePlan &dp)
+{
+    dp.spans.clear();
+    dp.events_used = 0;
+    for (int i = 0; i < KT_COUNT; ++i) {
+        dp.kt_ms[i] = 0.0;
+        dp.kt_n[i] = 0;
+    }
+}
+
+void ensure_expansions(DevicePlan &dp, int32_t F)
+{
+    if (F <= dp.Fcap) return;
+    if (dp.Q) (void)hipFree(dp.Q);
+    if (dp.L) (void)hipFree(dp.L);
+    dp.Q = dp.L = nullptr;
+    dp.Fcap = 0;
+    const size_t bytes = sizeof(double) * (size_t)F * dp.hp.cells.size() * dp.ncoef;
+    hip_check(hipMalloc(&dp.Q, bytes), "hipMalloc Q");
+    hip_check(hipMalloc(&dp.L, bytes), "hipMalloc L");
+    dp.Fcap = F;
+}
+
+void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t st)
+{
+    const HostPlan &hp = dp.hp;
+    const int64_t C = (int64_t)hp.cells.size();
+    const int p = hp.p;
+    ensure_expansions(dp, F);
+    dp.last_F = F;
+    fill(dp.Q, (int64_t)F * C * dp.ncoef, 0.0, st);
+    fill(dp.L, (int64_t)F * C * dp.ncoef, 0.0, st);
+    {
+        KTimer kt(dp, KT_P2M, st);
+        if (dp.n_p2m_cells > 0) {
+            k_p2m<<<dim3(dp.n_p2m_cells, F), dim3(kP2MThreads), 0, st>>>(dp.p2m_cells, dp.cell_i, dp.cell_c, C,
+                                                                          dp.tet_xyz, dp.tet_node, hp.n_tets, dp.quad,
+                                                                          dp.nq, M, hp.n_nodes, p, dp.Q);
+            hip_check(hipGetLastError(), "k_p2m launch");
+        }
+    }
+    {
+        KTimer kt(dp, KT_M2M, st);
+        for (int Lv = hp.depth - 1; Lv >= 0; --Lv) {
+            int b = dp.m2m_level_ptr[Lv], e = dp.m2m_level_ptr[Lv + 1];
+            if (e > b) {
+                k_m2m<<<dim3(e - b, F), dim3(kShiftThreads), 0, st>>>(dp.m2m_cells + b, dp.cell_i, dp.cell_c, C, p,
+                                                                        dp.Q);
+                hip_check(hipGetLastError(), "k_m2m launch");
+            }
+        }
+    }
+    {
+        KTimer kt(dp, KT_M2L, st);
+        if (dp.n_m2l_cells > 0) {
+            k_m2l<<<dim3(dp.n_m2l_cells, F), dim3(kM2LThreads), 0, st>>>(dp.m2l_cells, dp.m2l_ptr, dp.m2l_src,
+                                                                          dp.cell_c, C, p, dp.Q, dp.L);
+            hip_check(hipGetLastError(), "k_m2l launch");
+        }
+    }
+    {
+        KTimer kt(dp, KT_L2L, st);
+        for (int Lv = 1; Lv <= hp.depth; ++Lv) {
+            int b = dp.l2l_level_ptr[Lv], e = dp.l2l_level_ptr[Lv + 1];
+            if (e > b) {
+                k_l2l<<<dim3(e - b, F), dim3(kShiftThreads), 0, st>>>(dp.l2l_cells + b, dp.cell_i, dp.cell_c, C, p,
+                                                                        dp.L);
+                hip_check(hipGetLastError(), "k_l2l launch");
+            }
+        }
+    }
+    {
+        KTimer kt(dp, KT_L2P, st);
+        const unsigned nb = (unsigned)((hp.n_targets + 255) / 256);
+        k_l2p<<<dim3(nb, F), dim3(256), 0, st>>>(dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, hp.n_targets, dp.cell_c, C, p,
+                                                 dp.L, u);
+        hip_check(hipGetLastError(), "k_l2p launch");
+    }
+    {
+        KTimer kt(dp, KT_P2P, st);
+        run_p2p(dp, false, M, F, u, st);
+    }
+}
+
+void run_direct(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t st)
+{
+    fill(u, (int64_t)F * dp.hp.n_targets, 0.0, st);
+    run_p2p(dp, true, M, F, u, st);
+}
+
+// ---------------------------------------------------------------------------
+// quadrature: Gauss-Jacobi nodes on [0, 1] for the weight (1 - t)^alpha by
+// bracketing the sign changes of the Jacobi polynomial and bisection, weights
+// from the classical closed form; collapsed onto the simplex.
+// ---------------------------------------------------------------------------
+namespace {
+
+void jacobi_eval(int n, double a, double x, double &P, double &dP)
+{
+    // P_n^{(a,0)}(x) by the three-term recurrence, derivative by the standard identity
+    double p0 = 1.0, p1 = 0.5 * (a + 2.0) * x + 0.5 * a;
+    if (n == 0) {
+        P = 1.0;
+        dP = 0.0;
+        return;
+    }
+    const double b = 0.0;
+    for (int k = 2; k <= n; ++k) {
+        const double c = 2.0 * k + a + b;
+        const double a1 = 2.0 * k * (k + a + b) * (c - 2.0);
+        const double a2 = (c - 1.0) * (a * a - b * b);
+        const double a3 = (c - 2.0) * (c - 1.0) * c;
+        const double a4 = 2.0 * (k + a - 1.0) * (k + b - 1.0) * c;
+        const double p2 = ((a2 + a3 * x) * p1 - a4 * p0) / a1;
+        p0 = p1;
+        p1 = p2;
+    }
+    P = p1;
+    const double c = 2.0 * n + a + b;
+    dP = (n * (a - b - c * x) * p1 + 2.0 * (n + a) * (n + b) * p0) / (c * (1.0 - x * x));
+}
+
+void gauss_jacobi01(int n, double a, std::vector<double> &t, std::vector<double> &w)
+{
+    t.clear();
+    w.clear();
+    const int grid = 20000;
+    double xl = -1.0 + 1e-14, Pl, dPl;
+    jacobi_eval(n, a, xl, Pl, dPl);
+    for (int i = 1; i <= grid && (int)t.size() < n; ++i) {
+        double xr = -1.0 + 2.0 * i / grid - (i == grid ? 1e-14 : 0.0), Pr, dPr;
+        jacobi_eval(n, a, xr, Pr, dPr);
+        if ((Pl < 0.0) != (Pr < 0.0)) {
+            double lo = xl, hi = xr, flo = Pl;
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi), fm, dm;
+                jacobi_eval(n, a, mid, fm, dm);
+                if ((fm < 0.0) == (flo < 0.0)) {
+                    lo = mid;
+                    flo = fm;
+                } else {
+                    hi = mid;
+                }
+            }
+            double x = 0.5 * (lo + hi), P, dP;
+            jacobi_eval(n, a, x, P, dP);
+            // classical weight for weight (1-x)^a on [-1,1], b = 0
+            const double lw = std::lgamma(n + a + 1.0) + std::lgamma(n + 1.0) - std::lgamma(n + a + 1.0) -
+                              std::lgamma(n + 1.0) + (a + 1.0) * std::log(2.0);
+            const double wx = std::exp(lw) / ((1.0 - x * x) * dP * dP);
+            t.push_back(0.5 * (x + 1.0));
+            w.push_back(wx * std::pow(2.0, -a - 1.0));
+        }
+        xl = xr;
+        Pl = Pr;
+    }
+}
+
+}  // namespace
+
+std::vector<double> simplex_rule(int deg, int *npts)
+{
+    const int q = (deg + 2) / 2;  // 2q - 1 >= deg
+    std::vector<double> ta, wa, tb, wb, tc, wc;
+    gauss_jacobi01(q, 2.0, ta, wa);
+    gauss_jacobi01(q, 1.0, tb, wb);
+    gauss_jacobi01(q, 0.0, tc, wc);
+    std::vector<double> out;
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j)
+            for (int k = 0; k < q; ++k) {
+                const double a = ta[i], b = tb[j], c = tc[k];
+                out.push_back(a);
+                out.push_back((1.0 - a) * b);
+                out.push_back((1.0 - a) * (1.0 - b) * c);
+                out.push_back(wa[i] * wb[j] * wc[k]);
+            }
+    *npts = q * q * q;
+    return out;
+}
+
+}  // namespace tfmm

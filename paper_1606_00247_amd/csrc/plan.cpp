@@ -1,0 +1,292 @@
+// Host-side plan: mesh validation and orientation, octree over tets (by
+// centroid) and targets (Sec. 3.1), acceptance radii (Sec. 3.2) and the dual
+// tree traversal (Sec. 3.3, Listings 1-2) producing the M2L and P2P lists.
+//
+// Built without floating-point contraction (-ffp-contract=off): the octant
+// keys, cell centres, radii and the acceptance test are evaluated with fixed
+// expressions so that the same mesh always gives the same tree and lists.
+#include "plan.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+
+#include "../../include/tetfmm.h"
+
+namespace tfmm {
+
+namespace {
+
+constexpr int kMaxDepth = 21;
+constexpr double kKeyScale = 2097152.0;  // 2^21
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw PlanError{code, msg}; }
+
+uint32_t axis_key(double xd, double o, double S)
+{
+    double y = (xd - o) / S;
+    double z = std::floor(y * kKeyScale);
+    if (z < 0.0) z = 0.0;
+    if (z > kKeyScale - 1.0) z = kKeyScale - 1.0;
+    return static_cast<uint32_t>(z);
+}
+
+// Interleave three 21-bit keys, x in the lowest bit of every triple: the
+// triple at bit 3*(21-L) is the octant of level L (bit 0 x, bit 1 y, bit 2 z).
+uint64_t morton(uint32_t kx, uint32_t ky, uint32_t kz)
+{
+    uint64_t c = 0;
+    for (int b = 0; b < kMaxDepth; ++b) {
+        c |= static_cast<uint64_t>((kx >> b) & 1u) << (3 * b);
+        c |= static_cast<uint64_t>((ky >> b) & 1u) << (3 * b + 1);
+        c |= static_cast<uint64_t>((kz >> b) & 1u) << (3 * b + 2);
+    }
+    return c;
+}
+
+inline int octant_at(uint64_t code, int level) { return static_cast<int>((code >> (3 * (kMaxDepth - level))) & 7u); }
+
+double dist3(const double *a, const double *b)
+{
+    double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    return std::sqrt((dx * dx + dy * dy) + dz * dz);
+}
+
+std::vector<int32_t> sorted_order(const std::vector<uint64_t> &codes)
+{
+    std::vector<int32_t> idx(codes.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return codes[a] < codes[b]; });
+    return idx;
+}
+
+}  // namespace
+
+void build_host_plan(HostPlan &hp, const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
+                     const double *targets, int64_t n_targets, int p, int leaf, double theta)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!nodes || !tets) fail(TFMM_EINVAL, "nodes and tets must not be NULL");
+    if (n_nodes < 4 || n_tets < 1) fail(TFMM_EINVAL, "need at least 4 nodes and 1 tet");
+    if (n_nodes > INT32_MAX || n_tets > INT32_MAX / 4) fail(TFMM_EINVAL, "mesh too large for 32-bit indices");
+    if (targets && (n_targets < 1 || n_targets > INT32_MAX)) fail(TFMM_EINVAL, "bad number of targets");
+    if (p < 1 || p > TFMM_PMAX) fail(TFMM_EINVAL, "expansion order p out of range");
+    if (leaf < 1) fail(TFMM_EINVAL, "leaf_size must be >= 1");
+    if (!(theta > 0.0 && theta < 1.0)) fail(TFMM_EINVAL, "theta must lie in (0, 1)");
+
+    hp.p = p;
+    hp.leaf = leaf;
+    hp.theta = theta;
+    hp.n_nodes = n_nodes;
+    hp.n_tets = n_tets;
+    hp.targets_are_nodes = targets == nullptr;
+    if (!targets) {
+        targets = nodes;
+        n_targets = n_nodes;
+    }
+    hp.n_targets = n_targets;
+
+    for (int64_t i = 0; i < 3 * n_nodes; ++i)
+        if (!std::isfinite(nodes[i])) fail(TFMM_ENONFINITE, "non-finite node coordinate");
+    for (int64_t i = 0; i < 3 * n_targets; ++i)
+        if (!std::isfinite(targets[i])) fail(TFMM_ENONFINITE, "non-finite target coordinate");
+    for (int64_t i = 0; i < 4 * n_tets; ++i)
+        if (tets[i] < 0 || tets[i] >= n_nodes) fail(TFMM_EINDEX, "tet node index out of range");
+    hp.nodes.assign(nodes, nodes + 3 * n_nodes);
+
+    // orientation and degeneracy
+    std::vector<int32_t> tv(tets, tets + 4 * n_tets);
+    for (int64_t t = 0; t < n_tets; ++t) {
+        int32_t *q = &tv[4 * t];
+        const double *a = nodes + 3 * (int64_t)q[0], *b = nodes + 3 * (int64_t)q[1];
+        const double *c = nodes + 3 * (int64_t)q[2], *d = nodes + 3 * (int64_t)q[3];
+        double e1[3], e2[3], e3[3];
+        for (int k = 0; k < 3; ++k) {
+            e1[k] = b[k] - a[k];
+            e2[k] = c[k] - a[k];
+            e3[k] = d[k] - a[k];
+        }
+        double det = e1[0] * (e2[1] * e3[2] - e2[2] * e3[1]) - e1[1] * (e2[0] * e3[2] - e2[2] * e3[0]) +
+                     e1[2] * (e2[0] * e3[1] - e2[1] * e3[0]);
+        const double *V[4] = {a, b, c, d};
+        double lsum = 0.0;
+        for (int i = 0; i < 4; ++i)
+            for (int j = i + 1; j < 4; ++j) lsum += dist3(V[i], V[j]);
+        double lm = lsum / 6.0;
+        if (!(std::fabs(det) > 1e-12 * lm * lm * lm)) fail(TFMM_EDEGEN, "degenerate tetrahedron " + std::to_string(t));
+        if (det < 0.0) std::swap(q[2], q[3]);
+    }
+
+    // bounding cube of nodes and targets
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) lo[k] = hi[k] = nodes[k];
+    auto grow = [&](const double *x, int64_t n) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], x[3 * i + k]);
+                hi[k] = std::max(hi[k], x[3 * i + k]);
+            }
+    };
+    grow(nodes, n_nodes);
+    grow(targets, n_targets);
+    double ext = 0.0;
+    for (int k = 0; k < 3; ++k) ext = std::max(ext, hi[k] - lo[k]);
+    hp.side = ext * (1.0 + std::ldexp(1.0, -20));
+    for (int k = 0; k < 3; ++k) hp.origin[k] = (lo[k] + hi[k]) * 0.5 - 0.5 * hp.side;
+
+    // Morton codes: tets by centroid, targets by position
+    std::vector<uint64_t> tcode(n_tets), xcode(n_targets);
+    for (int64_t t = 0; t < n_tets; ++t) {
+        const int32_t *q = &tets[4 * t];  // input order: the centroid is symmetric
+        uint32_t k3[3];
+        for (int k = 0; k < 3; ++k) {
+            double cen = ((nodes[3 * (int64_t)q[0] + k] + nodes[3 * (int64_t)q[1] + k]) +
+                          (nodes[3 * (int64_t)q[2] + k] + nodes[3 * (int64_t)q[3] + k])) *
+                         0.25;
+            k3[k] = axis_key(cen, hp.origin[k], hp.side);
+        }
+        tcode[t] = morton(k3[0], k3[1], k3[2]);
+    }
+    for (int64_t i = 0; i < n_targets; ++i) {
+        uint32_t k3[3];
+        for (int k = 0; k < 3; ++k) k3[k] = axis_key(targets[3 * i + k], hp.origin[k], hp.side);
+        xcode[i] = morton(k3[0], k3[1], k3[2]);
+    }
+    hp.tet_perm = sorted_order(tcode);
+    hp.tgt_perm = sorted_order(xcode);
+    std::vector<uint64_t> tcs(n_tets), xcs(n_targets);
+    hp.tet_nodes.resize(4 * n_tets);
+    for (int64_t s = 0; s < n_tets; ++s) {
+        int32_t t = hp.tet_perm[s];
+        tcs[s] = tcode[t];
+        for (int c = 0; c < 4; ++c) hp.tet_nodes[4 * s + c] = tv[4 * (int64_t)t + c];
+    }
+    hp.tgt_xyz.resize(3 * n_targets);
+    for (int64_t s = 0; s < n_targets; ++s) {
+        int32_t i = hp.tgt_perm[s];
+        xcs[s] = xcode[i];
+        for (int k = 0; k < 3; ++k) hp.tgt_xyz[3 * s + k] = targets[3 * (int64_t)i + k];
+    }
+
+    // octree, level by level
+    auto centre = [&](Cell &C) {
+        double s = std::ldexp(hp.side, -C.level);
+        C.c[0] = hp.origin[0] + ((double)C.ix + 0.5) * s;
+        C.c[1] = hp.origin[1] + ((double)C.iy + 0.5) * s;
+        C.c[2] = hp.origin[2] + ((double)C.iz + 0.5) * s;
+    };
+    hp.cells.clear();
+    Cell root{};
+    root.level = 0;
+    root.tbeg = 0;
+    root.tend = (int32_t)n_tets;
+    root.xbeg = 0;
+    root.xend = (int32_t)n_targets;
+    root.parent = -1;
+    centre(root);
+    hp.cells.push_back(root);
+    hp.level_begin = {0};
+    int64_t lb = 0, le = 1;
+    for (int L = 0;; ++L) {
+        hp.level_begin.push_back((int32_t)le);
+        for (int64_t ci = lb; ci < le; ++ci) {
+            Cell C = hp.cells[ci];
+            int32_t nt = C.tend - C.tbeg, nx = C.xend - C.xbeg;
+            hp.cells[ci].cbeg = (int32_t)hp.cells.size();
+            hp.cells[ci].nchild = 0;
+            if (!((nt > leaf || nx > leaf) && L < kMaxDepth)) continue;
+            int32_t tb = C.tbeg, xb = C.xbeg;
+            for (int o = 0; o < 8; ++o) {
+                int32_t te = (int32_t)(std::partition_point(tcs.begin() + tb, tcs.begin() + C.tend,
+                                                           [&](uint64_t c) { return octant_at(c, L + 1) <= o; }) -
+                                       tcs.begin());
+                int32_t xe = (int32_t)(std::partition_point(xcs.begin() + xb, xcs.begin() + C.xend,
+                                                           [&](uint64_t c) { return octant_at(c, L + 1) <= o; }) -
+                                       xcs.begin());
+                if (te > tb || xe > xb) {
+                    Cell K{};
+                    K.level = L + 1;
+                    K.ix = 2 * C.ix + (o & 1);
+                    K.iy = 2 * C.iy + ((o >> 1) & 1);
+                    K.iz = 2 * C.iz + ((o >> 2) & 1);
+                    K.tbeg = tb;
+                    K.tend = te;
+                    K.xbeg = xb;
+                    K.xend = xe;
+                    K.parent = (int32_t)ci;
+                    centre(K);
+                    hp.cells.push_back(K);
+                    hp.cells[ci].nchild++;
+                }
+                tb = te;
+                xb = xe;
+            }
+        }
+        lb = le;
+        le = (int64_t)hp.cells.size();
+        if (le == lb) break;
+    }
+    // level_begin: [L] = first cell of level L for L = 0..depth, [depth+1] = n_cells
+    hp.depth = (int)hp.level_begin.size() - 2;
+
+    // radii: farthest tet corner (source role) and farthest target (target role)
+    for (auto &C : hp.cells) {
+        double rs = 0.0, rt = 0.0;
+        for (int32_t s = C.tbeg; s < C.tend; ++s)
+            for (int c = 0; c < 4; ++c) rs = std::max(rs, dist3(&hp.nodes[3 * (int64_t)hp.tet_nodes[4 * s + c]], C.c));
+        for (int32_t s = C.xbeg; s < C.xend; ++s) rt = std::max(rt, dist3(&hp.tgt_xyz[3 * (int64_t)s], C.c));
+        C.rsrc = rs;
+        C.rtgt = rt;
+    }
+
+    // dual tree traversal
+    const double th2 = theta * theta;
+    std::vector<std::pair<int32_t, int32_t>> m2l, stack;
+    hp.p2p_a.clear();
+    hp.p2p_b.clear();
+    hp.n_p2p_pairs = 0;
+    auto interact = [&](int32_t a, int32_t b) {
+        const Cell &A = hp.cells[a], &B = hp.cells[b];
+        if (A.xend == A.xbeg || B.tend == B.tbeg) return;
+        double dx = A.c[0] - B.c[0], dy = A.c[1] - B.c[1], dz = A.c[2] - B.c[2];
+        double d2 = (dx * dx + dy * dy) + dz * dz;
+        double rr = A.rtgt + B.rsrc;
+        if (rr * rr < th2 * d2) {
+            m2l.emplace_back(a, b);
+        } else if (A.nchild == 0 && B.nchild == 0) {
+            hp.p2p_a.push_back(a);
+            hp.p2p_b.push_back(b);
+            hp.n_p2p_pairs += (int64_t)(A.xend - A.xbeg) * (int64_t)(B.tend - B.tbeg);
+        } else {
+            stack.emplace_back(a, b);
+        }
+    };
+    interact(0, 0);
+    while (!stack.empty()) {
+        auto [a, b] = stack.back();
+        stack.pop_back();
+        const Cell &A = hp.cells[a], &B = hp.cells[b];
+        bool split_target = A.level < B.level;  // larger target cube; ties split the source
+        if (split_target && A.nchild == 0) split_target = false;
+        if (!split_target && B.nchild == 0) split_target = true;
+        if (split_target) {
+            for (int32_t k = 0, cb = A.cbeg, n = A.nchild; k < n; ++k) interact(cb + k, b);
+        } else {
+            for (int32_t k = 0, cb = B.cbeg, n = B.nchild; k < n; ++k) interact(a, cb + k);
+        }
+    }
+    // M2L as CSR by target cell (stable: list order within a target kept)
+    const int64_t nc = (int64_t)hp.cells.size();
+    hp.m2l_ptr.assign(nc + 1, 0);
+    for (auto &pr : m2l) hp.m2l_ptr[pr.first + 1]++;
+    for (int64_t i = 0; i < nc; ++i) hp.m2l_ptr[i + 1] += hp.m2l_ptr[i];
+    hp.m2l_src.resize(m2l.size());
+    {
+        std::vector<int32_t> fill(hp.m2l_ptr.begin(), hp.m2l_ptr.end() - 1);
+        for (auto &pr : m2l) hp.m2l_src[fill[pr.first]++] = pr.second;
+    }
+    hp.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace tfmm

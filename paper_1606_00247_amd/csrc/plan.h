@@ -1,0 +1,69 @@
+// Host-side plan of the tetrahedral FMM: validated and oriented mesh, octree
+// over tets and targets, cell radii and the interaction lists of the dual tree
+// traversal.  Pure C++ (no HIP); compiled without floating-point contraction
+// so that every discrete decision (octant keys, radii, the acceptance test) is
+// reproducible bit for bit.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace tfmm {
+
+struct Cell {
+    int32_t level;
+    int32_t ix, iy, iz;
+    double c[3];           // geometric centre of the cube
+    int32_t tbeg, tend;    // tets [tbeg, tend) in sorted order
+    int32_t xbeg, xend;    // targets [xbeg, xend) in sorted order
+    int32_t cbeg, nchild;  // children are cells [cbeg, cbeg + nchild)
+    int32_t parent;        // -1 for the root
+    double rsrc, rtgt;     // acceptance radii (Sec. 3.2)
+};
+
+struct HostPlan {
+    // parameters
+    int p = 0, leaf = 0;
+    double theta = 0.0;
+    int64_t n_nodes = 0, n_tets = 0, n_targets = 0;
+    bool targets_are_nodes = true;
+
+    // bounding cube
+    double origin[3] = {0, 0, 0};
+    double side = 0.0;
+
+    // mesh (input order)
+    std::vector<double> nodes;  // [n_nodes][3]
+
+    // tets in octree order, corners oriented to positive volume
+    std::vector<int32_t> tet_perm;  // sorted -> input tet index
+    std::vector<int32_t> tet_nodes; // [n_tets][4] node indices
+
+    // targets in octree order
+    std::vector<int32_t> tgt_perm;  // sorted -> input target index
+    std::vector<double> tgt_xyz;    // [n_targets][3] sorted
+
+    // tree: cells grouped by level, children of one parent contiguous
+    std::vector<Cell> cells;
+    std::vector<int32_t> level_begin;  // cells of level L are [level_begin[L], level_begin[L+1])
+    int depth = 0;
+
+    // interaction lists
+    std::vector<int32_t> m2l_ptr, m2l_src;  // CSR by target cell
+    std::vector<int32_t> p2p_a, p2p_b;      // P2P leaf pairs (target, source)
+    int64_t n_p2p_pairs = 0;                // sum of ntargets(A) * ntets(B)
+
+    double setup_seconds = 0.0;
+};
+
+// Error raised by the plan builder: code is one of the TFMM_E* values.
+struct PlanError {
+    int code;
+    std::string msg;
+};
+
+// Builds the plan.  Throws PlanError on invalid input.
+void build_host_plan(HostPlan &hp, const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
+                     const double *targets, int64_t n_targets, int p, int leaf, double theta);
+
+}  // namespace tfmm

@@ -1,0 +1,160 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bar: FP64 throughout, relative L2 <= 1e-12 against the oracle (the two sum in
+different orders, nothing else differs).  Every case prints what it runs
+before it touches the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import meshgen
+import paper_1606_00247_amd as T
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+def _run(torch, plan, M, direct=False):
+    Md = torch.from_numpy(np.ascontiguousarray(M)).to("cuda:0")
+    u = (T.tfmm_direct if direct else T.tfmm_evaluate)(plan, Md)
+    torch.cuda.synchronize()
+    return u.cpu().numpy()
+
+
+def test_direct_small_all_targets(torch_dev, orc):
+    nodes, tets = meshgen.box_mesh(8, seed=0)
+    M = meshgen.random_fields(nodes.shape[0], F=3, seed=1)
+    _say("direct cube8 F=3", nodes.shape, tets.shape)
+    P = T.tfmm_plan_create(nodes, tets, p=6, leaf_size=32, theta=0.5)
+    u = _run(torch_dev, P, M, direct=True)
+    ref = orc.direct(nodes, tets, M)
+    for f in range(3):
+        assert _rel(u[f], ref[f]) <= TOL
+
+
+def test_direct_uniform_box_closed_form(torch_dev):
+    """Independent of the oracle: the GPU direct sum reproduces the box closed form."""
+    from tests import closed_forms as cf
+    nodes, tets = meshgen.box_mesh(5, seed=2)
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((3, 3))
+    b = rng.standard_normal(3)
+    M = nodes @ A.T + b
+    _say("direct affine box 5^3")
+    P = T.tfmm_plan_create(nodes, tets, p=4, leaf_size=16, theta=0.5)
+    u = _run(torch_dev, P, M, direct=True)
+    ue = np.array([cf.box_potential_affine(x, A, b) for x in nodes])
+    assert _rel(u, ue) <= 1e-13
+
+
+@pytest.mark.parametrize("n,p,leaf,theta,F", [(8, 6, 32, 0.5, 1), (6, 8, 8, 0.45, 2), (5, 4, 4, 0.6, 5),
+                                              ((9, 4, 6), 10, 16, 0.5, 1), (4, 1, 2, 0.3, 1), (7, 3, 1, 0.5, 1)])
+def test_fmm_matches_oracle(torch_dev, orc, n, p, leaf, theta, F):
+    nodes, tets = meshgen.box_mesh(n, seed=3)
+    M = meshgen.random_fields(nodes.shape[0], F=F, seed=5)
+    _say("fmm", n, p, leaf, theta, F)
+    P = T.tfmm_plan_create(nodes, tets, p=p, leaf_size=leaf, theta=theta)
+    u = _run(torch_dev, P, M)
+    O = orc.FMM(nodes, tets, p, leaf, theta)
+    ref = O.evaluate(M)
+    for f in range(F):
+        assert _rel(u[f], ref[f]) <= TOL, f
+
+
+def test_expansions_match_oracle(torch_dev, orc):
+    """Stage parity: multipole (P2M + M2M) and local (M2L + L2L) coefficients per cell."""
+    nodes, tets = meshgen.box_mesh(6, seed=8)
+    M = meshgen.random_fields(nodes.shape[0], F=1, seed=9)[0]
+    p, leaf, theta = 7, 8, 0.5
+    _say("expansions", p, leaf, theta)
+    P = T.tfmm_plan_create(nodes, tets, p=p, leaf_size=leaf, theta=theta)
+    _run(torch_dev, P, M)
+    O = orc.FMM(nodes, tets, p, leaf, theta)
+    O.evaluate(M)
+    cg, _ = T.tfmm_plan_cells(P)
+    co, _ = O.cells()
+    pos = {tuple(c[:4]): i for i, c in enumerate(co)}
+    perm = np.array([pos[tuple(c[:4])] for c in cg])
+    for which in ("Q", "L"):
+        g = T.tfmm_plan_expansions(P, which)
+        o = O.expansions(which)[perm]
+        for i in range(g.shape[0]):
+            if cg[i][4] == 0 and which == "Q":
+                continue  # no tets: no multipole
+            if cg[i][5] == 0 and which == "L":
+                continue  # no targets: local expansion unused
+            scale = np.abs(o[i]).max()
+            if scale == 0.0:
+                assert np.abs(g[i]).max() == 0.0
+                continue
+            assert np.abs(g[i] - o[i]).max() <= 1e-12 * scale, (which, i, cg[i])
+
+
+def test_explicit_targets_and_flat_film(torch_dev, orc):
+    """Off-mesh targets (inside, outside, on faces) and an unjittered film whose
+    nodes are coplanar and collinear with many faces and edges."""
+    nodes, tets = meshgen.box_mesh((12, 12, 2), lo=(-3, -3, 0), hi=(3, 3, 0.5), jitter=0.0)
+    rng = np.random.default_rng(3)
+    tg = np.concatenate([rng.uniform(-3.5, 3.5, (200, 3)) * [1, 1, 0.3], nodes[::7]])
+    M = meshgen.vortex_field(nodes, (0, 0), 3.0, seed=1)
+    _say("film targets")
+    P = T.tfmm_plan_create(nodes, tets, targets=tg, p=6, leaf_size=16, theta=0.5)
+    u = _run(torch_dev, P, M)
+    O = orc.FMM(nodes, tets, 6, 16, 0.5, targets=tg)
+    assert _rel(u, O.evaluate(M)) <= TOL
+    ud = _run(torch_dev, P, M, direct=True)
+    assert _rel(ud, orc.direct(nodes, tets, M, targets=tg)) <= TOL
+
+
+def test_single_tet_and_tiny(torch_dev, orc):
+    v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
+    t = np.array([[0, 2, 1, 3]], dtype=np.int32)  # negative orientation on purpose
+    M = np.array([[1.0, 0, 0], [0, 1, 0], [0, 0, 1], [0.3, -0.2, 0.5]])
+    _say("single tet")
+    P = T.tfmm_plan_create(v, t, p=3, leaf_size=4, theta=0.5)
+    u = _run(torch_dev, P, M)
+    ud = _run(torch_dev, P, M, direct=True)
+    ref = orc.direct(v, t, M)
+    assert _rel(u, ref) <= TOL and _rel(ud, ref) <= TOL
+
+
+def test_deterministic_to_rounding(torch_dev):
+    nodes, tets = meshgen.box_mesh(10, seed=1)
+    M = meshgen.random_fields(nodes.shape[0], F=1, seed=2)[0]
+    _say("determinism")
+    P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=16, theta=0.5)
+    a = _run(torch_dev, P, M)
+    b = _run(torch_dev, P, M)
+    assert np.abs(a - b).max() <= 1e-15 * np.abs(a).max()
+
+
+def test_device_argument_errors(torch_dev):
+    nodes, tets = meshgen.box_mesh(3)
+    P = T.tfmm_plan_create(nodes, tets, p=4, leaf_size=8, theta=0.5)
+    torch = torch_dev
+    with pytest.raises(ValueError):
+        T.tfmm_evaluate(P, torch.zeros((nodes.shape[0], 3), dtype=torch.float32, device="cuda:0"))
+    with pytest.raises(ValueError):
+        T.tfmm_evaluate(P, torch.zeros((nodes.shape[0] + 1, 3), dtype=torch.float64, device="cuda:0"))
+    with pytest.raises(T.TetFMMError):
+        T._check(T._load().tfmm_evaluate(P.handle, None, 1, None, None))
