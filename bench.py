@@ -113,7 +113,7 @@ def main():
         bound = "alu"
     else:
         flops = st["n_m2l"] * W["F"] * 2 * m2l_terms(W["p"])
-        bound = "alu"
+        bound = "mfma"
     t_dom = ktimes[dom][0] * 1e-3
     achieved = flops / t_dom / 1e12
     roof = {"kernel": dom, "bound": bound, "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,

@@ -131,13 +131,12 @@ void upload_plan(DevicePlan &dp)
         dp.cell_i = dev_upload(ci, B);
     }
     {
-        std::vector<int32_t> p2m, m2m, l2l, m2lc;
+        std::vector<int32_t> p2m, m2m, l2l;
         dp.m2m_level_ptr.assign(hp.depth + 2, 0);
         dp.l2l_level_ptr.assign(hp.depth + 2, 0);
         for (int64_t c = 0; c < C; ++c) {
             const Cell &K = hp.cells[c];
             if (K.nchild == 0 && K.tend > K.tbeg) p2m.push_back((int32_t)c);
-            if (hp.m2l_ptr[c + 1] > hp.m2l_ptr[c]) m2lc.push_back((int32_t)c);
         }
         for (int Lv = 0; Lv <= hp.depth; ++Lv) {
             dp.m2m_level_ptr[Lv] = (int32_t)m2m.size();
@@ -151,13 +150,9 @@ void upload_plan(DevicePlan &dp)
         dp.m2m_level_ptr[hp.depth + 1] = (int32_t)m2m.size();
         dp.l2l_level_ptr[hp.depth + 1] = (int32_t)l2l.size();
         dp.n_p2m_cells = (int32_t)p2m.size();
-        dp.n_m2l_cells = (int32_t)m2lc.size();
         dp.p2m_cells = dev_upload(p2m, B);
         dp.m2m_cells = dev_upload(m2m, B);
         dp.l2l_cells = dev_upload(l2l, B);
-        dp.m2l_cells = dev_upload(m2lc, B);
-        dp.m2l_ptr = dev_upload(hp.m2l_ptr, B);
-        dp.m2l_src = dev_upload(hp.m2l_src, B);
     }
     {
         // P2P: source leaves with their target-leaf lists, cut into blocks of <= 64 tets
@@ -193,6 +188,20 @@ void upload_plan(DevicePlan &dp)
         dp.p2p_idx = dev_upload(idx, B);
     }
     {
+        dp.n_m2l_keys = (int32_t)(hp.m2l_keys.size() / 4);
+        dp.n_m2l_tiles = (int32_t)(hp.m2l_tile_ptr.size() - 1);
+        dp.m2l_keys = dev_upload(hp.m2l_keys, B);
+        dp.m2l_tile_tgt = dev_upload(hp.m2l_tile_tgt, B);
+        dp.m2l_tile_ptr = dev_upload(hp.m2l_tile_ptr, B);
+        dp.m2l_ent_key = dev_upload(hp.m2l_ent_key, B);
+        dp.m2l_ent_src = dev_upload(hp.m2l_ent_src, B);
+        const size_t tb = sizeof(double) * std::max<size_t>(1, (size_t)dp.n_m2l_keys * dp.ncoef);
+        hip_check(hipMalloc(&dp.m2l_D, tb), "hipMalloc M2L table");
+        B += (int64_t)tb;
+        build_m2l_table(dp);
+        dp.qpad = (dp.ncoef + 3) / 4 * 4;
+    }
+    {
         int np = 0;
         std::vector<double> q = simplex_rule(hp.p, &np);
         dp.nq = np;
@@ -206,8 +215,9 @@ void free_plan(DevicePlan &dp)
     for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
     dp.event_pool.clear();
     void *ptrs[] = {dp.tet_xyz, dp.tet_node, dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, dp.cell_c, dp.cell_i,
-                    dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.m2l_cells, dp.m2l_ptr, dp.m2l_src, dp.p2p_blk,
-                    dp.p2p_idx, dp.quad, dp.Q, dp.L};
+                    dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.p2p_blk,
+                    dp.p2p_idx, dp.quad, dp.Q, dp.L, dp.Qt, dp.m2l_keys, dp.m2l_D, dp.m2l_tile_tgt,
+                    dp.m2l_tile_ptr, dp.m2l_ent_key, dp.m2l_ent_src};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -345,7 +355,8 @@ int tfmm_plan_stats(tfmm_plan plan, tfmm_stats *out)
     out->n_p2p_pairs = hp.n_p2p_pairs;
     out->ncoef = plan->dp.ncoef;
     out->device_bytes = plan->dp.device_bytes +
-                        (int64_t)(2 * sizeof(double) * (size_t)plan->dp.Fcap * hp.cells.size() * plan->dp.ncoef);
+                        (int64_t)(sizeof(double) * (size_t)plan->dp.Fcap * hp.cells.size() *
+                                  (2 * (size_t)plan->dp.ncoef + (size_t)plan->dp.qpad));
     out->setup_seconds = hp.setup_seconds;
     return TFMM_OK;
 }

@@ -43,9 +43,16 @@ struct DevicePlan {
     std::vector<int32_t> m2m_level_ptr;
     int32_t *l2l_cells = nullptr;  // per level: non-root cells holding targets
     std::vector<int32_t> l2l_level_ptr;
-    int32_t *m2l_cells = nullptr;  // target cells with a non-empty M2L list
-    int32_t n_m2l_cells = 0;
-    int32_t *m2l_ptr = nullptr, *m2l_src = nullptr;
+    // M2L on matrix cores: translation keys and their derivative tables
+    // D_k(rho), rho = (c_A - c_B) / side(B); target tiles with one entry per key
+    int32_t *m2l_keys = nullptr;  // [nkeys][4]
+    double *m2l_D = nullptr;      // [nkeys][ncoef]
+    int32_t n_m2l_keys = 0;
+    int32_t *m2l_tile_tgt = nullptr, *m2l_tile_ptr = nullptr, *m2l_ent_key = nullptr, *m2l_ent_src = nullptr;
+    int32_t n_m2l_tiles = 0;
+    // scaled multipoles Qt_n = (-1)^|n| Q_n / (n! s^|n|): [Fcap][C][qpad]
+    double *Qt = nullptr;
+    int32_t qpad = 0;
     // P2P: blocks of <= 64 tets of one source leaf with their target list
     int32_t *p2p_blk = nullptr;  // [nblk][4]: tbeg, tend, ibeg, iend into p2p_idx
     int32_t n_p2p_blk = 0;
@@ -83,6 +90,8 @@ void reset_timing(DevicePlan &dp);
 void upload_plan(DevicePlan &dp);
 void free_plan(DevicePlan &dp);
 void ensure_expansions(DevicePlan &dp, int32_t F);
+// Fill the M2L derivative tables (after the keys are uploaded).
+void build_m2l_table(DevicePlan &dp);
 
 // Queue the FMM evaluation of F fields on `stream`.
 void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t stream);

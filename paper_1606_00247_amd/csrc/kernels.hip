@@ -3,7 +3,8 @@
 //   p2m   multipole coefficients of the tets of a leaf (eq. expCoeffs) by an
 //         exact collapsed Gauss-Jacobi rule, reduced per leaf in LDS
 //   m2m   binomial shift of child multipoles to the parent centre
-//   m2l   multipole -> local translation of the Cartesian Taylor expansion
+//   m2l   multipole -> local translation of the Cartesian Taylor expansion on
+//         FP64 matrix cores, target cells in tiles sharing translation keys
 //   l2l   binomial shift of a local expansion to the child centres
 //   l2p   evaluation of the local expansion at the targets (writes u)
 //   p2p   exact near-field tet-to-target potential (Sec. 2.1), source-major:
@@ -297,81 +298,204 @@ __global__ __launch_bounds__(kShiftThreads) void k_l2l(const int32_t *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// M2L.  One wavefront per target cell (blockIdx.x), field blockIdx.y.
-// With D_k(R) = d^k/dR^k (1/|R|) and Qh_n = (-1)^|n| Q_n / n!:
-//   l_m(A) = 1/(4 pi m!) sum_B sum_{|n|>=1, |n|+|m|<=p} D_{n+m}(c_A - c_B) Qh_n(B)
-// D is generated degree by degree by
-//   |k| r^2 D_k = -(2|k|-1) sum_i k_i R_i D_{k-e_i} - (|k|-1) sum_i k_i (k_i-1) D_{k-2e_i}
+// M2L on matrix cores.
+//
+// With cell sides s and the scaled multipoles
+//   Qt_n(B) = (-1)^|n| Q_n(B) / (n! s_B^|n|),
+// and rho = (c_A - c_B) / s_B, dl = level(B) - level(A), the translation is
+//   l_m(A) = 1 / (4 pi m! s_A^(|m|+1)) * Lt_m(A),
+//   Lt_m(A) = sum_B 2^(dl (|m|+1)) sum_{|n|>=1, |n|+|m|<=p} D_{n+m}(rho) Qt_n(B),
+// D_k = d^k (1/|rho|) depending only on the key (dl, rho): one table row per
+// distinct key serves every level.  A tile of 16 target cells of one level
+// runs through the keys its cells use; per key the 16 source multipoles form
+// the B operand (columns without that key are zero), the Hankel matrix
+// H[m][n] = D_{n+m} the A operand, and the FP64 16x16x4 MFMA accumulates
+// Lt for all 16 cells in registers.  Rows m are tiled by 16; row tile rt
+// only needs columns n < ncoef(p - |m_min(rt)|) (|n| + |m| <= p).
 // ---------------------------------------------------------------------------
-constexpr int kM2LThreads = 64;
-constexpr int kM2LPerLane = (kNcoefMax + kM2LThreads - 1) / kM2LThreads;
+typedef double d4_t __attribute__((ext_vector_type(4)));
+constexpr int kM2LWaves = 4;
 
-__global__ __launch_bounds__(kM2LThreads) void k_m2l(const int32_t *__restrict__ tcells, const int32_t *__restrict__ ptr,
-                                                     const int32_t *__restrict__ src, const double *__restrict__ cell_c,
-                                                     int64_t C, int p, const double *__restrict__ Q,
-                                                     double *__restrict__ L)
+__host__ __device__ constexpr int deg_of_index(int k)
 {
-    __shared__ double s_D[kNcoefMax];
-    __shared__ double s_q[kNcoefMax];
-    const int A = tcells[blockIdx.x];
+    int d = 0;
+    while (ncoef_of(d) <= k) ++d;
+    return d;
+}
+__host__ __device__ constexpr int m2l_nrt(int P) { return (ncoef_of(P) + 15) / 16; }
+__host__ __device__ constexpr int m2l_ks(int P, int rt)
+{
+    const int d = deg_of_index(16 * rt);
+    if (d >= P) return 0;
+    return (ncoef_of(P - d) - 1 + 3) / 4;  // columns n = 1 .. ncoef(P-d)-1, 4 per step
+}
+__host__ __device__ constexpr int m2l_total_ks(int P)
+{
+    int s = 0;
+    for (int rt = 0; rt < m2l_nrt(P); ++rt) s += m2l_ks(P, rt);
+    return s;
+}
+__host__ __device__ constexpr int m2l_kstr(int P)
+{
+    int k = 4 * m2l_ks(P, 0) + 1;  // columns 0 .. 4 KS
+    while (k % 16 != 1) ++k;       // odd row stride: spreads the 16 columns over the banks
+    return k;
+}
+
+// Derivative tables: one thread per key.
+__global__ void k_m2l_table(const int32_t *__restrict__ keys, int nkeys, int p, double *__restrict__ D)
+{
+    const int key = blockIdx.x * blockDim.x + threadIdx.x;
+    if (key >= nkeys) return;
+    const int ncoef = ncoef_of(p);
+    const int dl = keys[4 * key];
+    const double unit = dl >= 0 ? 0.5 : ldexp(0.5, dl);  // rho = k * unit
+    const double Rx = keys[4 * key + 1] * unit, Ry = keys[4 * key + 2] * unit, Rz = keys[4 * key + 3] * unit;
+    const double r2 = (Rx * Rx + Ry * Ry) + Rz * Rz;
+    double *row = D + (int64_t)key * ncoef;
+    row[0] = 1.0 / sqrt(r2);
+    for (int k = 1; k < ncoef; ++k) {
+        const int kx = c_mi.v[k][0], ky = c_mi.v[k][1], kz = c_mi.v[k][2], d = c_mi.v[k][3];
+        double s1 = 0.0, s2 = 0.0;
+        if (kx > 0) s1 += kx * Rx * row[mi_index(kx - 1, ky, kz)];
+        if (ky > 0) s1 += ky * Ry * row[mi_index(kx, ky - 1, kz)];
+        if (kz > 0) s1 += kz * Rz * row[mi_index(kx, ky, kz - 1)];
+        if (kx > 1) s2 += kx * (kx - 1) * row[mi_index(kx - 2, ky, kz)];
+        if (ky > 1) s2 += ky * (ky - 1) * row[mi_index(kx, ky - 2, kz)];
+        if (kz > 1) s2 += kz * (kz - 1) * row[mi_index(kx, ky, kz - 2)];
+        row[k] = -((2.0 * d - 1.0) * s1 + (d - 1.0) * s2) / (d * r2);
+    }
+}
+
+// Qt = scaled multipoles of the cells holding tets; one thread per (cell, n).
+__global__ void k_qscale(const double *__restrict__ Q, const int32_t *__restrict__ cell_i, int64_t C, double side, int p,
+                         int qpad, double *__restrict__ Qt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int f = blockIdx.y;
     const int ncoef = ncoef_of(p);
-    const int lane = threadIdx.x;
-    const double ax = cell_c[A], ay = cell_c[C + A], az = cell_c[2 * C + A];
-    double acc[kM2LPerLane];
-#pragma unroll
-    for (int r = 0; r < kM2LPerLane; ++r) acc[r] = 0.0;
-    for (int j = ptr[A]; j < ptr[A + 1]; ++j) {
-        const int B = src[j];
-        const double Rx = ax - cell_c[B], Ry = ay - cell_c[C + B], Rz = az - cell_c[2 * C + B];
-        const double r2 = (Rx * Rx + Ry * Ry) + Rz * Rz;
-        const double *Qb = Q + ((int64_t)f * C + B) * ncoef;
-        __syncthreads();
-        for (int n = lane; n < ncoef; n += kM2LThreads) {
-            const int dn = c_mi.v[n][3];
-            const double sg = (dn & 1) ? -1.0 : 1.0;
-            s_q[n] = sg * Qb[n] * c_bin.invfact[c_mi.v[n][0]] * c_bin.invfact[c_mi.v[n][1]] * c_bin.invfact[c_mi.v[n][2]];
-        }
-        if (lane == 0) s_D[0] = 1.0 / sqrt(r2);
-        __syncthreads();
-        for (int d = 1; d <= p; ++d) {
-            const int b = d * (d + 1) * (d + 2) / 6, cnt = (d + 1) * (d + 2) / 2;
-            for (int e = lane; e < cnt; e += kM2LThreads) {
-                const int k = b + e;
-                const int kx = c_mi.v[k][0], ky = c_mi.v[k][1], kz = c_mi.v[k][2];
-                double s1 = 0.0, s2 = 0.0;
-                if (kx > 0) s1 += kx * Rx * s_D[mi_index(kx - 1, ky, kz)];
-                if (ky > 0) s1 += ky * Ry * s_D[mi_index(kx, ky - 1, kz)];
-                if (kz > 0) s1 += kz * Rz * s_D[mi_index(kx, ky, kz - 1)];
-                if (kx > 1) s2 += kx * (kx - 1) * s_D[mi_index(kx - 2, ky, kz)];
-                if (ky > 1) s2 += ky * (ky - 1) * s_D[mi_index(kx, ky - 2, kz)];
-                if (kz > 1) s2 += kz * (kz - 1) * s_D[mi_index(kx, ky, kz - 2)];
-                s_D[k] = -((2.0 * d - 1.0) * s1 + (d - 1.0) * s2) / (d * r2);
+    if (i >= C * qpad) return;
+    const int64_t c = i / qpad;
+    const int n = (int)(i % qpad);
+    double v = 0.0;
+    if (n < ncoef && cell_i[CI_N * c + CI_TEND] > cell_i[CI_N * c + CI_TBEG]) {
+        const int d = c_mi.v[n][3];
+        const double is = 1.0 / ldexp(side, -cell_i[CI_N * c + CI_LEVEL]);
+        double sp = 1.0;
+        for (int j = 0; j < d; ++j) sp *= is;
+        v = ((d & 1) ? -1.0 : 1.0) * Q[((int64_t)f * C + c) * ncoef + n] * sp * c_bin.invfact[c_mi.v[n][0]] *
+            c_bin.invfact[c_mi.v[n][1]] * c_bin.invfact[c_mi.v[n][2]];
+    }
+    Qt[((int64_t)f * C + c) * qpad + n] = v;
+}
+
+template <int P, int RT>
+__device__ __forceinline__ void m2l_rows(d4_t (&acc)[m2l_nrt(P)], const double *s_D, const double *s_Q,
+                                         const int16_t *s_idx, int lane, int wave, int dl,
+                                         const int (&degm)[m2l_nrt(P)], int pos)
+{
+    if constexpr (RT < m2l_nrt(P)) {
+        constexpr int KS = m2l_ks(P, RT);
+        constexpr int KSTR = m2l_kstr(P);
+        if constexpr (KS > 0) {
+            const double sc = dl ? ldexp(1.0, dl * (degm[RT] + 1)) : 1.0;
+            const double *qcol = s_Q + (lane & 15) * KSTR + 1 + (lane >> 4);
+            for (int ks = wave; ks < KS; ks += kM2LWaves) {
+                const int di = s_idx[(pos + ks) * 64 + lane];
+                const double a = di >= 0 ? s_D[di] * sc : 0.0;
+                const double b = qcol[4 * ks];
+                acc[RT] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[RT], 0, 0, 0);
             }
-            __syncthreads();
         }
-#pragma unroll
-        for (int r = 0; r < kM2LPerLane; ++r) {
-            const int m = lane + r * kM2LThreads;
-            if (m >= ncoef) break;
-            const int mx = c_mi.v[m][0], my = c_mi.v[m][1], mz = c_mi.v[m][2], dm = c_mi.v[m][3];
-            double s = 0.0;
-            for (int dn = 1; dn <= p - dm; ++dn)
-                for (int nx = dn; nx >= 0; --nx)
-                    for (int ny = dn - nx; ny >= 0; --ny) {
-                        const int nz = dn - nx - ny;
-                        s += s_D[mi_index(nx + mx, ny + my, nz + mz)] * s_q[mi_index(nx, ny, nz)];
-                    }
-            acc[r] += s;
+        m2l_rows<P, RT + 1>(acc, s_D, s_Q, s_idx, lane, wave, dl, degm, pos + KS);
+    }
+}
+
+// One workgroup of kM2LWaves wavefronts per target tile (blockIdx.x), field
+// blockIdx.y.  The key's D row and the 16 source columns are staged in LDS by
+// all threads; wave w runs the column steps ks = w, w + 4, ... of every row
+// tile; the partial accumulators are summed in LDS at the end.
+template <int P>
+__global__ __launch_bounds__(64 * kM2LWaves) void k_m2l_mfma(
+    const int32_t *__restrict__ tile_tgt, const int32_t *__restrict__ tile_ptr, const int32_t *__restrict__ ent_key,
+    const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys, const double *__restrict__ Dtab,
+    const double *__restrict__ Qt, int qpad, const int32_t *__restrict__ cell_i, double side, int64_t C,
+    double *__restrict__ L)
+{
+    constexpr int NC = ncoef_of(P), NRT = m2l_nrt(P), KSTR = m2l_kstr(P), TKS = m2l_total_ks(P);
+    static_assert(KSTR >= NC, "the staging buffer doubles as the reduction buffer");
+    __shared__ double s_D[NC];
+    __shared__ double s_Q[16 * KSTR];
+    __shared__ int16_t s_idx[TKS > 0 ? TKS * 64 : 1];
+    __shared__ int s_src[16];
+    const int tile = blockIdx.x, f = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // D index of every (row tile, column step, lane): -1 outside |n|+|m| <= P
+    {
+        int pos = 0;
+        for (int rt = 0; rt < NRT; ++rt) {
+            const int KS = m2l_ks(P, rt);
+            for (int i = tid; i < KS * 64; i += blockDim.x) {
+                const int ks = i >> 6, l = i & 63;
+                const int m = 16 * rt + (l & 15), n = 1 + 4 * ks + (l >> 4);
+                int di = -1;
+                if (m < NC && n < NC && c_mi.v[m][3] + c_mi.v[n][3] <= P)
+                    di = mi_index(c_mi.v[m][0] + c_mi.v[n][0], c_mi.v[m][1] + c_mi.v[n][1],
+                                  c_mi.v[m][2] + c_mi.v[n][2]);
+                s_idx[pos * 64 + i] = (int16_t)di;
+            }
+            pos += KS;
         }
     }
-    double *La = L + ((int64_t)f * C + A) * ncoef;
+    int degm[NRT];
 #pragma unroll
-    for (int r = 0; r < kM2LPerLane; ++r) {
-        const int m = lane + r * kM2LThreads;
-        if (m < ncoef)
-            La[m] = acc[r] * kInv4Pi * c_bin.invfact[c_mi.v[m][0]] * c_bin.invfact[c_mi.v[m][1]] *
-                    c_bin.invfact[c_mi.v[m][2]];
+    for (int rt = 0; rt < NRT; ++rt) {
+        const int m = 16 * rt + (lane & 15);
+        degm[rt] = m < NC ? c_mi.v[m][3] : 0;
+    }
+    for (int i = tid; i < 16 * KSTR; i += blockDim.x) s_Q[i] = 0.0;
+    d4_t acc[NRT];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt) acc[rt] = d4_t{0.0, 0.0, 0.0, 0.0};
+    const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
+    for (int e = e0; e < e1; ++e) {
+        const int key = ent_key[e];
+        const int dl = keys[4 * key];
+        __syncthreads();  // previous entry's MFMAs are done with LDS
+        if (tid < 16) s_src[tid] = ent_src[(int64_t)e * 16 + tid];
+        for (int k = tid; k < NC; k += blockDim.x) s_D[k] = Dtab[(int64_t)key * NC + k];
+        __syncthreads();
+        for (int i = tid; i < 16 * NC; i += blockDim.x) {
+            const int t = i / NC, n = i - t * NC;
+            const int src = s_src[t];
+            s_Q[t * KSTR + n] = src >= 0 ? Qt[((int64_t)f * C + src) * qpad + n] : 0.0;
+        }
+        __syncthreads();
+        m2l_rows<P, 0>(acc, s_D, s_Q, s_idx, lane, wave, dl, degm, 0);
+    }
+    // sum the waves' partial accumulators in LDS: red[t][m], t = column
+    __syncthreads();
+    double *red = s_Q;
+    for (int i = tid; i < 16 * KSTR; i += blockDim.x) red[i] = 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = 16 * rt + (lane >> 4) + 4 * r;
+            if (m < NC) atomicAdd(&red[(lane & 15) * KSTR + m], acc[rt][r]);
+        }
+    __syncthreads();
+    // l_m(A) = Lt_m / (4 pi m! s_A^(|m|+1))
+    for (int i = tid; i < 16 * NC; i += blockDim.x) {
+        const int t = i / NC, m = i - t * NC;
+        const int A = tile_tgt[tile * 16 + t];
+        if (A < 0) continue;
+        const double is = 1.0 / ldexp(side, -cell_i[CI_N * A + CI_LEVEL]);
+        double sp = is;
+        for (int j = 0; j < c_mi.v[m][3]; ++j) sp *= is;
+        L[((int64_t)f * C + A) * NC + m] = red[t * KSTR + m] * kInv4Pi * sp * c_bin.invfact[c_mi.v[m][0]] *
+                                          c_bin.invfact[c_mi.v[m][1]] * c_bin.invfact[c_mi.v[m][2]];
     }
 }
 
@@ -769,7 +893,42 @@ void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u,
     }
 }
 
+template <int P>
+void launch_m2l_p(DevicePlan &dp, int32_t F, hipStream_t st)
+{
+    const HostPlan &hp = dp.hp;
+    k_m2l_mfma<P><<<dim3(dp.n_m2l_tiles, F), dim3(64 * kM2LWaves), 0, st>>>(
+        dp.m2l_tile_tgt, dp.m2l_tile_ptr, dp.m2l_ent_key, dp.m2l_ent_src, dp.m2l_keys, dp.m2l_D, dp.Qt, dp.qpad,
+        dp.cell_i, hp.side, (int64_t)hp.cells.size(), dp.L);
+    hip_check(hipGetLastError(), "k_m2l_mfma launch");
+}
+
+void launch_m2l_mfma(DevicePlan &dp, int32_t F, hipStream_t st)
+{
+    switch (dp.hp.p) {
+    case 1: launch_m2l_p<1>(dp, F, st); break;
+    case 2: launch_m2l_p<2>(dp, F, st); break;
+    case 3: launch_m2l_p<3>(dp, F, st); break;
+    case 4: launch_m2l_p<4>(dp, F, st); break;
+    case 5: launch_m2l_p<5>(dp, F, st); break;
+    case 6: launch_m2l_p<6>(dp, F, st); break;
+    case 7: launch_m2l_p<7>(dp, F, st); break;
+    case 8: launch_m2l_p<8>(dp, F, st); break;
+    case 9: launch_m2l_p<9>(dp, F, st); break;
+    case 10: launch_m2l_p<10>(dp, F, st); break;
+    default: throw DeviceError{"unsupported expansion order"};
+    }
+}
+
 }  // namespace
+
+void build_m2l_table(DevicePlan &dp)
+{
+    if (dp.n_m2l_keys == 0) return;
+    k_m2l_table<<<dim3((dp.n_m2l_keys + 63) / 64), dim3(64)>>>(dp.m2l_keys, dp.n_m2l_keys, dp.hp.p, dp.m2l_D);
+    hip_check(hipGetLastError(), "k_m2l_table launch");
+    hip_check(hipDeviceSynchronize(), "k_m2l_table");
+}
 
 void collect_timing(DevicePlan &dp)
 {
@@ -799,11 +958,13 @@ void ensure_expansions(DevicePlan &dp, int32_t F)
     if (F <= dp.Fcap) return;
     if (dp.Q) (void)hipFree(dp.Q);
     if (dp.L) (void)hipFree(dp.L);
-    dp.Q = dp.L = nullptr;
+    if (dp.Qt) (void)hipFree(dp.Qt);
+    dp.Q = dp.L = dp.Qt = nullptr;
     dp.Fcap = 0;
     const size_t bytes = sizeof(double) * (size_t)F * dp.hp.cells.size() * dp.ncoef;
     hip_check(hipMalloc(&dp.Q, bytes), "hipMalloc Q");
     hip_check(hipMalloc(&dp.L, bytes), "hipMalloc L");
+    hip_check(hipMalloc(&dp.Qt, sizeof(double) * (size_t)F * dp.hp.cells.size() * dp.qpad), "hipMalloc Qt");
     dp.Fcap = F;
 }
 
@@ -838,10 +999,12 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
     }
     {
         KTimer kt(dp, KT_M2L, st);
-        if (dp.n_m2l_cells > 0) {
-            k_m2l<<<dim3(dp.n_m2l_cells, F), dim3(kM2LThreads), 0, st>>>(dp.m2l_cells, dp.m2l_ptr, dp.m2l_src,
-                                                                          dp.cell_c, C, p, dp.Q, dp.L);
-            hip_check(hipGetLastError(), "k_m2l launch");
+        if (dp.n_m2l_tiles > 0) {
+            const int64_t nq = C * dp.qpad;
+            k_qscale<<<dim3((unsigned)((nq + 255) / 256), F), dim3(256), 0, st>>>(dp.Q, dp.cell_i, C, hp.side, p, dp.qpad,
+                                                                                    dp.Qt);
+            hip_check(hipGetLastError(), "k_qscale launch");
+            launch_m2l_mfma(dp, F, st);
         }
     }
     {

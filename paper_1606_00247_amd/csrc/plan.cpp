@@ -8,9 +8,11 @@
 #include "plan.h"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <numeric>
+#include <unordered_map>
 
 #include "../../include/tetfmm.h"
 
@@ -286,7 +288,74 @@ void build_host_plan(HostPlan &hp, const double *nodes, int64_t n_nodes, const i
         std::vector<int32_t> fill(hp.m2l_ptr.begin(), hp.m2l_ptr.end() - 1);
         for (auto &pr : m2l) hp.m2l_src[fill[pr.first]++] = pr.second;
     }
+    build_m2l_tiles(hp);
     hp.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void build_m2l_tiles(HostPlan &hp)
+{
+    hp.m2l_keys.clear();
+    hp.m2l_tile_tgt.clear();
+    hp.m2l_tile_ptr.assign(1, 0);
+    hp.m2l_ent_key.clear();
+    hp.m2l_ent_src.clear();
+    std::unordered_map<uint64_t, int32_t> keymap;
+    auto key_of = [&](const Cell &A, const Cell &B) -> int32_t {
+        const int dl = B.level - A.level;
+        int64_t k[3];
+        const int32_t ia[3] = {A.ix, A.iy, A.iz}, ib[3] = {B.ix, B.iy, B.iz};
+        for (int d = 0; d < 3; ++d) {
+            if (dl >= 0)
+                k[d] = (2 * (int64_t)ia[d] + 1) * ((int64_t)1 << dl) - (2 * (int64_t)ib[d] + 1);
+            else
+                k[d] = (2 * (int64_t)ia[d] + 1) - (2 * (int64_t)ib[d] + 1) * ((int64_t)1 << (-dl));
+            if (k[d] <= -(1 << 19) || k[d] >= (1 << 19)) throw PlanError{TFMM_ENOTSUP, "M2L offset out of range"};
+        }
+        const uint64_t packed = ((uint64_t)(dl + 32) << 60) | ((uint64_t)(k[0] + (1 << 19)) << 40) |
+                                ((uint64_t)(k[1] + (1 << 19)) << 20) | (uint64_t)(k[2] + (1 << 19));
+        auto it = keymap.find(packed);
+        if (it != keymap.end()) return it->second;
+        const int32_t id = (int32_t)(hp.m2l_keys.size() / 4);
+        keymap.emplace(packed, id);
+        hp.m2l_keys.push_back(dl);
+        hp.m2l_keys.push_back((int32_t)k[0]);
+        hp.m2l_keys.push_back((int32_t)k[1]);
+        hp.m2l_keys.push_back((int32_t)k[2]);
+        return id;
+    };
+    const int64_t nc = (int64_t)hp.cells.size();
+    std::vector<int32_t> tile;
+    auto flush = [&]() {
+        if (tile.empty()) return;
+        std::vector<std::array<int32_t, 3>> trip;  // key, column, source
+        for (int t = 0; t < (int)tile.size(); ++t) {
+            const int32_t a = tile[t];
+            for (int32_t j = hp.m2l_ptr[a]; j < hp.m2l_ptr[a + 1]; ++j) {
+                const int32_t b = hp.m2l_src[j];
+                trip.push_back({key_of(hp.cells[a], hp.cells[b]), t, b});
+            }
+        }
+        std::sort(trip.begin(), trip.end());
+        for (size_t i = 0; i < trip.size();) {
+            const int32_t k = trip[i][0];
+            hp.m2l_ent_key.push_back(k);
+            const size_t base = hp.m2l_ent_src.size();
+            hp.m2l_ent_src.resize(base + kM2LTile, -1);
+            for (; i < trip.size() && trip[i][0] == k; ++i) hp.m2l_ent_src[base + trip[i][1]] = trip[i][2];
+        }
+        for (int t = 0; t < kM2LTile; ++t) hp.m2l_tile_tgt.push_back(t < (int)tile.size() ? tile[t] : -1);
+        hp.m2l_tile_ptr.push_back((int32_t)hp.m2l_ent_key.size());
+        tile.clear();
+    };
+    int cur_level = -1;
+    for (int64_t a = 0; a < nc; ++a) {
+        if (hp.m2l_ptr[a + 1] == hp.m2l_ptr[a]) continue;
+        if (hp.cells[a].level != cur_level || (int)tile.size() == kM2LTile) flush();
+        cur_level = hp.cells[a].level;
+        tile.push_back((int32_t)a);
+    }
+    flush();
+    if (hp.m2l_ent_key.size() > (size_t)INT32_MAX / kM2LTile) throw PlanError{TFMM_ENOTSUP, "too many M2L entries"};
 }
 
 }  // namespace tfmm
