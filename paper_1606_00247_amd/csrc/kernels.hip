@@ -389,89 +389,196 @@ __global__ void k_qscale(const double *__restrict__ Q, const int32_t *__restrict
     Qt[((int64_t)f * C + c) * qpad + n] = v;
 }
 
-template <int P, int RT>
-__device__ __forceinline__ void m2l_rows(d4_t (&acc)[m2l_nrt(P)], const double *s_D, const double *s_Q,
-                                         const int16_t *s_idx, int lane, int wave, int dl,
-                                         const int (&degm)[m2l_nrt(P)], int pos)
+// Column steps of wave W: ks = W, W + kM2LWaves, ... of every row tile.
+__host__ __device__ constexpr int m2l_wave_steps(int P, int W)
 {
-    if constexpr (RT < m2l_nrt(P)) {
-        constexpr int KS = m2l_ks(P, RT);
-        constexpr int KSTR = m2l_kstr(P);
-        if constexpr (KS > 0) {
-            const double sc = dl ? ldexp(1.0, dl * (degm[RT] + 1)) : 1.0;
-            const double *qcol = s_Q + (lane & 15) * KSTR + 1 + (lane >> 4);
-            for (int ks = wave; ks < KS; ks += kM2LWaves) {
-                const int di = s_idx[(pos + ks) * 64 + lane];
-                const double a = di >= 0 ? s_D[di] * sc : 0.0;
-                const double b = qcol[4 * ks];
-                acc[RT] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[RT], 0, 0, 0);
+    int s = 0;
+    for (int rt = 0; rt < m2l_nrt(P); ++rt) {
+        const int KS = m2l_ks(P, rt);
+        if (KS > W) s += (KS - W + kM2LWaves - 1) / kM2LWaves;
+    }
+    return s;
+}
+
+// Steps of wave W in issue order: column step ks = W, W + 4, ... (outer),
+// row tiles rt with ks < KS(rt) (inner), so consecutive MFMAs of a wave feed
+// different accumulators; row tile 0 (the longest) rotates over 2 of its own.
+// m2l_wave_index gives this lane's D-table index of the A-operand element of
+// every step (the zero slot NC outside |n| + |m| <= P).
+template <int P, int W>
+__device__ __forceinline__ void m2l_wave_index(int lane, int (&didx)[m2l_wave_steps(P, W) > 0 ? m2l_wave_steps(P, W) : 1])
+{
+    constexpr int NC = ncoef_of(P), NRT = m2l_nrt(P), KS0 = m2l_ks(P, 0);
+    int s = 0;
+#pragma unroll
+    for (int ks = W; ks < KS0; ks += kM2LWaves) {
+#pragma unroll
+        for (int rt = 0; rt < NRT; ++rt) {
+            if (ks < m2l_ks(P, rt)) {
+                const int m = 16 * rt + (lane & 15), n = 1 + 4 * ks + (lane >> 4);
+                int di = NC;  // the zero slot of the staged D row
+                if (m < NC && n < NC && c_mi.v[m][3] + c_mi.v[n][3] <= P)
+                    di = mi_index(c_mi.v[m][0] + c_mi.v[n][0], c_mi.v[m][1] + c_mi.v[n][1],
+                                  c_mi.v[m][2] + c_mi.v[n][2]);
+                didx[s++] = di;
             }
         }
-        m2l_rows<P, RT + 1>(acc, s_D, s_Q, s_idx, lane, wave, dl, degm, pos + KS);
+    }
+}
+
+template <int P, int W>
+__device__ __forceinline__ void m2l_wave_mfma(d4_t (&acc)[m2l_nrt(P)], d4_t (&acc0)[2], const double *s_D,
+                                              const double *s_Q,
+                                              const int (&didx)[m2l_wave_steps(P, W) > 0 ? m2l_wave_steps(P, W) : 1],
+                                              int lane)
+{
+    constexpr int NRT = m2l_nrt(P), KSTR = m2l_kstr(P), KS0 = m2l_ks(P, 0);
+    const double *qcol = s_Q + (lane & 15) * KSTR + 1 + (lane >> 4);
+    int s = 0, r0 = 0;
+#pragma unroll
+    for (int ks = W; ks < KS0; ks += kM2LWaves) {
+        const double b = qcol[4 * ks];
+#pragma unroll
+        for (int rt = 0; rt < NRT; ++rt) {
+            if (ks < m2l_ks(P, rt)) {
+                const double a = s_D[didx[s++]];
+                if (rt == 0) {
+                    acc0[r0 & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc0[r0 & 1], 0, 0, 0);
+                    ++r0;
+                } else {
+                    acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[rt], 0, 0, 0);
+                }
+            }
+        }
     }
 }
 
 // One workgroup of kM2LWaves wavefronts per target tile (blockIdx.x), field
-// blockIdx.y.  The key's D row and the 16 source columns are staged in LDS by
-// all threads; wave w runs the column steps ks = w, w + 4, ... of every row
-// tile; the partial accumulators are summed in LDS at the end.
+// blockIdx.y.  Per key, the D row and the 16 source columns are staged in LDS
+// by all threads; the next key's operands are fetched into registers while
+// the current key's MFMAs run.  Wave w runs column steps w, w + 4, ... of
+// every row tile; the partial accumulators are summed in LDS at the end.
+// Row scale of a level difference dl: Lt_m gets 2^(dl (|m|+1)).  The entries
+// of a tile are sorted by dl; when dl changes from a to b the accumulators are
+// multiplied by 2^((a - b)(|m|+1)) and at the end by 2^(dl_last (|m|+1)), so
+// every contribution carries its own factor without a multiply per MFMA.
 template <int P>
-__global__ __launch_bounds__(64 * kM2LWaves) void k_m2l_mfma(
+__device__ __forceinline__ void m2l_rescale(d4_t (&acc)[m2l_nrt(P)], int lane, int ddl)
+{
+    constexpr int NC = ncoef_of(P), NRT = m2l_nrt(P);
+    if (ddl == 0) return;
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = 16 * rt + (lane >> 4) + 4 * r;
+            const int dm = m < NC ? c_mi.v[m][3] : 0;
+            acc[rt][r] = ldexp(acc[rt][r], ddl * (dm + 1));
+        }
+}
+
+// One workgroup of kM2LWaves wavefronts per target tile (see k_m2l_mfma).
+// Two LDS buffers: while the MFMAs of key e read buffer e&1, the operands of
+// key e+1 are loaded into registers and stored to the other buffer; one
+// barrier per key.  Thread tid stages column t = tid/16 (one source cell),
+// coefficients n = tid%16 + 16 j.
+template <int P, int W>
+__device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, const int32_t *__restrict__ ent_key,
+                                         const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys,
+                                         const double *__restrict__ Dtab, const double *__restrict__ Qt, int qpad,
+                                         int64_t C, double *s_D, double *s_Q, d4_t (&acc)[m2l_nrt(P)])
+{
+    constexpr int NC = ncoef_of(P), KSTR = m2l_kstr(P), DSTR = NC + 1;
+    constexpr int NT = 64 * kM2LWaves;
+    static_assert(NT == 256, "16 columns x 16 threads");
+    constexpr int QREG = (NC + 15) / 16, DREG = (NC + NT - 1) / NT;
+    const int tile = blockIdx.x, f = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int tcol = tid >> 4, tn = tid & 15;
+    int didx[m2l_wave_steps(P, W) > 0 ? m2l_wave_steps(P, W) : 1];
+    m2l_wave_index<P, W>(lane, didx);
+    d4_t acc0[2] = {d4_t{0.0, 0.0, 0.0, 0.0}, d4_t{0.0, 0.0, 0.0, 0.0}};
+    const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
+    double pq[QREG], pd[DREG];
+    int pdl = 0;
+    auto fetch = [&](int e) {
+        const int key = ent_key[e];
+        pdl = keys[4 * key];
+#pragma unroll
+        for (int j = 0; j < DREG; ++j) {
+            const int k = tid + NT * j;
+            pd[j] = k < NC ? Dtab[(int64_t)key * NC + k] : 0.0;
+        }
+        const int src = ent_src[(int64_t)e * 16 + tcol];
+        const double *q = Qt + ((int64_t)f * C + (src >= 0 ? src : 0)) * qpad;
+#pragma unroll
+        for (int j = 0; j < QREG; ++j) {
+            const int n = tn + 16 * j;
+            pq[j] = (src >= 0 && n < NC) ? q[n] : 0.0;
+        }
+    };
+    auto store = [&](int buf) {
+        double *D = s_D + buf * DSTR;
+        double *Qb = s_Q + buf * 16 * KSTR + tcol * KSTR;
+#pragma unroll
+        for (int j = 0; j < DREG; ++j) {
+            const int k = tid + NT * j;
+            if (k < NC) D[k] = pd[j];
+        }
+#pragma unroll
+        for (int j = 0; j < QREG; ++j) {
+            const int n = tn + 16 * j;
+            if (n < NC) Qb[n] = pq[j];
+        }
+    };
+    if (e0 >= e1) return;
+    fetch(e0);
+    int cur_dl = pdl;
+    store(0);
+    __syncthreads();
+    for (int e = e0; e < e1; ++e) {
+        const int buf = (e - e0) & 1;
+        const int dl = pdl;
+        if (e + 1 < e1) fetch(e + 1);
+        if (dl != cur_dl) {  // entries are sorted by dl: at most a few switches per tile
+            acc[0] += acc0[0] + acc0[1];
+            acc0[0] = acc0[1] = d4_t{0.0, 0.0, 0.0, 0.0};
+            m2l_rescale<P>(acc, lane, cur_dl - dl);
+            cur_dl = dl;
+        }
+        m2l_wave_mfma<P, W>(acc, acc0, s_D + buf * DSTR, s_Q + buf * 16 * KSTR, didx, lane);
+        if (e + 1 < e1) store(buf ^ 1);
+        __syncthreads();
+    }
+    acc[0] += acc0[0] + acc0[1];
+    m2l_rescale<P>(acc, lane, cur_dl);
+}
+
+template <int P>
+__global__ __launch_bounds__(64 * kM2LWaves, (P <= 8 ? 2 : 1)) void k_m2l_mfma(
     const int32_t *__restrict__ tile_tgt, const int32_t *__restrict__ tile_ptr, const int32_t *__restrict__ ent_key,
     const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys, const double *__restrict__ Dtab,
     const double *__restrict__ Qt, int qpad, const int32_t *__restrict__ cell_i, double side, int64_t C,
     double *__restrict__ L)
 {
-    constexpr int NC = ncoef_of(P), NRT = m2l_nrt(P), KSTR = m2l_kstr(P), TKS = m2l_total_ks(P);
+    constexpr int NC = ncoef_of(P), NRT = m2l_nrt(P), KSTR = m2l_kstr(P);
     static_assert(KSTR >= NC, "the staging buffer doubles as the reduction buffer");
-    __shared__ double s_D[NC];
-    __shared__ double s_Q[16 * KSTR];
-    __shared__ int16_t s_idx[TKS > 0 ? TKS * 64 : 1];
-    __shared__ int s_src[16];
+    static_assert(kM2LWaves == 4, "wave specialisation below");
+    __shared__ double s_D[2 * (NC + 1)];
+    __shared__ double s_Q[2 * 16 * KSTR];
     const int tile = blockIdx.x, f = blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // D index of every (row tile, column step, lane): -1 outside |n|+|m| <= P
-    {
-        int pos = 0;
-        for (int rt = 0; rt < NRT; ++rt) {
-            const int KS = m2l_ks(P, rt);
-            for (int i = tid; i < KS * 64; i += blockDim.x) {
-                const int ks = i >> 6, l = i & 63;
-                const int m = 16 * rt + (l & 15), n = 1 + 4 * ks + (l >> 4);
-                int di = -1;
-                if (m < NC && n < NC && c_mi.v[m][3] + c_mi.v[n][3] <= P)
-                    di = mi_index(c_mi.v[m][0] + c_mi.v[n][0], c_mi.v[m][1] + c_mi.v[n][1],
-                                  c_mi.v[m][2] + c_mi.v[n][2]);
-                s_idx[pos * 64 + i] = (int16_t)di;
-            }
-            pos += KS;
-        }
-    }
-    int degm[NRT];
-#pragma unroll
-    for (int rt = 0; rt < NRT; ++rt) {
-        const int m = 16 * rt + (lane & 15);
-        degm[rt] = m < NC ? c_mi.v[m][3] : 0;
-    }
-    for (int i = tid; i < 16 * KSTR; i += blockDim.x) s_Q[i] = 0.0;
+    for (int i = tid; i < 2 * 16 * KSTR; i += blockDim.x) s_Q[i] = 0.0;  // column padding stays zero
+    for (int i = tid; i < 2 * (NC + 1); i += blockDim.x) s_D[i] = 0.0;   // zero slot NC of each buffer
+    __syncthreads();
     d4_t acc[NRT];
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt) acc[rt] = d4_t{0.0, 0.0, 0.0, 0.0};
-    const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
-    for (int e = e0; e < e1; ++e) {
-        const int key = ent_key[e];
-        const int dl = keys[4 * key];
-        __syncthreads();  // previous entry's MFMAs are done with LDS
-        if (tid < 16) s_src[tid] = ent_src[(int64_t)e * 16 + tid];
-        for (int k = tid; k < NC; k += blockDim.x) s_D[k] = Dtab[(int64_t)key * NC + k];
-        __syncthreads();
-        for (int i = tid; i < 16 * NC; i += blockDim.x) {
-            const int t = i / NC, n = i - t * NC;
-            const int src = s_src[t];
-            s_Q[t * KSTR + n] = src >= 0 ? Qt[((int64_t)f * C + src) * qpad + n] : 0.0;
-        }
-        __syncthreads();
-        m2l_rows<P, 0>(acc, s_D, s_Q, s_idx, lane, wave, dl, degm, 0);
+    switch (wave) {
+    case 0: m2l_tile<P, 0>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, s_D, s_Q, acc); break;
+    case 1: m2l_tile<P, 1>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, s_D, s_Q, acc); break;
+    case 2: m2l_tile<P, 2>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, s_D, s_Q, acc); break;
+    default: m2l_tile<P, 3>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, s_D, s_Q, acc); break;
     }
     // sum the waves' partial accumulators in LDS: red[t][m], t = column
     __syncthreads();

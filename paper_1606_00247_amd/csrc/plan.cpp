@@ -335,7 +335,13 @@ void build_m2l_tiles(HostPlan &hp)
                 trip.push_back({key_of(hp.cells[a], hp.cells[b]), t, b});
             }
         }
-        std::sort(trip.begin(), trip.end());
+        // entries sorted by level difference, then key (the kernel rescales
+        // its accumulators when the level difference changes)
+        std::sort(trip.begin(), trip.end(), [&](const std::array<int32_t, 3> &x, const std::array<int32_t, 3> &y) {
+            const int32_t dx = hp.m2l_keys[4 * (size_t)x[0]], dy = hp.m2l_keys[4 * (size_t)y[0]];
+            if (dx != dy) return dx < dy;
+            return x < y;
+        });
         for (size_t i = 0; i < trip.size();) {
             const int32_t k = trip[i][0];
             hp.m2l_ent_key.push_back(k);
