@@ -206,6 +206,10 @@ void upload_plan(DevicePlan &dp)
         std::vector<double> q = simplex_rule(hp.p, &np);
         dp.nq = np;
         dp.quad = dev_upload(q, B);
+        const size_t mb = sizeof(double) * std::max<size_t>(1, (size_t)T * dp.ncoef);
+        hip_check(hipMalloc(&dp.tet_mom, mb), "hipMalloc tet moments");
+        B += (int64_t)mb;
+        build_tet_moments(dp);
     }
 }
 
@@ -216,7 +220,7 @@ void free_plan(DevicePlan &dp)
     dp.event_pool.clear();
     void *ptrs[] = {dp.tet_xyz, dp.tet_node, dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, dp.cell_c, dp.cell_i,
                     dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.p2p_blk,
-                    dp.p2p_idx, dp.quad, dp.Q, dp.L, dp.Qt, dp.m2l_keys, dp.m2l_D, dp.m2l_tile_tgt,
+                    dp.p2p_idx, dp.quad, dp.tet_mom, dp.Q, dp.L, dp.Qt, dp.m2l_keys, dp.m2l_D, dp.m2l_tile_tgt,
                     dp.m2l_tile_ptr, dp.m2l_ent_key, dp.m2l_ent_src};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);

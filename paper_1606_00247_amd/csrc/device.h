@@ -58,7 +58,9 @@ struct DevicePlan {
     int32_t n_p2p_blk = 0;
     int32_t *p2p_idx = nullptr;  // sorted-target indices
     int64_t n_p2p_idx = 0;
-    // quadrature rule for P2M: [nq][4] = lambda1, lambda2, lambda3, weight
+    // geometric moments of every tet about its leaf centre: [T][ncoef]
+    double *tet_mom = nullptr;
+    // quadrature rule for the moments: [nq][4] = lambda1, lambda2, lambda3, weight
     double *quad = nullptr;
     int32_t nq = 0;
     // expansions [Fcap][C][ncoef]
@@ -90,6 +92,8 @@ void reset_timing(DevicePlan &dp);
 void upload_plan(DevicePlan &dp);
 void free_plan(DevicePlan &dp);
 void ensure_expansions(DevicePlan &dp, int32_t F);
+// Geometric moments of the tets (after the rule and cells are uploaded).
+void build_tet_moments(DevicePlan &dp);
 // Fill the M2L derivative tables (after the keys are uploaded).
 void build_m2l_table(DevicePlan &dp);
 

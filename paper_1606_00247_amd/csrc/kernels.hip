@@ -1,7 +1,7 @@
 // HIP kernels of the tetrahedral FMM for CDNA4 (gfx950), FP64.
 //
-//   p2m   multipole coefficients of the tets of a leaf (eq. expCoeffs) by an
-//         exact collapsed Gauss-Jacobi rule, reduced per leaf in LDS
+//   p2m   multipole coefficients of a leaf (eq. expCoeffs) from the tets'
+//         geometric moments (exact quadrature, once per plan) and affine M
 //   m2m   binomial shift of child multipoles to the parent centre
 //   m2l   multipole -> local translation of the Cartesian Taylor expansion on
 //         FP64 matrix cores, target cells in tiles sharing translation keys
@@ -97,105 +97,177 @@ __global__ void k_fill(double *__restrict__ a, int64_t n, double v)
 }
 
 // ---------------------------------------------------------------------------
-// P2M.  One workgroup per leaf with tets (blockIdx.x), field blockIdx.y.
-//   W_{k,m} = sum_points w M_k(y) (y - c)^m,  |m| <= p-1
-//   Q_n     = sum_k n_k W_{k, n - e_k},  Q_0 = 0
-// Points are (tet, quadrature node) pairs, CH at a time: every thread builds
-// one point's powers of (y - c) and w M(y) in LDS, then thread j accumulates
-// monomial j over the chunk.
+// P2M (eq. expCoeffs).  M is affine on a tet, M_k(y) = M_k(c) + sum_d G_kd
+// (y_d - c_d) with G = dM/dy, so with the geometric moments of the tet about
+// its leaf centre c,  S_m = int_T (y - c)^m dy  (|m| <= p),
+//   Q_n = sum_k n_k int_T M_k(y) (y - c)^{n - e_k} dy
+//       = sum_k n_k [ M_k(c) S_{n-e_k} + sum_d G_kd S_{n-e_k+e_d} ].
+// S depends on the mesh only: k_tet_moments computes it once per plan with
+// an exact collapsed Gauss-Jacobi rule (degree p); k_p2m streams it.
 // ---------------------------------------------------------------------------
+constexpr int kMomThreads = 256;
+constexpr int kMomChunk = 256;
+
+// One workgroup per leaf holding tets: S of each of its tets, [T][ncoef].
+__global__ __launch_bounds__(kMomThreads) void k_tet_moments(const int32_t *__restrict__ cells,
+                                                             const int32_t *__restrict__ cell_i,
+                                                             const double *__restrict__ cell_c, int64_t C,
+                                                             const double *__restrict__ tet_xyz, int64_t T,
+                                                             const double *__restrict__ quad, int nq, int p,
+                                                             double *__restrict__ mom)
+{
+    __shared__ double s_pw[kMomChunk][3][kPmax + 1];  // powers 0..p of (y - c)
+    __shared__ double s_w[kMomChunk];
+    const int cell = cells[blockIdx.x];
+    const int tbeg = cell_i[CI_N * cell + CI_TBEG], tend = cell_i[CI_N * cell + CI_TEND];
+    const double cc[3] = {cell_c[cell], cell_c[C + cell], cell_c[2 * C + cell]};
+    const int ncoef = ncoef_of(p);
+    const int tid = threadIdx.x;
+    for (int t = tbeg; t < tend; ++t) {
+        double v[4][3];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v[c][k] = tet_xyz[(int64_t)(3 * c + k) * T + t];
+        double e[3][3];
+#pragma unroll
+        for (int c = 1; c < 4; ++c)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) e[c - 1][k] = v[c][k] - v[0][k];
+        const double vol6 = fabs(e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                                 e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                                 e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]));
+        double acc[2] = {0.0, 0.0};
+        for (int base = 0; base < nq; base += kMomChunk) {
+            __syncthreads();
+            const int q = base + tid;
+            if (q < nq) {
+                const double l1 = quad[4 * q], l2 = quad[4 * q + 1], l3 = quad[4 * q + 2];
+                const double l0 = 1.0 - (l1 + l2 + l3);
+                s_w[tid] = quad[4 * q + 3] * vol6;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double y = ((l0 * (v[0][k] - cc[k]) + l1 * (v[1][k] - cc[k])) + l2 * (v[2][k] - cc[k])) +
+                                     l3 * (v[3][k] - cc[k]);
+                    double pw = 1.0;
+                    for (int j = 0; j <= p; ++j) {
+                        s_pw[tid][k][j] = pw;
+                        pw *= y;
+                    }
+                }
+            }
+            __syncthreads();
+            const int n = min(kMomChunk, nq - base);
+            for (int r = 0; r < 2; ++r) {
+                const int m = tid + r * kMomThreads;
+                if (m >= ncoef) break;
+                const int a = c_mi.v[m][0], b = c_mi.v[m][1], c = c_mi.v[m][2];
+                double s = 0.0;
+                for (int i = 0; i < n; ++i) s += s_w[i] * (s_pw[i][0][a] * s_pw[i][1][b] * s_pw[i][2][c]);
+                acc[r] += s;
+            }
+        }
+        for (int r = 0; r < 2; ++r) {
+            const int m = tid + r * kMomThreads;
+            if (m < ncoef) mom[(int64_t)t * ncoef + m] = acc[r];
+        }
+    }
+}
+
+// One workgroup per leaf holding tets (blockIdx.x), field blockIdx.y.
 constexpr int kP2MThreads = 256;
-constexpr int kP2MChunk = 256;
 
 __global__ __launch_bounds__(kP2MThreads) void k_p2m(const int32_t *__restrict__ cells, const int32_t *__restrict__ cell_i,
                                                      const double *__restrict__ cell_c, int64_t C,
                                                      const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node,
-                                                     int64_t T, const double *__restrict__ quad, int nq,
+                                                     int64_t T, const double *__restrict__ mom,
                                                      const double *__restrict__ M, int64_t n_nodes, int p,
                                                      double *__restrict__ Q)
 {
-    __shared__ double s_pw[kP2MChunk][3][kPmax];  // powers 0..p-1 of (y - c)
-    __shared__ double s_wm[kP2MChunk][3];
-    __shared__ double s_W[3][ncoef_of(kPmax - 1)];
+    __shared__ double s_S[kNcoefMax];
+    __shared__ double s_m[12];  // M(c) [3], G [3][3] of the current tet
     const int cell = cells[blockIdx.x];
     const int f = blockIdx.y;
     const double *Mf = M + (int64_t)f * n_nodes * 3;
     const int tbeg = cell_i[CI_N * cell + CI_TBEG], tend = cell_i[CI_N * cell + CI_TEND];
-    const double cx = cell_c[cell], cy = cell_c[C + cell], cz = cell_c[2 * C + cell];
-    const int nmono = ncoef_of(p - 1);
     const int ncoef = ncoef_of(p);
     const int tid = threadIdx.x;
-    int ma = 0, mb = 0, mc = 0;
-    if (tid < nmono) {
-        ma = c_mi.v[tid][0];
-        mb = c_mi.v[tid][1];
-        mc = c_mi.v[tid][2];
-    }
-    double W0 = 0.0, W1 = 0.0, W2 = 0.0;
-    const int npts = (tend - tbeg) * nq;
-    for (int base = 0; base < npts; base += kP2MChunk) {
-        const int g = base + tid;
-        if (g < npts) {
-            const int t = tbeg + g / nq, q = g % nq;
-            const double l1 = quad[4 * q], l2 = quad[4 * q + 1], l3 = quad[4 * q + 2], w = quad[4 * q + 3];
-            const double l0 = 1.0 - (l1 + l2 + l3);
-            double v[4][3], m[4][3];
+    double acc[2] = {0.0, 0.0};
+    for (int t = tbeg; t < tend; ++t) {
+        __syncthreads();
+        for (int m = tid; m < ncoef; m += blockDim.x) s_S[m] = mom[(int64_t)t * ncoef + m];
+        if (tid == 0) {
+            double v[4][3], mm[4][3];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int nd = tet_node[(int64_t)c * T + t];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     v[c][k] = tet_xyz[(int64_t)(3 * c + k) * T + t];
-                    m[c][k] = Mf[3 * (int64_t)nd + k];
+                    mm[c][k] = Mf[3 * (int64_t)nd + k];
                 }
             }
-            double e[3][3];
-#pragma unroll
-            for (int c = 1; c < 4; ++c)
-#pragma unroll
-                for (int k = 0; k < 3; ++k) e[c - 1][k] = v[c][k] - v[0][k];
-            const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
-                               e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
-                               e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
-            const double wv = w * fabs(det);  // 6 |V| w
-            const double cc[3] = {cx, cy, cz};
+            double e1[3], e2[3], e3[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const double y = l0 * v[0][k] + l1 * v[1][k] + l2 * v[2][k] + l3 * v[3][k] - cc[k];
-                s_wm[tid][k] = wv * (l0 * m[0][k] + l1 * m[1][k] + l2 * m[2][k] + l3 * m[3][k]);
-                double pw = 1.0;
-                for (int j = 0; j < p; ++j) {
-                    s_pw[tid][k][j] = pw;
-                    pw *= y;
-                }
+                e1[k] = v[1][k] - v[0][k];
+                e2[k] = v[2][k] - v[0][k];
+                e3[k] = v[3][k] - v[0][k];
+            }
+            double g[4][3];
+            g[1][0] = e2[1] * e3[2] - e2[2] * e3[1];
+            g[1][1] = e2[2] * e3[0] - e2[0] * e3[2];
+            g[1][2] = e2[0] * e3[1] - e2[1] * e3[0];
+            g[2][0] = e3[1] * e1[2] - e3[2] * e1[1];
+            g[2][1] = e3[2] * e1[0] - e3[0] * e1[2];
+            g[2][2] = e3[0] * e1[1] - e3[1] * e1[0];
+            g[3][0] = e1[1] * e2[2] - e1[2] * e2[1];
+            g[3][1] = e1[2] * e2[0] - e1[0] * e2[2];
+            g[3][2] = e1[0] * e2[1] - e1[1] * e2[0];
+            const double idet = 1.0 / (e1[0] * g[1][0] + e1[1] * g[1][1] + e1[2] * g[1][2]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                g[1][k] *= idet;
+                g[2][k] *= idet;
+                g[3][k] *= idet;
+                g[0][k] = -(g[1][k] + g[2][k] + g[3][k]);
+            }
+            const double dc[3] = {cell_c[cell] - v[0][0], cell_c[C + cell] - v[0][1], cell_c[2 * C + cell] - v[0][2]};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                double G[3];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) G[b] = mm[0][a] * g[0][b] + mm[1][a] * g[1][b] + mm[2][a] * g[2][b] + mm[3][a] * g[3][b];
+                s_m[a] = mm[0][a] + (G[0] * dc[0] + G[1] * dc[1] + G[2] * dc[2]);  // M_a(c)
+                s_m[3 + 3 * a] = G[0];
+                s_m[4 + 3 * a] = G[1];
+                s_m[5 + 3 * a] = G[2];
             }
         }
         __syncthreads();
-        if (tid < nmono) {
-            const int n = min(kP2MChunk, npts - base);
-            for (int i = 0; i < n; ++i) {
-                const double mono = s_pw[i][0][ma] * s_pw[i][1][mb] * s_pw[i][2][mc];
-                W0 += s_wm[i][0] * mono;
-                W1 += s_wm[i][1] * mono;
-                W2 += s_wm[i][2] * mono;
+        for (int r = 0; r < 2; ++r) {
+            const int n = tid + r * kP2MThreads;
+            if (n >= ncoef) break;
+            const int nv[3] = {c_mi.v[n][0], c_mi.v[n][1], c_mi.v[n][2]};
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (nv[k] == 0) continue;
+                int b[3] = {nv[0], nv[1], nv[2]};
+                b[k] -= 1;  // n - e_k
+                double w = s_m[k] * s_S[mi_index(b[0], b[1], b[2])];
+                w += s_m[3 + 3 * k] * s_S[mi_index(b[0] + 1, b[1], b[2])];
+                w += s_m[4 + 3 * k] * s_S[mi_index(b[0], b[1] + 1, b[2])];
+                w += s_m[5 + 3 * k] * s_S[mi_index(b[0], b[1], b[2] + 1)];
+                s += nv[k] * w;
             }
+            acc[r] += s;
         }
-        __syncthreads();
     }
-    if (tid < nmono) {
-        s_W[0][tid] = W0;
-        s_W[1][tid] = W1;
-        s_W[2][tid] = W2;
-    }
-    __syncthreads();
     double *Qc = Q + ((int64_t)f * C + cell) * ncoef;
-    for (int n = tid; n < ncoef; n += blockDim.x) {
-        const int nx = c_mi.v[n][0], ny = c_mi.v[n][1], nz = c_mi.v[n][2];
-        double s = 0.0;
-        if (nx > 0) s += nx * s_W[0][mi_index(nx - 1, ny, nz)];
-        if (ny > 0) s += ny * s_W[1][mi_index(nx, ny - 1, nz)];
-        if (nz > 0) s += nz * s_W[2][mi_index(nx, ny, nz - 1)];
-        Qc[n] = s;
+    for (int r = 0; r < 2; ++r) {
+        const int n = tid + r * kP2MThreads;
+        if (n < ncoef) Qc[n] = acc[r];
     }
 }
 
@@ -800,6 +872,45 @@ __device__ inline void tet_prepare(const double *__restrict__ tet_xyz, const int
     }
 }
 
+// ln(num / den) for positive finite num, den, with one division: writing
+// num = a 2^i, den = b 2^j (a, b in [1/2, 1)), the ratio a/b is brought into
+// [1/sqrt2, sqrt2) by a factor 2 on a or b (the differences below are then
+// exact), and ln(a/b) = 2 atanh(s), s = (a - b)/(a + b), |s| <= 0.1716, is
+// summed by its odd series sum s^(2k+1)/(2k+1) to k = 11 (next term < 1e-18);
+// the power of two enters as (i - j) ln 2 with ln 2 split into a 32-bit-exact
+// head and a tail (Cody & Waite).
+__device__ __forceinline__ double log_ratio(double num, double den)
+{
+    int ei, ej;
+    double a = frexp(num, &ei), b = frexp(den, &ej);
+    int e = ei - ej;
+    const double kSqrt2 = 1.4142135623730951;
+    if (a * kSqrt2 < b) {  // a/b < 1/sqrt2
+        a += a;
+        e -= 1;
+    } else if (a > b * kSqrt2) {  // a/b > sqrt2
+        b += b;
+        e += 1;
+    }
+    const double sv = (a - b) / (a + b);
+    const double z = sv * sv;
+    double q = 1.0 / 23.0;
+    q = fma(q, z, 1.0 / 21.0);
+    q = fma(q, z, 1.0 / 19.0);
+    q = fma(q, z, 1.0 / 17.0);
+    q = fma(q, z, 1.0 / 15.0);
+    q = fma(q, z, 1.0 / 13.0);
+    q = fma(q, z, 1.0 / 11.0);
+    q = fma(q, z, 1.0 / 9.0);
+    q = fma(q, z, 1.0 / 7.0);
+    q = fma(q, z, 1.0 / 5.0);
+    q = fma(q, z, 1.0 / 3.0);
+    const double t = 2.0 * sv * z * q;  // 2 atanh(s) - 2 s
+    const double kLn2Hi = 6.93147180369123816490e-01, kLn2Lo = 1.90821492927058770002e-10;
+    const double de = (double)e;
+    return fma(de, kLn2Hi, fma(de, kLn2Lo, t) + 2.0 * sv);
+}
+
 // Geometric part of one pair: I0_k, g_e, h_k and d_0.
 __device__ __forceinline__ void pair_geometry(const double x[3], const TetGeom &G, double I0[4], double ge[6],
                                               double h[4], double d0[3])
@@ -836,7 +947,7 @@ __device__ __forceinline__ void pair_geometry(const double x[3], const TetGeom &
         const double num = fwd ? (R[b] + lb) : (bwd ? (R[a] - la) : (R[b] + lb) * (R[a] - la));
         const double den = fwd ? (R[a] + la) : (bwd ? (R[b] - lb) : r0sq);
         const bool ok = (R[a] > 0.0) && (R[b] > 0.0) && (den > 0.0);
-        const double f = ok ? log(num / den) : 0.0;  // factors t0 and R0^2 vanish otherwise
+        const double f = ok ? log_ratio(num, den) : 0.0;  // factors t0 and R0^2 vanish otherwise
         fl[e] = f * il;
         ge[e] = r0sq * f + lb * R[b] - la * R[a];
     }
@@ -1029,6 +1140,16 @@ void launch_m2l_mfma(DevicePlan &dp, int32_t F, hipStream_t st)
 
 }  // namespace
 
+void build_tet_moments(DevicePlan &dp)
+{
+    if (dp.n_p2m_cells == 0) return;
+    k_tet_moments<<<dim3(dp.n_p2m_cells), dim3(kMomThreads)>>>(dp.p2m_cells, dp.cell_i, dp.cell_c,
+                                                               (int64_t)dp.hp.cells.size(), dp.tet_xyz, dp.hp.n_tets,
+                                                               dp.quad, dp.nq, dp.hp.p, dp.tet_mom);
+    hip_check(hipGetLastError(), "k_tet_moments launch");
+    hip_check(hipDeviceSynchronize(), "k_tet_moments");
+}
+
 void build_m2l_table(DevicePlan &dp)
 {
     if (dp.n_m2l_keys == 0) return;
@@ -1088,8 +1209,8 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
         KTimer kt(dp, KT_P2M, st);
         if (dp.n_p2m_cells > 0) {
             k_p2m<<<dim3(dp.n_p2m_cells, F), dim3(kP2MThreads), 0, st>>>(dp.p2m_cells, dp.cell_i, dp.cell_c, C,
-                                                                          dp.tet_xyz, dp.tet_node, hp.n_tets, dp.quad,
-                                                                          dp.nq, M, hp.n_nodes, p, dp.Q);
+                                                                          dp.tet_xyz, dp.tet_node, hp.n_tets, dp.tet_mom,
+                                                                          M, hp.n_nodes, p, dp.Q);
             hip_check(hipGetLastError(), "k_p2m launch");
         }
     }
