@@ -52,6 +52,26 @@ def m2l_terms(p):
     return tot
 
 
+def kernel_source_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1606_00247_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_cube40.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernels_sha256") != kernel_source_hash() or kernel not in t.get("bytes_per_launch", {}):
+        return None
+    return t["bytes_per_launch"][kernel]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +81,10 @@ def main():
     ap.add_argument("--theta", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (calibrates HBM byte counters in a profile)")
+    ap.add_argument("--variant-steps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -84,6 +108,14 @@ def main():
     setup_s = time.time() - t0
     st = T.tfmm_plan_stats(plan)
     u = torch.empty((W["F"], nodes.shape[0]), dtype=torch.float64, device=dev)
+
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # reference: FP64 direct sum over all targets (GPU), outside the timed region
     ud = T.tfmm_direct(plan, Md)
@@ -117,7 +149,7 @@ def main():
     t_dom = ktimes[dom][0] * 1e-3
     achieved = flops / t_dom / 1e12
     roof = {"kernel": dom, "bound": bound, "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None}
+            "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom)}
 
     out = {
         "metric": METRIC,
@@ -142,6 +174,31 @@ def main():
         "counts": {"n_p2p_pairs": st["n_p2p_pairs"], "n_m2l": st["n_m2l"], "n_cells": st["n_cells"]},
         "roofline": roof,
     }
+
+    if not args.no_variants:
+        # the mixed-precision and field-batched forms on the same mesh
+        variants = {}
+        for name, prec, F in (("m2l_fp32", T.M2L_FP32, 1), ("fields16_fp64", T.M2L_FP64, 16),
+                              ("fields16_m2l_fp32", T.M2L_FP32, 16)):
+            T.tfmm_plan_set_m2l_precision(plan, prec)
+            Mv = torch.from_numpy(meshgen.random_fields(nodes.shape[0], F=F, seed=1)).to(dev)
+            uv = torch.empty((F, nodes.shape[0]), dtype=torch.float64, device=dev)
+            T.tfmm_evaluate(plan, Mv, uv)
+            udv = T.tfmm_direct(plan, Mv) if F > 1 else ud
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.variant_steps):
+                T.tfmm_evaluate(plan, Mv, uv)
+            torch.cuda.synchronize()
+            dv = (time.perf_counter() - t1) / args.variant_steps
+            ev = max(float(torch.linalg.norm(uv[f] - udv[f]) / torch.linalg.norm(udv[f])) for f in range(F))
+            variants[name] = {"value": nodes.shape[0] * F / dv, "unit": "evals/s", "ms_per_step": dv * 1e3,
+                              "fields": F, "m2l": "fp32" if prec == T.M2L_FP32 else "fp64",
+                              "rel_l2_vs_direct_max_over_fields": ev,
+                              "speedup_vs_plain": (nodes.shape[0] * F / dv) / value}
+            del Mv, uv, udv
+        T.tfmm_plan_set_m2l_precision(plan, T.M2L_FP64)
+        out["variants"] = variants
 
     if not args.no_cpu_baseline:
         import oracle

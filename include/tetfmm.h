@@ -49,8 +49,9 @@ extern "C" {
 /* largest expansion order p accepted */
 #define TFMM_PMAX 10
 
-/* M2L arithmetic */
-#define TFMM_M2L_FP64 0 /* plain FP64 */
+/* M2L arithmetic (P2M, M2M, L2L, L2P and the near field are always FP64) */
+#define TFMM_M2L_FP64 0 /* FP64 matrix cores */
+#define TFMM_M2L_FP32 1 /* FP32 matrix cores on level-scaled expansions, FP64 elsewhere */
 
 typedef struct tfmm_plan_s *tfmm_plan; /* opaque, owned by the library */
 
@@ -64,7 +65,9 @@ typedef struct tfmm_plan_s *tfmm_plan; /* opaque, owned by the library */
  *  theta      multipole acceptance parameter (Sec. 3.2): cells A (target)
  *             and B (source) interact through M2L iff
  *             r_tgt(A) + r_src(B) < theta |c_A - c_B|.  0 < theta < 1.
- *  m2l_precision  TFMM_M2L_FP64.
+ *  m2l_precision  TFMM_M2L_FP64 or TFMM_M2L_FP32 (the translation operands
+ *             are scaled per level so that all magnitudes are O(1); the
+ *             local expansions are accumulated and stored in FP64).
  *  device     HIP device ordinal; -1 builds a host-only plan (tree and lists
  *             without any device allocation: only tfmm_plan_stats,
  *             tfmm_plan_lists and tfmm_plan_cells work on it).
@@ -122,6 +125,9 @@ int tfmm_evaluate(tfmm_plan plan, const double *M, int32_t F, double *u, void *h
  * targets and all tets, in FP64.  Same arguments and errors as tfmm_evaluate.
  */
 int tfmm_direct(tfmm_plan plan, const double *M, int32_t F, double *u, void *hip_stream);
+
+/* Switch the M2L arithmetic of an existing plan (TFMM_M2L_FP64 / _FP32). */
+int tfmm_plan_set_m2l_precision(tfmm_plan plan, int32_t m2l_precision);
 
 /* Synchronous convenience forms with host arrays (copies in and out). */
 int tfmm_evaluate_host(tfmm_plan plan, const double *M, int32_t F, double *u);

@@ -17,7 +17,7 @@ __all__ = [
     "TetFMMError", "Plan", "tfmm_plan_create", "tfmm_evaluate", "tfmm_direct", "tfmm_evaluate_host",
     "tfmm_direct_host", "tfmm_plan_stats", "tfmm_plan_lists", "tfmm_plan_cells", "tfmm_plan_expansions",
     "tfmm_plan_destroy", "tfmm_last_error", "tfmm_simplex_rule", "tfmm_set_timing", "tfmm_kernel_times",
-    "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS",
+    "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS", "tfmm_plan_set_m2l_precision", "M2L_FP64", "M2L_FP32",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -25,6 +25,8 @@ _LIBPATH = os.path.join(_HERE, "libtetfmm.so")
 _lib = None
 
 TFMM_PMAX = 10
+M2L_FP64 = 0
+M2L_FP32 = 1
 KERNEL_NAMES = ("p2m", "m2m", "m2l", "l2l", "l2p", "p2p")
 ERRORS = {-1: "EINVAL", -2: "EINDEX", -3: "EDEGEN", -4: "ENONFINITE", -5: "ENOMEM", -6: "EDEVICE", -7: "ENOTSUP"}
 
@@ -74,6 +76,7 @@ def _load():
         "tfmm_plan_cells": (C.c_int64, [C.c_void_p, _i32p, _dp]),
         "tfmm_plan_expansions": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
         "tfmm_plan_destroy": (C.c_int, [C.c_void_p]),
+        "tfmm_plan_set_m2l_precision": (C.c_int, [C.c_void_p, C.c_int32]),
         "tfmm_last_error": (C.c_char_p, []),
         "tfmm_simplex_rule": (C.c_int, [C.c_int32, _dp, _i32p]),
         "tfmm_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -229,6 +232,12 @@ def tfmm_plan_expansions(plan, which):
     out = np.zeros((st["n_cells"], st["ncoef"]))
     _check(_load().tfmm_plan_expansions(plan.handle, {"Q": 0, "L": 1}[which], _ptr(out, _dp)))
     return out
+
+
+def tfmm_plan_set_m2l_precision(plan, m2l_precision):
+    """M2L arithmetic of an existing plan: M2L_FP64 or M2L_FP32."""
+    _check(_load().tfmm_plan_set_m2l_precision(plan.handle, int(m2l_precision)))
+    plan.params["m2l_precision"] = int(m2l_precision)
 
 
 def tfmm_plan_destroy(plan):

@@ -189,17 +189,13 @@ void upload_plan(DevicePlan &dp)
     }
     {
         dp.n_m2l_keys = (int32_t)(hp.m2l_keys.size() / 4);
-        dp.n_m2l_tiles = (int32_t)(hp.m2l_tile_ptr.size() - 1);
         dp.m2l_keys = dev_upload(hp.m2l_keys, B);
-        dp.m2l_tile_tgt = dev_upload(hp.m2l_tile_tgt, B);
-        dp.m2l_tile_ptr = dev_upload(hp.m2l_tile_ptr, B);
-        dp.m2l_ent_key = dev_upload(hp.m2l_ent_key, B);
-        dp.m2l_ent_src = dev_upload(hp.m2l_ent_src, B);
         const size_t tb = sizeof(double) * std::max<size_t>(1, (size_t)dp.n_m2l_keys * dp.ncoef);
         hip_check(hipMalloc(&dp.m2l_D, tb), "hipMalloc M2L table");
         B += (int64_t)tb;
         build_m2l_table(dp);
         dp.qpad = (dp.ncoef + 3) / 4 * 4;
+        ensure_m2l_tiles(dp, 16);
     }
     {
         int np = 0;
@@ -219,11 +215,15 @@ void free_plan(DevicePlan &dp)
     for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
     dp.event_pool.clear();
     void *ptrs[] = {dp.tet_xyz, dp.tet_node, dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, dp.cell_c, dp.cell_i,
-                    dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.p2p_blk,
-                    dp.p2p_idx, dp.quad, dp.tet_mom, dp.Q, dp.L, dp.Qt, dp.m2l_keys, dp.m2l_D, dp.m2l_tile_tgt,
-                    dp.m2l_tile_ptr, dp.m2l_ent_key, dp.m2l_ent_src};
+                    dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.p2p_blk, dp.p2p_idx, dp.quad, dp.tet_mom, dp.Q,
+                    dp.L, dp.Qt, dp.Qtf, dp.m2l_keys, dp.m2l_D, dp.m2l_Df};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (auto &t : dp.m2l_tiles) {
+        void *tp[] = {t.tile_tgt, t.tile_ptr, t.ent_key, t.ent_src};
+        for (void *p : tp)
+            if (p) (void)hipFree(p);
+    }
 }
 
 }  // namespace tfmm
@@ -237,13 +237,15 @@ int tfmm_plan_create(const double *nodes, int64_t n_nodes, const int32_t *tets, 
 {
     if (out) *out = nullptr;
     if (!prm || !out) return set_error(TFMM_EINVAL, "prm and out must not be NULL");
-    if (prm->m2l_precision != TFMM_M2L_FP64) return set_error(TFMM_ENOTSUP, "unsupported m2l_precision");
+    if (prm->m2l_precision != TFMM_M2L_FP64 && prm->m2l_precision != TFMM_M2L_FP32)
+        return set_error(TFMM_ENOTSUP, "unsupported m2l_precision");
     return guarded([&]() -> int {
         auto t0 = std::chrono::steady_clock::now();
         std::unique_ptr<tfmm_plan_s> P(new tfmm_plan_s());
         tfmm::build_host_plan(P->dp.hp, nodes, n_nodes, tets, n_tets, targets, n_targets, prm->p, prm->leaf_size,
                               prm->theta);
         P->dp.ncoef = (prm->p + 1) * (prm->p + 2) * (prm->p + 3) / 6;
+        P->dp.m2l_precision = prm->m2l_precision;
         if (prm->device >= 0) {
             int ndev = 0;
             if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
@@ -434,6 +436,15 @@ int tfmm_plan_expansions(tfmm_plan plan, int32_t which, double *out)
         tfmm::hip_check(hipMemcpy(out, src, per * sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy expansions");
         return TFMM_OK;
     });
+}
+
+int tfmm_plan_set_m2l_precision(tfmm_plan plan, int32_t m2l_precision)
+{
+    if (!plan) return set_error(TFMM_EINVAL, "NULL plan");
+    if (m2l_precision != TFMM_M2L_FP64 && m2l_precision != TFMM_M2L_FP32)
+        return set_error(TFMM_ENOTSUP, "unsupported m2l_precision");
+    plan->dp.m2l_precision = m2l_precision;
+    return TFMM_OK;
 }
 
 int tfmm_simplex_rule(int32_t degree, double *out, int32_t *npts)

@@ -44,14 +44,24 @@ struct DevicePlan {
     int32_t *l2l_cells = nullptr;  // per level: non-root cells holding targets
     std::vector<int32_t> l2l_level_ptr;
     // M2L on matrix cores: translation keys and their derivative tables
-    // D_k(rho), rho = (c_A - c_B) / side(B); target tiles with one entry per key
+    // D_k(rho), rho = (c_A - c_B) / side(B), in FP64 and (on demand) FP32
     int32_t *m2l_keys = nullptr;  // [nkeys][4]
     double *m2l_D = nullptr;      // [nkeys][ncoef]
+    float *m2l_Df = nullptr;
     int32_t n_m2l_keys = 0;
-    int32_t *m2l_tile_tgt = nullptr, *m2l_tile_ptr = nullptr, *m2l_ent_key = nullptr, *m2l_ent_src = nullptr;
-    int32_t n_m2l_tiles = 0;
-    // scaled multipoles Qt_n = (-1)^|n| Q_n / (n! s^|n|): [Fcap][C][qpad]
+    // target tiles of 16, 8, 4, 2, 1 cells (built on demand; 16 / tpt fields per tile)
+    struct Tiles {
+        int tpt = 0;
+        int32_t *tile_tgt = nullptr, *tile_ptr = nullptr, *ent_key = nullptr, *ent_src = nullptr;
+        int32_t ntiles = 0;
+        int64_t nent = 0;
+    };
+    Tiles m2l_tiles[5];
+    int m2l_precision = 0;  // TFMM_M2L_*
+    // scaled multipoles Qt_n = (-1)^|n| Q_n / (n! s^|n|): [Fcap][C][qpad] (FP64 or FP32)
     double *Qt = nullptr;
+    float *Qtf = nullptr;
+    int32_t qt_cap = 0, qtf_cap = 0;
     int32_t qpad = 0;
     // P2P: blocks of <= 64 tets of one source leaf with their target list
     int32_t *p2p_blk = nullptr;  // [nblk][4]: tbeg, tend, ibeg, iend into p2p_idx
@@ -96,6 +106,8 @@ void ensure_expansions(DevicePlan &dp, int32_t F);
 void build_tet_moments(DevicePlan &dp);
 // Fill the M2L derivative tables (after the keys are uploaded).
 void build_m2l_table(DevicePlan &dp);
+// Tiles of tpt target cells (16, 8, 4, 2 or 1), built and uploaded once.
+DevicePlan::Tiles &ensure_m2l_tiles(DevicePlan &dp, int tpt);
 
 // Queue the FMM evaluation of F fields on `stream`.
 void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t stream);

@@ -369,24 +369,32 @@ __global__ __launch_bounds__(kShiftThreads) void k_l2l(const int32_t *__restrict
     }
 }
 
-// ---------------------------------------------------------------------------
-// M2L on matrix cores.
-//
-// With cell sides s and the scaled multipoles
-//   Qt_n(B) = (-1)^|n| Q_n(B) / (n! s_B^|n|),
-// and rho = (c_A - c_B) / s_B, dl = level(B) - level(A), the translation is
-//   l_m(A) = 1 / (4 pi m! s_A^(|m|+1)) * Lt_m(A),
-//   Lt_m(A) = sum_B 2^(dl (|m|+1)) sum_{|n|>=1, |n|+|m|<=p} D_{n+m}(rho) Qt_n(B),
-// D_k = d^k (1/|rho|) depending only on the key (dl, rho): one table row per
-// distinct key serves every level.  A tile of 16 target cells of one level
-// runs through the keys its cells use; per key the 16 source multipoles form
-// the B operand (columns without that key are zero), the Hankel matrix
-// H[m][n] = D_{n+m} the A operand, and the FP64 16x16x4 MFMA accumulates
-// Lt for all 16 cells in registers.  Rows m are tiled by 16; row tile rt
-// only needs columns n < ncoef(p - |m_min(rt)|) (|n| + |m| <= p).
-// ---------------------------------------------------------------------------
-typedef double d4_t __attribute__((ext_vector_type(4)));
 constexpr int kM2LWaves = 4;
+
+// The two matrix-core shapes used by M2L: 16x16x4 with FP64 or FP32 operands.
+// A (16 x 4): lane l holds row l%16, column l/16; B (4 x 16): lane l holds
+// row l/16, column l%16.  The 16x16 result: lane l, register r holds
+// column l%16 and row (l/16) + 4r (FP64) or 4(l/16) + r (FP32).
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    using v4 = double __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(double a, double b, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+    using v4 = float __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(float a, float b, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
 
 __host__ __device__ constexpr int deg_of_index(int k)
 {
@@ -401,20 +409,26 @@ __host__ __device__ constexpr int m2l_ks(int P, int rt)
     if (d >= P) return 0;
     return (ncoef_of(P - d) - 1 + 3) / 4;  // columns n = 1 .. ncoef(P-d)-1, 4 per step
 }
-__host__ __device__ constexpr int m2l_total_ks(int P)
-{
-    int s = 0;
-    for (int rt = 0; rt < m2l_nrt(P); ++rt) s += m2l_ks(P, rt);
-    return s;
-}
 __host__ __device__ constexpr int m2l_kstr(int P)
 {
     int k = 4 * m2l_ks(P, 0) + 1;  // columns 0 .. 4 KS
     while (k % 16 != 1) ++k;       // odd row stride: spreads the 16 columns over the banks
     return k;
 }
+// Column steps of wave W: ks = W, W + kM2LWaves, ... of every row tile.
+__host__ __device__ constexpr int m2l_wave_steps(int P, int W)
+{
+    int s = 0;
+    for (int rt = 0; rt < m2l_nrt(P); ++rt) {
+        const int KS = m2l_ks(P, rt);
+        if (KS > W) s += (KS - W + kM2LWaves - 1) / kM2LWaves;
+    }
+    return s;
+}
+template <int P, int W>
+using M2LIdx = int[m2l_wave_steps(P, W) > 0 ? m2l_wave_steps(P, W) : 1];
 
-// Derivative tables: one thread per key.
+// Derivative tables: one thread per key, D_k(rho) for |k| <= p.
 __global__ void k_m2l_table(const int32_t *__restrict__ keys, int nkeys, int p, double *__restrict__ D)
 {
     const int key = blockIdx.x * blockDim.x + threadIdx.x;
@@ -439,9 +453,16 @@ __global__ void k_m2l_table(const int32_t *__restrict__ keys, int nkeys, int p, 
     }
 }
 
+__global__ void k_to_float(const double *__restrict__ a, int64_t n, float *__restrict__ b)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) b[i] = (float)a[i];
+}
+
 // Qt = scaled multipoles of the cells holding tets; one thread per (cell, n).
+template <typename T>
 __global__ void k_qscale(const double *__restrict__ Q, const int32_t *__restrict__ cell_i, int64_t C, double side, int p,
-                         int qpad, double *__restrict__ Qt)
+                         int qpad, T *__restrict__ Qt)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int f = blockIdx.y;
@@ -458,18 +479,7 @@ __global__ void k_qscale(const double *__restrict__ Q, const int32_t *__restrict
         v = ((d & 1) ? -1.0 : 1.0) * Q[((int64_t)f * C + c) * ncoef + n] * sp * c_bin.invfact[c_mi.v[n][0]] *
             c_bin.invfact[c_mi.v[n][1]] * c_bin.invfact[c_mi.v[n][2]];
     }
-    Qt[((int64_t)f * C + c) * qpad + n] = v;
-}
-
-// Column steps of wave W: ks = W, W + kM2LWaves, ... of every row tile.
-__host__ __device__ constexpr int m2l_wave_steps(int P, int W)
-{
-    int s = 0;
-    for (int rt = 0; rt < m2l_nrt(P); ++rt) {
-        const int KS = m2l_ks(P, rt);
-        if (KS > W) s += (KS - W + kM2LWaves - 1) / kM2LWaves;
-    }
-    return s;
+    Qt[((int64_t)f * C + c) * qpad + n] = (T)v;
 }
 
 // Steps of wave W in issue order: column step ks = W, W + 4, ... (outer),
@@ -478,7 +488,7 @@ __host__ __device__ constexpr int m2l_wave_steps(int P, int W)
 // m2l_wave_index gives this lane's D-table index of the A-operand element of
 // every step (the zero slot NC outside |n| + |m| <= P).
 template <int P, int W>
-__device__ __forceinline__ void m2l_wave_index(int lane, int (&didx)[m2l_wave_steps(P, W) > 0 ? m2l_wave_steps(P, W) : 1])
+__device__ __forceinline__ void m2l_wave_index(int lane, M2LIdx<P, W> &didx)
 {
     constexpr int NC = ncoef_of(P), NRT = m2l_nrt(P), KS0 = m2l_ks(P, 0);
     int s = 0;
@@ -498,44 +508,37 @@ __device__ __forceinline__ void m2l_wave_index(int lane, int (&didx)[m2l_wave_st
     }
 }
 
-template <int P, int W>
-__device__ __forceinline__ void m2l_wave_mfma(d4_t (&acc)[m2l_nrt(P)], d4_t (&acc0)[2], const double *s_D,
-                                              const double *s_Q,
-                                              const int (&didx)[m2l_wave_steps(P, W) > 0 ? m2l_wave_steps(P, W) : 1],
-                                              int lane)
+template <typename T, int P, int W>
+__device__ __forceinline__ void m2l_wave_mfma(typename Mfma<T>::v4 (&acc)[m2l_nrt(P)], typename Mfma<T>::v4 (&acc0)[2],
+                                              const T *s_D, const T *s_Q, const M2LIdx<P, W> &didx, int lane)
 {
     constexpr int NRT = m2l_nrt(P), KSTR = m2l_kstr(P), KS0 = m2l_ks(P, 0);
-    const double *qcol = s_Q + (lane & 15) * KSTR + 1 + (lane >> 4);
+    const T *qcol = s_Q + (lane & 15) * KSTR + 1 + (lane >> 4);
     int s = 0, r0 = 0;
 #pragma unroll
     for (int ks = W; ks < KS0; ks += kM2LWaves) {
-        const double b = qcol[4 * ks];
+        const T b = qcol[4 * ks];
 #pragma unroll
         for (int rt = 0; rt < NRT; ++rt) {
             if (ks < m2l_ks(P, rt)) {
-                const double a = s_D[didx[s++]];
+                const T a = s_D[didx[s++]];
                 if (rt == 0) {
-                    acc0[r0 & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc0[r0 & 1], 0, 0, 0);
+                    acc0[r0 & 1] = Mfma<T>::mma(a, b, acc0[r0 & 1]);
                     ++r0;
                 } else {
-                    acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[rt], 0, 0, 0);
+                    acc[rt] = Mfma<T>::mma(a, b, acc[rt]);
                 }
             }
         }
     }
 }
 
-// One workgroup of kM2LWaves wavefronts per target tile (blockIdx.x), field
-// blockIdx.y.  Per key, the D row and the 16 source columns are staged in LDS
-// by all threads; the next key's operands are fetched into registers while
-// the current key's MFMAs run.  Wave w runs column steps w, w + 4, ... of
-// every row tile; the partial accumulators are summed in LDS at the end.
 // Row scale of a level difference dl: Lt_m gets 2^(dl (|m|+1)).  The entries
 // of a tile are sorted by dl; when dl changes from a to b the accumulators are
 // multiplied by 2^((a - b)(|m|+1)) and at the end by 2^(dl_last (|m|+1)), so
 // every contribution carries its own factor without a multiply per MFMA.
-template <int P>
-__device__ __forceinline__ void m2l_rescale(d4_t (&acc)[m2l_nrt(P)], int lane, int ddl)
+template <typename T, int P>
+__device__ __forceinline__ void m2l_rescale(typename Mfma<T>::v4 (&acc)[m2l_nrt(P)], int lane, int ddl)
 {
     constexpr int NC = ncoef_of(P), NRT = m2l_nrt(P);
     if (ddl == 0) return;
@@ -543,35 +546,43 @@ __device__ __forceinline__ void m2l_rescale(d4_t (&acc)[m2l_nrt(P)], int lane, i
     for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int m = 16 * rt + (lane >> 4) + 4 * r;
+            const int m = 16 * rt + Mfma<T>::row(lane, r);
             const int dm = m < NC ? c_mi.v[m][3] : 0;
-            acc[rt][r] = ldexp(acc[rt][r], ddl * (dm + 1));
+            acc[rt][r] = (T)ldexp((double)acc[rt][r], ddl * (dm + 1));
         }
 }
+
+// Geometry of a tile: TPT target cells x FPT fields = 16 MFMA columns,
+// column c = t * FPT + g (target slot t, field f0 + g).
+struct M2LCols {
+    int tpt, fpt, f0, F;
+};
 
 // One workgroup of kM2LWaves wavefronts per target tile (see k_m2l_mfma).
 // Two LDS buffers: while the MFMAs of key e read buffer e&1, the operands of
 // key e+1 are loaded into registers and stored to the other buffer; one
-// barrier per key.  Thread tid stages column t = tid/16 (one source cell),
-// coefficients n = tid%16 + 16 j.
-template <int P, int W>
+// barrier per key.  Thread tid stages column tid/16, coefficients
+// n = tid%16 + 16 j.
+template <typename T, int P, int W>
 __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, const int32_t *__restrict__ ent_key,
                                          const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys,
-                                         const double *__restrict__ Dtab, const double *__restrict__ Qt, int qpad,
-                                         int64_t C, double *s_D, double *s_Q, d4_t (&acc)[m2l_nrt(P)])
+                                         const T *__restrict__ Dtab, const T *__restrict__ Qt, int qpad, int64_t C,
+                                         M2LCols cols, T *s_D, T *s_Q, typename Mfma<T>::v4 (&acc)[m2l_nrt(P)])
 {
+    using v4 = typename Mfma<T>::v4;
     constexpr int NC = ncoef_of(P), KSTR = m2l_kstr(P), DSTR = NC + 1;
     constexpr int NT = 64 * kM2LWaves;
     static_assert(NT == 256, "16 columns x 16 threads");
     constexpr int QREG = (NC + 15) / 16, DREG = (NC + NT - 1) / NT;
-    const int tile = blockIdx.x, f = blockIdx.y;
+    const int tile = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63;
     const int tcol = tid >> 4, tn = tid & 15;
-    int didx[m2l_wave_steps(P, W) > 0 ? m2l_wave_steps(P, W) : 1];
+    const int tslot = tcol / cols.fpt, field = cols.f0 + tcol % cols.fpt;
+    M2LIdx<P, W> didx;
     m2l_wave_index<P, W>(lane, didx);
-    d4_t acc0[2] = {d4_t{0.0, 0.0, 0.0, 0.0}, d4_t{0.0, 0.0, 0.0, 0.0}};
+    v4 acc0[2] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
     const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
-    double pq[QREG], pd[DREG];
+    T pq[QREG], pd[DREG];
     int pdl = 0;
     auto fetch = [&](int e) {
         const int key = ent_key[e];
@@ -579,19 +590,19 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, c
 #pragma unroll
         for (int j = 0; j < DREG; ++j) {
             const int k = tid + NT * j;
-            pd[j] = k < NC ? Dtab[(int64_t)key * NC + k] : 0.0;
+            pd[j] = k < NC ? Dtab[(int64_t)key * NC + k] : (T)0;
         }
-        const int src = ent_src[(int64_t)e * 16 + tcol];
-        const double *q = Qt + ((int64_t)f * C + (src >= 0 ? src : 0)) * qpad;
+        const int src = field < cols.F ? ent_src[(int64_t)e * cols.tpt + tslot] : -1;
+        const T *q = Qt + ((int64_t)(src >= 0 ? field : 0) * C + (src >= 0 ? src : 0)) * qpad;
 #pragma unroll
         for (int j = 0; j < QREG; ++j) {
             const int n = tn + 16 * j;
-            pq[j] = (src >= 0 && n < NC) ? q[n] : 0.0;
+            pq[j] = (src >= 0 && n < NC) ? q[n] : (T)0;
         }
     };
     auto store = [&](int buf) {
-        double *D = s_D + buf * DSTR;
-        double *Qb = s_Q + buf * 16 * KSTR + tcol * KSTR;
+        T *D = s_D + buf * DSTR;
+        T *Qb = s_Q + buf * 16 * KSTR + tcol * KSTR;
 #pragma unroll
         for (int j = 0; j < DREG; ++j) {
             const int k = tid + NT * j;
@@ -614,67 +625,89 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, c
         if (e + 1 < e1) fetch(e + 1);
         if (dl != cur_dl) {  // entries are sorted by dl: at most a few switches per tile
             acc[0] += acc0[0] + acc0[1];
-            acc0[0] = acc0[1] = d4_t{0.0, 0.0, 0.0, 0.0};
-            m2l_rescale<P>(acc, lane, cur_dl - dl);
+            acc0[0] = acc0[1] = v4{0, 0, 0, 0};
+            m2l_rescale<T, P>(acc, lane, cur_dl - dl);
             cur_dl = dl;
         }
-        m2l_wave_mfma<P, W>(acc, acc0, s_D + buf * DSTR, s_Q + buf * 16 * KSTR, didx, lane);
+        m2l_wave_mfma<T, P, W>(acc, acc0, s_D + buf * DSTR, s_Q + buf * 16 * KSTR, didx, lane);
         if (e + 1 < e1) store(buf ^ 1);
         __syncthreads();
     }
     acc[0] += acc0[0] + acc0[1];
-    m2l_rescale<P>(acc, lane, cur_dl);
+    m2l_rescale<T, P>(acc, lane, cur_dl);
 }
 
-template <int P>
+// ---------------------------------------------------------------------------
+// M2L on matrix cores.
+//
+// With cell sides s and the scaled multipoles
+//   Qt_n(B) = (-1)^|n| Q_n(B) / (n! s_B^|n|),
+// and rho = (c_A - c_B) / s_B, dl = level(B) - level(A), the translation is
+//   l_m(A) = 1 / (4 pi m! s_A^(|m|+1)) * Lt_m(A),
+//   Lt_m(A) = sum_B 2^(dl (|m|+1)) sum_{|n|>=1, |n|+|m|<=p} D_{n+m}(rho) Qt_n(B),
+// D_k = d^k (1/|rho|) depending only on the key (dl, rho): one table row per
+// distinct key serves every level, and all magnitudes are O(1) (the FP32 form
+// needs no other scaling).  A tile (16 MFMA columns: TPT target cells of one
+// level x FPT fields) runs through the keys its cells use; per key the source
+// multipoles form the B operand (columns without that key are zero), the
+// Hankel matrix H[m][n] = D_{n+m} the A operand, and the 16x16x4 MFMA
+// accumulates Lt for all columns in registers.  Rows m are tiled by 16; row
+// tile rt only needs columns n < ncoef(p - |m_min(rt)|) (|n| + |m| <= p).
+// Four wavefronts split the column steps; their partial sums meet in LDS.
+// ---------------------------------------------------------------------------
+template <typename T, int P>
 __global__ __launch_bounds__(64 * kM2LWaves, (P <= 8 ? 2 : 1)) void k_m2l_mfma(
     const int32_t *__restrict__ tile_tgt, const int32_t *__restrict__ tile_ptr, const int32_t *__restrict__ ent_key,
-    const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys, const double *__restrict__ Dtab,
-    const double *__restrict__ Qt, int qpad, const int32_t *__restrict__ cell_i, double side, int64_t C,
-    double *__restrict__ L)
+    const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys, const T *__restrict__ Dtab,
+    const T *__restrict__ Qt, int qpad, const int32_t *__restrict__ cell_i, double side, int64_t C, int tpt, int fpt,
+    int F, double *__restrict__ L)
 {
+    using v4 = typename Mfma<T>::v4;
     constexpr int NC = ncoef_of(P), NRT = m2l_nrt(P), KSTR = m2l_kstr(P);
     static_assert(KSTR >= NC, "the staging buffer doubles as the reduction buffer");
     static_assert(kM2LWaves == 4, "wave specialisation below");
-    __shared__ double s_D[2 * (NC + 1)];
-    __shared__ double s_Q[2 * 16 * KSTR];
-    const int tile = blockIdx.x, f = blockIdx.y;
+    static_assert(2 * sizeof(T) >= sizeof(double), "reduction buffer fits in the staging buffers");
+    __shared__ T s_D[2 * (NC + 1)];
+    __shared__ __align__(16) T s_Q[2 * 16 * KSTR];
+    const int tile = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int i = tid; i < 2 * 16 * KSTR; i += blockDim.x) s_Q[i] = 0.0;  // column padding stays zero
-    for (int i = tid; i < 2 * (NC + 1); i += blockDim.x) s_D[i] = 0.0;   // zero slot NC of each buffer
+    const M2LCols cols{tpt, fpt, (int)blockIdx.y * fpt, F};
+    for (int i = tid; i < 2 * 16 * KSTR; i += blockDim.x) s_Q[i] = (T)0;  // column padding stays zero
+    for (int i = tid; i < 2 * (NC + 1); i += blockDim.x) s_D[i] = (T)0;   // zero slot NC of each buffer
     __syncthreads();
-    d4_t acc[NRT];
+    v4 acc[NRT];
 #pragma unroll
-    for (int rt = 0; rt < NRT; ++rt) acc[rt] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int rt = 0; rt < NRT; ++rt) acc[rt] = v4{0, 0, 0, 0};
     switch (wave) {
-    case 0: m2l_tile<P, 0>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, s_D, s_Q, acc); break;
-    case 1: m2l_tile<P, 1>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, s_D, s_Q, acc); break;
-    case 2: m2l_tile<P, 2>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, s_D, s_Q, acc); break;
-    default: m2l_tile<P, 3>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, s_D, s_Q, acc); break;
+    case 0: m2l_tile<T, P, 0>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, s_D, s_Q, acc); break;
+    case 1: m2l_tile<T, P, 1>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, s_D, s_Q, acc); break;
+    case 2: m2l_tile<T, P, 2>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, s_D, s_Q, acc); break;
+    default: m2l_tile<T, P, 3>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, s_D, s_Q, acc); break;
     }
-    // sum the waves' partial accumulators in LDS: red[t][m], t = column
+    // sum the waves' partial accumulators in LDS (FP64): red[c][m], c = column
     __syncthreads();
-    double *red = s_Q;
+    double *red = reinterpret_cast<double *>(s_Q);
     for (int i = tid; i < 16 * KSTR; i += blockDim.x) red[i] = 0.0;
     __syncthreads();
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int m = 16 * rt + (lane >> 4) + 4 * r;
-            if (m < NC) atomicAdd(&red[(lane & 15) * KSTR + m], acc[rt][r]);
+            const int m = 16 * rt + Mfma<T>::row(lane, r);
+            if (m < NC) atomicAdd(&red[(lane & 15) * KSTR + m], (double)acc[rt][r]);
         }
     __syncthreads();
     // l_m(A) = Lt_m / (4 pi m! s_A^(|m|+1))
     for (int i = tid; i < 16 * NC; i += blockDim.x) {
-        const int t = i / NC, m = i - t * NC;
-        const int A = tile_tgt[tile * 16 + t];
-        if (A < 0) continue;
+        const int c = i / NC, m = i - c * NC;
+        const int field = cols.f0 + c % fpt;
+        const int A = tile_tgt[tile * tpt + c / fpt];
+        if (A < 0 || field >= F) continue;
         const double is = 1.0 / ldexp(side, -cell_i[CI_N * A + CI_LEVEL]);
         double sp = is;
         for (int j = 0; j < c_mi.v[m][3]; ++j) sp *= is;
-        L[((int64_t)f * C + A) * NC + m] = red[t * KSTR + m] * kInv4Pi * sp * c_bin.invfact[c_mi.v[m][0]] *
-                                          c_bin.invfact[c_mi.v[m][1]] * c_bin.invfact[c_mi.v[m][2]];
+        L[((int64_t)field * C + A) * NC + m] = red[c * KSTR + m] * kInv4Pi * sp * c_bin.invfact[c_mi.v[m][0]] *
+                                              c_bin.invfact[c_mi.v[m][1]] * c_bin.invfact[c_mi.v[m][2]];
     }
 }
 
@@ -1111,30 +1144,77 @@ void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u,
     }
 }
 
-template <int P>
-void launch_m2l_p(DevicePlan &dp, int32_t F, hipStream_t st)
+template <typename T, int P>
+void launch_m2l_p(DevicePlan &dp, const DevicePlan::Tiles &tl, const T *D, const T *Qt, int fpt, int32_t F,
+                  hipStream_t st)
 {
     const HostPlan &hp = dp.hp;
-    k_m2l_mfma<P><<<dim3(dp.n_m2l_tiles, F), dim3(64 * kM2LWaves), 0, st>>>(
-        dp.m2l_tile_tgt, dp.m2l_tile_ptr, dp.m2l_ent_key, dp.m2l_ent_src, dp.m2l_keys, dp.m2l_D, dp.Qt, dp.qpad,
-        dp.cell_i, hp.side, (int64_t)hp.cells.size(), dp.L);
+    const unsigned groups = (unsigned)((F + fpt - 1) / fpt);
+    k_m2l_mfma<T, P><<<dim3(tl.ntiles, groups), dim3(64 * kM2LWaves), 0, st>>>(
+        tl.tile_tgt, tl.tile_ptr, tl.ent_key, tl.ent_src, dp.m2l_keys, D, Qt, dp.qpad, dp.cell_i, hp.side,
+        (int64_t)hp.cells.size(), tl.tpt, fpt, F, dp.L);
     hip_check(hipGetLastError(), "k_m2l_mfma launch");
 }
 
-void launch_m2l_mfma(DevicePlan &dp, int32_t F, hipStream_t st)
+template <typename T>
+void launch_m2l_t(DevicePlan &dp, const DevicePlan::Tiles &tl, const T *D, const T *Qt, int fpt, int32_t F,
+                  hipStream_t st)
 {
     switch (dp.hp.p) {
-    case 1: launch_m2l_p<1>(dp, F, st); break;
-    case 2: launch_m2l_p<2>(dp, F, st); break;
-    case 3: launch_m2l_p<3>(dp, F, st); break;
-    case 4: launch_m2l_p<4>(dp, F, st); break;
-    case 5: launch_m2l_p<5>(dp, F, st); break;
-    case 6: launch_m2l_p<6>(dp, F, st); break;
-    case 7: launch_m2l_p<7>(dp, F, st); break;
-    case 8: launch_m2l_p<8>(dp, F, st); break;
-    case 9: launch_m2l_p<9>(dp, F, st); break;
-    case 10: launch_m2l_p<10>(dp, F, st); break;
+    case 1: launch_m2l_p<T, 1>(dp, tl, D, Qt, fpt, F, st); break;
+    case 2: launch_m2l_p<T, 2>(dp, tl, D, Qt, fpt, F, st); break;
+    case 3: launch_m2l_p<T, 3>(dp, tl, D, Qt, fpt, F, st); break;
+    case 4: launch_m2l_p<T, 4>(dp, tl, D, Qt, fpt, F, st); break;
+    case 5: launch_m2l_p<T, 5>(dp, tl, D, Qt, fpt, F, st); break;
+    case 6: launch_m2l_p<T, 6>(dp, tl, D, Qt, fpt, F, st); break;
+    case 7: launch_m2l_p<T, 7>(dp, tl, D, Qt, fpt, F, st); break;
+    case 8: launch_m2l_p<T, 8>(dp, tl, D, Qt, fpt, F, st); break;
+    case 9: launch_m2l_p<T, 9>(dp, tl, D, Qt, fpt, F, st); break;
+    case 10: launch_m2l_p<T, 10>(dp, tl, D, Qt, fpt, F, st); break;
     default: throw DeviceError{"unsupported expansion order"};
+    }
+}
+
+// Scaled multipoles, then the translations, in the plan's M2L precision.
+void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
+{
+    const HostPlan &hp = dp.hp;
+    const int64_t C = (int64_t)hp.cells.size();
+    int fpt = 1;
+    while (fpt * 2 <= std::min<int32_t>(F, 16)) fpt *= 2;
+    const DevicePlan::Tiles &tl = ensure_m2l_tiles(dp, 16 / fpt);
+    if (tl.ntiles == 0) return;
+    const int64_t nq = C * dp.qpad;
+    const dim3 qgrid((unsigned)((nq + 255) / 256), F);
+    if (dp.m2l_precision == TFMM_M2L_FP32) {
+        if (!dp.m2l_Df) {
+            const int64_t n = (int64_t)dp.n_m2l_keys * dp.ncoef;
+            hip_check(hipMalloc(&dp.m2l_Df, sizeof(float) * std::max<int64_t>(n, 1)), "hipMalloc M2L table f32");
+            k_to_float<<<dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, st>>>(dp.m2l_D, n,
+                                                                                                        dp.m2l_Df);
+            hip_check(hipGetLastError(), "k_to_float launch");
+        }
+        if (dp.qtf_cap < F) {
+            if (dp.Qtf) (void)hipFree(dp.Qtf);
+            dp.Qtf = nullptr;
+            dp.qtf_cap = 0;
+            hip_check(hipMalloc(&dp.Qtf, sizeof(float) * (size_t)F * C * dp.qpad), "hipMalloc Qt f32");
+            dp.qtf_cap = F;
+        }
+        k_qscale<float><<<qgrid, dim3(256), 0, st>>>(dp.Q, dp.cell_i, C, hp.side, hp.p, dp.qpad, dp.Qtf);
+        hip_check(hipGetLastError(), "k_qscale launch");
+        launch_m2l_t<float>(dp, tl, dp.m2l_Df, dp.Qtf, fpt, F, st);
+    } else {
+        if (dp.qt_cap < F) {
+            if (dp.Qt) (void)hipFree(dp.Qt);
+            dp.Qt = nullptr;
+            dp.qt_cap = 0;
+            hip_check(hipMalloc(&dp.Qt, sizeof(double) * (size_t)F * C * dp.qpad), "hipMalloc Qt");
+            dp.qt_cap = F;
+        }
+        k_qscale<double><<<qgrid, dim3(256), 0, st>>>(dp.Q, dp.cell_i, C, hp.side, hp.p, dp.qpad, dp.Qt);
+        hip_check(hipGetLastError(), "k_qscale launch");
+        launch_m2l_t<double>(dp, tl, dp.m2l_D, dp.Qt, fpt, F, st);
     }
 }
 
@@ -1156,6 +1236,31 @@ void build_m2l_table(DevicePlan &dp)
     k_m2l_table<<<dim3((dp.n_m2l_keys + 63) / 64), dim3(64)>>>(dp.m2l_keys, dp.n_m2l_keys, dp.hp.p, dp.m2l_D);
     hip_check(hipGetLastError(), "k_m2l_table launch");
     hip_check(hipDeviceSynchronize(), "k_m2l_table");
+}
+
+DevicePlan::Tiles &ensure_m2l_tiles(DevicePlan &dp, int tpt)
+{
+    int slot = 0;
+    while ((16 >> slot) != tpt && slot < 4) ++slot;
+    if ((16 >> slot) != tpt) throw DeviceError{"bad M2L tile width"};
+    DevicePlan::Tiles &t = dp.m2l_tiles[slot];
+    if (t.tpt == tpt) return t;
+    M2LTiles h;
+    build_m2l_tiles(dp.hp, tpt, h);
+    auto up = [&](const std::vector<int32_t> &v, int32_t *&d) {
+        hip_check(hipMalloc(&d, sizeof(int32_t) * std::max<size_t>(v.size(), 1)), "hipMalloc M2L tiles");
+        if (!v.empty())
+            hip_check(hipMemcpy(d, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice), "hipMemcpy M2L tiles");
+        dp.device_bytes += (int64_t)(sizeof(int32_t) * std::max<size_t>(v.size(), 1));
+    };
+    up(h.tile_tgt, t.tile_tgt);
+    up(h.tile_ptr, t.tile_ptr);
+    up(h.ent_key, t.ent_key);
+    up(h.ent_src, t.ent_src);
+    t.ntiles = (int32_t)(h.tile_ptr.size() - 1);
+    t.nent = (int64_t)h.ent_key.size();
+    t.tpt = tpt;
+    return t;
 }
 
 void collect_timing(DevicePlan &dp)
@@ -1186,13 +1291,11 @@ void ensure_expansions(DevicePlan &dp, int32_t F)
     if (F <= dp.Fcap) return;
     if (dp.Q) (void)hipFree(dp.Q);
     if (dp.L) (void)hipFree(dp.L);
-    if (dp.Qt) (void)hipFree(dp.Qt);
-    dp.Q = dp.L = dp.Qt = nullptr;
+    dp.Q = dp.L = nullptr;
     dp.Fcap = 0;
     const size_t bytes = sizeof(double) * (size_t)F * dp.hp.cells.size() * dp.ncoef;
     hip_check(hipMalloc(&dp.Q, bytes), "hipMalloc Q");
     hip_check(hipMalloc(&dp.L, bytes), "hipMalloc L");
-    hip_check(hipMalloc(&dp.Qt, sizeof(double) * (size_t)F * dp.hp.cells.size() * dp.qpad), "hipMalloc Qt");
     dp.Fcap = F;
 }
 
@@ -1227,13 +1330,7 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
     }
     {
         KTimer kt(dp, KT_M2L, st);
-        if (dp.n_m2l_tiles > 0) {
-            const int64_t nq = C * dp.qpad;
-            k_qscale<<<dim3((unsigned)((nq + 255) / 256), F), dim3(256), 0, st>>>(dp.Q, dp.cell_i, C, hp.side, p, dp.qpad,
-                                                                                    dp.Qt);
-            hip_check(hipGetLastError(), "k_qscale launch");
-            launch_m2l_mfma(dp, F, st);
-        }
+        run_m2l(dp, F, st);
     }
     {
         KTimer kt(dp, KT_L2L, st);

@@ -55,6 +55,8 @@ double dist3(const double *a, const double *b)
     return std::sqrt((dx * dx + dy * dy) + dz * dz);
 }
 
+void build_m2l_keys(HostPlan &hp);
+
 std::vector<int32_t> sorted_order(const std::vector<uint64_t> &codes)
 {
     std::vector<int32_t> idx(codes.size());
@@ -288,52 +290,70 @@ void build_host_plan(HostPlan &hp, const double *nodes, int64_t n_nodes, const i
         std::vector<int32_t> fill(hp.m2l_ptr.begin(), hp.m2l_ptr.end() - 1);
         for (auto &pr : m2l) hp.m2l_src[fill[pr.first]++] = pr.second;
     }
-    build_m2l_tiles(hp);
+    build_m2l_keys(hp);
     hp.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
-void build_m2l_tiles(HostPlan &hp)
+namespace {
+
+void build_m2l_keys(HostPlan &hp)
 {
     hp.m2l_keys.clear();
-    hp.m2l_tile_tgt.clear();
-    hp.m2l_tile_ptr.assign(1, 0);
-    hp.m2l_ent_key.clear();
-    hp.m2l_ent_src.clear();
+    hp.m2l_pair_key.assign(hp.m2l_src.size(), -1);
     std::unordered_map<uint64_t, int32_t> keymap;
-    auto key_of = [&](const Cell &A, const Cell &B) -> int32_t {
-        const int dl = B.level - A.level;
-        int64_t k[3];
-        const int32_t ia[3] = {A.ix, A.iy, A.iz}, ib[3] = {B.ix, B.iy, B.iz};
-        for (int d = 0; d < 3; ++d) {
-            if (dl >= 0)
-                k[d] = (2 * (int64_t)ia[d] + 1) * ((int64_t)1 << dl) - (2 * (int64_t)ib[d] + 1);
-            else
-                k[d] = (2 * (int64_t)ia[d] + 1) - (2 * (int64_t)ib[d] + 1) * ((int64_t)1 << (-dl));
-            if (k[d] <= -(1 << 19) || k[d] >= (1 << 19)) throw PlanError{TFMM_ENOTSUP, "M2L offset out of range"};
+    const int64_t nc = (int64_t)hp.cells.size();
+    for (int64_t a = 0; a < nc; ++a) {
+        const Cell &A = hp.cells[a];
+        for (int32_t j = hp.m2l_ptr[a]; j < hp.m2l_ptr[a + 1]; ++j) {
+            const Cell &B = hp.cells[hp.m2l_src[j]];
+            const int dl = B.level - A.level;
+            int64_t k[3];
+            const int32_t ia[3] = {A.ix, A.iy, A.iz}, ib[3] = {B.ix, B.iy, B.iz};
+            for (int d = 0; d < 3; ++d) {
+                if (dl >= 0)
+                    k[d] = (2 * (int64_t)ia[d] + 1) * ((int64_t)1 << dl) - (2 * (int64_t)ib[d] + 1);
+                else
+                    k[d] = (2 * (int64_t)ia[d] + 1) - (2 * (int64_t)ib[d] + 1) * ((int64_t)1 << (-dl));
+                if (k[d] <= -(1 << 19) || k[d] >= (1 << 19)) throw PlanError{TFMM_ENOTSUP, "M2L offset out of range"};
+            }
+            const uint64_t packed = ((uint64_t)(dl + 32) << 60) | ((uint64_t)(k[0] + (1 << 19)) << 40) |
+                                    ((uint64_t)(k[1] + (1 << 19)) << 20) | (uint64_t)(k[2] + (1 << 19));
+            auto it = keymap.find(packed);
+            int32_t id;
+            if (it != keymap.end()) {
+                id = it->second;
+            } else {
+                id = (int32_t)(hp.m2l_keys.size() / 4);
+                keymap.emplace(packed, id);
+                hp.m2l_keys.push_back(dl);
+                hp.m2l_keys.push_back((int32_t)k[0]);
+                hp.m2l_keys.push_back((int32_t)k[1]);
+                hp.m2l_keys.push_back((int32_t)k[2]);
+            }
+            hp.m2l_pair_key[j] = id;
         }
-        const uint64_t packed = ((uint64_t)(dl + 32) << 60) | ((uint64_t)(k[0] + (1 << 19)) << 40) |
-                                ((uint64_t)(k[1] + (1 << 19)) << 20) | (uint64_t)(k[2] + (1 << 19));
-        auto it = keymap.find(packed);
-        if (it != keymap.end()) return it->second;
-        const int32_t id = (int32_t)(hp.m2l_keys.size() / 4);
-        keymap.emplace(packed, id);
-        hp.m2l_keys.push_back(dl);
-        hp.m2l_keys.push_back((int32_t)k[0]);
-        hp.m2l_keys.push_back((int32_t)k[1]);
-        hp.m2l_keys.push_back((int32_t)k[2]);
-        return id;
-    };
+    }
+}
+
+}  // namespace
+
+void build_m2l_tiles(const HostPlan &hp, int tpt, M2LTiles &out)
+{
+    out.tpt = tpt;
+    out.tile_tgt.clear();
+    out.tile_ptr.assign(1, 0);
+    out.ent_key.clear();
+    out.ent_src.clear();
     const int64_t nc = (int64_t)hp.cells.size();
     std::vector<int32_t> tile;
+    std::vector<std::array<int32_t, 3>> trip;  // key, slot, source
     auto flush = [&]() {
         if (tile.empty()) return;
-        std::vector<std::array<int32_t, 3>> trip;  // key, column, source
+        trip.clear();
         for (int t = 0; t < (int)tile.size(); ++t) {
             const int32_t a = tile[t];
-            for (int32_t j = hp.m2l_ptr[a]; j < hp.m2l_ptr[a + 1]; ++j) {
-                const int32_t b = hp.m2l_src[j];
-                trip.push_back({key_of(hp.cells[a], hp.cells[b]), t, b});
-            }
+            for (int32_t j = hp.m2l_ptr[a]; j < hp.m2l_ptr[a + 1]; ++j)
+                trip.push_back({hp.m2l_pair_key[j], t, hp.m2l_src[j]});
         }
         // entries sorted by level difference, then key (the kernel rescales
         // its accumulators when the level difference changes)
@@ -344,24 +364,24 @@ void build_m2l_tiles(HostPlan &hp)
         });
         for (size_t i = 0; i < trip.size();) {
             const int32_t k = trip[i][0];
-            hp.m2l_ent_key.push_back(k);
-            const size_t base = hp.m2l_ent_src.size();
-            hp.m2l_ent_src.resize(base + kM2LTile, -1);
-            for (; i < trip.size() && trip[i][0] == k; ++i) hp.m2l_ent_src[base + trip[i][1]] = trip[i][2];
+            out.ent_key.push_back(k);
+            const size_t base = out.ent_src.size();
+            out.ent_src.resize(base + tpt, -1);
+            for (; i < trip.size() && trip[i][0] == k; ++i) out.ent_src[base + trip[i][1]] = trip[i][2];
         }
-        for (int t = 0; t < kM2LTile; ++t) hp.m2l_tile_tgt.push_back(t < (int)tile.size() ? tile[t] : -1);
-        hp.m2l_tile_ptr.push_back((int32_t)hp.m2l_ent_key.size());
+        for (int t = 0; t < tpt; ++t) out.tile_tgt.push_back(t < (int)tile.size() ? tile[t] : -1);
+        out.tile_ptr.push_back((int32_t)out.ent_key.size());
+        if (out.ent_key.size() > (size_t)INT32_MAX / 16) throw PlanError{TFMM_ENOTSUP, "too many M2L entries"};
         tile.clear();
     };
     int cur_level = -1;
     for (int64_t a = 0; a < nc; ++a) {
         if (hp.m2l_ptr[a + 1] == hp.m2l_ptr[a]) continue;
-        if (hp.cells[a].level != cur_level || (int)tile.size() == kM2LTile) flush();
+        if (hp.cells[a].level != cur_level || (int)tile.size() == tpt) flush();
         cur_level = hp.cells[a].level;
         tile.push_back((int32_t)a);
     }
     flush();
-    if (hp.m2l_ent_key.size() > (size_t)INT32_MAX / kM2LTile) throw PlanError{TFMM_ENOTSUP, "too many M2L entries"};
 }
 
 }  // namespace tfmm

@@ -53,21 +53,26 @@ struct HostPlan {
     std::vector<int32_t> p2p_a, p2p_b;      // P2P leaf pairs (target, source)
     int64_t n_p2p_pairs = 0;                // sum of ntargets(A) * ntets(B)
 
-    // M2L grouped for matrix cores: target cells in tiles of kM2LTile cells of
-    // one level; per tile a list of entries, one per distinct translation key
-    // used by its cells, with the source cell of each tile column (-1: none).
-    // key = (dlevel, kx, ky, kz): dlevel = level(B) - level(A), k = (c_A - c_B)
-    // in units of half the smaller cube side (exact integers).
+    // M2L translation keys: key = (dlevel, kx, ky, kz), dlevel = level(B) -
+    // level(A), k = (c_A - c_B) in units of half the smaller cube side (exact
+    // integers); one key id per M2L pair (same order as m2l_src)
     std::vector<int32_t> m2l_keys;      // [nkeys][4]
-    std::vector<int32_t> m2l_tile_tgt;  // [ntiles][kM2LTile]
-    std::vector<int32_t> m2l_tile_ptr;  // [ntiles + 1] into the entries
-    std::vector<int32_t> m2l_ent_key;   // [nent]
-    std::vector<int32_t> m2l_ent_src;   // [nent][kM2LTile]
+    std::vector<int32_t> m2l_pair_key;  // [n_m2l]
 
     double setup_seconds = 0.0;
 };
 
-constexpr int kM2LTile = 16;
+// M2L grouped for matrix cores: target cells in tiles of `tpt` cells of one
+// level; per tile a list of entries, one per distinct key used by its cells
+// (sorted by level difference, then key), with the source cell of each tile
+// slot (-1: none).
+struct M2LTiles {
+    int tpt = 0;
+    std::vector<int32_t> tile_tgt;  // [ntiles][tpt]
+    std::vector<int32_t> tile_ptr;  // [ntiles + 1] into the entries
+    std::vector<int32_t> ent_key;   // [nent]
+    std::vector<int32_t> ent_src;   // [nent][tpt]
+};
 
 // Error raised by the plan builder: code is one of the TFMM_E* values.
 struct PlanError {
@@ -75,8 +80,8 @@ struct PlanError {
     std::string msg;
 };
 
-// Groups the M2L pairs of a built plan into target tiles and translation keys.
-void build_m2l_tiles(HostPlan &hp);
+// Groups the M2L pairs of a built plan into target tiles of tpt cells.
+void build_m2l_tiles(const HostPlan &hp, int tpt, M2LTiles &out);
 
 // Builds the plan.  Throws PlanError on invalid input.
 void build_host_plan(HostPlan &hp, const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,

@@ -81,6 +81,39 @@ def test_fmm_matches_oracle(torch_dev, orc, n, p, leaf, theta, F):
         assert _rel(u[f], ref[f]) <= TOL, f
 
 
+@pytest.mark.parametrize("F", [3, 16, 20])
+def test_fmm_field_batches_match_oracle(torch_dev, orc, F):
+    """Several fields share the M2L tiles as matrix columns (tiles of 16/F target
+    cells x F fields, F >= 16 in groups of 16): every field must equal the
+    oracle's single-field result."""
+    nodes, tets = meshgen.box_mesh(6, seed=11)
+    M = meshgen.random_fields(nodes.shape[0], F=F, seed=12)
+    _say("fmm fields", F)
+    P = T.tfmm_plan_create(nodes, tets, p=6, leaf_size=8, theta=0.5)
+    u = _run(torch_dev, P, M)
+    ref = orc.FMM(nodes, tets, 6, 8, 0.5).evaluate(M)
+    for f in range(F):
+        assert _rel(u[f], ref[f]) <= TOL, f
+
+
+def test_fp32_m2l_accuracy(torch_dev, orc):
+    """FP32 matrix-core M2L on level-scaled expansions: close to the FP64 FMM,
+    and its error against the direct sum stays at the FMM's own level."""
+    nodes, tets = meshgen.box_mesh(12, seed=13)
+    M = meshgen.random_fields(nodes.shape[0], F=2, seed=14)
+    _say("fp32 m2l")
+    P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=16, theta=0.5)
+    u64 = _run(torch_dev, P, M)
+    ud = _run(torch_dev, P, M, direct=True)
+    T.tfmm_plan_set_m2l_precision(P, T.M2L_FP32)
+    u32 = _run(torch_dev, P, M)
+    for f in range(2):
+        e64 = _rel(u64[f], ud[f])
+        e32 = _rel(u32[f], ud[f])
+        assert _rel(u32[f], u64[f]) <= 1e-6
+        assert e32 <= e64 + 1e-6
+
+
 def test_expansions_match_oracle(torch_dev, orc):
     """Stage parity: multipole (P2M + M2M) and local (M2L + L2L) coefficients per cell."""
     nodes, tets = meshgen.box_mesh(6, seed=8)
