@@ -186,16 +186,20 @@ def main():
             T.tfmm_evaluate(plan, Mv, uv)
             udv = T.tfmm_direct(plan, Mv) if F > 1 else ud
             torch.cuda.synchronize()
+            T.tfmm_set_timing(plan, True)
             t1 = time.perf_counter()
             for _ in range(args.variant_steps):
                 T.tfmm_evaluate(plan, Mv, uv)
             torch.cuda.synchronize()
             dv = (time.perf_counter() - t1) / args.variant_steps
+            kv = T.tfmm_kernel_times(plan)
+            T.tfmm_set_timing(plan, False)
             ev = max(float(torch.linalg.norm(uv[f] - udv[f]) / torch.linalg.norm(udv[f])) for f in range(F))
             variants[name] = {"value": nodes.shape[0] * F / dv, "unit": "evals/s", "ms_per_step": dv * 1e3,
                               "fields": F, "m2l": "fp32" if prec == T.M2L_FP32 else "fp64",
                               "rel_l2_vs_direct_max_over_fields": ev,
-                              "speedup_vs_plain": (nodes.shape[0] * F / dv) / value}
+                              "speedup_vs_plain": (nodes.shape[0] * F / dv) / value,
+                              "kernel_ms": {k: round(v[0], 4) for k, v in kv.items()}}
             del Mv, uv, udv
         T.tfmm_plan_set_m2l_precision(plan, T.M2L_FP64)
         out["variants"] = variants

@@ -83,6 +83,19 @@ __host__ __device__ constexpr int ncoef_of(int p) { return (p + 1) * (p + 2) * (
 
 constexpr double kInv4Pi = 0.07957747154594767;  // 1/(4 pi)
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  A grid of 8 * ceil(n/8) workgroups in x is remapped so that XCD x
+// runs items [x * per, (x + 1) * per): neighbouring items (Morton order) share
+// an L2.  Returns -1 for the padding workgroups.
+constexpr int kXcds = 8;
+__host__ __device__ constexpr unsigned xcd_grid(int n) { return (unsigned)(kXcds * ((n + kXcds - 1) / kXcds)); }
+__device__ __forceinline__ int xcd_item(int n)
+{
+    const int w = blockIdx.x, per = (n + kXcds - 1) / kXcds;
+    const int item = (w % kXcds) * per + w / kXcds;
+    return item < n ? item : -1;
+}
+
 // cell int fields
 enum { CI_TBEG = 0, CI_TEND, CI_XBEG, CI_XEND, CI_CBEG, CI_NCHILD, CI_PARENT, CI_LEVEL, CI_N };
 
@@ -182,11 +195,13 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m(const int32_t *__restrict__
                                                      const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node,
                                                      int64_t T, const double *__restrict__ mom,
                                                      const double *__restrict__ M, int64_t n_nodes, int p,
-                                                     double *__restrict__ Q)
+                                                     int ncells, double *__restrict__ Q)
 {
     __shared__ double s_S[kNcoefMax];
     __shared__ double s_m[12];  // M(c) [3], G [3][3] of the current tet
-    const int cell = cells[blockIdx.x];
+    const int item = xcd_item(ncells);
+    if (item < 0) return;
+    const int cell = cells[item];
     const int f = blockIdx.y;
     const double *Mf = M + (int64_t)f * n_nodes * 3;
     const int tbeg = cell_i[CI_N * cell + CI_TBEG], tend = cell_i[CI_N * cell + CI_TEND];
@@ -567,14 +582,14 @@ template <typename T, int P, int W>
 __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, const int32_t *__restrict__ ent_key,
                                          const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys,
                                          const T *__restrict__ Dtab, const T *__restrict__ Qt, int qpad, int64_t C,
-                                         M2LCols cols, T *s_D, T *s_Q, typename Mfma<T>::v4 (&acc)[m2l_nrt(P)])
+                                         M2LCols cols, int tile, T *s_D, T *s_Q,
+                                         typename Mfma<T>::v4 (&acc)[m2l_nrt(P)])
 {
     using v4 = typename Mfma<T>::v4;
     constexpr int NC = ncoef_of(P), KSTR = m2l_kstr(P), DSTR = NC + 1;
     constexpr int NT = 64 * kM2LWaves;
     static_assert(NT == 256, "16 columns x 16 threads");
     constexpr int QREG = (NC + 15) / 16, DREG = (NC + NT - 1) / NT;
-    const int tile = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63;
     const int tcol = tid >> 4, tn = tid & 15;
     const int tslot = tcol / cols.fpt, field = cols.f0 + tcol % cols.fpt;
@@ -660,7 +675,7 @@ __global__ __launch_bounds__(64 * kM2LWaves, (P <= 8 ? 2 : 1)) void k_m2l_mfma(
     const int32_t *__restrict__ tile_tgt, const int32_t *__restrict__ tile_ptr, const int32_t *__restrict__ ent_key,
     const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys, const T *__restrict__ Dtab,
     const T *__restrict__ Qt, int qpad, const int32_t *__restrict__ cell_i, double side, int64_t C, int tpt, int fpt,
-    int F, double *__restrict__ L)
+    int F, int ntiles, double *__restrict__ L)
 {
     using v4 = typename Mfma<T>::v4;
     constexpr int NC = ncoef_of(P), NRT = m2l_nrt(P), KSTR = m2l_kstr(P);
@@ -670,6 +685,7 @@ __global__ __launch_bounds__(64 * kM2LWaves, (P <= 8 ? 2 : 1)) void k_m2l_mfma(
     __shared__ T s_D[2 * (NC + 1)];
     __shared__ __align__(16) T s_Q[2 * 16 * KSTR];
     const int tile = blockIdx.x;
+    if (tile >= ntiles) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const M2LCols cols{tpt, fpt, (int)blockIdx.y * fpt, F};
     for (int i = tid; i < 2 * 16 * KSTR; i += blockDim.x) s_Q[i] = (T)0;  // column padding stays zero
@@ -679,10 +695,10 @@ __global__ __launch_bounds__(64 * kM2LWaves, (P <= 8 ? 2 : 1)) void k_m2l_mfma(
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt) acc[rt] = v4{0, 0, 0, 0};
     switch (wave) {
-    case 0: m2l_tile<T, P, 0>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, s_D, s_Q, acc); break;
-    case 1: m2l_tile<T, P, 1>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, s_D, s_Q, acc); break;
-    case 2: m2l_tile<T, P, 2>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, s_D, s_Q, acc); break;
-    default: m2l_tile<T, P, 3>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, s_D, s_Q, acc); break;
+    case 0: m2l_tile<T, P, 0>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, tile, s_D, s_Q, acc); break;
+    case 1: m2l_tile<T, P, 1>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, tile, s_D, s_Q, acc); break;
+    case 2: m2l_tile<T, P, 2>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, tile, s_D, s_Q, acc); break;
+    default: m2l_tile<T, P, 3>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, tile, s_D, s_Q, acc); break;
     }
     // sum the waves' partial accumulators in LDS (FP64): red[c][m], c = column
     __syncthreads();
@@ -1006,60 +1022,70 @@ __device__ __forceinline__ void pair_geometry(const double x[3], const TetGeom &
     }
 }
 
+// Tets staged in LDS at a time for FCH fields (geometry 240 B + 208 B per
+// field per tet): 64 tets up to 4 fields, 32 up to 8, 16 up to 16.
+__host__ __device__ constexpr int p2p_stage(int FCH) { return FCH >= 16 ? 16 : (FCH >= 8 ? 32 : 64); }
+
 template <int FCH>
-__global__ __launch_bounds__(kP2PThreads) void k_p2p(const int32_t *__restrict__ blk, int direct_tets, int64_t T,
+__global__ __launch_bounds__(kP2PThreads) void k_p2p(const int32_t *__restrict__ blk, int nblk, int direct_tets, int64_t T,
                                                      const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node,
                                                      const int32_t *__restrict__ idx, const double *__restrict__ tgt_xyz,
                                                      const int32_t *__restrict__ tgt_perm, int64_t N,
                                                      const double *__restrict__ M, int64_t n_nodes, int f0,
                                                      double *__restrict__ u)
 {
-    __shared__ TetGeom s_g[kP2PTets];
-    __shared__ TetField s_f[kP2PTets][FCH];
+    constexpr int BT = p2p_stage(FCH);
+    __shared__ TetGeom s_g[BT];
+    __shared__ TetField s_f[BT][FCH];
+    const int b = xcd_item(nblk);
+    if (b < 0) return;
     int tb, te, ib, ie;
     if (direct_tets) {  // direct sum: consecutive tets, all targets
-        tb = blockIdx.x * kP2PTets;
+        tb = b * kP2PTets;
         te = min<int64_t>(T, tb + kP2PTets);
         ib = 0;
         ie = (int)N;
     } else {
-        tb = blk[4 * blockIdx.x];
-        te = blk[4 * blockIdx.x + 1];
-        ib = blk[4 * blockIdx.x + 2];
-        ie = blk[4 * blockIdx.x + 3];
+        tb = blk[4 * b];
+        te = blk[4 * b + 1];
+        ib = blk[4 * b + 2];
+        ie = blk[4 * b + 3];
     }
-    const int nt = te - tb;
     const double *Mf0 = M + (int64_t)f0 * n_nodes * 3;
-    for (int t = threadIdx.x; t < nt; t += blockDim.x)
-        tet_prepare(tet_xyz, tet_node, T, tb + t, Mf0, n_nodes, FCH, s_g[t], s_f[t]);
-    __syncthreads();
-    for (int i = ib + threadIdx.x; i < ie; i += blockDim.x) {
-        const int s = direct_tets ? i : idx[i];
-        const double x[3] = {tgt_xyz[s], tgt_xyz[N + s], tgt_xyz[2 * N + s]};
-        double acc[FCH];
+    for (int sb = tb; sb < te; sb += BT) {
+        const int nt = min(BT, te - sb);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nt; t += blockDim.x)
+            tet_prepare(tet_xyz, tet_node, T, sb + t, Mf0, n_nodes, FCH, s_g[t], s_f[t]);
+        __syncthreads();
+        for (int i = ib + threadIdx.x; i < ie; i += blockDim.x) {
+            const int s = direct_tets ? i : idx[i];
+            const double x[3] = {tgt_xyz[s], tgt_xyz[N + s], tgt_xyz[2 * N + s]};
+            double acc[FCH];
 #pragma unroll
-        for (int f = 0; f < FCH; ++f) acc[f] = 0.0;
-        for (int t = 0; t < nt; ++t) {
-            double I0[4], ge[6], h[4], d0[3];
-            pair_geometry(x, s_g[t], I0, ge, h, d0);
+            for (int f = 0; f < FCH; ++f) acc[f] = 0.0;
+            for (int t = 0; t < nt; ++t) {
+                double I0[4], ge[6], h[4], d0[3];
+                pair_geometry(x, s_g[t], I0, ge, h, d0);
 #pragma unroll
-            for (int f = 0; f < FCH; ++f) {
-                const TetField &F1 = s_f[t][f];
-                double v = 0.0;
+                for (int f = 0; f < FCH; ++f) {
+                    const TetField &F1 = s_f[t][f];
+                    double v = 0.0;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const double alpha =
-                        F1.a[k] - (d0[0] * F1.b[k][0] + d0[1] * F1.b[k][1] + d0[2] * F1.b[k][2]) + F1.c[k] * h[k];
-                    v += alpha * I0[k];
+                    for (int k = 0; k < 4; ++k) {
+                        const double alpha =
+                            F1.a[k] - (d0[0] * F1.b[k][0] + d0[1] * F1.b[k][1] + d0[2] * F1.b[k][2]) + F1.c[k] * h[k];
+                        v += alpha * I0[k];
+                    }
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) v += F1.g[e] * ge[e];
+                    acc[f] += v;
                 }
-#pragma unroll
-                for (int e = 0; e < 6; ++e) v += F1.g[e] * ge[e];
-                acc[f] += v;
             }
-        }
-        const int64_t o = tgt_perm[s];
+            const int64_t o = tgt_perm[s];
 #pragma unroll
-        for (int f = 0; f < FCH; ++f) atomicAdd(&u[(int64_t)(f0 + f) * N + o], acc[f] * kInv4Pi);
+            for (int f = 0; f < FCH; ++f) atomicAdd(&u[(int64_t)(f0 + f) * N + o], acc[f] * kInv4Pi);
+        }
     }
 }
 
@@ -1120,7 +1146,7 @@ void launch_p2p(DevicePlan &dp, bool direct, int f0, const double *M, double *u,
     const HostPlan &hp = dp.hp;
     unsigned nblk = direct ? (unsigned)((hp.n_tets + kP2PTets - 1) / kP2PTets) : (unsigned)dp.n_p2p_blk;
     if (nblk == 0) return;
-    k_p2p<FCH><<<dim3(nblk), dim3(kP2PThreads), 0, st>>>(dp.p2p_blk, direct ? 1 : 0, hp.n_tets, dp.tet_xyz,
+    k_p2p<FCH><<<dim3(xcd_grid((int)nblk)), dim3(kP2PThreads), 0, st>>>(dp.p2p_blk, (int)nblk, direct ? 1 : 0, hp.n_tets, dp.tet_xyz,
                                                          dp.tet_node, dp.p2p_idx, dp.tgt_xyz, dp.tgt_perm,
                                                          hp.n_targets, M, hp.n_nodes, f0, u);
     hip_check(hipGetLastError(), "k_p2p launch");
@@ -1130,8 +1156,14 @@ void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u,
 {
     int f = 0;
     while (f < F) {
-        int left = F - f;
-        if (left >= 4) {
+        const int left = F - f;
+        if (left >= 16) {
+            launch_p2p<16>(dp, direct, f, M, u, st);
+            f += 16;
+        } else if (left >= 8) {
+            launch_p2p<8>(dp, direct, f, M, u, st);
+            f += 8;
+        } else if (left >= 4) {
             launch_p2p<4>(dp, direct, f, M, u, st);
             f += 4;
         } else if (left >= 2) {
@@ -1152,7 +1184,7 @@ void launch_m2l_p(DevicePlan &dp, const DevicePlan::Tiles &tl, const T *D, const
     const unsigned groups = (unsigned)((F + fpt - 1) / fpt);
     k_m2l_mfma<T, P><<<dim3(tl.ntiles, groups), dim3(64 * kM2LWaves), 0, st>>>(
         tl.tile_tgt, tl.tile_ptr, tl.ent_key, tl.ent_src, dp.m2l_keys, D, Qt, dp.qpad, dp.cell_i, hp.side,
-        (int64_t)hp.cells.size(), tl.tpt, fpt, F, dp.L);
+        (int64_t)hp.cells.size(), tl.tpt, fpt, F, tl.ntiles, dp.L);
     hip_check(hipGetLastError(), "k_m2l_mfma launch");
 }
 
@@ -1311,9 +1343,9 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
     {
         KTimer kt(dp, KT_P2M, st);
         if (dp.n_p2m_cells > 0) {
-            k_p2m<<<dim3(dp.n_p2m_cells, F), dim3(kP2MThreads), 0, st>>>(dp.p2m_cells, dp.cell_i, dp.cell_c, C,
-                                                                          dp.tet_xyz, dp.tet_node, hp.n_tets, dp.tet_mom,
-                                                                          M, hp.n_nodes, p, dp.Q);
+            k_p2m<<<dim3(xcd_grid(dp.n_p2m_cells), F), dim3(kP2MThreads), 0, st>>>(
+                dp.p2m_cells, dp.cell_i, dp.cell_c, C, dp.tet_xyz, dp.tet_node, hp.n_tets, dp.tet_mom, M, hp.n_nodes, p,
+                dp.n_p2m_cells, dp.Q);
             hip_check(hipGetLastError(), "k_p2m launch");
         }
     }
