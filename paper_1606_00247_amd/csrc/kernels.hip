@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/tetfmm.h"
@@ -187,31 +188,41 @@ __global__ __launch_bounds__(kMomThreads) void k_tet_moments(const int32_t *__re
     }
 }
 
-// One workgroup per leaf holding tets (blockIdx.x), field blockIdx.y.
+// P2M, M2M and L2L process FC fields per workgroup (blockIdx.y = field
+// chunk): the field-independent work (moments, shift coefficients) is done
+// once and applied to all FC fields.
+__host__ __device__ constexpr int field_chunk(int F) { return F >= 16 ? 16 : (F >= 4 ? 4 : 1); }
+
+// One workgroup per leaf holding tets (XCD-contiguous), FC fields.
 constexpr int kP2MThreads = 256;
 
+template <int FC>
 __global__ __launch_bounds__(kP2MThreads) void k_p2m(const int32_t *__restrict__ cells, const int32_t *__restrict__ cell_i,
                                                      const double *__restrict__ cell_c, int64_t C,
                                                      const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node,
                                                      int64_t T, const double *__restrict__ mom,
-                                                     const double *__restrict__ M, int64_t n_nodes, int p,
+                                                     const double *__restrict__ M, int64_t n_nodes, int F, int p,
                                                      int ncells, double *__restrict__ Q)
 {
     __shared__ double s_S[kNcoefMax];
-    __shared__ double s_m[12];  // M(c) [3], G [3][3] of the current tet
+    __shared__ double s_m[FC][12];  // per field: M(c) [3], G [3][3] of the current tet
     const int item = xcd_item(ncells);
     if (item < 0) return;
     const int cell = cells[item];
-    const int f = blockIdx.y;
-    const double *Mf = M + (int64_t)f * n_nodes * 3;
+    const int f0 = blockIdx.y * FC;
     const int tbeg = cell_i[CI_N * cell + CI_TBEG], tend = cell_i[CI_N * cell + CI_TEND];
     const int ncoef = ncoef_of(p);
     const int tid = threadIdx.x;
-    double acc[2] = {0.0, 0.0};
+    double acc[2][FC];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int j = 0; j < FC; ++j) acc[r][j] = 0.0;
     for (int t = tbeg; t < tend; ++t) {
         __syncthreads();
         for (int m = tid; m < ncoef; m += blockDim.x) s_S[m] = mom[(int64_t)t * ncoef + m];
-        if (tid == 0) {
+        if (tid < FC && f0 + tid < F) {
+            const double *Mf = M + (int64_t)(f0 + tid) * n_nodes * 3;
             double v[4][3], mm[4][3];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -253,61 +264,82 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m(const int32_t *__restrict__
                 double G[3];
 #pragma unroll
                 for (int b = 0; b < 3; ++b) G[b] = mm[0][a] * g[0][b] + mm[1][a] * g[1][b] + mm[2][a] * g[2][b] + mm[3][a] * g[3][b];
-                s_m[a] = mm[0][a] + (G[0] * dc[0] + G[1] * dc[1] + G[2] * dc[2]);  // M_a(c)
-                s_m[3 + 3 * a] = G[0];
-                s_m[4 + 3 * a] = G[1];
-                s_m[5 + 3 * a] = G[2];
+                s_m[tid][a] = mm[0][a] + (G[0] * dc[0] + G[1] * dc[1] + G[2] * dc[2]);  // M_a(c)
+                s_m[tid][3 + 3 * a] = G[0];
+                s_m[tid][4 + 3 * a] = G[1];
+                s_m[tid][5 + 3 * a] = G[2];
             }
         }
         __syncthreads();
+#pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int n = tid + r * kP2MThreads;
-            if (n >= ncoef) break;
-            const int nv[3] = {c_mi.v[n][0], c_mi.v[n][1], c_mi.v[n][2]};
-            double s = 0.0;
+            if (n < ncoef) {
+                const int nv[3] = {c_mi.v[n][0], c_mi.v[n][1], c_mi.v[n][2]};
+                // S_{n-e_k} and S_{n-e_k+e_d} of this coefficient, shared by all fields
+                double sv[3][4];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                if (nv[k] == 0) continue;
-                int b[3] = {nv[0], nv[1], nv[2]};
-                b[k] -= 1;  // n - e_k
-                double w = s_m[k] * s_S[mi_index(b[0], b[1], b[2])];
-                w += s_m[3 + 3 * k] * s_S[mi_index(b[0] + 1, b[1], b[2])];
-                w += s_m[4 + 3 * k] * s_S[mi_index(b[0], b[1] + 1, b[2])];
-                w += s_m[5 + 3 * k] * s_S[mi_index(b[0], b[1], b[2] + 1)];
-                s += nv[k] * w;
+                for (int k = 0; k < 3; ++k) {
+                    int b[3] = {nv[0], nv[1], nv[2]};
+                    b[k] = b[k] > 0 ? b[k] - 1 : 0;
+                    sv[k][0] = nv[k] ? s_S[mi_index(b[0], b[1], b[2])] : 0.0;
+                    sv[k][1] = nv[k] ? s_S[mi_index(b[0] + 1, b[1], b[2])] : 0.0;
+                    sv[k][2] = nv[k] ? s_S[mi_index(b[0], b[1] + 1, b[2])] : 0.0;
+                    sv[k][3] = nv[k] ? s_S[mi_index(b[0], b[1], b[2] + 1)] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < FC; ++j) {
+                    double sacc = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const double w = s_m[j][k] * sv[k][0] + s_m[j][3 + 3 * k] * sv[k][1] +
+                                         s_m[j][4 + 3 * k] * sv[k][2] + s_m[j][5 + 3 * k] * sv[k][3];
+                        sacc += nv[k] * w;
+                    }
+                    acc[r][j] += sacc;
+                }
             }
-            acc[r] += s;
         }
     }
-    double *Qc = Q + ((int64_t)f * C + cell) * ncoef;
+#pragma unroll
     for (int r = 0; r < 2; ++r) {
         const int n = tid + r * kP2MThreads;
-        if (n < ncoef) Qc[n] = acc[r];
+        if (n >= ncoef) continue;
+#pragma unroll
+        for (int j = 0; j < FC; ++j)
+            if (f0 + j < F) Q[((int64_t)(f0 + j) * C + cell) * ncoef + n] = acc[r][j];
     }
 }
 
 // ---------------------------------------------------------------------------
-// M2M.  One workgroup per parent cell of a level (blockIdx.x), field blockIdx.y.
+// M2M.  One workgroup per parent cell of a level (blockIdx.x), FC fields.
 //   Q_n(P) = sum_children sum_{k <= n} C(n,k) (c_C - c_P)^{n-k} Q_k(C)
 // ---------------------------------------------------------------------------
 constexpr int kShiftThreads = 256;
 
+template <int FC>
 __global__ __launch_bounds__(kShiftThreads) void k_m2m(const int32_t *__restrict__ cells, const int32_t *__restrict__ cell_i,
-                                                       const double *__restrict__ cell_c, int64_t C, int p,
+                                                       const double *__restrict__ cell_c, int64_t C, int F, int p,
                                                        double *__restrict__ Q)
 {
-    __shared__ double s_q[kNcoefMax];
+    __shared__ double s_q[FC][kNcoefMax];
     __shared__ double s_pw[3][kPmax + 1];
     const int cell = cells[blockIdx.x];
-    const int f = blockIdx.y;
+    const int f0 = blockIdx.y * FC;
     const int ncoef = ncoef_of(p);
     const int cbeg = cell_i[CI_N * cell + CI_CBEG], nch = cell_i[CI_N * cell + CI_NCHILD];
-    double acc[2] = {0.0, 0.0};
+    double acc[2][FC];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int j = 0; j < FC; ++j) acc[r][j] = 0.0;
     for (int ch = cbeg; ch < cbeg + nch; ++ch) {
         if (cell_i[CI_N * ch + CI_TEND] == cell_i[CI_N * ch + CI_TBEG]) continue;  // no tets
         __syncthreads();
-        const double *Qc = Q + ((int64_t)f * C + ch) * ncoef;
-        for (int n = threadIdx.x; n < ncoef; n += blockDim.x) s_q[n] = Qc[n];
+        for (int i = threadIdx.x; i < FC * ncoef; i += blockDim.x) {
+            const int j = i / ncoef, n = i - j * ncoef;
+            s_q[j][n] = f0 + j < F ? Q[((int64_t)(f0 + j) * C + ch) * ncoef + n] : 0.0;
+        }
         if (threadIdx.x < 3) {
             const int k = threadIdx.x;
             const double dlt = cell_c[k * C + ch] - cell_c[k * C + cell];
@@ -318,45 +350,54 @@ __global__ __launch_bounds__(kShiftThreads) void k_m2m(const int32_t *__restrict
             }
         }
         __syncthreads();
+#pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int n = threadIdx.x + r * blockDim.x;
-            if (n >= ncoef) break;
+            if (n >= ncoef) continue;
             const int nx = c_mi.v[n][0], ny = c_mi.v[n][1], nz = c_mi.v[n][2];
-            double s = 0.0;
             for (int kx = 0; kx <= nx; ++kx) {
                 const double ax = c_bin.c[nx][kx] * s_pw[0][nx - kx];
                 for (int ky = 0; ky <= ny; ++ky) {
                     const double axy = ax * c_bin.c[ny][ky] * s_pw[1][ny - ky];
-                    for (int kz = 0; kz <= nz; ++kz)
-                        s += axy * c_bin.c[nz][kz] * s_pw[2][nz - kz] * s_q[mi_index(kx, ky, kz)];
+                    for (int kz = 0; kz <= nz; ++kz) {
+                        const double cf = axy * c_bin.c[nz][kz] * s_pw[2][nz - kz];
+                        const int ki = mi_index(kx, ky, kz);
+#pragma unroll
+                        for (int j = 0; j < FC; ++j) acc[r][j] += cf * s_q[j][ki];
+                    }
                 }
             }
-            acc[r] += s;
         }
     }
-    double *Qp = Q + ((int64_t)f * C + cell) * ncoef;
+#pragma unroll
     for (int r = 0; r < 2; ++r) {
         const int n = threadIdx.x + r * blockDim.x;
-        if (n < ncoef) Qp[n] = acc[r];
+        if (n >= ncoef) continue;
+#pragma unroll
+        for (int j = 0; j < FC; ++j)
+            if (f0 + j < F) Q[((int64_t)(f0 + j) * C + cell) * ncoef + n] = acc[r][j];
     }
 }
 
 // ---------------------------------------------------------------------------
-// L2L.  One workgroup per child cell of a level (blockIdx.x), field blockIdx.y.
+// L2L.  One workgroup per child cell of a level (blockIdx.x), FC fields.
 //   l_m(C) += sum_{k >= m, |k| <= p} C(k,m) (c_C - c_P)^{k-m} l_k(P)
 // ---------------------------------------------------------------------------
+template <int FC>
 __global__ __launch_bounds__(kShiftThreads) void k_l2l(const int32_t *__restrict__ cells, const int32_t *__restrict__ cell_i,
-                                                       const double *__restrict__ cell_c, int64_t C, int p,
+                                                       const double *__restrict__ cell_c, int64_t C, int F, int p,
                                                        double *__restrict__ L)
 {
-    __shared__ double s_l[kNcoefMax];
+    __shared__ double s_l[FC][kNcoefMax];
     __shared__ double s_pw[3][kPmax + 1];
     const int cell = cells[blockIdx.x];
-    const int f = blockIdx.y;
+    const int f0 = blockIdx.y * FC;
     const int ncoef = ncoef_of(p);
     const int par = cell_i[CI_N * cell + CI_PARENT];
-    const double *Lp = L + ((int64_t)f * C + par) * ncoef;
-    for (int n = threadIdx.x; n < ncoef; n += blockDim.x) s_l[n] = Lp[n];
+    for (int i = threadIdx.x; i < FC * ncoef; i += blockDim.x) {
+        const int j = i / ncoef, n = i - j * ncoef;
+        s_l[j][n] = f0 + j < F ? L[((int64_t)(f0 + j) * C + par) * ncoef + n] : 0.0;
+    }
     if (threadIdx.x < 3) {
         const int k = threadIdx.x;
         const double dlt = cell_c[k * C + cell] - cell_c[k * C + par];
@@ -367,20 +408,26 @@ __global__ __launch_bounds__(kShiftThreads) void k_l2l(const int32_t *__restrict
         }
     }
     __syncthreads();
-    double *Lc = L + ((int64_t)f * C + cell) * ncoef;
     for (int m = threadIdx.x; m < ncoef; m += blockDim.x) {
-        const int mx = c_mi.v[m][0], my = c_mi.v[m][1], mz = c_mi.v[m][2], dm = c_mi.v[m][3];
-        double s = 0.0;
+        const int mx = c_mi.v[m][0], my = c_mi.v[m][1], mz = c_mi.v[m][2];
+        double acc[FC];
+#pragma unroll
+        for (int j = 0; j < FC; ++j) acc[j] = 0.0;
         for (int kx = mx; kx <= p - (my + mz); ++kx) {
             const double ax = c_bin.c[kx][mx] * s_pw[0][kx - mx];
             for (int ky = my; ky <= p - kx - mz; ++ky) {
                 const double axy = ax * c_bin.c[ky][my] * s_pw[1][ky - my];
-                for (int kz = mz; kz <= p - kx - ky; ++kz)
-                    s += axy * c_bin.c[kz][mz] * s_pw[2][kz - mz] * s_l[mi_index(kx, ky, kz)];
+                for (int kz = mz; kz <= p - kx - ky; ++kz) {
+                    const double cf = axy * c_bin.c[kz][mz] * s_pw[2][kz - mz];
+                    const int ki = mi_index(kx, ky, kz);
+#pragma unroll
+                    for (int j = 0; j < FC; ++j) acc[j] += cf * s_l[j][ki];
+                }
             }
         }
-        (void)dm;
-        Lc[m] += s;
+#pragma unroll
+        for (int j = 0; j < FC; ++j)
+            if (f0 + j < F) L[((int64_t)(f0 + j) * C + cell) * ncoef + m] += acc[j];
     }
 }
 
@@ -1099,6 +1146,17 @@ void hip_check(hipError_t e, const char *what)
 
 namespace {
 
+// Calls fn with std::integral_constant<int, field_chunk(F)>.
+template <class Fn>
+void launch_fc(int F, Fn &&fn)
+{
+    switch (field_chunk(F)) {
+    case 16: fn(std::integral_constant<int, 16>{}); break;
+    case 4: fn(std::integral_constant<int, 4>{}); break;
+    default: fn(std::integral_constant<int, 1>{}); break;
+    }
+}
+
 hipEvent_t pool_event(DevicePlan &dp)
 {
     if (dp.events_used == dp.event_pool.size()) {
@@ -1342,22 +1400,24 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
     fill(dp.L, (int64_t)F * C * dp.ncoef, 0.0, st);
     {
         KTimer kt(dp, KT_P2M, st);
-        if (dp.n_p2m_cells > 0) {
-            k_p2m<<<dim3(xcd_grid(dp.n_p2m_cells), F), dim3(kP2MThreads), 0, st>>>(
-                dp.p2m_cells, dp.cell_i, dp.cell_c, C, dp.tet_xyz, dp.tet_node, hp.n_tets, dp.tet_mom, M, hp.n_nodes, p,
-                dp.n_p2m_cells, dp.Q);
+        if (dp.n_p2m_cells > 0) launch_fc(F, [&](auto fc) {
+            constexpr int FC = decltype(fc)::value;
+            k_p2m<FC><<<dim3(xcd_grid(dp.n_p2m_cells), (F + FC - 1) / FC), dim3(kP2MThreads), 0, st>>>(
+                dp.p2m_cells, dp.cell_i, dp.cell_c, C, dp.tet_xyz, dp.tet_node, hp.n_tets, dp.tet_mom, M, hp.n_nodes, F,
+                p, dp.n_p2m_cells, dp.Q);
             hip_check(hipGetLastError(), "k_p2m launch");
-        }
+        });
     }
     {
         KTimer kt(dp, KT_M2M, st);
         for (int Lv = hp.depth - 1; Lv >= 0; --Lv) {
             int b = dp.m2m_level_ptr[Lv], e = dp.m2m_level_ptr[Lv + 1];
-            if (e > b) {
-                k_m2m<<<dim3(e - b, F), dim3(kShiftThreads), 0, st>>>(dp.m2m_cells + b, dp.cell_i, dp.cell_c, C, p,
-                                                                        dp.Q);
+            if (e > b) launch_fc(F, [&](auto fc) {
+                constexpr int FC = decltype(fc)::value;
+                k_m2m<FC><<<dim3(e - b, (F + FC - 1) / FC), dim3(kShiftThreads), 0, st>>>(dp.m2m_cells + b, dp.cell_i,
+                                                                                             dp.cell_c, C, F, p, dp.Q);
                 hip_check(hipGetLastError(), "k_m2m launch");
-            }
+            });
         }
     }
     {
@@ -1368,11 +1428,12 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
         KTimer kt(dp, KT_L2L, st);
         for (int Lv = 1; Lv <= hp.depth; ++Lv) {
             int b = dp.l2l_level_ptr[Lv], e = dp.l2l_level_ptr[Lv + 1];
-            if (e > b) {
-                k_l2l<<<dim3(e - b, F), dim3(kShiftThreads), 0, st>>>(dp.l2l_cells + b, dp.cell_i, dp.cell_c, C, p,
-                                                                        dp.L);
+            if (e > b) launch_fc(F, [&](auto fc) {
+                constexpr int FC = decltype(fc)::value;
+                k_l2l<FC><<<dim3(e - b, (F + FC - 1) / FC), dim3(kShiftThreads), 0, st>>>(dp.l2l_cells + b, dp.cell_i,
+                                                                                             dp.cell_c, C, F, p, dp.L);
                 hip_check(hipGetLastError(), "k_l2l launch");
-            }
+            });
         }
     }
     {
