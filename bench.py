@@ -43,13 +43,10 @@ WORKLOADS = {
 
 
 def m2l_terms(p):
-    """(m, n) pairs of the truncated M2L: |n| >= 1, |n| + |m| <= p."""
-    tot = 0
-    for dm in range(p + 1):
-        nm = (dm + 1) * (dm + 2) // 2
-        nn = sum((d + 1) * (d + 2) // 2 for d in range(1, p - dm + 1))
-        tot += nm * nn
-    return tot
+    """Multiply-adds of one translation as computed: the harmonic reduction
+    keeps the indices with z-component <= 1 on both sides ((2d+1) of degree d),
+    |n| >= 1, |m| <= p - 1, |n| + |m| <= p (1284 at p = 8)."""
+    return sum((2 * dm + 1) * (2 * dn + 1) for dm in range(p) for dn in range(1, p - dm + 1))
 
 
 def kernel_source_hash():

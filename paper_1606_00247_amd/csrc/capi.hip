@@ -190,11 +190,11 @@ void upload_plan(DevicePlan &dp)
     {
         dp.n_m2l_keys = (int32_t)(hp.m2l_keys.size() / 4);
         dp.m2l_keys = dev_upload(hp.m2l_keys, B);
-        const size_t tb = sizeof(double) * std::max<size_t>(1, (size_t)dp.n_m2l_keys * dp.ncoef);
+        const size_t tb = sizeof(double) * std::max<size_t>(1, (size_t)dp.n_m2l_keys * m2l_table_width(hp.p));
         hip_check(hipMalloc(&dp.m2l_D, tb), "hipMalloc M2L table");
         B += (int64_t)tb;
         build_m2l_table(dp);
-        dp.qpad = (dp.ncoef + 3) / 4 * 4;
+        dp.qpad = (m2l_reduced_width(hp.p) + 3) / 4 * 4;
         ensure_m2l_tiles(dp, 16);
     }
     {

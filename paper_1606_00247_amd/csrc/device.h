@@ -10,6 +10,12 @@
 
 namespace tfmm {
 
+// M2L runs on the harmonic reduction of the expansions: reduced multipoles
+// have the (p+1)^2 indices with n_z <= 1, the per-key derivative table the
+// 1 + 3p(p+1)/2 derivatives with k_z <= 2.
+inline int m2l_reduced_width(int p) { return (p + 1) * (p + 1); }
+inline int m2l_table_width(int p) { return 1 + 3 * p * (p + 1) / 2; }
+
 // Thrown by launchers on HIP failures (converted to TFMM_EDEVICE at the ABI).
 struct DeviceError {
     std::string msg;
@@ -46,7 +52,7 @@ struct DevicePlan {
     // M2L on matrix cores: translation keys and their derivative tables
     // D_k(rho), rho = (c_A - c_B) / side(B), in FP64 and (on demand) FP32
     int32_t *m2l_keys = nullptr;  // [nkeys][4]
-    double *m2l_D = nullptr;      // [nkeys][ncoef]
+    double *m2l_D = nullptr;      // [nkeys][m2l_table_width(p)]
     float *m2l_Df = nullptr;
     int32_t n_m2l_keys = 0;
     // target tiles of 16, 8, 4, 2, 1 cells (built on demand; 16 / tpt fields per tile)

@@ -458,18 +458,74 @@ struct Mfma<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-__host__ __device__ constexpr int deg_of_index(int k)
+// ---------------------------------------------------------------------------
+// Harmonic reduction of the translation.  D_k = d^k (1/|R|) is harmonic, so
+// D_{k + 2e_z} = -D_{k + 2e_x} - D_{k + 2e_y}: every term of the contraction
+// sum_n D_{n+m} Qt_n with n_z >= 2 folds, degree by degree, onto the n_z <= 1
+// terms (Qr = reduced multipoles), and every output with m_z >= 2 follows from
+// the m_z <= 1 outputs of the same degree.  Both keep |n| and |m|, so the
+// truncation |n| + |m| <= p is unchanged and the result is the same
+// contraction up to rounding, with (p+1)^2 instead of ncoef(p) indices per
+// side (81 vs 165 at p = 8).
+//
+// Reduced indices (z <= 1), degree d block at d^2:
+//   ridx(x, y, 0) = d^2 + y,   ridx(x, y, 1) = d^2 + d + 1 + y.
+// Derivative table per key, entries with k_z <= 2 only, degree d block at
+//   sd(d) = 0 (d = 0), 1 + 3 d (d - 1) / 2:  didx = sd(d) + {0, d + 1, 2d + 1}[k_z] + k_y.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int nr_of(int p) { return (p + 1) * (p + 1); }
+__host__ __device__ constexpr int nd_of(int p) { return 1 + 3 * p * (p + 1) / 2; }
+__host__ __device__ constexpr int rdeg(int j)
 {
     int d = 0;
-    while (ncoef_of(d) <= k) ++d;
+    while ((d + 1) * (d + 1) <= j) ++d;
     return d;
 }
-__host__ __device__ constexpr int m2l_nrt(int P) { return (ncoef_of(P) + 15) / 16; }
+__host__ __device__ constexpr int ridx(int x, int y, int z)
+{
+    const int d = x + y + z;
+    return d * d + z * (d + 1) + y;
+}
+__host__ __device__ constexpr int didx_of(int x, int y, int z)
+{
+    const int d = x + y + z;
+    return (d == 0 ? 0 : 1 + 3 * d * (d - 1) / 2) + (z == 0 ? 0 : (z == 1 ? d + 1 : 2 * d + 1)) + y;
+}
+constexpr int kNrMax = (kPmax + 1) * (kPmax + 1);
+constexpr int kNdMax = 1 + 3 * kPmax * (kPmax + 1) / 2;
+struct RedTable {
+    int8_t r[kNrMax][4];  // reduced index -> x, y, z, d
+    int8_t d[kNdMax][4];  // table index -> x, y, z, d
+};
+constexpr RedTable make_red()
+{
+    RedTable t{};
+    for (int d = 0; d <= kPmax; ++d)
+        for (int z = 0; z <= 2; ++z)
+            for (int y = 0; y + z <= d; ++y) {
+                const int x = d - y - z;
+                if (z <= 1) {
+                    const int j = ridx(x, y, z);
+                    t.r[j][0] = (int8_t)x, t.r[j][1] = (int8_t)y, t.r[j][2] = (int8_t)z, t.r[j][3] = (int8_t)d;
+                }
+                const int k = didx_of(x, y, z);
+                t.d[k][0] = (int8_t)x, t.d[k][1] = (int8_t)y, t.d[k][2] = (int8_t)z, t.d[k][3] = (int8_t)d;
+            }
+    return t;
+}
+__constant__ RedTable c_red = make_red();
+
+// MFMA tiling of the reduced contraction: rows m = reduced indices of degree
+// <= p - 1 (degree p rows only meet n = 0, and Q_0 = 0), in tiles of 16;
+// columns n = 1 .. nr(p) - 1 in steps of 4; row tile rt only needs columns
+// of degree <= p - |m_min(rt)|.
+__host__ __device__ constexpr int m2l_nrows(int P) { return P * P; }
+__host__ __device__ constexpr int m2l_nrt(int P) { return (m2l_nrows(P) + 15) / 16; }
 __host__ __device__ constexpr int m2l_ks(int P, int rt)
 {
-    const int d = deg_of_index(16 * rt);
+    const int d = rdeg(16 * rt);
     if (d >= P) return 0;
-    return (ncoef_of(P - d) - 1 + 3) / 4;  // columns n = 1 .. ncoef(P-d)-1, 4 per step
+    return (nr_of(P - d) - 1 + 3) / 4;
 }
 __host__ __device__ constexpr int m2l_kstr(int P)
 {
@@ -490,27 +546,29 @@ __host__ __device__ constexpr int m2l_wave_steps(int P, int W)
 template <int P, int W>
 using M2LIdx = int[m2l_wave_steps(P, W) > 0 ? m2l_wave_steps(P, W) : 1];
 
-// Derivative tables: one thread per key, D_k(rho) for |k| <= p.
+// Derivative tables: one thread per key, D_k(rho) for |k| <= p, k_z <= 2, by
+//   |k| r^2 D_k = -(2|k| - 1) sum_i k_i rho_i D_{k-e_i} - (|k| - 1) sum_i k_i (k_i - 1) D_{k-2e_i}
+// (every term on the right has k_z no larger than k's).
 __global__ void k_m2l_table(const int32_t *__restrict__ keys, int nkeys, int p, double *__restrict__ D)
 {
     const int key = blockIdx.x * blockDim.x + threadIdx.x;
     if (key >= nkeys) return;
-    const int ncoef = ncoef_of(p);
+    const int nd = nd_of(p);
     const int dl = keys[4 * key];
     const double unit = dl >= 0 ? 0.5 : ldexp(0.5, dl);  // rho = k * unit
     const double Rx = keys[4 * key + 1] * unit, Ry = keys[4 * key + 2] * unit, Rz = keys[4 * key + 3] * unit;
     const double r2 = (Rx * Rx + Ry * Ry) + Rz * Rz;
-    double *row = D + (int64_t)key * ncoef;
+    double *row = D + (int64_t)key * nd;
     row[0] = 1.0 / sqrt(r2);
-    for (int k = 1; k < ncoef; ++k) {
-        const int kx = c_mi.v[k][0], ky = c_mi.v[k][1], kz = c_mi.v[k][2], d = c_mi.v[k][3];
+    for (int k = 1; k < nd; ++k) {
+        const int kx = c_red.d[k][0], ky = c_red.d[k][1], kz = c_red.d[k][2], d = c_red.d[k][3];
         double s1 = 0.0, s2 = 0.0;
-        if (kx > 0) s1 += kx * Rx * row[mi_index(kx - 1, ky, kz)];
-        if (ky > 0) s1 += ky * Ry * row[mi_index(kx, ky - 1, kz)];
-        if (kz > 0) s1 += kz * Rz * row[mi_index(kx, ky, kz - 1)];
-        if (kx > 1) s2 += kx * (kx - 1) * row[mi_index(kx - 2, ky, kz)];
-        if (ky > 1) s2 += ky * (ky - 1) * row[mi_index(kx, ky - 2, kz)];
-        if (kz > 1) s2 += kz * (kz - 1) * row[mi_index(kx, ky, kz - 2)];
+        if (kx > 0) s1 += kx * Rx * row[didx_of(kx - 1, ky, kz)];
+        if (ky > 0) s1 += ky * Ry * row[didx_of(kx, ky - 1, kz)];
+        if (kz > 0) s1 += kz * Rz * row[didx_of(kx, ky, kz - 1)];
+        if (kx > 1) s2 += kx * (kx - 1) * row[didx_of(kx - 2, ky, kz)];
+        if (ky > 1) s2 += ky * (ky - 1) * row[didx_of(kx, ky - 2, kz)];
+        if (kz > 1) s2 += kz * (kz - 1) * row[didx_of(kx, ky, kz - 2)];
         row[k] = -((2.0 * d - 1.0) * s1 + (d - 1.0) * s2) / (d * r2);
     }
 }
@@ -521,10 +579,13 @@ __global__ void k_to_float(const double *__restrict__ a, int64_t n, float *__res
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x) b[i] = (float)a[i];
 }
 
-// Qt = scaled multipoles of the cells holding tets; one thread per (cell, n).
+// Reduced scaled multipoles of the cells holding tets; one thread per
+// (cell, reduced index n = (a, b, c), c <= 1):
+//   Qr_n = (-1)^|n| s_B^-|n| sum_{j >= 0} (-1)^j sum_{i <= j} C(j, i) Q_n'/n'!,
+//   n' = (a - 2i, b - 2(j - i), c + 2j).
 template <typename T>
-__global__ void k_qscale(const double *__restrict__ Q, const int32_t *__restrict__ cell_i, int64_t C, double side, int p,
-                         int qpad, T *__restrict__ Qt)
+__global__ void k_qreduce(const double *__restrict__ Q, const int32_t *__restrict__ cell_i, int64_t C, double side,
+                          int p, int qpad, T *__restrict__ Qr)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int f = blockIdx.y;
@@ -533,26 +594,35 @@ __global__ void k_qscale(const double *__restrict__ Q, const int32_t *__restrict
     const int64_t c = i / qpad;
     const int n = (int)(i % qpad);
     double v = 0.0;
-    if (n < ncoef && cell_i[CI_N * c + CI_TEND] > cell_i[CI_N * c + CI_TBEG]) {
-        const int d = c_mi.v[n][3];
+    if (n < nr_of(p) && cell_i[CI_N * c + CI_TEND] > cell_i[CI_N * c + CI_TBEG]) {
+        const int a = c_red.r[n][0], b = c_red.r[n][1], cz = c_red.r[n][2], d = c_red.r[n][3];
+        const double *q = Q + ((int64_t)f * C + c) * ncoef;
+        for (int j = 0; cz + 2 * j <= d; ++j) {
+            double sj = 0.0;
+            for (int k = 0; k <= j; ++k) {
+                const int x = a - 2 * k, y = b - 2 * (j - k), z = cz + 2 * j;
+                if (x < 0 || y < 0) continue;
+                sj += c_bin.c[j][k] * q[mi_index(x, y, z)] * c_bin.invfact[x] * c_bin.invfact[y] * c_bin.invfact[z];
+            }
+            v += (j & 1) ? -sj : sj;
+        }
         const double is = 1.0 / ldexp(side, -cell_i[CI_N * c + CI_LEVEL]);
         double sp = 1.0;
         for (int j = 0; j < d; ++j) sp *= is;
-        v = ((d & 1) ? -1.0 : 1.0) * Q[((int64_t)f * C + c) * ncoef + n] * sp * c_bin.invfact[c_mi.v[n][0]] *
-            c_bin.invfact[c_mi.v[n][1]] * c_bin.invfact[c_mi.v[n][2]];
+        v *= ((d & 1) ? -sp : sp);
     }
-    Qt[((int64_t)f * C + c) * qpad + n] = (T)v;
+    Qr[((int64_t)f * C + c) * qpad + n] = (T)v;
 }
 
 // Steps of wave W in issue order: column step ks = W, W + 4, ... (outer),
 // row tiles rt with ks < KS(rt) (inner), so consecutive MFMAs of a wave feed
 // different accumulators; row tile 0 (the longest) rotates over 2 of its own.
 // m2l_wave_index gives this lane's D-table index of the A-operand element of
-// every step (the zero slot NC outside |n| + |m| <= P).
+// every step (the zero slot ND outside |n| + |m| <= P).
 template <int P, int W>
 __device__ __forceinline__ void m2l_wave_index(int lane, M2LIdx<P, W> &didx)
 {
-    constexpr int NC = ncoef_of(P), NRT = m2l_nrt(P), KS0 = m2l_ks(P, 0);
+    constexpr int NR = nr_of(P), NROW = m2l_nrows(P), ND = nd_of(P), NRT = m2l_nrt(P), KS0 = m2l_ks(P, 0);
     int s = 0;
 #pragma unroll
     for (int ks = W; ks < KS0; ks += kM2LWaves) {
@@ -560,10 +630,10 @@ __device__ __forceinline__ void m2l_wave_index(int lane, M2LIdx<P, W> &didx)
         for (int rt = 0; rt < NRT; ++rt) {
             if (ks < m2l_ks(P, rt)) {
                 const int m = 16 * rt + (lane & 15), n = 1 + 4 * ks + (lane >> 4);
-                int di = NC;  // the zero slot of the staged D row
-                if (m < NC && n < NC && c_mi.v[m][3] + c_mi.v[n][3] <= P)
-                    di = mi_index(c_mi.v[m][0] + c_mi.v[n][0], c_mi.v[m][1] + c_mi.v[n][1],
-                                  c_mi.v[m][2] + c_mi.v[n][2]);
+                int di = ND;  // the zero slot of the staged D row
+                if (m < NROW && n < NR && c_red.r[m][3] + c_red.r[n][3] <= P)
+                    di = didx_of(c_red.r[m][0] + c_red.r[n][0], c_red.r[m][1] + c_red.r[n][1],
+                                 c_red.r[m][2] + c_red.r[n][2]);
                 didx[s++] = di;
             }
         }
@@ -602,14 +672,14 @@ __device__ __forceinline__ void m2l_wave_mfma(typename Mfma<T>::v4 (&acc)[m2l_nr
 template <typename T, int P>
 __device__ __forceinline__ void m2l_rescale(typename Mfma<T>::v4 (&acc)[m2l_nrt(P)], int lane, int ddl)
 {
-    constexpr int NC = ncoef_of(P), NRT = m2l_nrt(P);
+    constexpr int NROW = m2l_nrows(P), NRT = m2l_nrt(P);
     if (ddl == 0) return;
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int m = 16 * rt + Mfma<T>::row(lane, r);
-            const int dm = m < NC ? c_mi.v[m][3] : 0;
+            const int dm = m < NROW ? c_red.r[m][3] : 0;
             acc[rt][r] = (T)ldexp((double)acc[rt][r], ddl * (dm + 1));
         }
 }
@@ -628,15 +698,15 @@ struct M2LCols {
 template <typename T, int P, int W>
 __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, const int32_t *__restrict__ ent_key,
                                          const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys,
-                                         const T *__restrict__ Dtab, const T *__restrict__ Qt, int qpad, int64_t C,
+                                         const T *__restrict__ Dtab, const T *__restrict__ Qr, int qpad, int64_t C,
                                          M2LCols cols, int tile, T *s_D, T *s_Q,
                                          typename Mfma<T>::v4 (&acc)[m2l_nrt(P)])
 {
     using v4 = typename Mfma<T>::v4;
-    constexpr int NC = ncoef_of(P), KSTR = m2l_kstr(P), DSTR = NC + 1;
+    constexpr int NR = nr_of(P), ND = nd_of(P), KSTR = m2l_kstr(P), DSTR = ND + 1;
     constexpr int NT = 64 * kM2LWaves;
     static_assert(NT == 256, "16 columns x 16 threads");
-    constexpr int QREG = (NC + 15) / 16, DREG = (NC + NT - 1) / NT;
+    constexpr int QREG = (NR + 15) / 16, DREG = (ND + NT - 1) / NT;
     const int tid = threadIdx.x, lane = tid & 63;
     const int tcol = tid >> 4, tn = tid & 15;
     const int tslot = tcol / cols.fpt, field = cols.f0 + tcol % cols.fpt;
@@ -652,14 +722,14 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, c
 #pragma unroll
         for (int j = 0; j < DREG; ++j) {
             const int k = tid + NT * j;
-            pd[j] = k < NC ? Dtab[(int64_t)key * NC + k] : (T)0;
+            pd[j] = k < ND ? Dtab[(int64_t)key * ND + k] : (T)0;
         }
         const int src = field < cols.F ? ent_src[(int64_t)e * cols.tpt + tslot] : -1;
-        const T *q = Qt + ((int64_t)(src >= 0 ? field : 0) * C + (src >= 0 ? src : 0)) * qpad;
+        const T *q = Qr + ((int64_t)(src >= 0 ? field : 0) * C + (src >= 0 ? src : 0)) * qpad;
 #pragma unroll
         for (int j = 0; j < QREG; ++j) {
             const int n = tn + 16 * j;
-            pq[j] = (src >= 0 && n < NC) ? q[n] : (T)0;
+            pq[j] = (src >= 0 && n < NR) ? q[n] : (T)0;
         }
     };
     auto store = [&](int buf) {
@@ -668,12 +738,12 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, c
 #pragma unroll
         for (int j = 0; j < DREG; ++j) {
             const int k = tid + NT * j;
-            if (k < NC) D[k] = pd[j];
+            if (k < ND) D[k] = pd[j];
         }
 #pragma unroll
         for (int j = 0; j < QREG; ++j) {
             const int n = tn + 16 * j;
-            if (n < NC) Qb[n] = pq[j];
+            if (n < NR) Qb[n] = pq[j];
         }
     };
     if (e0 >= e1) return;
@@ -709,43 +779,46 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, c
 //   Lt_m(A) = sum_B 2^(dl (|m|+1)) sum_{|n|>=1, |n|+|m|<=p} D_{n+m}(rho) Qt_n(B),
 // D_k = d^k (1/|rho|) depending only on the key (dl, rho): one table row per
 // distinct key serves every level, and all magnitudes are O(1) (the FP32 form
-// needs no other scaling).  A tile (16 MFMA columns: TPT target cells of one
-// level x FPT fields) runs through the keys its cells use; per key the source
-// multipoles form the B operand (columns without that key are zero), the
-// Hankel matrix H[m][n] = D_{n+m} the A operand, and the 16x16x4 MFMA
-// accumulates Lt for all columns in registers.  Rows m are tiled by 16; row
-// tile rt only needs columns n < ncoef(p - |m_min(rt)|) (|n| + |m| <= p).
-// Four wavefronts split the column steps; their partial sums meet in LDS.
+// needs no other scaling).  The contraction runs on the harmonic reduction
+// (reduced multipoles Qr, outputs Lr with m_z <= 1); the epilogue expands Lr
+// to all m by
+//   Lt_(x, y, c + 2j) = (-1)^j sum_{i <= j} C(j, i) Lr_(x + 2i, y + 2(j - i), c).
+// A tile (16 MFMA columns: TPT target cells of one level x FPT fields) runs
+// through the keys its cells use; per key the source multipoles form the B
+// operand (columns without that key are zero), the Hankel matrix
+// H[m][n] = D_{n+m} the A operand, and the 16x16x4 MFMA accumulates Lr for
+// all columns in registers.  Four wavefronts split the column steps; their
+// partial sums meet in LDS.
 // ---------------------------------------------------------------------------
 template <typename T, int P>
-__global__ __launch_bounds__(64 * kM2LWaves, (P <= 8 ? 2 : 1)) void k_m2l_mfma(
+__global__ __launch_bounds__(64 * kM2LWaves, 2) void k_m2l_mfma(
     const int32_t *__restrict__ tile_tgt, const int32_t *__restrict__ tile_ptr, const int32_t *__restrict__ ent_key,
     const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys, const T *__restrict__ Dtab,
-    const T *__restrict__ Qt, int qpad, const int32_t *__restrict__ cell_i, double side, int64_t C, int tpt, int fpt,
+    const T *__restrict__ Qr, int qpad, const int32_t *__restrict__ cell_i, double side, int64_t C, int tpt, int fpt,
     int F, int ntiles, double *__restrict__ L)
 {
     using v4 = typename Mfma<T>::v4;
-    constexpr int NC = ncoef_of(P), NRT = m2l_nrt(P), KSTR = m2l_kstr(P);
-    static_assert(KSTR >= NC, "the staging buffer doubles as the reduction buffer");
+    constexpr int NC = ncoef_of(P), NROW = m2l_nrows(P), ND = nd_of(P), NRT = m2l_nrt(P), KSTR = m2l_kstr(P);
+    static_assert(KSTR >= NROW, "the staging buffer doubles as the reduction buffer");
     static_assert(kM2LWaves == 4, "wave specialisation below");
     static_assert(2 * sizeof(T) >= sizeof(double), "reduction buffer fits in the staging buffers");
-    __shared__ T s_D[2 * (NC + 1)];
+    __shared__ T s_D[2 * (ND + 1)];
     __shared__ __align__(16) T s_Q[2 * 16 * KSTR];
     const int tile = blockIdx.x;
     if (tile >= ntiles) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const M2LCols cols{tpt, fpt, (int)blockIdx.y * fpt, F};
     for (int i = tid; i < 2 * 16 * KSTR; i += blockDim.x) s_Q[i] = (T)0;  // column padding stays zero
-    for (int i = tid; i < 2 * (NC + 1); i += blockDim.x) s_D[i] = (T)0;   // zero slot NC of each buffer
+    for (int i = tid; i < 2 * (ND + 1); i += blockDim.x) s_D[i] = (T)0;   // zero slot ND of each buffer
     __syncthreads();
     v4 acc[NRT];
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt) acc[rt] = v4{0, 0, 0, 0};
     switch (wave) {
-    case 0: m2l_tile<T, P, 0>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, tile, s_D, s_Q, acc); break;
-    case 1: m2l_tile<T, P, 1>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, tile, s_D, s_Q, acc); break;
-    case 2: m2l_tile<T, P, 2>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, tile, s_D, s_Q, acc); break;
-    default: m2l_tile<T, P, 3>(tile_ptr, ent_key, ent_src, keys, Dtab, Qt, qpad, C, cols, tile, s_D, s_Q, acc); break;
+    case 0: m2l_tile<T, P, 0>(tile_ptr, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
+    case 1: m2l_tile<T, P, 1>(tile_ptr, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
+    case 2: m2l_tile<T, P, 2>(tile_ptr, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
+    default: m2l_tile<T, P, 3>(tile_ptr, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
     }
     // sum the waves' partial accumulators in LDS (FP64): red[c][m], c = column
     __syncthreads();
@@ -757,20 +830,27 @@ __global__ __launch_bounds__(64 * kM2LWaves, (P <= 8 ? 2 : 1)) void k_m2l_mfma(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int m = 16 * rt + Mfma<T>::row(lane, r);
-            if (m < NC) atomicAdd(&red[(lane & 15) * KSTR + m], (double)acc[rt][r]);
+            if (m < NROW) atomicAdd(&red[(lane & 15) * KSTR + m], (double)acc[rt][r]);
         }
     __syncthreads();
-    // l_m(A) = Lt_m / (4 pi m! s_A^(|m|+1))
+    // expand to all m, then l_m(A) = Lt_m / (4 pi m! s_A^(|m|+1))
     for (int i = tid; i < 16 * NC; i += blockDim.x) {
         const int c = i / NC, m = i - c * NC;
         const int field = cols.f0 + c % fpt;
         const int A = tile_tgt[tile * tpt + c / fpt];
         if (A < 0 || field >= F) continue;
+        const int mx = c_mi.v[m][0], my = c_mi.v[m][1], mz = c_mi.v[m][2], dm = c_mi.v[m][3];
+        double lt = 0.0;
+        if (dm < P) {
+            const int j = mz >> 1, cz = mz & 1;
+            for (int k = 0; k <= j; ++k) lt += c_bin.c[j][k] * red[c * KSTR + ridx(mx + 2 * k, my + 2 * (j - k), cz)];
+            if (j & 1) lt = -lt;
+        }
         const double is = 1.0 / ldexp(side, -cell_i[CI_N * A + CI_LEVEL]);
         double sp = is;
-        for (int j = 0; j < c_mi.v[m][3]; ++j) sp *= is;
-        L[((int64_t)field * C + A) * NC + m] = red[c * KSTR + m] * kInv4Pi * sp * c_bin.invfact[c_mi.v[m][0]] *
-                                              c_bin.invfact[c_mi.v[m][1]] * c_bin.invfact[c_mi.v[m][2]];
+        for (int k = 0; k < dm; ++k) sp *= is;
+        L[((int64_t)field * C + A) * NC + m] =
+            lt * kInv4Pi * sp * c_bin.invfact[mx] * c_bin.invfact[my] * c_bin.invfact[mz];
     }
 }
 
@@ -1278,7 +1358,7 @@ void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
     const dim3 qgrid((unsigned)((nq + 255) / 256), F);
     if (dp.m2l_precision == TFMM_M2L_FP32) {
         if (!dp.m2l_Df) {
-            const int64_t n = (int64_t)dp.n_m2l_keys * dp.ncoef;
+            const int64_t n = (int64_t)dp.n_m2l_keys * nd_of(hp.p);
             hip_check(hipMalloc(&dp.m2l_Df, sizeof(float) * std::max<int64_t>(n, 1)), "hipMalloc M2L table f32");
             k_to_float<<<dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, st>>>(dp.m2l_D, n,
                                                                                                         dp.m2l_Df);
@@ -1291,8 +1371,8 @@ void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
             hip_check(hipMalloc(&dp.Qtf, sizeof(float) * (size_t)F * C * dp.qpad), "hipMalloc Qt f32");
             dp.qtf_cap = F;
         }
-        k_qscale<float><<<qgrid, dim3(256), 0, st>>>(dp.Q, dp.cell_i, C, hp.side, hp.p, dp.qpad, dp.Qtf);
-        hip_check(hipGetLastError(), "k_qscale launch");
+        k_qreduce<float><<<qgrid, dim3(256), 0, st>>>(dp.Q, dp.cell_i, C, hp.side, hp.p, dp.qpad, dp.Qtf);
+        hip_check(hipGetLastError(), "k_qreduce launch");
         launch_m2l_t<float>(dp, tl, dp.m2l_Df, dp.Qtf, fpt, F, st);
     } else {
         if (dp.qt_cap < F) {
@@ -1302,8 +1382,8 @@ void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
             hip_check(hipMalloc(&dp.Qt, sizeof(double) * (size_t)F * C * dp.qpad), "hipMalloc Qt");
             dp.qt_cap = F;
         }
-        k_qscale<double><<<qgrid, dim3(256), 0, st>>>(dp.Q, dp.cell_i, C, hp.side, hp.p, dp.qpad, dp.Qt);
-        hip_check(hipGetLastError(), "k_qscale launch");
+        k_qreduce<double><<<qgrid, dim3(256), 0, st>>>(dp.Q, dp.cell_i, C, hp.side, hp.p, dp.qpad, dp.Qt);
+        hip_check(hipGetLastError(), "k_qreduce launch");
         launch_m2l_t<double>(dp, tl, dp.m2l_D, dp.Qt, fpt, F, st);
     }
 }

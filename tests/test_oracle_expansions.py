@@ -194,3 +194,43 @@ def test_multipole_far_field_formula(orc):
     exact = orc.tet_potential(x, v, M)
     assert abs(approx - exact) <= 1e-10 * abs(exact)
     assert len(mi) == len(Q)
+
+
+def test_taylor_coefficients_harmonic_and_reduced_contraction(orc):
+    """1/|x| is harmonic, so D_n = (-1)^|n| n! a_n satisfies
+    D_{n+2e_x} + D_{n+2e_y} + D_{n+2e_z} = 0.  Hence the truncated M2L sum
+    sum_n D_{n+m} q_n (|n| + |m| <= p) over all n equals the sum over n_z <= 1
+    of a reduced q (each n_z >= 2 term folded onto same-degree n_z <= 1 terms),
+    and the outputs with m_z >= 2 follow from those with m_z <= 1."""
+    p = 8
+    mi = [tuple(int(k) for k in n) for n in orc.multi_indices(p)]
+    idx = {n: i for i, n in enumerate(mi)}
+    fact = lambda n: math.factorial(n[0]) * math.factorial(n[1]) * math.factorial(n[2])
+    rng = np.random.default_rng(5)
+    x = rng.uniform(1.0, 2.0, 3) * rng.choice([-1, 1], 3)
+    a = orc.taylor_coeffs(x, p)
+    D = {n: (-1) ** sum(n) * fact(n) * a[idx[n]] for n in mi}
+    for n in mi:
+        if sum(n) + 2 <= p:
+            s = sum(D[(n[0] + 2 * (k == 0), n[1] + 2 * (k == 1), n[2] + 2 * (k == 2))] for k in range(3))
+            assert abs(s) <= 1e-13 * max(abs(D[(n[0] + 2, n[1], n[2])]), 1.0)
+    q = {n: (rng.standard_normal() if sum(n) >= 1 else 0.0) for n in mi}
+    full = {m: sum(D[tuple(a_ + b_ for a_, b_ in zip(n, m))] * q[n] for n in mi if sum(n) + sum(m) <= p) for m in mi}
+    qr = {}
+    for (nx, ny, nz) in mi:
+        if nz > 1:
+            continue
+        v = 0.0
+        for j in range((sum((nx, ny, nz)) - nz) // 2 + 1):
+            for i in range(j + 1):
+                src = (nx - 2 * i, ny - 2 * (j - i), nz + 2 * j)
+                if min(src) >= 0:
+                    v += (-1) ** j * math.comb(j, i) * q[src]
+        qr[(nx, ny, nz)] = v
+    red = {m: sum(D[tuple(a_ + b_ for a_, b_ in zip(n, m))] * qr[n] for n in qr if sum(n) + sum(m) <= p)
+           for m in mi if m[2] <= 1}
+    scale = max(abs(v) for v in full.values())
+    for m in mi:
+        j, c = m[2] // 2, m[2] % 2
+        v = (-1) ** j * sum(math.comb(j, i) * red[(m[0] + 2 * i, m[1] + 2 * (j - i), c)] for i in range(j + 1))
+        assert abs(v - full[m]) <= 1e-12 * scale, m
