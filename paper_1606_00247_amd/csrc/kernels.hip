@@ -546,7 +546,8 @@ __host__ __device__ constexpr int m2l_wave_steps(int P, int W)
 template <int P, int W>
 using M2LIdx = int[m2l_wave_steps(P, W) > 0 ? m2l_wave_steps(P, W) : 1];
 
-// Derivative tables: one thread per key, D_k(rho) for |k| <= p, k_z <= 2, by
+// Derivative tables: one thread per key, 2^(dl (|k| + 1)) D_k(rho) for
+// |k| <= p, k_z <= 2, with D_k by
 //   |k| r^2 D_k = -(2|k| - 1) sum_i k_i rho_i D_{k-e_i} - (|k| - 1) sum_i k_i (k_i - 1) D_{k-2e_i}
 // (every term on the right has k_z no larger than k's).
 __global__ void k_m2l_table(const int32_t *__restrict__ keys, int nkeys, int p, double *__restrict__ D)
@@ -571,6 +572,8 @@ __global__ void k_m2l_table(const int32_t *__restrict__ keys, int nkeys, int p, 
         if (kz > 1) s2 += kz * (kz - 1) * row[didx_of(kx, ky, kz - 2)];
         row[k] = -((2.0 * d - 1.0) * s1 + (d - 1.0) * s2) / (d * r2);
     }
+    // level-difference factor 2^(dl (|k| + 1)) (exact)
+    for (int k = 0; k < nd; ++k) row[k] = ldexp(row[k], dl * (c_red.d[k][3] + 1));
 }
 
 __global__ void k_to_float(const double *__restrict__ a, int64_t n, float *__restrict__ b)
@@ -665,25 +668,6 @@ __device__ __forceinline__ void m2l_wave_mfma(typename Mfma<T>::v4 (&acc)[m2l_nr
     }
 }
 
-// Row scale of a level difference dl: Lt_m gets 2^(dl (|m|+1)).  The entries
-// of a tile are sorted by dl; when dl changes from a to b the accumulators are
-// multiplied by 2^((a - b)(|m|+1)) and at the end by 2^(dl_last (|m|+1)), so
-// every contribution carries its own factor without a multiply per MFMA.
-template <typename T, int P>
-__device__ __forceinline__ void m2l_rescale(typename Mfma<T>::v4 (&acc)[m2l_nrt(P)], int lane, int ddl)
-{
-    constexpr int NROW = m2l_nrows(P), NRT = m2l_nrt(P);
-    if (ddl == 0) return;
-#pragma unroll
-    for (int rt = 0; rt < NRT; ++rt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int m = 16 * rt + Mfma<T>::row(lane, r);
-            const int dm = m < NROW ? c_red.r[m][3] : 0;
-            acc[rt][r] = (T)ldexp((double)acc[rt][r], ddl * (dm + 1));
-        }
-}
-
 // Geometry of a tile: TPT target cells x FPT fields = 16 MFMA columns,
 // column c = t * FPT + g (target slot t, field f0 + g).
 struct M2LCols {
@@ -715,7 +699,9 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, c
     v4 acc0[2] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
     const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
     T pq[QREG], pd[DREG];
-    int pdl = 0;
+    int pdl = 0, qdeg[QREG];
+#pragma unroll
+    for (int j = 0; j < QREG; ++j) qdeg[j] = rdeg(tn + 16 * j);
     auto fetch = [&](int e) {
         const int key = ent_key[e];
         pdl = keys[4 * key];
@@ -743,30 +729,21 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, c
 #pragma unroll
         for (int j = 0; j < QREG; ++j) {
             const int n = tn + 16 * j;
-            if (n < NR) Qb[n] = pq[j];
+            if (n < NR) Qb[n] = ldexp(pq[j], -pdl * qdeg[j]);  // 2^(-dl |n|), exact
         }
     };
     if (e0 >= e1) return;
     fetch(e0);
-    int cur_dl = pdl;
     store(0);
     __syncthreads();
     for (int e = e0; e < e1; ++e) {
         const int buf = (e - e0) & 1;
-        const int dl = pdl;
         if (e + 1 < e1) fetch(e + 1);
-        if (dl != cur_dl) {  // entries are sorted by dl: at most a few switches per tile
-            acc[0] += acc0[0] + acc0[1];
-            acc0[0] = acc0[1] = v4{0, 0, 0, 0};
-            m2l_rescale<T, P>(acc, lane, cur_dl - dl);
-            cur_dl = dl;
-        }
         m2l_wave_mfma<T, P, W>(acc, acc0, s_D + buf * DSTR, s_Q + buf * 16 * KSTR, didx, lane);
         if (e + 1 < e1) store(buf ^ 1);
         __syncthreads();
     }
     acc[0] += acc0[0] + acc0[1];
-    m2l_rescale<T, P>(acc, lane, cur_dl);
 }
 
 // ---------------------------------------------------------------------------
@@ -779,7 +756,9 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, c
 //   Lt_m(A) = sum_B 2^(dl (|m|+1)) sum_{|n|>=1, |n|+|m|<=p} D_{n+m}(rho) Qt_n(B),
 // D_k = d^k (1/|rho|) depending only on the key (dl, rho): one table row per
 // distinct key serves every level, and all magnitudes are O(1) (the FP32 form
-// needs no other scaling).  The contraction runs on the harmonic reduction
+// needs no other scaling).  The level factor splits exactly as
+// 2^(dl (|n|+|m|+1)) * 2^(-dl |n|): the first is in the key's table, the
+// second is applied to the multipoles as they are staged.  The contraction runs on the harmonic reduction
 // (reduced multipoles Qr, outputs Lr with m_z <= 1); the epilogue expands Lr
 // to all m by
 //   Lt_(x, y, c + 2j) = (-1)^j sum_{i <= j} C(j, i) Lr_(x + 2i, y + 2(j - i), c).
