@@ -220,7 +220,7 @@ void free_plan(DevicePlan &dp)
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : dp.m2l_tiles) {
-        void *tp[] = {t.tile_tgt, t.tile_ptr, t.ent_key, t.ent_src};
+        void *tp[] = {t.tile_tgt, t.tile_rng, t.ent_key, t.ent_src};
         for (void *p : tp)
             if (p) (void)hipFree(p);
     }

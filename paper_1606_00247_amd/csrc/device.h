@@ -58,7 +58,7 @@ struct DevicePlan {
     // target tiles of 16, 8, 4, 2, 1 cells (built on demand; 16 / tpt fields per tile)
     struct Tiles {
         int tpt = 0;
-        int32_t *tile_tgt = nullptr, *tile_ptr = nullptr, *ent_key = nullptr, *ent_src = nullptr;
+        int32_t *tile_tgt = nullptr, *tile_rng = nullptr, *ent_key = nullptr, *ent_src = nullptr;
         int32_t ntiles = 0;
         int64_t nent = 0;
     };

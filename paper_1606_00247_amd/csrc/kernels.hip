@@ -432,6 +432,9 @@ __global__ __launch_bounds__(kShiftThreads) void k_l2l(const int32_t *__restrict
 }
 
 constexpr int kM2LWaves = 4;
+// entries per M2L work item: a tile's keys are cut into pieces of this many,
+// so that the workgroups of one launch fill the chip evenly
+constexpr int kM2LMaxEntries = 256;
 
 // The two matrix-core shapes used by M2L: 16x16x4 with FP64 or FP32 operands.
 // A (16 x 4): lane l holds row l%16, column l/16; B (4 x 16): lane l holds
@@ -680,7 +683,7 @@ struct M2LCols {
 // barrier per key.  Thread tid stages column tid/16, coefficients
 // n = tid%16 + 16 j.
 template <typename T, int P, int W>
-__device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, const int32_t *__restrict__ ent_key,
+__device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_rng, const int32_t *__restrict__ ent_key,
                                          const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys,
                                          const T *__restrict__ Dtab, const T *__restrict__ Qr, int qpad, int64_t C,
                                          M2LCols cols, int tile, T *s_D, T *s_Q,
@@ -697,7 +700,7 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, c
     M2LIdx<P, W> didx;
     m2l_wave_index<P, W>(lane, didx);
     v4 acc0[2] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
-    const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
+    const int e0 = tile_rng[2 * tile], e1 = tile_rng[2 * tile + 1];
     T pq[QREG], pd[DREG];
     int pdl = 0, qdeg[QREG];
 #pragma unroll
@@ -771,7 +774,7 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_ptr, c
 // ---------------------------------------------------------------------------
 template <typename T, int P>
 __global__ __launch_bounds__(64 * kM2LWaves, 2) void k_m2l_mfma(
-    const int32_t *__restrict__ tile_tgt, const int32_t *__restrict__ tile_ptr, const int32_t *__restrict__ ent_key,
+    const int32_t *__restrict__ tile_tgt, const int32_t *__restrict__ tile_rng, const int32_t *__restrict__ ent_key,
     const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys, const T *__restrict__ Dtab,
     const T *__restrict__ Qr, int qpad, const int32_t *__restrict__ cell_i, double side, int64_t C, int tpt, int fpt,
     int F, int ntiles, double *__restrict__ L)
@@ -794,10 +797,10 @@ __global__ __launch_bounds__(64 * kM2LWaves, 2) void k_m2l_mfma(
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt) acc[rt] = v4{0, 0, 0, 0};
     switch (wave) {
-    case 0: m2l_tile<T, P, 0>(tile_ptr, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
-    case 1: m2l_tile<T, P, 1>(tile_ptr, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
-    case 2: m2l_tile<T, P, 2>(tile_ptr, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
-    default: m2l_tile<T, P, 3>(tile_ptr, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
+    case 0: m2l_tile<T, P, 0>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
+    case 1: m2l_tile<T, P, 1>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
+    case 2: m2l_tile<T, P, 2>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
+    default: m2l_tile<T, P, 3>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
     }
     // sum the waves' partial accumulators in LDS (FP64): red[c][m], c = column
     __syncthreads();
@@ -828,8 +831,8 @@ __global__ __launch_bounds__(64 * kM2LWaves, 2) void k_m2l_mfma(
         const double is = 1.0 / ldexp(side, -cell_i[CI_N * A + CI_LEVEL]);
         double sp = is;
         for (int k = 0; k < dm; ++k) sp *= is;
-        L[((int64_t)field * C + A) * NC + m] =
-            lt * kInv4Pi * sp * c_bin.invfact[mx] * c_bin.invfact[my] * c_bin.invfact[mz];
+        atomicAdd(&L[((int64_t)field * C + A) * NC + m],
+                  lt * kInv4Pi * sp * c_bin.invfact[mx] * c_bin.invfact[my] * c_bin.invfact[mz]);
     }
 }
 
@@ -894,8 +897,7 @@ __global__ __launch_bounds__(256) void k_l2p(const double *__restrict__ tgt_xyz,
 //   F0 = (1,2,3), F1 = (0,3,2), F2 = (0,1,3), F3 = (0,2,1)
 // and edges e0..e5 = (0,1),(0,2),(0,3),(1,2),(1,3),(2,3).
 // ---------------------------------------------------------------------------
-constexpr int kP2PThreads = 256;
-constexpr int kP2PTets = 64;  // tets per block
+constexpr int kP2PTets = 64;  // tets per block (direct sum)
 constexpr int kEa[6] = {0, 0, 0, 1, 1, 2};
 constexpr int kEb[6] = {1, 2, 3, 2, 3, 3};
 // face k: its three edges and the orientation sign of each
@@ -916,10 +918,12 @@ struct TetField {
     double g[6];     // gamma_e
 };
 
+// Geometry of tet t and the coefficients of one field (nodal values Mf);
+// the geometry is written to *Gout when Gout is not null.
 __device__ inline void tet_prepare(const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node, int64_t T,
-                                   int64_t t, const double *__restrict__ M, int64_t n_nodes, int F, TetGeom &G,
-                                   TetField *fld)
+                                   int64_t t, const double *__restrict__ Mf, TetGeom *Gout, TetField &F1)
 {
+    TetGeom G;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -978,11 +982,11 @@ __device__ inline void tet_prepare(const double *__restrict__ tet_xyz, const int
         gl[3][k] *= idet;
         gl[0][k] = -(gl[1][k] + gl[2][k] + gl[3][k]);
     }
+    if (Gout) *Gout = G;
     int nd[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) nd[c] = tet_node[(int64_t)c * T + t];
-    for (int f = 0; f < F; ++f) {
-        const double *Mf = M + (int64_t)f * n_nodes * 3;
+    {
         double m[4][3];
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -992,7 +996,6 @@ __device__ inline void tet_prepare(const double *__restrict__ tet_xyz, const int
         double divM = 0.0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) divM += m[c][0] * gl[c][0] + m[c][1] * gl[c][1] + m[c][2] * gl[c][2];
-        TetField &F1 = fld[f];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             // G^T n = sum_i (M_i . n) grad lambda_i
@@ -1027,6 +1030,20 @@ __device__ inline void tet_prepare(const double *__restrict__ tet_xyz, const int
     }
 }
 
+// n / d for finite nonzero d of moderate range: the hardware reciprocal
+// estimate, two Newton-Raphson steps r <- r + r (1 - d r), then the quotient
+// with one residual correction q <- q + r (n - d q).
+__device__ __forceinline__ double div_nr(double n, double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    const double q = n * r;
+    return fma(r, fma(-d, q, n), q);
+}
+
 // ln(num / den) for positive finite num, den, with one division: writing
 // num = a 2^i, den = b 2^j (a, b in [1/2, 1)), the ratio a/b is brought into
 // [1/sqrt2, sqrt2) by a factor 2 on a or b (the differences below are then
@@ -1047,7 +1064,7 @@ __device__ __forceinline__ double log_ratio(double num, double den)
         b += b;
         e += 1;
     }
-    const double sv = (a - b) / (a + b);
+    const double sv = div_nr(a - b, a + b);
     const double z = sv * sv;
     double q = 1.0 / 23.0;
     q = fma(q, z, 1.0 / 21.0);
@@ -1066,9 +1083,49 @@ __device__ __forceinline__ double log_ratio(double num, double den)
     return fma(de, kLn2Hi, fma(de, kLn2Lo, t) + 2.0 * sv);
 }
 
-// Geometric part of one pair: I0_k, g_e, h_k and d_0.
-__device__ __forceinline__ void pair_geometry(const double x[3], const TetGeom &G, double I0[4], double ge[6],
-                                              double h[4], double d0[3])
+// atan2(y, x) in (-pi, pi], 0 for y = x = 0, with one division: with
+// a = min(|x|, |y|), b = max(|x|, |y|), atan(a/b) in [0, pi/4] is reduced to
+// t in [0, tan(pi/8)] by t = a/b or, above tan(pi/8), pi/4 - atan(t),
+// t = (b - a)/(b + a); atan(t) = t + t^3 Q(t^2) with Q the degree-10
+// polynomial interpolating (atan(sqrt z)/sqrt z - 1)/z at the Chebyshev
+// points of [0, tan(pi/8)^2] (relative error of atan(t) below 5e-18); the
+// octant and quadrant follow by pi/2 - r and pi - r, the sign from y.
+__device__ __forceinline__ double atan2_nr(double y, double x)
+{
+    const double ay = fabs(y), ax = fabs(x);
+    const double b = fmax(ay, ax), a = fmin(ay, ax);
+    const double kTanPi8 = 0.41421356237309503;
+    const bool big = a > kTanPi8 * b;
+    const double num = big ? b - a : a;
+    const double den = big ? b + a : (b > 0.0 ? b : 1.0);
+    const double t = div_nr(num, den);
+    const double z = t * t;
+    double q = -1.91768871190622589893e-2;
+    q = fma(q, z, 3.923165829558719130283e-2);
+    q = fma(q, z, -5.085449737940259861323e-2);
+    q = fma(q, z, 5.858148912802209881646e-2);
+    q = fma(q, z, -6.664511447381948000098e-2);
+    q = fma(q, z, 7.692183190826086563693e-2);
+    q = fma(q, z, -9.090904578123901890479e-2);
+    q = fma(q, z, 1.111111101525636172749e-1);
+    q = fma(q, z, -1.428571428466654292249e-1);
+    q = fma(q, z, 1.999999999999552067782e-1);
+    q = fma(q, z, -3.333333333333333015966e-1);
+    const double at = fma(t * z, q, t);
+    const double kPi = 3.141592653589793116, kPi2 = 1.5707963267948965580, kPi4 = 0.78539816339744827900;
+    double r = big ? kPi4 - at : at;
+    r = ay > ax ? kPi2 - r : r;
+    r = x < 0.0 ? kPi - r : r;
+    return copysign(r, y);
+}
+
+// One pair (target x, tet G with FCH fields): adds 4 pi u_T(x) of every field
+// to acc.  The edges are taken one at a time (the edges (a, b) listed first in
+// the faces give the faces' triple products for the solid angles), forming the
+// geometric integrals I0_k and g_e, which are then contracted with each field.
+template <int FCH>
+__device__ __forceinline__ void pair_accumulate(const double x[3], const TetGeom &G, const TetField *fld,
+                                                double (&acc)[FCH])
 {
     double d[4][3], R2[4], R[4];
 #pragma unroll
@@ -1078,23 +1135,27 @@ __device__ __forceinline__ void pair_geometry(const double x[3], const TetGeom &
         R2[c] = d[c][0] * d[c][0] + d[c][1] * d[c][1] + d[c][2] * d[c][2];
         R[c] = sqrt(R2[c]);
     }
-    d0[0] = d[0][0];
-    d0[1] = d[0][1];
-    d0[2] = d[0][2];
     double D[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = a + 1; b < 4; ++b) D[a][b] = D[b][a] = d[a][0] * d[b][0] + d[a][1] * d[b][1] + d[a][2] * d[b][2];
-    double cx[6][3], fl[6];
+    double h[4], I0[4], ge[6], det[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int a = kFv[k][0];
+        h[k] = G.n[k][0] * d[a][0] + G.n[k][1] * d[a][1] + G.n[k][2] * d[a][2];
+        I0[k] = 0.0;
+    }
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
         const int a = kEa[e], b = kEb[e];
         const double il = G.il[e];
-        cx[e][0] = d[a][1] * d[b][2] - d[a][2] * d[b][1];
-        cx[e][1] = d[a][2] * d[b][0] - d[a][0] * d[b][2];
-        cx[e][2] = d[a][0] * d[b][1] - d[a][1] * d[b][0];
-        const double r0sq = (cx[e][0] * cx[e][0] + cx[e][1] * cx[e][1] + cx[e][2] * cx[e][2]) * (il * il);
+        double cx[3];
+        cx[0] = d[a][1] * d[b][2] - d[a][2] * d[b][1];
+        cx[1] = d[a][2] * d[b][0] - d[a][0] * d[b][2];
+        cx[2] = d[a][0] * d[b][1] - d[a][1] * d[b][0];
+        const double r0sq = (cx[0] * cx[0] + cx[1] * cx[1] + cx[2] * cx[2]) * (il * il);
         const double la = (D[a][b] - R2[a]) * il;  // (v_a - x) . e_hat
         const double lb = (R2[b] - D[a][b]) * il;  // (v_b - x) . e_hat
         // f = ln((R_b + l_b)/(R_a + l_a)) in a form free of cancellation
@@ -1102,45 +1163,65 @@ __device__ __forceinline__ void pair_geometry(const double x[3], const TetGeom &
         const double num = fwd ? (R[b] + lb) : (bwd ? (R[a] - la) : (R[b] + lb) * (R[a] - la));
         const double den = fwd ? (R[a] + la) : (bwd ? (R[b] - lb) : r0sq);
         const bool ok = (R[a] > 0.0) && (R[b] > 0.0) && (den > 0.0);
-        const double f = ok ? log_ratio(num, den) : 0.0;  // factors t0 and R0^2 vanish otherwise
-        fl[e] = f * il;
-        ge[e] = r0sq * f + lb * R[b] - la * R[a];
+        const double fe = ok ? log_ratio(num, den) : 0.0;  // factors t0 and R0^2 vanish otherwise
+        const double fl = fe * il;
+        ge[e] = r0sq * fe + lb * R[b] - la * R[a];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                if (kFe[k][j] != e) continue;
+                // t0 |e| = s n_k . (d_a x d_b)
+                I0[k] += kFs[k][j] * (G.n[k][0] * cx[0] + G.n[k][1] * cx[1] + G.n[k][2] * cx[2]) * fl;
+                if (j == 0) {  // det[d_a, d_b, d_c] = d_c . (d_a x d_b)
+                    const int c = kFv[k][2];
+                    det[k] = kFs[k][0] * (d[c][0] * cx[0] + d[c][1] * cx[1] + d[c][2] * cx[2]);
+                }
+            }
     }
-    // faces
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int a = kFv[k][0], b = kFv[k][1], c = kFv[k][2];
-        const double hk = G.n[k][0] * d[a][0] + G.n[k][1] * d[a][1] + G.n[k][2] * d[a][2];
-        h[k] = hk;
-        // det[d_a, d_b, d_c] = d_c . (d_a x d_b); edge (a,b) of face k is kFe[k][0]
-        const int e0 = kFe[k][0];
-        const double det = kFs[k][0] * (d[c][0] * cx[e0][0] + d[c][1] * cx[e0][1] + d[c][2] * cx[e0][2]);
         const double den = R[a] * R[b] * R[c] + D[a][b] * R[c] + D[a][c] * R[b] + D[b][c] * R[a];
-        const double omega = 2.0 * atan2(det, den);
-        double s = -hk * omega;
+        I0[k] -= h[k] * (2.0 * atan2_nr(det[k], den));  // - h_k Omega_k
+    }
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int e = kFe[k][j];
-            const double t0l = kFs[k][j] * (G.n[k][0] * cx[e][0] + G.n[k][1] * cx[e][1] + G.n[k][2] * cx[e][2]);
-            s += t0l * fl[e];
+    for (int f = 0; f < FCH; ++f) {
+        const TetField &F1 = fld[f];
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            // alpha_k = M(x).n_k + h_k (n_k.G n_k - div M / 2)
+            const double alpha =
+                F1.a[k] - (d[0][0] * F1.b[k][0] + d[0][1] * F1.b[k][1] + d[0][2] * F1.b[k][2]) + F1.c[k] * h[k];
+            v = fma(alpha, I0[k], v);
         }
-        I0[k] = s;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) v = fma(F1.g[e], ge[e], v);
+        acc[f] += v;
     }
 }
 
-// Tets staged in LDS at a time for FCH fields (geometry 240 B + 208 B per
-// field per tet): 64 tets up to 4 fields, 32 up to 8, 16 up to 16.
-__host__ __device__ constexpr int p2p_stage(int FCH) { return FCH >= 16 ? 16 : (FCH >= 8 ? 32 : 64); }
+// One workgroup per block of <= 64 tets of a source leaf (direct sum: 64
+// consecutive tets, all targets): one wavefront for one or two fields, four
+// for more (they share the staged field coefficients).  Tets are staged in
+// LDS BT at a time, thread l preparing field l % FCH of tet l / FCH (geometry
+// 240 B + 208 B per field per tet); every thread then takes targets
+// ib + l, ib + l + NT, ... over the staged tets and adds its potentials
+// atomically.
+__host__ __device__ constexpr int p2p_threads(int FCH) { return FCH <= 2 ? 64 : 256; }
+__host__ __device__ constexpr int p2p_stage(int FCH) { return FCH <= 2 ? 16 : (FCH >= 16 ? 16 : (FCH >= 8 ? 32 : 64)); }
 
 template <int FCH>
-__global__ __launch_bounds__(kP2PThreads) void k_p2p(const int32_t *__restrict__ blk, int nblk, int direct_tets, int64_t T,
+__global__ __launch_bounds__(p2p_threads(FCH), 2) void k_p2p(const int32_t *__restrict__ blk, int nblk, int direct_tets, int64_t T,
                                                      const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node,
                                                      const int32_t *__restrict__ idx, const double *__restrict__ tgt_xyz,
                                                      const int32_t *__restrict__ tgt_perm, int64_t N,
                                                      const double *__restrict__ M, int64_t n_nodes, int f0,
                                                      double *__restrict__ u)
 {
-    constexpr int BT = p2p_stage(FCH);
+    constexpr int BT = p2p_stage(FCH), NT = p2p_threads(FCH);
+    static_assert(BT * FCH <= NT, "one thread per staged tet and field");
     __shared__ TetGeom s_g[BT];
     __shared__ TetField s_f[BT][FCH];
     const int b = xcd_item(nblk);
@@ -1157,37 +1238,25 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(const int32_t *__restrict__
         ib = blk[4 * b + 2];
         ie = blk[4 * b + 3];
     }
-    const double *Mf0 = M + (int64_t)f0 * n_nodes * 3;
+    const int lane = threadIdx.x;
     for (int sb = tb; sb < te; sb += BT) {
         const int nt = min(BT, te - sb);
         __syncthreads();
-        for (int t = threadIdx.x; t < nt; t += blockDim.x)
-            tet_prepare(tet_xyz, tet_node, T, sb + t, Mf0, n_nodes, FCH, s_g[t], s_f[t]);
+        {
+            const int t = lane / FCH, f = lane % FCH;
+            if (t < nt)
+                tet_prepare(tet_xyz, tet_node, T, sb + t, M + (int64_t)(f0 + f) * n_nodes * 3, f == 0 ? &s_g[t] : nullptr,
+                            s_f[t][f]);
+        }
         __syncthreads();
-        for (int i = ib + threadIdx.x; i < ie; i += blockDim.x) {
+        for (int i = ib + lane; i < ie; i += NT) {
             const int s = direct_tets ? i : idx[i];
             const double x[3] = {tgt_xyz[s], tgt_xyz[N + s], tgt_xyz[2 * N + s]};
             double acc[FCH];
 #pragma unroll
             for (int f = 0; f < FCH; ++f) acc[f] = 0.0;
-            for (int t = 0; t < nt; ++t) {
-                double I0[4], ge[6], h[4], d0[3];
-                pair_geometry(x, s_g[t], I0, ge, h, d0);
-#pragma unroll
-                for (int f = 0; f < FCH; ++f) {
-                    const TetField &F1 = s_f[t][f];
-                    double v = 0.0;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const double alpha =
-                            F1.a[k] - (d0[0] * F1.b[k][0] + d0[1] * F1.b[k][1] + d0[2] * F1.b[k][2]) + F1.c[k] * h[k];
-                        v += alpha * I0[k];
-                    }
-#pragma unroll
-                    for (int e = 0; e < 6; ++e) v += F1.g[e] * ge[e];
-                    acc[f] += v;
-                }
-            }
+#pragma unroll 1
+            for (int t = 0; t < nt; ++t) pair_accumulate<FCH>(x, s_g[t], s_f[t], acc);
             const int64_t o = tgt_perm[s];
 #pragma unroll
             for (int f = 0; f < FCH; ++f) atomicAdd(&u[(int64_t)(f0 + f) * N + o], acc[f] * kInv4Pi);
@@ -1263,7 +1332,7 @@ void launch_p2p(DevicePlan &dp, bool direct, int f0, const double *M, double *u,
     const HostPlan &hp = dp.hp;
     unsigned nblk = direct ? (unsigned)((hp.n_tets + kP2PTets - 1) / kP2PTets) : (unsigned)dp.n_p2p_blk;
     if (nblk == 0) return;
-    k_p2p<FCH><<<dim3(xcd_grid((int)nblk)), dim3(kP2PThreads), 0, st>>>(dp.p2p_blk, (int)nblk, direct ? 1 : 0, hp.n_tets, dp.tet_xyz,
+    k_p2p<FCH><<<dim3(xcd_grid((int)nblk)), dim3(p2p_threads(FCH)), 0, st>>>(dp.p2p_blk, (int)nblk, direct ? 1 : 0, hp.n_tets, dp.tet_xyz,
                                                          dp.tet_node, dp.p2p_idx, dp.tgt_xyz, dp.tgt_perm,
                                                          hp.n_targets, M, hp.n_nodes, f0, u);
     hip_check(hipGetLastError(), "k_p2p launch");
@@ -1300,7 +1369,7 @@ void launch_m2l_p(DevicePlan &dp, const DevicePlan::Tiles &tl, const T *D, const
     const HostPlan &hp = dp.hp;
     const unsigned groups = (unsigned)((F + fpt - 1) / fpt);
     k_m2l_mfma<T, P><<<dim3(tl.ntiles, groups), dim3(64 * kM2LWaves), 0, st>>>(
-        tl.tile_tgt, tl.tile_ptr, tl.ent_key, tl.ent_src, dp.m2l_keys, D, Qt, dp.qpad, dp.cell_i, hp.side,
+        tl.tile_tgt, tl.tile_rng, tl.ent_key, tl.ent_src, dp.m2l_keys, D, Qt, dp.qpad, dp.cell_i, hp.side,
         (int64_t)hp.cells.size(), tl.tpt, fpt, F, tl.ntiles, dp.L);
     hip_check(hipGetLastError(), "k_m2l_mfma launch");
 }
@@ -1395,7 +1464,7 @@ DevicePlan::Tiles &ensure_m2l_tiles(DevicePlan &dp, int tpt)
     DevicePlan::Tiles &t = dp.m2l_tiles[slot];
     if (t.tpt == tpt) return t;
     M2LTiles h;
-    build_m2l_tiles(dp.hp, tpt, h);
+    build_m2l_tiles(dp.hp, tpt, kM2LMaxEntries, h);
     auto up = [&](const std::vector<int32_t> &v, int32_t *&d) {
         hip_check(hipMalloc(&d, sizeof(int32_t) * std::max<size_t>(v.size(), 1)), "hipMalloc M2L tiles");
         if (!v.empty())
@@ -1403,10 +1472,10 @@ DevicePlan::Tiles &ensure_m2l_tiles(DevicePlan &dp, int tpt)
         dp.device_bytes += (int64_t)(sizeof(int32_t) * std::max<size_t>(v.size(), 1));
     };
     up(h.tile_tgt, t.tile_tgt);
-    up(h.tile_ptr, t.tile_ptr);
+    up(h.tile_rng, t.tile_rng);
     up(h.ent_key, t.ent_key);
     up(h.ent_src, t.ent_src);
-    t.ntiles = (int32_t)(h.tile_ptr.size() - 1);
+    t.ntiles = (int32_t)(h.tile_rng.size() / 2);
     t.nent = (int64_t)h.ent_key.size();
     t.tpt = tpt;
     return t;

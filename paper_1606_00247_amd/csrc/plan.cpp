@@ -337,15 +337,16 @@ void build_m2l_keys(HostPlan &hp)
 
 }  // namespace
 
-void build_m2l_tiles(const HostPlan &hp, int tpt, M2LTiles &out)
+void build_m2l_tiles(const HostPlan &hp, int tpt, int max_ent, M2LTiles &out)
 {
     out.tpt = tpt;
     out.tile_tgt.clear();
-    out.tile_ptr.assign(1, 0);
+    out.tile_rng.clear();
     out.ent_key.clear();
     out.ent_src.clear();
     const int64_t nc = (int64_t)hp.cells.size();
-    std::vector<int32_t> tile;
+    std::vector<int32_t> tile, tgt;
+    std::vector<std::array<int32_t, 2>> rng;
     std::vector<std::array<int32_t, 3>> trip;  // key, slot, source
     auto flush = [&]() {
         if (tile.empty()) return;
@@ -355,13 +356,13 @@ void build_m2l_tiles(const HostPlan &hp, int tpt, M2LTiles &out)
             for (int32_t j = hp.m2l_ptr[a]; j < hp.m2l_ptr[a + 1]; ++j)
                 trip.push_back({hp.m2l_pair_key[j], t, hp.m2l_src[j]});
         }
-        // entries sorted by level difference, then key (the kernel rescales
-        // its accumulators when the level difference changes)
+        // entries sorted by level difference, then key
         std::sort(trip.begin(), trip.end(), [&](const std::array<int32_t, 3> &x, const std::array<int32_t, 3> &y) {
             const int32_t dx = hp.m2l_keys[4 * (size_t)x[0]], dy = hp.m2l_keys[4 * (size_t)y[0]];
             if (dx != dy) return dx < dy;
             return x < y;
         });
+        const int32_t e0 = (int32_t)out.ent_key.size();
         for (size_t i = 0; i < trip.size();) {
             const int32_t k = trip[i][0];
             out.ent_key.push_back(k);
@@ -369,8 +370,12 @@ void build_m2l_tiles(const HostPlan &hp, int tpt, M2LTiles &out)
             out.ent_src.resize(base + tpt, -1);
             for (; i < trip.size() && trip[i][0] == k; ++i) out.ent_src[base + trip[i][1]] = trip[i][2];
         }
-        for (int t = 0; t < tpt; ++t) out.tile_tgt.push_back(t < (int)tile.size() ? tile[t] : -1);
-        out.tile_ptr.push_back((int32_t)out.ent_key.size());
+        const int32_t e1 = (int32_t)out.ent_key.size();
+        // work items of at most max_ent entries sharing the tile's targets
+        for (int32_t b = e0; b < e1; b += max_ent) {
+            for (int t = 0; t < tpt; ++t) tgt.push_back(t < (int)tile.size() ? tile[t] : -1);
+            rng.push_back({b, std::min(e1, b + max_ent)});
+        }
         if (out.ent_key.size() > (size_t)INT32_MAX / 16) throw PlanError{TFMM_ENOTSUP, "too many M2L entries"};
         tile.clear();
     };
@@ -382,6 +387,19 @@ void build_m2l_tiles(const HostPlan &hp, int tpt, M2LTiles &out)
         tile.push_back((int32_t)a);
     }
     flush();
+    // longest work items first (stable: ties keep the octree order)
+    std::vector<int32_t> ord(rng.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int32_t)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+        return rng[x][1] - rng[x][0] > rng[y][1] - rng[y][0];
+    });
+    out.tile_tgt.reserve(tgt.size());
+    out.tile_rng.reserve(2 * rng.size());
+    for (int32_t i : ord) {
+        out.tile_tgt.insert(out.tile_tgt.end(), tgt.begin() + (size_t)i * tpt, tgt.begin() + (size_t)(i + 1) * tpt);
+        out.tile_rng.push_back(rng[i][0]);
+        out.tile_rng.push_back(rng[i][1]);
+    }
 }
 
 }  // namespace tfmm

@@ -65,11 +65,13 @@ struct HostPlan {
 // M2L grouped for matrix cores: target cells in tiles of `tpt` cells of one
 // level; per tile a list of entries, one per distinct key used by its cells
 // (sorted by level difference, then key), with the source cell of each tile
-// slot (-1: none).
+// slot (-1: none).  A tile's entries are cut into work items of at most
+// max_ent entries (each adds its part to the tiles' local expansions), and
+// the work items are ordered longest first.
 struct M2LTiles {
     int tpt = 0;
-    std::vector<int32_t> tile_tgt;  // [ntiles][tpt]
-    std::vector<int32_t> tile_ptr;  // [ntiles + 1] into the entries
+    std::vector<int32_t> tile_tgt;  // [nitems][tpt] target cells (-1: empty slot)
+    std::vector<int32_t> tile_rng;  // [nitems][2] entry range [begin, end)
     std::vector<int32_t> ent_key;   // [nent]
     std::vector<int32_t> ent_src;   // [nent][tpt]
 };
@@ -80,8 +82,9 @@ struct PlanError {
     std::string msg;
 };
 
-// Groups the M2L pairs of a built plan into target tiles of tpt cells.
-void build_m2l_tiles(const HostPlan &hp, int tpt, M2LTiles &out);
+// Groups the M2L pairs of a built plan into target tiles of tpt cells and
+// work items of at most max_ent entries.
+void build_m2l_tiles(const HostPlan &hp, int tpt, int max_ent, M2LTiles &out);
 
 // Builds the plan.  Throws PlanError on invalid input.
 void build_host_plan(HostPlan &hp, const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
