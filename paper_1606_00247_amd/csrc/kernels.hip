@@ -188,14 +188,75 @@ __global__ __launch_bounds__(kMomThreads) void k_tet_moments(const int32_t *__re
     }
 }
 
-// P2M, M2M and L2L process FC fields per workgroup (blockIdx.y = field
-// chunk): the field-independent work (moments, shift coefficients) is done
-// once and applied to all FC fields.
+// ---------------------------------------------------------------------------
+// P2M.  One workgroup per leaf holding tets (XCD-contiguous), FC fields per
+// workgroup (blockIdx.y = field chunk).  With the per-tet moments
+// S_m = int_T (y - c)^m (exact, once per plan) and, per field, the affine
+// magnetisation M(y) = M(c) + G (y - c) of the tet,
+//   Q_n = sum_T sum_k n_k [M_k(c) S_{n-e_k} + sum_d G_kd S_{n-e_k+e_d}].
+// Tets are staged kP2MStage at a time: their moments and the 12 field values
+// of every (tet, field) pair (one thread each) go to LDS, then every thread
+// accumulates its coefficients n over the staged tets for all FC fields.
+// ---------------------------------------------------------------------------
 __host__ __device__ constexpr int field_chunk(int F) { return F >= 16 ? 16 : (F >= 4 ? 4 : 1); }
-
-// One workgroup per leaf holding tets (XCD-contiguous), FC fields.
 constexpr int kP2MThreads = 256;
+constexpr int kP2MStage = 16;
 
+// M(c) [3] and G [3][3] of tet t for one field (nodal values Mf).
+__device__ inline void tet_affine_field(const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node,
+                                        int64_t T, int64_t t, const double *__restrict__ Mf, const double c[3],
+                                        double *__restrict__ out)
+{
+    double v[4][3], mm[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int nd = tet_node[(int64_t)q * T + t];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            v[q][k] = tet_xyz[(int64_t)(3 * q + k) * T + t];
+            mm[q][k] = Mf[3 * (int64_t)nd + k];
+        }
+    }
+    double e1[3], e2[3], e3[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = v[1][k] - v[0][k];
+        e2[k] = v[2][k] - v[0][k];
+        e3[k] = v[3][k] - v[0][k];
+    }
+    // gradients of the barycentric coordinates
+    double g[4][3];
+    g[1][0] = e2[1] * e3[2] - e2[2] * e3[1];
+    g[1][1] = e2[2] * e3[0] - e2[0] * e3[2];
+    g[1][2] = e2[0] * e3[1] - e2[1] * e3[0];
+    g[2][0] = e3[1] * e1[2] - e3[2] * e1[1];
+    g[2][1] = e3[2] * e1[0] - e3[0] * e1[2];
+    g[2][2] = e3[0] * e1[1] - e3[1] * e1[0];
+    g[3][0] = e1[1] * e2[2] - e1[2] * e2[1];
+    g[3][1] = e1[2] * e2[0] - e1[0] * e2[2];
+    g[3][2] = e1[0] * e2[1] - e1[1] * e2[0];
+    const double idet = 1.0 / (e1[0] * g[1][0] + e1[1] * g[1][1] + e1[2] * g[1][2]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        g[1][k] *= idet;
+        g[2][k] *= idet;
+        g[3][k] *= idet;
+        g[0][k] = -(g[1][k] + g[2][k] + g[3][k]);
+    }
+    const double dc[3] = {c[0] - v[0][0], c[1] - v[0][1], c[2] - v[0][2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double G[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) G[b] = mm[0][a] * g[0][b] + mm[1][a] * g[1][b] + mm[2][a] * g[2][b] + mm[3][a] * g[3][b];
+        out[a] = mm[0][a] + (G[0] * dc[0] + G[1] * dc[1] + G[2] * dc[2]);  // M_a(c)
+        out[3 + 3 * a] = G[0];
+        out[4 + 3 * a] = G[1];
+        out[5 + 3 * a] = G[2];
+    }
+}
+
+// Dynamic LDS: S [kP2MStage][ncoef], W [kP2MStage][FC][12] doubles.
 template <int FC>
 __global__ __launch_bounds__(kP2MThreads) void k_p2m(const int32_t *__restrict__ cells, const int32_t *__restrict__ cell_i,
                                                      const double *__restrict__ cell_c, int64_t C,
@@ -204,99 +265,67 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m(const int32_t *__restrict__
                                                      const double *__restrict__ M, int64_t n_nodes, int F, int p,
                                                      int ncells, double *__restrict__ Q)
 {
-    __shared__ double s_S[kNcoefMax];
-    __shared__ double s_m[FC][12];  // per field: M(c) [3], G [3][3] of the current tet
+    extern __shared__ double s_dyn[];
+    const int ncoef = ncoef_of(p);
+    double *s_S = s_dyn;                        // [kP2MStage][ncoef]
+    double *s_W = s_dyn + kP2MStage * ncoef;    // [kP2MStage][FC][12]
     const int item = xcd_item(ncells);
     if (item < 0) return;
     const int cell = cells[item];
     const int f0 = blockIdx.y * FC;
     const int tbeg = cell_i[CI_N * cell + CI_TBEG], tend = cell_i[CI_N * cell + CI_TEND];
-    const int ncoef = ncoef_of(p);
     const int tid = threadIdx.x;
+    const double cc[3] = {cell_c[cell], cell_c[C + cell], cell_c[2 * C + cell]};
     double acc[2][FC];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int j = 0; j < FC; ++j) acc[r][j] = 0.0;
-    for (int t = tbeg; t < tend; ++t) {
+    for (int sb = tbeg; sb < tend; sb += kP2MStage) {
+        const int nt = min(kP2MStage, tend - sb);
         __syncthreads();
-        for (int m = tid; m < ncoef; m += blockDim.x) s_S[m] = mom[(int64_t)t * ncoef + m];
-        if (tid < FC && f0 + tid < F) {
-            const double *Mf = M + (int64_t)(f0 + tid) * n_nodes * 3;
-            double v[4][3], mm[4][3];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int nd = tet_node[(int64_t)c * T + t];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    v[c][k] = tet_xyz[(int64_t)(3 * c + k) * T + t];
-                    mm[c][k] = Mf[3 * (int64_t)nd + k];
-                }
-            }
-            double e1[3], e2[3], e3[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                e1[k] = v[1][k] - v[0][k];
-                e2[k] = v[2][k] - v[0][k];
-                e3[k] = v[3][k] - v[0][k];
-            }
-            double g[4][3];
-            g[1][0] = e2[1] * e3[2] - e2[2] * e3[1];
-            g[1][1] = e2[2] * e3[0] - e2[0] * e3[2];
-            g[1][2] = e2[0] * e3[1] - e2[1] * e3[0];
-            g[2][0] = e3[1] * e1[2] - e3[2] * e1[1];
-            g[2][1] = e3[2] * e1[0] - e3[0] * e1[2];
-            g[2][2] = e3[0] * e1[1] - e3[1] * e1[0];
-            g[3][0] = e1[1] * e2[2] - e1[2] * e2[1];
-            g[3][1] = e1[2] * e2[0] - e1[0] * e2[2];
-            g[3][2] = e1[0] * e2[1] - e1[1] * e2[0];
-            const double idet = 1.0 / (e1[0] * g[1][0] + e1[1] * g[1][1] + e1[2] * g[1][2]);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                g[1][k] *= idet;
-                g[2][k] *= idet;
-                g[3][k] *= idet;
-                g[0][k] = -(g[1][k] + g[2][k] + g[3][k]);
-            }
-            const double dc[3] = {cell_c[cell] - v[0][0], cell_c[C + cell] - v[0][1], cell_c[2 * C + cell] - v[0][2]};
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                double G[3];
-#pragma unroll
-                for (int b = 0; b < 3; ++b) G[b] = mm[0][a] * g[0][b] + mm[1][a] * g[1][b] + mm[2][a] * g[2][b] + mm[3][a] * g[3][b];
-                s_m[tid][a] = mm[0][a] + (G[0] * dc[0] + G[1] * dc[1] + G[2] * dc[2]);  // M_a(c)
-                s_m[tid][3 + 3 * a] = G[0];
-                s_m[tid][4 + 3 * a] = G[1];
-                s_m[tid][5 + 3 * a] = G[2];
-            }
+        for (int i = tid; i < nt * ncoef; i += blockDim.x) s_S[i] = mom[(int64_t)sb * ncoef + i];
+        for (int i = tid; i < nt * FC; i += blockDim.x) {
+            const int t = i / FC, j = i - t * FC;
+            if (f0 + j < F)
+                tet_affine_field(tet_xyz, tet_node, T, sb + t, M + (int64_t)(f0 + j) * n_nodes * 3, cc,
+                                 s_W + (t * FC + j) * 12);
+            else
+                for (int q = 0; q < 12; ++q) s_W[(t * FC + j) * 12 + q] = 0.0;
         }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int n = tid + r * kP2MThreads;
-            if (n < ncoef) {
-                const int nv[3] = {c_mi.v[n][0], c_mi.v[n][1], c_mi.v[n][2]};
-                // S_{n-e_k} and S_{n-e_k+e_d} of this coefficient, shared by all fields
+            if (n >= ncoef) continue;
+            const int nv[3] = {c_mi.v[n][0], c_mi.v[n][1], c_mi.v[n][2]};
+            // indices of S_{n-e_k} and S_{n-e_k+e_d}
+            int si[3][4];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                int b[3] = {nv[0], nv[1], nv[2]};
+                b[k] = b[k] > 0 ? b[k] - 1 : 0;
+                si[k][0] = mi_index(b[0], b[1], b[2]);
+                si[k][1] = mi_index(b[0] + 1, b[1], b[2]);
+                si[k][2] = mi_index(b[0], b[1] + 1, b[2]);
+                si[k][3] = mi_index(b[0], b[1], b[2] + 1);
+            }
+            for (int t = 0; t < nt; ++t) {
+                const double *S = s_S + t * ncoef;
                 double sv[3][4];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    int b[3] = {nv[0], nv[1], nv[2]};
-                    b[k] = b[k] > 0 ? b[k] - 1 : 0;
-                    sv[k][0] = nv[k] ? s_S[mi_index(b[0], b[1], b[2])] : 0.0;
-                    sv[k][1] = nv[k] ? s_S[mi_index(b[0] + 1, b[1], b[2])] : 0.0;
-                    sv[k][2] = nv[k] ? s_S[mi_index(b[0], b[1] + 1, b[2])] : 0.0;
-                    sv[k][3] = nv[k] ? s_S[mi_index(b[0], b[1], b[2] + 1)] : 0.0;
-                }
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) sv[k][q] = nv[k] ? nv[k] * S[si[k][q]] : 0.0;
 #pragma unroll
                 for (int j = 0; j < FC; ++j) {
-                    double sacc = 0.0;
+                    const double *w = s_W + (t * FC + j) * 12;
+                    double sacc = acc[r][j];
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const double w = s_m[j][k] * sv[k][0] + s_m[j][3 + 3 * k] * sv[k][1] +
-                                         s_m[j][4 + 3 * k] * sv[k][2] + s_m[j][5 + 3 * k] * sv[k][3];
-                        sacc += nv[k] * w;
-                    }
-                    acc[r][j] += sacc;
+                    for (int k = 0; k < 3; ++k)
+                        sacc += w[k] * sv[k][0] + w[3 + 3 * k] * sv[k][1] + w[4 + 3 * k] * sv[k][2] +
+                                w[5 + 3 * k] * sv[k][3];
+                    acc[r][j] = sacc;
                 }
             }
         }
@@ -312,122 +341,110 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m(const int32_t *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// M2M.  One workgroup per parent cell of a level (blockIdx.x), FC fields.
-//   Q_n(P) = sum_children sum_{k <= n} C(n,k) (c_C - c_P)^{n-k} Q_k(C)
+// M2M and L2L as three one-dimensional binomial shifts.  The shift by t of a
+// multipole (k <= n) or local (k >= m, |k| <= p) expansion factorises over the
+// axes, C(n, k) t^(n-k) = prod_i C(n_i, k_i) t_i^(n_i - k_i), so it is applied
+// axis by axis (at most p + 1 terms per coefficient and axis).  A workgroup
+// holds kShiftItems items (children) of 32 lanes each, one field
+// (blockIdx.y); LDS holds two buffers of kShiftItems x ncoef doubles.
 // ---------------------------------------------------------------------------
-constexpr int kShiftThreads = 256;
+constexpr int kShiftItems = 8;
+constexpr int kShiftThreads = 32 * kShiftItems;
 
-template <int FC>
-__global__ __launch_bounds__(kShiftThreads) void k_m2m(const int32_t *__restrict__ cells, const int32_t *__restrict__ cell_i,
-                                                       const double *__restrict__ cell_c, int64_t C, int F, int p,
-                                                       double *__restrict__ Q)
+template <bool Up>
+__device__ __forceinline__ void shift_pass(const double *__restrict__ in, double *__restrict__ out, int ncoef, int p,
+                                           int ax, double t, int lane)
 {
-    __shared__ double s_q[FC][kNcoefMax];
-    __shared__ double s_pw[3][kPmax + 1];
-    const int cell = cells[blockIdx.x];
-    const int f0 = blockIdx.y * FC;
-    const int ncoef = ncoef_of(p);
-    const int cbeg = cell_i[CI_N * cell + CI_CBEG], nch = cell_i[CI_N * cell + CI_NCHILD];
-    double acc[2][FC];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int j = 0; j < FC; ++j) acc[r][j] = 0.0;
-    for (int ch = cbeg; ch < cbeg + nch; ++ch) {
-        if (cell_i[CI_N * ch + CI_TEND] == cell_i[CI_N * ch + CI_TBEG]) continue;  // no tets
-        __syncthreads();
-        for (int i = threadIdx.x; i < FC * ncoef; i += blockDim.x) {
-            const int j = i / ncoef, n = i - j * ncoef;
-            s_q[j][n] = f0 + j < F ? Q[((int64_t)(f0 + j) * C + ch) * ncoef + n] : 0.0;
-        }
-        if (threadIdx.x < 3) {
-            const int k = threadIdx.x;
-            const double dlt = cell_c[k * C + ch] - cell_c[k * C + cell];
-            double pw = 1.0;
-            for (int j = 0; j <= p; ++j) {
-                s_pw[k][j] = pw;
-                pw *= dlt;
+    for (int n = lane; n < ncoef; n += 32) {
+        int v[3] = {c_mi.v[n][0], c_mi.v[n][1], c_mi.v[n][2]};
+        const int a = v[ax], rest = c_mi.v[n][3] - a;
+        double acc = 0.0, pw = 1.0;
+        if (Up) {  // out_n = sum_{k <= a} C(a, k) t^(a-k) in_(.., k, ..)
+            for (int k = a; k >= 0; --k) {
+                v[ax] = k;
+                acc += c_bin.c[a][k] * pw * in[mi_index(v[0], v[1], v[2])];
+                pw *= t;
+            }
+        } else {  // out_m = sum_{a <= k <= p - rest} C(k, a) t^(k-a) in_(.., k, ..)
+            for (int k = a; k <= p - rest; ++k) {
+                v[ax] = k;
+                acc += c_bin.c[k][a] * pw * in[mi_index(v[0], v[1], v[2])];
+                pw *= t;
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int n = threadIdx.x + r * blockDim.x;
-            if (n >= ncoef) continue;
-            const int nx = c_mi.v[n][0], ny = c_mi.v[n][1], nz = c_mi.v[n][2];
-            for (int kx = 0; kx <= nx; ++kx) {
-                const double ax = c_bin.c[nx][kx] * s_pw[0][nx - kx];
-                for (int ky = 0; ky <= ny; ++ky) {
-                    const double axy = ax * c_bin.c[ny][ky] * s_pw[1][ny - ky];
-                    for (int kz = 0; kz <= nz; ++kz) {
-                        const double cf = axy * c_bin.c[nz][kz] * s_pw[2][nz - kz];
-                        const int ki = mi_index(kx, ky, kz);
-#pragma unroll
-                        for (int j = 0; j < FC; ++j) acc[r][j] += cf * s_q[j][ki];
-                    }
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int n = threadIdx.x + r * blockDim.x;
-        if (n >= ncoef) continue;
-#pragma unroll
-        for (int j = 0; j < FC; ++j)
-            if (f0 + j < F) Q[((int64_t)(f0 + j) * C + cell) * ncoef + n] = acc[r][j];
+        out[n] = acc;
     }
 }
 
-// ---------------------------------------------------------------------------
-// L2L.  One workgroup per child cell of a level (blockIdx.x), FC fields.
-//   l_m(C) += sum_{k >= m, |k| <= p} C(k,m) (c_C - c_P)^{k-m} l_k(P)
-// ---------------------------------------------------------------------------
-template <int FC>
-__global__ __launch_bounds__(kShiftThreads) void k_l2l(const int32_t *__restrict__ cells, const int32_t *__restrict__ cell_i,
-                                                       const double *__restrict__ cell_c, int64_t C, int F, int p,
-                                                       double *__restrict__ L)
+// M2M: one workgroup per parent of a level; child g of the parent is item g.
+//   Q_n(P) = sum_children sum_{k <= n} C(n,k) (c_C - c_P)^{n-k} Q_k(C)
+__global__ __launch_bounds__(kShiftThreads) void k_m2m(const int32_t *__restrict__ cells, const int32_t *__restrict__ cell_i,
+                                                       const double *__restrict__ cell_c, int64_t C, int p,
+                                                       double *__restrict__ Q)
 {
-    __shared__ double s_l[FC][kNcoefMax];
-    __shared__ double s_pw[3][kPmax + 1];
-    const int cell = cells[blockIdx.x];
-    const int f0 = blockIdx.y * FC;
+    extern __shared__ double s_dyn[];
     const int ncoef = ncoef_of(p);
-    const int par = cell_i[CI_N * cell + CI_PARENT];
-    for (int i = threadIdx.x; i < FC * ncoef; i += blockDim.x) {
-        const int j = i / ncoef, n = i - j * ncoef;
-        s_l[j][n] = f0 + j < F ? L[((int64_t)(f0 + j) * C + par) * ncoef + n] : 0.0;
-    }
-    if (threadIdx.x < 3) {
-        const int k = threadIdx.x;
-        const double dlt = cell_c[k * C + cell] - cell_c[k * C + par];
-        double pw = 1.0;
-        for (int j = 0; j <= p; ++j) {
-            s_pw[k][j] = pw;
-            pw *= dlt;
-        }
+    double *s_a = s_dyn, *s_b = s_dyn + kShiftItems * ncoef;
+    const int cell = cells[blockIdx.x];
+    const int f = blockIdx.y;
+    const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    const int cbeg = cell_i[CI_N * cell + CI_CBEG], nch = cell_i[CI_N * cell + CI_NCHILD];
+    const int ch = cbeg + g;
+    const bool act = g < nch && cell_i[CI_N * ch + CI_TEND] > cell_i[CI_N * ch + CI_TBEG];
+    double t[3] = {0.0, 0.0, 0.0};
+    if (act) {
+        for (int n = lane; n < ncoef; n += 32) s_a[g * ncoef + n] = Q[((int64_t)f * C + ch) * ncoef + n];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) t[k] = cell_c[k * C + ch] - cell_c[k * C + cell];
     }
     __syncthreads();
-    for (int m = threadIdx.x; m < ncoef; m += blockDim.x) {
-        const int mx = c_mi.v[m][0], my = c_mi.v[m][1], mz = c_mi.v[m][2];
-        double acc[FC];
+    if (act) shift_pass<true>(s_a + g * ncoef, s_b + g * ncoef, ncoef, p, 0, t[0], lane);
+    __syncthreads();
+    if (act) shift_pass<true>(s_b + g * ncoef, s_a + g * ncoef, ncoef, p, 1, t[1], lane);
+    __syncthreads();
+    if (act) shift_pass<true>(s_a + g * ncoef, s_b + g * ncoef, ncoef, p, 2, t[2], lane);
+    __syncthreads();
+    for (int n = threadIdx.x; n < ncoef; n += blockDim.x) {
+        double q = 0.0;
+        for (int c = 0; c < nch && c < kShiftItems; ++c)
+            if (cell_i[CI_N * (cbeg + c) + CI_TEND] > cell_i[CI_N * (cbeg + c) + CI_TBEG]) q += s_b[c * ncoef + n];
+        Q[((int64_t)f * C + cell) * ncoef + n] = q;
+    }
+}
+
+// L2L: items are kShiftItems consecutive child cells of a level (each with
+// its own parent).
+//   l_m(C) += sum_{k >= m, |k| <= p} C(k,m) (c_C - c_P)^{k-m} l_k(P)
+__global__ __launch_bounds__(kShiftThreads) void k_l2l(const int32_t *__restrict__ cells, int ncells,
+                                                       const int32_t *__restrict__ cell_i,
+                                                       const double *__restrict__ cell_c, int64_t C, int p,
+                                                       double *__restrict__ L)
+{
+    extern __shared__ double s_dyn[];
+    const int ncoef = ncoef_of(p);
+    double *s_a = s_dyn, *s_b = s_dyn + kShiftItems * ncoef;
+    const int f = blockIdx.y;
+    const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    const int it = blockIdx.x * kShiftItems + g;
+    const bool act = it < ncells;
+    int cell = 0;
+    double t[3] = {0.0, 0.0, 0.0};
+    if (act) {
+        cell = cells[it];
+        const int par = cell_i[CI_N * cell + CI_PARENT];
+        for (int n = lane; n < ncoef; n += 32) s_a[g * ncoef + n] = L[((int64_t)f * C + par) * ncoef + n];
 #pragma unroll
-        for (int j = 0; j < FC; ++j) acc[j] = 0.0;
-        for (int kx = mx; kx <= p - (my + mz); ++kx) {
-            const double ax = c_bin.c[kx][mx] * s_pw[0][kx - mx];
-            for (int ky = my; ky <= p - kx - mz; ++ky) {
-                const double axy = ax * c_bin.c[ky][my] * s_pw[1][ky - my];
-                for (int kz = mz; kz <= p - kx - ky; ++kz) {
-                    const double cf = axy * c_bin.c[kz][mz] * s_pw[2][kz - mz];
-                    const int ki = mi_index(kx, ky, kz);
-#pragma unroll
-                    for (int j = 0; j < FC; ++j) acc[j] += cf * s_l[j][ki];
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < FC; ++j)
-            if (f0 + j < F) L[((int64_t)(f0 + j) * C + cell) * ncoef + m] += acc[j];
+        for (int k = 0; k < 3; ++k) t[k] = cell_c[k * C + cell] - cell_c[k * C + par];
+    }
+    __syncthreads();
+    if (act) shift_pass<false>(s_a + g * ncoef, s_b + g * ncoef, ncoef, p, 0, t[0], lane);
+    __syncthreads();
+    if (act) shift_pass<false>(s_b + g * ncoef, s_a + g * ncoef, ncoef, p, 1, t[1], lane);
+    __syncthreads();
+    if (act) {
+        shift_pass<false>(s_a + g * ncoef, s_b + g * ncoef, ncoef, p, 2, t[2], lane);
+        // the lanes that wrote out[n] add it (no barrier needed)
+        for (int n = lane; n < ncoef; n += 32) L[((int64_t)f * C + cell) * ncoef + n] += s_b[g * ncoef + n];
     }
 }
 
@@ -1526,11 +1543,13 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
     dp.last_F = F;
     fill(dp.Q, (int64_t)F * C * dp.ncoef, 0.0, st);
     fill(dp.L, (int64_t)F * C * dp.ncoef, 0.0, st);
+    const size_t shift_lds = sizeof(double) * 2 * kShiftItems * (size_t)dp.ncoef;
     {
         KTimer kt(dp, KT_P2M, st);
         if (dp.n_p2m_cells > 0) launch_fc(F, [&](auto fc) {
             constexpr int FC = decltype(fc)::value;
-            k_p2m<FC><<<dim3(xcd_grid(dp.n_p2m_cells), (F + FC - 1) / FC), dim3(kP2MThreads), 0, st>>>(
+            const size_t lds = sizeof(double) * (size_t)kP2MStage * (dp.ncoef + 12 * FC);
+            k_p2m<FC><<<dim3(xcd_grid(dp.n_p2m_cells), (F + FC - 1) / FC), dim3(kP2MThreads), lds, st>>>(
                 dp.p2m_cells, dp.cell_i, dp.cell_c, C, dp.tet_xyz, dp.tet_node, hp.n_tets, dp.tet_mom, M, hp.n_nodes, F,
                 p, dp.n_p2m_cells, dp.Q);
             hip_check(hipGetLastError(), "k_p2m launch");
@@ -1540,12 +1559,11 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
         KTimer kt(dp, KT_M2M, st);
         for (int Lv = hp.depth - 1; Lv >= 0; --Lv) {
             int b = dp.m2m_level_ptr[Lv], e = dp.m2m_level_ptr[Lv + 1];
-            if (e > b) launch_fc(F, [&](auto fc) {
-                constexpr int FC = decltype(fc)::value;
-                k_m2m<FC><<<dim3(e - b, (F + FC - 1) / FC), dim3(kShiftThreads), 0, st>>>(dp.m2m_cells + b, dp.cell_i,
-                                                                                             dp.cell_c, C, F, p, dp.Q);
+            if (e > b) {
+                k_m2m<<<dim3(e - b, F), dim3(kShiftThreads), shift_lds, st>>>(dp.m2m_cells + b, dp.cell_i, dp.cell_c,
+                                                                                  C, p, dp.Q);
                 hip_check(hipGetLastError(), "k_m2m launch");
-            });
+            }
         }
     }
     {
@@ -1556,12 +1574,11 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
         KTimer kt(dp, KT_L2L, st);
         for (int Lv = 1; Lv <= hp.depth; ++Lv) {
             int b = dp.l2l_level_ptr[Lv], e = dp.l2l_level_ptr[Lv + 1];
-            if (e > b) launch_fc(F, [&](auto fc) {
-                constexpr int FC = decltype(fc)::value;
-                k_l2l<FC><<<dim3(e - b, (F + FC - 1) / FC), dim3(kShiftThreads), 0, st>>>(dp.l2l_cells + b, dp.cell_i,
-                                                                                             dp.cell_c, C, F, p, dp.L);
+            if (e > b) {
+                k_l2l<<<dim3((e - b + kShiftItems - 1) / kShiftItems, F), dim3(kShiftThreads), shift_lds, st>>>(
+                    dp.l2l_cells + b, e - b, dp.cell_i, dp.cell_c, C, p, dp.L);
                 hip_check(hipGetLastError(), "k_l2l launch");
-            });
+            }
         }
     }
     {
