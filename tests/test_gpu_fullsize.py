@@ -1,0 +1,135 @@
+"""GPU checks at the full sizes of the benchmark configurations.
+
+The FP64 FMM is compared with the oracle FMM on seeded samples of targets (the
+oracle evaluates them one by one), and every form is compared with the FP64
+direct sum on sampled targets (a plan whose explicit targets are the sample).
+Configurations: the 40^3 cube (384,000 tets, p=8, leaf 64), the 512x512x4
+film (6.29M tets, vortex field, FP32 M2L), 64 random fields on the 64^3 cube
+(1.57M tets) and the jittered sphere of radius 1 on a 96^3 grid (~2.78M
+tets, uniform M).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import meshgen
+import paper_1606_00247_amd as T
+
+pytestmark = pytest.mark.gpu
+
+FMM_TOL = 1e-12  # FP64 FMM vs oracle FMM
+ACC_TOL = 1e-5   # any form vs the FP64 direct sum
+# opening angles calibrated for <= 1e-5 against the direct sum at p = 8
+# (film: 2.6e-5 at 0.5, 5.3e-6 at 0.4; 64^3 cube: 1.3e-5 at 0.5, 4.9e-6 at 0.45)
+FILM_THETA = 0.4
+CUBE64_THETA = 0.45
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _eval(torch, plan, M, direct=False):
+    Md = torch.from_numpy(np.ascontiguousarray(M)).to("cuda:0")
+    u = (T.tfmm_direct if direct else T.tfmm_evaluate)(plan, Md)
+    torch.cuda.synchronize()
+    return u.cpu().numpy()
+
+
+def _direct_at(torch, nodes, tets, M, idx):
+    """FP64 direct sum at the nodes idx (a plan with those nodes as targets)."""
+    P = T.tfmm_plan_create(nodes, tets, targets=nodes[idx], p=2, leaf_size=64, theta=0.5)
+    return _eval(torch, P, M, direct=True)
+
+
+def _sample(n, k, seed):
+    return np.sort(np.random.default_rng(seed).choice(n, k, replace=False))
+
+
+def test_cube40_fp64_vs_oracle_sampled_and_direct(torch_dev, orc):
+    nodes, tets = meshgen.box_mesh(40, seed=0)
+    M = meshgen.random_fields(nodes.shape[0], F=1, seed=1)
+    _say("cube40 fp64 vs oracle (sampled) and direct")
+    P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=64, theta=0.5)
+    u = _eval(torch_dev, P, M)
+    ud = _eval(torch_dev, P, M, direct=True)
+    assert _rel(u[0], ud[0]) <= ACC_TOL
+    idx = _sample(nodes.shape[0], 96, 7)
+    O = orc.FMM(nodes, tets, 8, 64, 0.5)
+    uo = O.evaluate_sample(M, idx)
+    assert _rel(u[:, idx], uo) <= FMM_TOL
+
+
+def test_film_oracle_parity_and_full_film_accuracy(torch_dev, orc):
+    """Unjittered film (coplanar and collinear placements everywhere): FP64
+    parity with the oracle on a 128x128x4 film of the same family, then the
+    512x512x4 film (6.29M tets) with FP32 M2L against the direct sum."""
+    nodes, tets = meshgen.film_mesh(128, 128, 4, half=16.0, thickness=1.0)
+    M = meshgen.vortex_field(nodes, (0.0, 0.0), 16.0, seed=1)
+    _say("film 128 fp64 vs oracle (sampled)")
+    P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=64, theta=0.5)
+    u = _eval(torch_dev, P, M)
+    idx = _sample(nodes.shape[0], 64, 3)
+    uo = orc.FMM(nodes, tets, 8, 64, 0.5).evaluate_sample(M, idx)
+    assert _rel(u[idx], uo) <= FMM_TOL
+    del P
+
+    nodes, tets = meshgen.film_mesh()
+    M = meshgen.vortex_field(nodes, (0.0, 0.0), 64.0, seed=1)
+    _say("film 512 fp32 m2l vs direct (sampled)", tets.shape)
+    P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=64, theta=FILM_THETA, m2l_precision=T.M2L_FP32)
+    u32 = _eval(torch_dev, P, M)
+    T.tfmm_plan_set_m2l_precision(P, T.M2L_FP64)
+    u64 = _eval(torch_dev, P, M)
+    del P
+    idx = _sample(nodes.shape[0], 1024, 4)
+    ud = _direct_at(torch_dev, nodes, tets, M, idx)
+    assert _rel(u64[idx], ud) <= ACC_TOL
+    assert _rel(u32[idx], ud) <= ACC_TOL
+    assert _rel(u32, u64) <= 1e-6
+
+
+def test_cube64_64_fields_fp32(torch_dev):
+    nodes, tets = meshgen.box_mesh(64, seed=0)
+    F = 64
+    M = meshgen.random_fields(nodes.shape[0], F=F, seed=1)
+    _say("cube64 x 64 fields fp32 m2l vs direct (sampled)", tets.shape)
+    P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=64, theta=CUBE64_THETA, m2l_precision=T.M2L_FP32)
+    u = _eval(torch_dev, P, M)
+    del P
+    idx = _sample(nodes.shape[0], 256, 5)
+    ud = _direct_at(torch_dev, nodes, tets, M, idx)
+    errs = [_rel(u[f, idx], ud[f]) for f in range(F)]
+    assert max(errs) <= ACC_TOL, max(errs)
+
+
+def test_sphere_uniform_field(torch_dev):
+    """Sphere of radius 1 (96^3 grid, ~2.78M tets), M = (0, 0, 1): the FMM
+    agrees with the direct sum, and inside (|r| < 0.8) both approach the
+    exact u = M.r/3 of the true sphere up to the staircase boundary."""
+    nodes, tets = meshgen.sphere_mesh(96)
+    M = meshgen.uniform_field(nodes.shape[0], (0.0, 0.0, 1.0))
+    _say("sphere 96 fp64", tets.shape)
+    P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=64, theta=0.5)
+    u = _eval(torch_dev, P, M)
+    del P
+    inner = np.flatnonzero(np.linalg.norm(nodes, axis=1) < 0.8)
+    idx = inner[_sample(inner.size, 512, 6)]
+    ud = _direct_at(torch_dev, nodes, tets, M, idx)
+    assert _rel(u[idx], ud) <= ACC_TOL
+    exact = nodes[idx, 2] / 3.0
+    assert _rel(ud, exact) <= 2e-2
