@@ -176,7 +176,7 @@ def main():
         # the mixed-precision and field-batched forms on the same mesh
         variants = {}
         for name, prec, F in (("m2l_fp32", T.M2L_FP32, 1), ("fields16_fp64", T.M2L_FP64, 16),
-                              ("fields16_m2l_fp32", T.M2L_FP32, 16)):
+                              ("fields16_m2l_fp32", T.M2L_FP32, 16), ("fields16_m2l_bf16x3", T.M2L_BF16X3, 16)):
             T.tfmm_plan_set_m2l_precision(plan, prec)
             Mv = torch.from_numpy(meshgen.random_fields(nodes.shape[0], F=F, seed=1)).to(dev)
             uv = torch.empty((F, nodes.shape[0]), dtype=torch.float64, device=dev)
@@ -193,7 +193,8 @@ def main():
             T.tfmm_set_timing(plan, False)
             ev = max(float(torch.linalg.norm(uv[f] - udv[f]) / torch.linalg.norm(udv[f])) for f in range(F))
             variants[name] = {"value": nodes.shape[0] * F / dv, "unit": "evals/s", "ms_per_step": dv * 1e3,
-                              "fields": F, "m2l": "fp32" if prec == T.M2L_FP32 else "fp64",
+                              "fields": F, "m2l": {T.M2L_FP64: "fp64", T.M2L_FP32: "fp32", T.M2L_BF16X3: "bf16x3",
+                                                   T.M2L_BF16X6: "bf16x6"}[prec],
                               "rel_l2_vs_direct_max_over_fields": ev,
                               "speedup_vs_plain": (nodes.shape[0] * F / dv) / value,
                               "kernel_ms": {k: round(v[0], 4) for k, v in kv.items()}}

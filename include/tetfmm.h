@@ -52,6 +52,8 @@ extern "C" {
 /* M2L arithmetic (P2M, M2M, L2L, L2P and the near field are always FP64) */
 #define TFMM_M2L_FP64 0 /* FP64 matrix cores */
 #define TFMM_M2L_FP32 1 /* FP32 matrix cores on level-scaled expansions, FP64 elsewhere */
+#define TFMM_M2L_BF16X3 2 /* FP32 operands split into BF16 parts, 3 part products, FP32 accumulation */
+#define TFMM_M2L_BF16X6 3 /* as BF16X3 with 6 part products (about FP32 accuracy) */
 
 typedef struct tfmm_plan_s *tfmm_plan; /* opaque, owned by the library */
 
@@ -65,9 +67,12 @@ typedef struct tfmm_plan_s *tfmm_plan; /* opaque, owned by the library */
  *  theta      multipole acceptance parameter (Sec. 3.2): cells A (target)
  *             and B (source) interact through M2L iff
  *             r_tgt(A) + r_src(B) < theta |c_A - c_B|.  0 < theta < 1.
- *  m2l_precision  TFMM_M2L_FP64 or TFMM_M2L_FP32 (the translation operands
- *             are scaled per level so that all magnitudes are O(1); the
- *             local expansions are accumulated and stored in FP64).
+ *  m2l_precision  TFMM_M2L_FP64, TFMM_M2L_FP32, TFMM_M2L_BF16X3 or
+ *             TFMM_M2L_BF16X6 (the translation operands are scaled per level
+ *             so that all magnitudes are O(1); the BF16 forms split the FP32
+ *             operands into three BF16 parts and sum 3 or 6 of the part
+ *             products in FP32; the local expansions are accumulated and
+ *             stored in FP64).
  *  device     HIP device ordinal; -1 builds a host-only plan (tree and lists
  *             without any device allocation: only tfmm_plan_stats,
  *             tfmm_plan_lists and tfmm_plan_cells work on it).
@@ -126,7 +131,7 @@ int tfmm_evaluate(tfmm_plan plan, const double *M, int32_t F, double *u, void *h
  */
 int tfmm_direct(tfmm_plan plan, const double *M, int32_t F, double *u, void *hip_stream);
 
-/* Switch the M2L arithmetic of an existing plan (TFMM_M2L_FP64 / _FP32). */
+/* Switch the M2L arithmetic of an existing plan (one of TFMM_M2L_*). */
 int tfmm_plan_set_m2l_precision(tfmm_plan plan, int32_t m2l_precision);
 
 /* Synchronous convenience forms with host arrays (copies in and out). */

@@ -17,7 +17,7 @@ __all__ = [
     "TetFMMError", "Plan", "tfmm_plan_create", "tfmm_evaluate", "tfmm_direct", "tfmm_evaluate_host",
     "tfmm_direct_host", "tfmm_plan_stats", "tfmm_plan_lists", "tfmm_plan_cells", "tfmm_plan_expansions",
     "tfmm_plan_destroy", "tfmm_last_error", "tfmm_simplex_rule", "tfmm_set_timing", "tfmm_kernel_times",
-    "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS", "tfmm_plan_set_m2l_precision", "M2L_FP64", "M2L_FP32",
+    "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS", "tfmm_plan_set_m2l_precision", "M2L_FP64", "M2L_FP32", "M2L_BF16X3", "M2L_BF16X6",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -27,6 +27,8 @@ _lib = None
 TFMM_PMAX = 10
 M2L_FP64 = 0
 M2L_FP32 = 1
+M2L_BF16X3 = 2
+M2L_BF16X6 = 3
 KERNEL_NAMES = ("p2m", "m2m", "m2l", "l2l", "l2p", "p2p")
 ERRORS = {-1: "EINVAL", -2: "EINDEX", -3: "EDEGEN", -4: "ENONFINITE", -5: "ENOMEM", -6: "EDEVICE", -7: "ENOTSUP"}
 
@@ -235,7 +237,7 @@ def tfmm_plan_expansions(plan, which):
 
 
 def tfmm_plan_set_m2l_precision(plan, m2l_precision):
-    """M2L arithmetic of an existing plan: M2L_FP64 or M2L_FP32."""
+    """M2L arithmetic of an existing plan: M2L_FP64, M2L_FP32, M2L_BF16X3 or M2L_BF16X6."""
     _check(_load().tfmm_plan_set_m2l_precision(plan.handle, int(m2l_precision)))
     plan.params["m2l_precision"] = int(m2l_precision)
 

@@ -237,7 +237,7 @@ int tfmm_plan_create(const double *nodes, int64_t n_nodes, const int32_t *tets, 
 {
     if (out) *out = nullptr;
     if (!prm || !out) return set_error(TFMM_EINVAL, "prm and out must not be NULL");
-    if (prm->m2l_precision != TFMM_M2L_FP64 && prm->m2l_precision != TFMM_M2L_FP32)
+    if (prm->m2l_precision < TFMM_M2L_FP64 || prm->m2l_precision > TFMM_M2L_BF16X6)
         return set_error(TFMM_ENOTSUP, "unsupported m2l_precision");
     return guarded([&]() -> int {
         auto t0 = std::chrono::steady_clock::now();
@@ -441,7 +441,7 @@ int tfmm_plan_expansions(tfmm_plan plan, int32_t which, double *out)
 int tfmm_plan_set_m2l_precision(tfmm_plan plan, int32_t m2l_precision)
 {
     if (!plan) return set_error(TFMM_EINVAL, "NULL plan");
-    if (m2l_precision != TFMM_M2L_FP64 && m2l_precision != TFMM_M2L_FP32)
+    if (m2l_precision < TFMM_M2L_FP64 || m2l_precision > TFMM_M2L_BF16X6)
         return set_error(TFMM_ENOTSUP, "unsupported m2l_precision");
     plan->dp.m2l_precision = m2l_precision;
     return TFMM_OK;

@@ -854,6 +854,228 @@ __global__ __launch_bounds__(64 * kM2LWaves, 2) void k_m2l_mfma(
 }
 
 // ---------------------------------------------------------------------------
+// M2L with split BF16 operands on matrix cores (v_mfma_f32_16x16x32_bf16).
+//
+// The FP32 operands of the FP32 form (derivative rows and reduced multipoles,
+// all O(1) by the level scaling) are split as they are staged into LDS,
+// x = x0 + x1 + x2 with x0 = bf16(x), x1 = bf16(x - x0), x2 = bf16(x - x0 - x1)
+// (each difference exact in FP32), and the product is formed from the part
+// products of total order < NP: NP = 2 takes a0 b0 + a0 b1 + a1 b0 (BF16x3),
+// NP = 3 adds a1 b1 + a0 b2 + a2 b0 (BF16x6), accumulated in FP32.
+// Operand layout: A (16 x 32): lane l holds row l%16, columns 8(l/16) + i;
+// B (32 x 16): lane l holds rows 8(l/16) + i, column l%16; result as the
+// FP32 16x16x4 form (row 4(l/16) + r, column l%16).
+// Column steps are 32 wide (n = 1 + 32 ks + ...); the (row tile, step) pairs
+// are dealt to two wavefronts in turn.
+// ---------------------------------------------------------------------------
+constexpr int kM2LBWaves = 2;
+using bf16x8 = __bf16 __attribute__((ext_vector_type(8)));
+
+__host__ __device__ constexpr int m2lb_ks(int P, int rt)
+{
+    const int d = rdeg(16 * rt);
+    if (d >= P) return 0;
+    return (nr_of(P - d) - 1 + 31) / 32;
+}
+__host__ __device__ constexpr int m2lb_kstr(int P) { return 32 * m2lb_ks(P, 0) + 8; }  // bf16 per staged column
+// number of (rt, ks) steps of wave W: steps in order ks-major, dealt in turn
+__host__ __device__ constexpr int m2lb_wave_steps(int P, int W)
+{
+    int s = 0, c = 0;
+    for (int ks = 0; ks < m2lb_ks(P, 0); ++ks)
+        for (int rt = 0; rt < m2l_nrt(P); ++rt)
+            if (ks < m2lb_ks(P, rt)) {
+                if (s % kM2LBWaves == W) ++c;
+                ++s;
+            }
+    return c;
+}
+// row tile and column step of the j-th step of wave W
+__host__ __device__ constexpr int m2lb_step(int P, int W, int j, bool want_rt)
+{
+    int s = 0, c = 0;
+    for (int ks = 0; ks < m2lb_ks(P, 0); ++ks)
+        for (int rt = 0; rt < m2l_nrt(P); ++rt)
+            if (ks < m2lb_ks(P, rt)) {
+                if (s % kM2LBWaves == W) {
+                    if (c == j) return want_rt ? rt : ks;
+                    ++c;
+                }
+                ++s;
+            }
+    return 0;
+}
+
+__device__ __forceinline__ void bf16_split3(float x, __bf16 &x0, __bf16 &x1, __bf16 &x2)
+{
+    x0 = (__bf16)x;
+    const float r1 = x - (float)x0;
+    x1 = (__bf16)r1;
+    x2 = (__bf16)(r1 - (float)x1);
+}
+
+template <int P, int NP, int W>
+__device__ __forceinline__ void m2lb_tile(const int32_t *__restrict__ tile_rng, const int32_t *__restrict__ ent_key,
+                                          const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys,
+                                          const float *__restrict__ Dtab, const float *__restrict__ Qr, int qpad,
+                                          int64_t C, M2LCols cols, int tile, __bf16 *s_D, __bf16 *s_Q,
+                                          Mfma<float>::v4 (&acc)[m2l_nrt(P)])
+{
+    using v4 = Mfma<float>::v4;
+    constexpr int NR = nr_of(P), NROW = m2l_nrows(P), ND = nd_of(P), KSTR = m2lb_kstr(P), DSTR = ND + 1;
+    constexpr int NT = 64 * kM2LBWaves, NS = m2lb_wave_steps(P, W);
+    static_assert(NT % 16 == 0, "16 columns");
+    constexpr int TPC = NT / 16;  // staging threads per column
+    constexpr int QREG = (NR + TPC - 1) / TPC, DREG = (ND + NT - 1) / NT;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int tcol = tid / TPC, tn = tid % TPC;
+    const int tslot = tcol / cols.fpt, field = cols.f0 + tcol % cols.fpt;
+    // A-operand table indices of this lane, per step (the zero slot ND outside |n| + |m| <= P)
+    int didx[NS > 0 ? NS : 1][8];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const int rt = m2lb_step(P, W, j, true), ks = m2lb_step(P, W, j, false);
+        const int m = 16 * rt + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int n = 1 + 32 * ks + 8 * (lane >> 4) + i;
+            int di = ND;
+            if (m < NROW && n < NR && c_red.r[m][3] + c_red.r[n][3] <= P)
+                di = didx_of(c_red.r[m][0] + c_red.r[n][0], c_red.r[m][1] + c_red.r[n][1], c_red.r[m][2] + c_red.r[n][2]);
+            didx[j][i] = di;
+        }
+    }
+    const int e0 = tile_rng[2 * tile], e1 = tile_rng[2 * tile + 1];
+    float pq[QREG], pd[DREG];
+    int pdl = 0, qdeg[QREG];
+#pragma unroll
+    for (int j = 0; j < QREG; ++j) qdeg[j] = rdeg(tn + TPC * j);
+    auto fetch = [&](int e) {
+        const int key = ent_key[e];
+        pdl = keys[4 * key];
+#pragma unroll
+        for (int j = 0; j < DREG; ++j) {
+            const int k = tid + NT * j;
+            pd[j] = k < ND ? Dtab[(int64_t)key * ND + k] : 0.0f;
+        }
+        const int src = field < cols.F ? ent_src[(int64_t)e * cols.tpt + tslot] : -1;
+        const float *q = Qr + ((int64_t)(src >= 0 ? field : 0) * C + (src >= 0 ? src : 0)) * qpad;
+#pragma unroll
+        for (int j = 0; j < QREG; ++j) {
+            const int n = tn + TPC * j;
+            pq[j] = (src >= 0 && n < NR) ? q[n] : 0.0f;
+        }
+    };
+    auto store = [&](int buf) {
+        __bf16 *D = s_D + buf * 3 * DSTR;
+#pragma unroll
+        for (int j = 0; j < DREG; ++j) {
+            const int k = tid + NT * j;
+            if (k < ND) bf16_split3(pd[j], D[k], D[DSTR + k], D[2 * DSTR + k]);
+        }
+        __bf16 *Qb = s_Q + buf * 3 * 16 * KSTR + tcol * KSTR;
+#pragma unroll
+        for (int j = 0; j < QREG; ++j) {
+            const int n = tn + TPC * j;
+            if (n >= 1 && n < NR)  // column n is stored at n - 1
+                bf16_split3(ldexpf(pq[j], -pdl * qdeg[j]), Qb[n - 1], Qb[16 * KSTR + n - 1], Qb[32 * KSTR + n - 1]);
+        }
+    };
+    if (e0 >= e1) return;
+    fetch(e0);
+    store(0);
+    __syncthreads();
+    for (int e = e0; e < e1; ++e) {
+        const int buf = (e - e0) & 1;
+        if (e + 1 < e1) fetch(e + 1);
+        const __bf16 *D = s_D + buf * 3 * DSTR;
+        const __bf16 *Qb = s_Q + buf * 3 * 16 * KSTR + (lane & 15) * KSTR + 8 * (lane >> 4);
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const int rt = m2lb_step(P, W, j, true), ks = m2lb_step(P, W, j, false);
+            bf16x8 a[NP], b[NP];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                b[q] = *reinterpret_cast<const bf16x8 *>(Qb + q * 16 * KSTR + 32 * ks);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) a[q][i] = D[q * DSTR + didx[j][i]];
+            }
+            // smallest terms first
+            if constexpr (NP == 3) {
+                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], acc[rt], 0, 0, 0);
+                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], acc[rt], 0, 0, 0);
+                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], acc[rt], 0, 0, 0);
+            }
+            acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], acc[rt], 0, 0, 0);
+            acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], acc[rt], 0, 0, 0);
+            acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], acc[rt], 0, 0, 0);
+        }
+        if (e + 1 < e1) store(buf ^ 1);
+        __syncthreads();
+    }
+}
+
+template <int P, int NP>
+__global__ __launch_bounds__(64 * kM2LBWaves, 2) void k_m2l_bf16(
+    const int32_t *__restrict__ tile_tgt, const int32_t *__restrict__ tile_rng, const int32_t *__restrict__ ent_key,
+    const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys, const float *__restrict__ Dtab,
+    const float *__restrict__ Qr, int qpad, const int32_t *__restrict__ cell_i, double side, int64_t C, int tpt, int fpt,
+    int F, int ntiles, double *__restrict__ L)
+{
+    using v4 = Mfma<float>::v4;
+    constexpr int NC = ncoef_of(P), NROW = m2l_nrows(P), ND = nd_of(P), NRT = m2l_nrt(P), KSTR = m2lb_kstr(P);
+    constexpr int RSTR = NROW + 1;  // reduction buffer row stride (doubles)
+    static_assert(kM2LBWaves == 2, "wave specialisation below");
+    static_assert(16 * RSTR * sizeof(double) <= 2 * 3 * 16 * KSTR * sizeof(__bf16), "reduction buffer fits");
+    __shared__ __bf16 s_D[2 * 3 * (ND + 1)];
+    __shared__ __align__(16) __bf16 s_Q[2 * 3 * 16 * KSTR];
+    const int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const M2LCols cols{tpt, fpt, (int)blockIdx.y * fpt, F};
+    for (int i = tid; i < 2 * 3 * 16 * KSTR; i += blockDim.x) s_Q[i] = (__bf16)0.0f;  // padding stays zero
+    for (int i = tid; i < 2 * 3 * (ND + 1); i += blockDim.x) s_D[i] = (__bf16)0.0f;   // zero slots
+    __syncthreads();
+    v4 acc[NRT];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt) acc[rt] = v4{0, 0, 0, 0};
+    if (wave == 0)
+        m2lb_tile<P, NP, 0>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc);
+    else
+        m2lb_tile<P, NP, 1>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc);
+    __syncthreads();
+    double *red = reinterpret_cast<double *>(s_Q);
+    for (int i = tid; i < 16 * RSTR; i += blockDim.x) red[i] = 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = 16 * rt + Mfma<float>::row(lane, r);
+            if (m < NROW) atomicAdd(&red[(lane & 15) * RSTR + m], (double)acc[rt][r]);
+        }
+    __syncthreads();
+    for (int i = tid; i < 16 * NC; i += blockDim.x) {
+        const int c = i / NC, m = i - c * NC;
+        const int field = cols.f0 + c % fpt;
+        const int A = tile_tgt[tile * tpt + c / fpt];
+        if (A < 0 || field >= F) continue;
+        const int mx = c_mi.v[m][0], my = c_mi.v[m][1], mz = c_mi.v[m][2], dm = c_mi.v[m][3];
+        double lt = 0.0;
+        if (dm < P) {
+            const int j = mz >> 1, cz = mz & 1;
+            for (int k = 0; k <= j; ++k) lt += c_bin.c[j][k] * red[c * RSTR + ridx(mx + 2 * k, my + 2 * (j - k), cz)];
+            if (j & 1) lt = -lt;
+        }
+        const double is = 1.0 / ldexp(side, -cell_i[CI_N * A + CI_LEVEL]);
+        double sp = is;
+        for (int k = 0; k < dm; ++k) sp *= is;
+        atomicAdd(&L[((int64_t)field * C + A) * NC + m],
+                  lt * kInv4Pi * sp * c_bin.invfact[mx] * c_bin.invfact[my] * c_bin.invfact[mz]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // L2P.  One thread per target (octree order); writes u[f][perm[i]].
 //   u(x) = sum_m l_m (x - c)^m
 // ---------------------------------------------------------------------------
@@ -1391,6 +1613,37 @@ void launch_m2l_p(DevicePlan &dp, const DevicePlan::Tiles &tl, const T *D, const
     hip_check(hipGetLastError(), "k_m2l_mfma launch");
 }
 
+template <int P, int NP>
+void launch_m2lb_p(DevicePlan &dp, const DevicePlan::Tiles &tl, const float *D, const float *Qt, int fpt, int32_t F,
+                   hipStream_t st)
+{
+    const HostPlan &hp = dp.hp;
+    const unsigned groups = (unsigned)((F + fpt - 1) / fpt);
+    k_m2l_bf16<P, NP><<<dim3(tl.ntiles, groups), dim3(64 * kM2LBWaves), 0, st>>>(
+        tl.tile_tgt, tl.tile_rng, tl.ent_key, tl.ent_src, dp.m2l_keys, D, Qt, dp.qpad, dp.cell_i, hp.side,
+        (int64_t)hp.cells.size(), tl.tpt, fpt, F, tl.ntiles, dp.L);
+    hip_check(hipGetLastError(), "k_m2l_bf16 launch");
+}
+
+template <int NP>
+void launch_m2lb_t(DevicePlan &dp, const DevicePlan::Tiles &tl, const float *D, const float *Qt, int fpt, int32_t F,
+                   hipStream_t st)
+{
+    switch (dp.hp.p) {
+    case 1: launch_m2lb_p<1, NP>(dp, tl, D, Qt, fpt, F, st); break;
+    case 2: launch_m2lb_p<2, NP>(dp, tl, D, Qt, fpt, F, st); break;
+    case 3: launch_m2lb_p<3, NP>(dp, tl, D, Qt, fpt, F, st); break;
+    case 4: launch_m2lb_p<4, NP>(dp, tl, D, Qt, fpt, F, st); break;
+    case 5: launch_m2lb_p<5, NP>(dp, tl, D, Qt, fpt, F, st); break;
+    case 6: launch_m2lb_p<6, NP>(dp, tl, D, Qt, fpt, F, st); break;
+    case 7: launch_m2lb_p<7, NP>(dp, tl, D, Qt, fpt, F, st); break;
+    case 8: launch_m2lb_p<8, NP>(dp, tl, D, Qt, fpt, F, st); break;
+    case 9: launch_m2lb_p<9, NP>(dp, tl, D, Qt, fpt, F, st); break;
+    case 10: launch_m2lb_p<10, NP>(dp, tl, D, Qt, fpt, F, st); break;
+    default: throw DeviceError{"unsupported expansion order"};
+    }
+}
+
 template <typename T>
 void launch_m2l_t(DevicePlan &dp, const DevicePlan::Tiles &tl, const T *D, const T *Qt, int fpt, int32_t F,
                   hipStream_t st)
@@ -1421,7 +1674,7 @@ void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
     if (tl.ntiles == 0) return;
     const int64_t nq = C * dp.qpad;
     const dim3 qgrid((unsigned)((nq + 255) / 256), F);
-    if (dp.m2l_precision == TFMM_M2L_FP32) {
+    if (dp.m2l_precision != TFMM_M2L_FP64) {  // FP32 operands (FP32, BF16x3, BF16x6)
         if (!dp.m2l_Df) {
             const int64_t n = (int64_t)dp.n_m2l_keys * nd_of(hp.p);
             hip_check(hipMalloc(&dp.m2l_Df, sizeof(float) * std::max<int64_t>(n, 1)), "hipMalloc M2L table f32");
@@ -1438,7 +1691,12 @@ void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
         }
         k_qreduce<float><<<qgrid, dim3(256), 0, st>>>(dp.Q, dp.cell_i, C, hp.side, hp.p, dp.qpad, dp.Qtf);
         hip_check(hipGetLastError(), "k_qreduce launch");
-        launch_m2l_t<float>(dp, tl, dp.m2l_Df, dp.Qtf, fpt, F, st);
+        if (dp.m2l_precision == TFMM_M2L_BF16X3)
+            launch_m2lb_t<2>(dp, tl, dp.m2l_Df, dp.Qtf, fpt, F, st);
+        else if (dp.m2l_precision == TFMM_M2L_BF16X6)
+            launch_m2lb_t<3>(dp, tl, dp.m2l_Df, dp.Qtf, fpt, F, st);
+        else
+            launch_m2l_t<float>(dp, tl, dp.m2l_Df, dp.Qtf, fpt, F, st);
     } else {
         if (dp.qt_cap < F) {
             if (dp.Qt) (void)hipFree(dp.Qt);

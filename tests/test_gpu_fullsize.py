@@ -5,7 +5,7 @@ oracle evaluates them one by one), and every form is compared with the FP64
 direct sum on sampled targets (a plan whose explicit targets are the sample).
 Configurations: the 40^3 cube (384,000 tets, p=8, leaf 64), the 512x512x4
 film (6.29M tets, vortex field, FP32 M2L), 64 random fields on the 64^3 cube
-(1.57M tets) and the jittered sphere of radius 1 on a 96^3 grid (~2.78M
+(1.57M tets, split-BF16 M2L) and the jittered sphere of radius 1 on a 96^3 grid (~2.78M
 tets, uniform M).
 """
 import sys
@@ -103,12 +103,12 @@ def test_film_oracle_parity_and_full_film_accuracy(torch_dev, orc):
     assert _rel(u32, u64) <= 1e-6
 
 
-def test_cube64_64_fields_fp32(torch_dev):
+def test_cube64_64_fields_bf16x3(torch_dev):
     nodes, tets = meshgen.box_mesh(64, seed=0)
     F = 64
     M = meshgen.random_fields(nodes.shape[0], F=F, seed=1)
-    _say("cube64 x 64 fields fp32 m2l vs direct (sampled)", tets.shape)
-    P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=64, theta=CUBE64_THETA, m2l_precision=T.M2L_FP32)
+    _say("cube64 x 64 fields bf16x3 m2l vs direct (sampled)", tets.shape)
+    P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=64, theta=CUBE64_THETA, m2l_precision=T.M2L_BF16X3)
     u = _eval(torch_dev, P, M)
     del P
     idx = _sample(nodes.shape[0], 256, 5)

@@ -114,6 +114,24 @@ def test_fp32_m2l_accuracy(torch_dev, orc):
         assert e32 <= e64 + 1e-6
 
 
+@pytest.mark.parametrize("prec,tol64", [(T.M2L_BF16X3, 5e-6), (T.M2L_BF16X6, 2e-6)])
+def test_bf16_split_m2l_accuracy(torch_dev, prec, tol64):
+    """Split-BF16 M2L (3 or 6 part products, FP32 accumulation): close to the
+    FP64 FMM, and its error against the direct sum stays within a few 1e-6 of
+    the FP64 FMM's own."""
+    nodes, tets = meshgen.box_mesh(12, seed=13)
+    M = meshgen.random_fields(nodes.shape[0], F=3, seed=15)
+    _say("bf16 split m2l", prec)
+    P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=16, theta=0.5)
+    u64 = _run(torch_dev, P, M)
+    ud = _run(torch_dev, P, M, direct=True)
+    T.tfmm_plan_set_m2l_precision(P, prec)
+    ub = _run(torch_dev, P, M)
+    for f in range(3):
+        assert _rel(ub[f], u64[f]) <= tol64
+        assert _rel(ub[f], ud[f]) <= _rel(u64[f], ud[f]) + 5e-6
+
+
 def test_expansions_match_oracle(torch_dev, orc):
     """Stage parity: multipole (P2M + M2M) and local (M2L + L2L) coefficients per cell."""
     nodes, tets = meshgen.box_mesh(6, seed=8)
