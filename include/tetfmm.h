@@ -56,6 +56,7 @@ extern "C" {
 #define TFMM_M2L_BF16X6 3 /* as BF16X3 with 6 part products (about FP32 accuracy) */
 
 typedef struct tfmm_plan_s *tfmm_plan; /* opaque, owned by the library */
+typedef struct tfmm_batch_s *tfmm_batch; /* opaque, owned by the library */
 
 /*
  * Parameters of the method.
@@ -197,6 +198,48 @@ const char *tfmm_last_error(void);
  */
 int tfmm_set_timing(tfmm_plan plan, int32_t on);
 int tfmm_kernel_times(tfmm_plan plan, double *ms /* [6] */, int64_t *launches /* [6] */);
+
+/*
+ * Schedule tuning.  Times evaluations of one (synthetic) field on hip_stream
+ * for a few choices of the M2L work item size (keys per workgroup) and of the
+ * P2P workgroup shape, and keeps the fastest; the arithmetic, and so every
+ * result, is the same for all choices.  Synchronises the stream; allocates
+ * and frees scratch device memory for one field.
+ * Errors: TFMM_EINVAL (NULL or host-only plan), TFMM_EDEVICE.
+ */
+int tfmm_plan_autotune(tfmm_plan plan, void *hip_stream);
+
+/*
+ * Ragged batches of meshes (one field each).  tfmm_batch_create builds one
+ * plan per mesh i from nodes[i] ([n_nodes[i]][3], host) and tets[i]
+ * ([n_tets[i]][4], host), targets = the nodes, all with the parameters prm
+ * (prm->device >= 0).  The caller may free its arrays on return.
+ * Errors: as tfmm_plan_create (the message names the mesh), TFMM_EINVAL for
+ * n_meshes < 1, NULL arrays or a host-only device.
+ */
+int tfmm_batch_create(int32_t n_meshes, const double *const *nodes, const int64_t *n_nodes,
+                      const int32_t *const *tets, const int64_t *n_tets, const tfmm_params *prm, tfmm_batch *out);
+
+/*
+ * Evaluate every mesh of the batch: M[i] device [n_nodes_i][3] FP64 nodal
+ * magnetisation, u[i] device [n_nodes_i] FP64 output (written, not added
+ * to).  The whole sequence of launches is captured once into a HIP graph
+ * (on an internal stream) and replayed on hip_stream while the M and u
+ * pointers and the plans' precision and schedule stay the same; a change
+ * re-captures.  Asynchronous like tfmm_evaluate.  With kernel timing enabled
+ * on any plan the launches run eagerly instead.
+ * Errors: TFMM_EINVAL (NULL arguments), TFMM_EDEVICE.
+ */
+int tfmm_batch_evaluate(tfmm_batch batch, const double *const *M, double *const *u, void *hip_stream);
+
+/* Tune every plan of the batch (tfmm_plan_autotune) and drop its graph. */
+int tfmm_batch_autotune(tfmm_batch batch, void *hip_stream);
+
+/* Plan of mesh i (owned by the batch: do not destroy it). */
+int tfmm_batch_plan(tfmm_batch batch, int32_t i, tfmm_plan *out);
+
+/* Destroy the batch, its plans and its graph.  NULL is accepted. */
+int tfmm_batch_destroy(tfmm_batch batch);
 
 #ifdef __cplusplus
 }

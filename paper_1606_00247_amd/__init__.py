@@ -18,6 +18,8 @@ __all__ = [
     "tfmm_direct_host", "tfmm_plan_stats", "tfmm_plan_lists", "tfmm_plan_cells", "tfmm_plan_expansions",
     "tfmm_plan_destroy", "tfmm_last_error", "tfmm_simplex_rule", "tfmm_set_timing", "tfmm_kernel_times",
     "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS", "tfmm_plan_set_m2l_precision", "M2L_FP64", "M2L_FP32", "M2L_BF16X3", "M2L_BF16X6",
+    "tfmm_plan_autotune", "tfmm_batch_create", "tfmm_batch_evaluate", "tfmm_batch_autotune", "tfmm_batch_plan",
+    "tfmm_batch_destroy", "Batch",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -83,6 +85,13 @@ def _load():
         "tfmm_simplex_rule": (C.c_int, [C.c_int32, _dp, _i32p]),
         "tfmm_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
         "tfmm_kernel_times": (C.c_int, [C.c_void_p, _dp, _i64p]),
+        "tfmm_plan_autotune": (C.c_int, [C.c_void_p, C.c_void_p]),
+        "tfmm_batch_create": (C.c_int, [C.c_int32, C.POINTER(_dp), _i64p, C.POINTER(_i32p), _i64p,
+                                        C.POINTER(_Params), C.POINTER(C.c_void_p)]),
+        "tfmm_batch_evaluate": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
+        "tfmm_batch_autotune": (C.c_int, [C.c_void_p, C.c_void_p]),
+        "tfmm_batch_plan": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+        "tfmm_batch_destroy": (C.c_int, [C.c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -203,6 +212,101 @@ def tfmm_evaluate_host(plan, M):
 
 def tfmm_direct_host(plan, M):
     return _host_call(_load().tfmm_direct_host, plan, M)
+
+
+def tfmm_plan_autotune(plan, stream=None):
+    """Pick the plan's schedule (M2L work item size, P2P workgroup shape) by timing."""
+    import torch
+    dev = torch.device("cuda", plan.device)
+    _check(_load().tfmm_plan_autotune(plan.handle, _stream_handle(stream, dev)))
+
+
+class _BorrowedPlan(Plan):
+    """A plan owned by a batch (not destroyed with this object)."""
+
+    def __del__(self):
+        pass
+
+
+class Batch:
+    """Owns a tfmm_batch handle: one plan per mesh, one field each."""
+
+    def __init__(self, handle, device, sizes, params):
+        self._h = C.c_void_p(handle)
+        self.device = device
+        self.sizes = sizes  # [(n_nodes, n_tets)]
+        self.params = params
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("batch was destroyed")
+        return self._h
+
+    def __len__(self):
+        return len(self.sizes)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.tfmm_batch_destroy(h)
+            self._h = None
+
+
+def tfmm_batch_create(meshes, p=8, leaf_size=64, theta=0.5, m2l_precision=0, device=0):
+    """meshes: sequence of (nodes [N_i, 3], tets [T_i, 4]) host arrays."""
+    lib = _load()
+    nodes = [np.ascontiguousarray(m[0], dtype=np.float64) for m in meshes]
+    tets = [np.ascontiguousarray(m[1], dtype=np.int32) for m in meshes]
+    n = len(nodes)
+    NP = (_dp * n)(*[_ptr(a, _dp) for a in nodes])
+    TP = (_i32p * n)(*[_ptr(a, _i32p) for a in tets])
+    nn = np.array([a.shape[0] for a in nodes], dtype=np.int64)
+    nt = np.array([a.shape[0] for a in tets], dtype=np.int64)
+    prm = _Params(int(p), int(leaf_size), float(theta), int(m2l_precision), int(device))
+    h = C.c_void_p()
+    _check(lib.tfmm_batch_create(n, NP, _ptr(nn, _i64p), TP, _ptr(nt, _i64p), C.byref(prm), C.byref(h)))
+    return Batch(h.value, int(device), list(zip(nn.tolist(), nt.tolist())),
+                 dict(p=int(p), leaf_size=int(leaf_size), theta=float(theta), m2l_precision=int(m2l_precision)))
+
+
+def tfmm_batch_evaluate(batch, M, u=None, stream=None):
+    """M: list of contiguous float64 CUDA tensors [n_nodes_i, 3]; returns the list u of [n_nodes_i]."""
+    import torch
+    if len(M) != len(batch):
+        raise ValueError("one M per mesh")
+    if u is None:
+        u = [torch.empty(n_i, dtype=torch.float64, device=m.device) for (n_i, _), m in zip(batch.sizes, M)]
+    for (n_i, _), m, ui in zip(batch.sizes, M, u):
+        if not (isinstance(m, torch.Tensor) and m.is_cuda and m.dtype == torch.float64 and m.is_contiguous()
+                and tuple(m.shape) == (n_i, 3) and m.device.index == batch.device):
+            raise ValueError("each M must be a contiguous float64 CUDA tensor [n_nodes_i, 3] on the batch's device")
+        if not (ui.is_cuda and ui.dtype == torch.float64 and ui.is_contiguous() and ui.numel() == n_i):
+            raise ValueError("each u must be a contiguous float64 CUDA tensor of n_nodes_i elements")
+    n = len(M)
+    MP = (C.c_void_p * n)(*[C.c_void_p(m.data_ptr()) for m in M])
+    UP = (C.c_void_p * n)(*[C.c_void_p(x.data_ptr()) for x in u])
+    _check(_load().tfmm_batch_evaluate(batch.handle, MP, UP, _stream_handle(stream, M[0].device)))
+    return u
+
+
+def tfmm_batch_autotune(batch, stream=None):
+    import torch
+    _check(_load().tfmm_batch_autotune(batch.handle, _stream_handle(stream, torch.device("cuda", batch.device))))
+
+
+def tfmm_batch_plan(batch, i):
+    """The plan of mesh i (owned by the batch)."""
+    h = C.c_void_p()
+    _check(_load().tfmm_batch_plan(batch.handle, int(i), C.byref(h)))
+    n_nodes = batch.sizes[i][0]
+    return _BorrowedPlan(h.value, batch.device, n_nodes, n_nodes, dict(batch.params))
+
+
+def tfmm_batch_destroy(batch):
+    if batch._h is not None:
+        _check(_load().tfmm_batch_destroy(batch._h))
+        batch._h = None
 
 
 def tfmm_plan_stats(plan):

@@ -20,6 +20,20 @@ struct tfmm_plan_s {
     bool on_device = false;
 };
 
+// A batch: one plan per mesh and the HIP graph of one evaluation of all of
+// them, captured on an internal stream for the M and u pointers it was made
+// with and replayed while they stay the same.
+struct tfmm_batch_s {
+    std::vector<tfmm_plan> plans;
+    int device = 0;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const double *> keyM;
+    std::vector<double *> keyU;
+    std::vector<uint64_t> keyGen;
+};
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -444,6 +458,7 @@ int tfmm_plan_set_m2l_precision(tfmm_plan plan, int32_t m2l_precision)
     if (m2l_precision < TFMM_M2L_FP64 || m2l_precision > TFMM_M2L_BF16X6)
         return set_error(TFMM_ENOTSUP, "unsupported m2l_precision");
     plan->dp.m2l_precision = m2l_precision;
+    ++plan->dp.schedule_gen;
     return TFMM_OK;
 }
 
@@ -488,6 +503,149 @@ int tfmm_kernel_times(tfmm_plan plan, double *ms, int64_t *launches)
         ms[i] = plan->dp.kt_n[i] ? plan->dp.kt_ms[i] / (double)plan->dp.kt_n[i] : 0.0;
         launches[i] = plan->dp.kt_n[i];
     }
+    return TFMM_OK;
+}
+
+int tfmm_plan_autotune(tfmm_plan plan, void *hip_stream)
+{
+    if (!plan) return set_error(TFMM_EINVAL, "NULL plan");
+    if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan cannot be tuned");
+    return guarded([&]() -> int {
+        DeviceScope ds(plan->dp.device);
+        tfmm::autotune(plan->dp, (hipStream_t)hip_stream);
+        return TFMM_OK;
+    });
+}
+
+static void batch_drop_graph(tfmm_batch b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->keyM.clear();
+    b->keyU.clear();
+    b->keyGen.clear();
+}
+
+int tfmm_batch_destroy(tfmm_batch batch)
+{
+    if (!batch) return TFMM_OK;
+    return guarded([&]() -> int {
+        {
+            DeviceScope ds(batch->device);
+            batch_drop_graph(batch);
+            if (batch->capture) (void)hipStreamDestroy(batch->capture);
+        }
+        int rc = TFMM_OK;
+        for (tfmm_plan p : batch->plans) {
+            const int r = tfmm_plan_destroy(p);
+            if (r && !rc) rc = r;
+        }
+        delete batch;
+        return rc;
+    });
+}
+
+int tfmm_batch_create(int32_t n_meshes, const double *const *nodes, const int64_t *n_nodes, const int32_t *const *tets,
+                      const int64_t *n_tets, const tfmm_params *prm, tfmm_batch *out)
+{
+    if (out) *out = nullptr;
+    if (!out || !prm || n_meshes < 1 || !nodes || !n_nodes || !tets || !n_tets)
+        return set_error(TFMM_EINVAL, "n_meshes >= 1 and non-NULL arrays required");
+    if (prm->device < 0) return set_error(TFMM_EINVAL, "a batch needs a device");
+    tfmm_batch b = nullptr;
+    int rc = guarded([&]() -> int {
+        b = new tfmm_batch_s();
+        b->device = prm->device;
+        return TFMM_OK;
+    });
+    if (rc) return rc;
+    for (int32_t i = 0; i < n_meshes; ++i) {
+        tfmm_plan p = nullptr;
+        rc = tfmm_plan_create(nodes[i], n_nodes[i], tets[i], n_tets[i], nullptr, 0, prm, &p);
+        if (rc) {
+            const std::string msg = "mesh " + std::to_string(i) + ": " + g_last_error;
+            (void)tfmm_batch_destroy(b);
+            return set_error(rc, msg);
+        }
+        b->plans.push_back(p);
+    }
+    rc = guarded([&]() -> int {
+        DeviceScope ds(b->device);
+        tfmm::hip_check(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "hipStreamCreate");
+        return TFMM_OK;
+    });
+    if (rc) {
+        (void)tfmm_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return TFMM_OK;
+}
+
+int tfmm_batch_evaluate(tfmm_batch batch, const double *const *M, double *const *u, void *hip_stream)
+{
+    if (!batch || !M || !u) return set_error(TFMM_EINVAL, "NULL argument");
+    const size_t n = batch->plans.size();
+    for (size_t i = 0; i < n; ++i)
+        if (!M[i] || !u[i]) return set_error(TFMM_EINVAL, "NULL M or u of mesh " + std::to_string(i));
+    return guarded([&]() -> int {
+        DeviceScope ds(batch->device);
+        hipStream_t st = (hipStream_t)hip_stream;
+        bool timing = false;
+        for (tfmm_plan p : batch->plans) timing = timing || p->dp.timing;
+        if (timing) {  // per-phase events cannot live in a graph: run eagerly
+            for (size_t i = 0; i < n; ++i) tfmm::run_evaluate(batch->plans[i]->dp, M[i], 1, u[i], st);
+            return TFMM_OK;
+        }
+        std::vector<uint64_t> gen(n);
+        for (size_t i = 0; i < n; ++i) gen[i] = batch->plans[i]->dp.schedule_gen;
+        const bool same = batch->exec && std::equal(batch->keyM.begin(), batch->keyM.end(), M) &&
+                          std::equal(batch->keyU.begin(), batch->keyU.end(), u) && gen == batch->keyGen;
+        if (!same) {
+            batch_drop_graph(batch);
+            for (tfmm_plan p : batch->plans) tfmm::prepare_evaluate(p->dp, 1);
+            tfmm::hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+            tfmm::hip_check(hipStreamBeginCapture(batch->capture, hipStreamCaptureModeThreadLocal),
+                            "hipStreamBeginCapture");
+            try {
+                for (size_t i = 0; i < n; ++i) tfmm::run_evaluate(batch->plans[i]->dp, M[i], 1, u[i], batch->capture);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(batch->capture, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            tfmm::hip_check(hipStreamEndCapture(batch->capture, &batch->graph), "hipStreamEndCapture");
+            tfmm::hip_check(hipGraphInstantiate(&batch->exec, batch->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+            batch->keyM.assign(M, M + n);
+            batch->keyU.assign(u, u + n);
+            batch->keyGen = gen;
+        }
+        tfmm::hip_check(hipGraphLaunch(batch->exec, st), "hipGraphLaunch");
+        return TFMM_OK;
+    });
+}
+
+int tfmm_batch_autotune(tfmm_batch batch, void *hip_stream)
+{
+    if (!batch) return set_error(TFMM_EINVAL, "NULL batch");
+    for (tfmm_plan p : batch->plans) {
+        const int rc = tfmm_plan_autotune(p, hip_stream);
+        if (rc) return rc;
+    }
+    return guarded([&]() -> int {
+        DeviceScope ds(batch->device);
+        batch_drop_graph(batch);
+        return TFMM_OK;
+    });
+}
+
+int tfmm_batch_plan(tfmm_batch batch, int32_t i, tfmm_plan *out)
+{
+    if (!batch || !out || i < 0 || (size_t)i >= batch->plans.size()) return set_error(TFMM_EINVAL, "bad batch index");
+    *out = batch->plans[i];
     return TFMM_OK;
 }
 

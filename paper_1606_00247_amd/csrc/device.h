@@ -57,13 +57,20 @@ struct DevicePlan {
     int32_t n_m2l_keys = 0;
     // target tiles of 16, 8, 4, 2, 1 cells (built on demand; 16 / tpt fields per tile)
     struct Tiles {
-        int tpt = 0;
+        int tpt = 0, max_ent = 0;
         int32_t *tile_tgt = nullptr, *tile_rng = nullptr, *ent_key = nullptr, *ent_src = nullptr;
         int32_t ntiles = 0;
         int64_t nent = 0;
     };
     Tiles m2l_tiles[5];
     int m2l_precision = 0;  // TFMM_M2L_*
+    // schedule knobs (tfmm_plan_autotune): keys per M2L work item, and four
+    // wavefronts per P2P workgroup also for one or two fields
+    int m2l_max_ent = 256;
+    bool p2p_wide = false;
+    // bumped whenever the launch sequence of an evaluation may change
+    // (precision, schedule), so that captured graphs are rebuilt
+    uint64_t schedule_gen = 0;
     // scaled multipoles Qt_n = (-1)^|n| Q_n / (n! s^|n|): [Fcap][C][qpad] (FP64 or FP32)
     double *Qt = nullptr;
     float *Qtf = nullptr;
@@ -115,6 +122,11 @@ void build_m2l_table(DevicePlan &dp);
 // Tiles of tpt target cells (16, 8, 4, 2 or 1), built and uploaded once.
 DevicePlan::Tiles &ensure_m2l_tiles(DevicePlan &dp, int tpt);
 
+// Allocate everything an evaluation of F fields needs (expansions, M2L tiles
+// and operand buffers), so that a later run_evaluate allocates nothing.
+void prepare_evaluate(DevicePlan &dp, int32_t F);
+// Pick the schedule knobs by timing evaluations on `stream` (synchronises).
+void autotune(DevicePlan &dp, hipStream_t stream);
 // Queue the FMM evaluation of F fields on `stream`.
 void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t stream);
 // Queue the O(N^2) direct sum of F fields on `stream`.

@@ -449,9 +449,7 @@ __global__ __launch_bounds__(kShiftThreads) void k_l2l(const int32_t *__restrict
 }
 
 constexpr int kM2LWaves = 4;
-// entries per M2L work item: a tile's keys are cut into pieces of this many,
-// so that the workgroups of one launch fill the chip evenly
-constexpr int kM2LMaxEntries = 256;
+
 
 // The two matrix-core shapes used by M2L: 16x16x4 with FP64 or FP32 operands.
 // A (16 x 4): lane l holds row l%16, column l/16; B (4 x 16): lane l holds
@@ -1448,18 +1446,22 @@ __device__ __forceinline__ void pair_accumulate(const double x[3], const TetGeom
 // 240 B + 208 B per field per tet); every thread then takes targets
 // ib + l, ib + l + NT, ... over the staged tets and adds its potentials
 // atomically.
-__host__ __device__ constexpr int p2p_threads(int FCH) { return FCH <= 2 ? 64 : 256; }
-__host__ __device__ constexpr int p2p_stage(int FCH) { return FCH <= 2 ? 16 : (FCH >= 16 ? 16 : (FCH >= 8 ? 32 : 64)); }
+// WIDE: four wavefronts also for one or two fields (a plan's tuning choice).
+__host__ __device__ constexpr int p2p_threads(int FCH, bool wide) { return FCH <= 2 && !wide ? 64 : 256; }
+__host__ __device__ constexpr int p2p_stage(int FCH, bool wide)
+{
+    return FCH <= 2 ? (wide ? 64 / FCH : 16) : (FCH >= 16 ? 16 : (FCH >= 8 ? 32 : 64));
+}
 
-template <int FCH>
-__global__ __launch_bounds__(p2p_threads(FCH), 2) void k_p2p(const int32_t *__restrict__ blk, int nblk, int direct_tets, int64_t T,
+template <int FCH, bool WIDE>
+__global__ __launch_bounds__(p2p_threads(FCH, WIDE), 2) void k_p2p(const int32_t *__restrict__ blk, int nblk, int direct_tets, int64_t T,
                                                      const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node,
                                                      const int32_t *__restrict__ idx, const double *__restrict__ tgt_xyz,
                                                      const int32_t *__restrict__ tgt_perm, int64_t N,
                                                      const double *__restrict__ M, int64_t n_nodes, int f0,
                                                      double *__restrict__ u)
 {
-    constexpr int BT = p2p_stage(FCH), NT = p2p_threads(FCH);
+    constexpr int BT = p2p_stage(FCH, WIDE), NT = p2p_threads(FCH, WIDE);
     static_assert(BT * FCH <= NT, "one thread per staged tet and field");
     __shared__ TetGeom s_g[BT];
     __shared__ TetField s_f[BT][FCH];
@@ -1565,16 +1567,25 @@ void fill(double *a, int64_t n, double v, hipStream_t st)
     hip_check(hipGetLastError(), "k_fill launch");
 }
 
-template <int FCH>
-void launch_p2p(DevicePlan &dp, bool direct, int f0, const double *M, double *u, hipStream_t st)
+template <int FCH, bool WIDE>
+void launch_p2p_w(DevicePlan &dp, bool direct, int f0, const double *M, double *u, hipStream_t st)
 {
     const HostPlan &hp = dp.hp;
     unsigned nblk = direct ? (unsigned)((hp.n_tets + kP2PTets - 1) / kP2PTets) : (unsigned)dp.n_p2p_blk;
     if (nblk == 0) return;
-    k_p2p<FCH><<<dim3(xcd_grid((int)nblk)), dim3(p2p_threads(FCH)), 0, st>>>(dp.p2p_blk, (int)nblk, direct ? 1 : 0, hp.n_tets, dp.tet_xyz,
-                                                         dp.tet_node, dp.p2p_idx, dp.tgt_xyz, dp.tgt_perm,
-                                                         hp.n_targets, M, hp.n_nodes, f0, u);
+    k_p2p<FCH, WIDE><<<dim3(xcd_grid((int)nblk)), dim3(p2p_threads(FCH, WIDE)), 0, st>>>(
+        dp.p2p_blk, (int)nblk, direct ? 1 : 0, hp.n_tets, dp.tet_xyz, dp.tet_node, dp.p2p_idx, dp.tgt_xyz, dp.tgt_perm,
+        hp.n_targets, M, hp.n_nodes, f0, u);
     hip_check(hipGetLastError(), "k_p2p launch");
+}
+
+template <int FCH>
+void launch_p2p(DevicePlan &dp, bool direct, int f0, const double *M, double *u, hipStream_t st)
+{
+    if (FCH <= 2 && dp.p2p_wide)
+        launch_p2p_w<FCH, true>(dp, direct, f0, M, u, st);
+    else
+        launch_p2p_w<FCH, false>(dp, direct, f0, M, u, st);
 }
 
 void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u, hipStream_t st)
@@ -1664,31 +1675,25 @@ void launch_m2l_t(DevicePlan &dp, const DevicePlan::Tiles &tl, const T *D, const
 }
 
 // Scaled multipoles, then the translations, in the plan's M2L precision.
+// Field tile width of M2L for F fields: FPT fields x 16/FPT target cells.
+int m2l_fpt(int32_t F)
+{
+    int fpt = 1;
+    while (fpt * 2 <= std::min<int32_t>(F, 16)) fpt *= 2;
+    return fpt;
+}
+
 void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
 {
     const HostPlan &hp = dp.hp;
     const int64_t C = (int64_t)hp.cells.size();
-    int fpt = 1;
-    while (fpt * 2 <= std::min<int32_t>(F, 16)) fpt *= 2;
+    const int fpt = m2l_fpt(F);
     const DevicePlan::Tiles &tl = ensure_m2l_tiles(dp, 16 / fpt);
     if (tl.ntiles == 0) return;
     const int64_t nq = C * dp.qpad;
     const dim3 qgrid((unsigned)((nq + 255) / 256), F);
     if (dp.m2l_precision != TFMM_M2L_FP64) {  // FP32 operands (FP32, BF16x3, BF16x6)
-        if (!dp.m2l_Df) {
-            const int64_t n = (int64_t)dp.n_m2l_keys * nd_of(hp.p);
-            hip_check(hipMalloc(&dp.m2l_Df, sizeof(float) * std::max<int64_t>(n, 1)), "hipMalloc M2L table f32");
-            k_to_float<<<dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, st>>>(dp.m2l_D, n,
-                                                                                                        dp.m2l_Df);
-            hip_check(hipGetLastError(), "k_to_float launch");
-        }
-        if (dp.qtf_cap < F) {
-            if (dp.Qtf) (void)hipFree(dp.Qtf);
-            dp.Qtf = nullptr;
-            dp.qtf_cap = 0;
-            hip_check(hipMalloc(&dp.Qtf, sizeof(float) * (size_t)F * C * dp.qpad), "hipMalloc Qt f32");
-            dp.qtf_cap = F;
-        }
+        if (!dp.m2l_Df || dp.qtf_cap < F) throw DeviceError{"M2L buffers not prepared"};
         k_qreduce<float><<<qgrid, dim3(256), 0, st>>>(dp.Q, dp.cell_i, C, hp.side, hp.p, dp.qpad, dp.Qtf);
         hip_check(hipGetLastError(), "k_qreduce launch");
         if (dp.m2l_precision == TFMM_M2L_BF16X3)
@@ -1698,13 +1703,7 @@ void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
         else
             launch_m2l_t<float>(dp, tl, dp.m2l_Df, dp.Qtf, fpt, F, st);
     } else {
-        if (dp.qt_cap < F) {
-            if (dp.Qt) (void)hipFree(dp.Qt);
-            dp.Qt = nullptr;
-            dp.qt_cap = 0;
-            hip_check(hipMalloc(&dp.Qt, sizeof(double) * (size_t)F * C * dp.qpad), "hipMalloc Qt");
-            dp.qt_cap = F;
-        }
+        if (dp.qt_cap < F) throw DeviceError{"M2L buffers not prepared"};
         k_qreduce<double><<<qgrid, dim3(256), 0, st>>>(dp.Q, dp.cell_i, C, hp.side, hp.p, dp.qpad, dp.Qt);
         hip_check(hipGetLastError(), "k_qreduce launch");
         launch_m2l_t<double>(dp, tl, dp.m2l_D, dp.Qt, fpt, F, st);
@@ -1737,9 +1736,12 @@ DevicePlan::Tiles &ensure_m2l_tiles(DevicePlan &dp, int tpt)
     while ((16 >> slot) != tpt && slot < 4) ++slot;
     if ((16 >> slot) != tpt) throw DeviceError{"bad M2L tile width"};
     DevicePlan::Tiles &t = dp.m2l_tiles[slot];
-    if (t.tpt == tpt) return t;
+    if (t.tpt == tpt && t.max_ent == dp.m2l_max_ent) return t;
+    for (int32_t *q : {t.tile_tgt, t.tile_rng, t.ent_key, t.ent_src})
+        if (q) (void)hipFree(q);
+    t = DevicePlan::Tiles{};
     M2LTiles h;
-    build_m2l_tiles(dp.hp, tpt, kM2LMaxEntries, h);
+    build_m2l_tiles(dp.hp, tpt, dp.m2l_max_ent, h);
     auto up = [&](const std::vector<int32_t> &v, int32_t *&d) {
         hip_check(hipMalloc(&d, sizeof(int32_t) * std::max<size_t>(v.size(), 1)), "hipMalloc M2L tiles");
         if (!v.empty())
@@ -1753,6 +1755,7 @@ DevicePlan::Tiles &ensure_m2l_tiles(DevicePlan &dp, int tpt)
     t.ntiles = (int32_t)(h.tile_rng.size() / 2);
     t.nent = (int64_t)h.ent_key.size();
     t.tpt = tpt;
+    t.max_ent = dp.m2l_max_ent;
     return t;
 }
 
@@ -1792,12 +1795,109 @@ void ensure_expansions(DevicePlan &dp, int32_t F)
     dp.Fcap = F;
 }
 
+void prepare_evaluate(DevicePlan &dp, int32_t F)
+{
+    const int64_t C = (int64_t)dp.hp.cells.size();
+    ensure_expansions(dp, F);
+    ensure_m2l_tiles(dp, 16 / m2l_fpt(F));
+    if (dp.m2l_precision != TFMM_M2L_FP64) {
+        if (!dp.m2l_Df) {
+            const int64_t n = (int64_t)dp.n_m2l_keys * nd_of(dp.hp.p);
+            hip_check(hipMalloc(&dp.m2l_Df, sizeof(float) * std::max<int64_t>(n, 1)), "hipMalloc M2L table f32");
+            k_to_float<<<dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536))), dim3(256)>>>(
+                dp.m2l_D, n, dp.m2l_Df);
+            hip_check(hipGetLastError(), "k_to_float launch");
+            hip_check(hipDeviceSynchronize(), "k_to_float");
+        }
+        if (dp.qtf_cap < F) {
+            if (dp.Qtf) (void)hipFree(dp.Qtf);
+            dp.Qtf = nullptr;
+            dp.qtf_cap = 0;
+            hip_check(hipMalloc(&dp.Qtf, sizeof(float) * (size_t)F * C * dp.qpad), "hipMalloc Qt f32");
+            dp.qtf_cap = F;
+        }
+    } else if (dp.qt_cap < F) {
+        if (dp.Qt) (void)hipFree(dp.Qt);
+        dp.Qt = nullptr;
+        dp.qt_cap = 0;
+        hip_check(hipMalloc(&dp.Qt, sizeof(double) * (size_t)F * C * dp.qpad), "hipMalloc Qt");
+        dp.qt_cap = F;
+    }
+}
+
+// Times one configuration: the median of three evaluations (after one warm
+// evaluation) with events on st.
+static float time_config(DevicePlan &dp, const double *M, double *u, hipStream_t st)
+{
+    prepare_evaluate(dp, 1);
+    run_evaluate(dp, M, 1, u, st);
+    hipEvent_t a, b;
+    hip_check(hipEventCreate(&a), "hipEventCreate");
+    hip_check(hipEventCreate(&b), "hipEventCreate");
+    float ms[3];
+    for (float &m : ms) {
+        hip_check(hipEventRecord(a, st), "hipEventRecord");
+        run_evaluate(dp, M, 1, u, st);
+        hip_check(hipEventRecord(b, st), "hipEventRecord");
+        hip_check(hipEventSynchronize(b), "hipEventSynchronize");
+        hip_check(hipEventElapsedTime(&m, a, b), "hipEventElapsedTime");
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    std::sort(ms, ms + 3);
+    return ms[1];
+}
+
+void autotune(DevicePlan &dp, hipStream_t st)
+{
+    const HostPlan &hp = dp.hp;
+    double *M = nullptr, *u = nullptr;
+    hip_check(hipMalloc(&M, sizeof(double) * 3 * std::max<int64_t>(hp.n_nodes, 1)), "hipMalloc tuning M");
+    if (hipMalloc(&u, sizeof(double) * std::max<int64_t>(hp.n_targets, 1)) != hipSuccess) {
+        (void)hipFree(M);
+        throw DeviceError{"hipMalloc tuning u failed"};
+    }
+    const bool timing = dp.timing;
+    dp.timing = false;
+    try {
+        fill(M, 3 * hp.n_nodes, 1.0, st);
+        // M2L work item size, then the P2P workgroup shape; the arithmetic of
+        // every candidate is the same, only the schedule differs
+        int best_ent = dp.m2l_max_ent;
+        float best = -1.f;
+        for (int ent : {128, 256, 512, 1024}) {
+            dp.m2l_max_ent = ent;
+            const float t = time_config(dp, M, u, st);
+            if (best < 0.f || t < best) best = t, best_ent = ent;
+        }
+        dp.m2l_max_ent = best_ent;
+        bool best_wide = false;
+        for (bool wide : {false, true}) {
+            dp.p2p_wide = wide;
+            const float t = time_config(dp, M, u, st);
+            if (!wide || t < best) best = t, best_wide = wide;
+        }
+        dp.p2p_wide = best_wide;
+        ++dp.schedule_gen;
+        prepare_evaluate(dp, 1);
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    } catch (...) {
+        dp.timing = timing;
+        (void)hipFree(M);
+        (void)hipFree(u);
+        throw;
+    }
+    dp.timing = timing;
+    (void)hipFree(M);
+    (void)hipFree(u);
+}
+
 void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t st)
 {
     const HostPlan &hp = dp.hp;
     const int64_t C = (int64_t)hp.cells.size();
     const int p = hp.p;
-    ensure_expansions(dp, F);
+    prepare_evaluate(dp, F);
     dp.last_F = F;
     fill(dp.Q, (int64_t)F * C * dp.ncoef, 0.0, st);
     fill(dp.L, (int64_t)F * C * dp.ncoef, 0.0, st);

@@ -127,3 +127,29 @@ def test_no_device_is_reported():
     with pytest.raises(T.TetFMMError) as e:
         T.tfmm_plan_create(nodes, tets, device=0)
     assert e.value.code == -6
+
+
+def test_batch_errors_without_device():
+    """Batch creation checks its arguments and needs a device; a bad mesh is
+    reported with its index; never a CPU fallback."""
+    import ctypes as C
+    import torch
+    lib = T._load()
+    out = C.c_void_p()
+    prm = T._Params(4, 8, 0.5, 0, 0)
+    assert lib.tfmm_batch_create(0, None, None, None, None, C.byref(prm), C.byref(out)) == -1
+    assert not out.value
+    meshes = [meshgen.box_mesh(2), meshgen.box_mesh(3)]
+    with pytest.raises(T.TetFMMError) as e:
+        T.tfmm_batch_create(meshes, p=4, leaf_size=8, device=-1)
+    assert e.value.code == -1
+    bad = meshes[1][1].copy()
+    bad[0, 0] = -5
+    if torch.cuda.device_count() == 0:
+        with pytest.raises(T.TetFMMError) as e:
+            T.tfmm_batch_create(meshes, p=4, leaf_size=8, device=0)
+        assert e.value.code == -6 and "mesh 0" in e.value.args[-1]
+    with pytest.raises(T.TetFMMError) as e:
+        T.tfmm_batch_create([meshes[0], (meshes[1][0], bad)], p=4, leaf_size=8, device=0)
+    assert e.value.code in (-2, -6)
+    assert lib.tfmm_batch_destroy(None) == 0

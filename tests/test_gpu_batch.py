@@ -1,0 +1,118 @@
+"""GPU tests of ragged batches (one HIP graph per batch) and schedule tuning.
+
+Graph replays are checked against eager evaluations of the same plans, with
+the program's own eager work (new fields written by torch) and
+synchronisations between the replays, and against the oracle FMM.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import meshgen
+import paper_1606_00247_amd as T
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _ragged(count, seed):
+    rng = np.random.default_rng(seed)
+    sizes = [(int(a), int(b), int(c)) for a, b, c in rng.integers(2, 9, size=(count, 3))]
+    return [meshgen.box_mesh(n, seed=seed + i) for i, n in enumerate(sizes)]
+
+
+def test_batch_graph_replays_match_eager_and_oracle(torch_dev, orc):
+    torch = torch_dev
+    meshes = _ragged(6, 21)
+    _say("batch of", len(meshes), [m[1].shape[0] for m in meshes])
+    B = T.tfmm_batch_create(meshes, p=6, leaf_size=16, theta=0.5)
+    M = [torch.empty((m[0].shape[0], 3), dtype=torch.float64, device="cuda:0") for m in meshes]
+    u = [torch.empty(m[0].shape[0], dtype=torch.float64, device="cuda:0") for m in meshes]
+    plans = [T.tfmm_batch_plan(B, i) for i in range(len(meshes))]
+    for r in range(3):
+        for i, m in enumerate(meshes):  # eager work between replays: new fields
+            M[i].copy_(torch.from_numpy(meshgen.random_fields(m[0].shape[0], F=1, seed=100 * r + i)[0]))
+        torch.cuda.synchronize()
+        T.tfmm_batch_evaluate(B, M, u)
+        torch.cuda.synchronize()
+        for i, m in enumerate(meshes):
+            ue = T.tfmm_evaluate(plans[i], M[i])
+            torch.cuda.synchronize()
+            assert _rel(u[i].cpu().numpy(), ue.cpu().numpy()) <= 1e-13, (r, i)
+            if r == 1:
+                uo = orc.FMM(m[0], m[1], 6, 16, 0.5).evaluate(M[i].cpu().numpy())
+                assert _rel(u[i].cpu().numpy(), uo) <= TOL, i
+    # new output buffers: the graph is captured again
+    u2 = [torch.empty_like(x) for x in u]
+    T.tfmm_batch_evaluate(B, M, u2)
+    torch.cuda.synchronize()
+    for a, b in zip(u, u2):
+        assert _rel(b.cpu().numpy(), a.cpu().numpy()) <= 1e-13
+    # a precision change of one plan re-captures too
+    T.tfmm_plan_set_m2l_precision(plans[2], T.M2L_FP32)
+    T.tfmm_batch_evaluate(B, M, u2)
+    torch.cuda.synchronize()
+    assert 0.0 < _rel(u2[2].cpu().numpy(), u[2].cpu().numpy()) <= 1e-6
+    T.tfmm_batch_destroy(B)
+
+
+def test_autotune_keeps_results(torch_dev, orc):
+    torch = torch_dev
+    nodes, tets = meshgen.box_mesh(10, seed=4)
+    M = meshgen.random_fields(nodes.shape[0], F=1, seed=6)[0]
+    _say("autotune cube10")
+    P = T.tfmm_plan_create(nodes, tets, p=7, leaf_size=16, theta=0.5)
+    T.tfmm_plan_autotune(P)
+    u = T.tfmm_evaluate(P, torch.from_numpy(M).to("cuda:0"))
+    torch.cuda.synchronize()
+    uo = orc.FMM(nodes, tets, 7, 16, 0.5).evaluate(M)
+    assert _rel(u.cpu().numpy(), uo) <= TOL
+    meshes = _ragged(4, 5)
+    B = T.tfmm_batch_create(meshes, p=6, leaf_size=8, theta=0.5)
+    T.tfmm_batch_autotune(B)
+    Ms = [torch.from_numpy(meshgen.random_fields(m[0].shape[0], F=1, seed=i)[0]).to("cuda:0")
+          for i, m in enumerate(meshes)]
+    us = T.tfmm_batch_evaluate(B, Ms)
+    torch.cuda.synchronize()
+    for i, m in enumerate(meshes):
+        uo = orc.FMM(m[0], m[1], 6, 8, 0.5).evaluate(Ms[i].cpu().numpy())
+        assert _rel(us[i].cpu().numpy(), uo) <= TOL, i
+
+
+def test_ragged32_batch_accuracy(torch_dev):
+    """The ragged batch of 32 jittered cubes with 2k-200k tets (log-uniform
+    sizes), one random field each: every mesh within 1e-5 of its direct sum."""
+    torch = torch_dev
+    ns = meshgen.ragged_sizes(32)
+    meshes = [meshgen.box_mesh(int(n), seed=i) for i, n in enumerate(ns)]
+    _say("ragged32", sum(m[1].shape[0] for m in meshes), "tets")
+    B = T.tfmm_batch_create(meshes, p=8, leaf_size=64, theta=0.5)
+    M = [torch.from_numpy(meshgen.random_fields(m[0].shape[0], F=1, seed=1 + i)[0]).to("cuda:0")
+         for i, m in enumerate(meshes)]
+    u = T.tfmm_batch_evaluate(B, M)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i in range(len(meshes)):
+        ud = T.tfmm_direct(T.tfmm_batch_plan(B, i), M[i])
+        torch.cuda.synchronize()
+        worst = max(worst, _rel(u[i].cpu().numpy(), ud.cpu().numpy()))
+    assert worst <= 1e-5, worst
