@@ -224,7 +224,9 @@ int tfmm_batch_create(int32_t n_meshes, const double *const *nodes, const int64_
  * Evaluate every mesh of the batch: M[i] device [n_nodes_i][3] FP64 nodal
  * magnetisation, u[i] device [n_nodes_i] FP64 output (written, not added
  * to).  The whole sequence of launches is captured once into a HIP graph
- * (on an internal stream) and replayed on hip_stream while the M and u
+ * (on internal streams; the meshes are spread over 4 branches that run
+ * concurrently, balanced by the plans' P2P and M2L counts) and replayed on
+ * hip_stream while the M and u
  * pointers and the plans' precision and schedule stay the same; a change
  * re-captures.  Asynchronous like tfmm_evaluate.  With kernel timing enabled
  * on any plan the launches run eagerly instead.

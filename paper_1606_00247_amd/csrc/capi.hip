@@ -21,12 +21,18 @@ struct tfmm_plan_s {
 };
 
 // A batch: one plan per mesh and the HIP graph of one evaluation of all of
-// them, captured on an internal stream for the M and u pointers it was made
-// with and replayed while they stay the same.
+// them, captured on internal streams for the M and u pointers it was made
+// with and replayed while they stay the same.  The meshes are dealt to
+// kBatchBranches branches of the graph (longest first by a cost estimate,
+// each to the least loaded branch), which the GPU runs concurrently.
+constexpr int kBatchBranches = 4;  // concurrent branches of a batch graph
+
 struct tfmm_batch_s {
     std::vector<tfmm_plan> plans;
     int device = 0;
     hipStream_t capture = nullptr;
+    hipStream_t branch[kBatchBranches] = {};
+    hipEvent_t fork = nullptr, join[kBatchBranches] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<const double *> keyM;
@@ -536,6 +542,11 @@ int tfmm_batch_destroy(tfmm_batch batch)
             DeviceScope ds(batch->device);
             batch_drop_graph(batch);
             if (batch->capture) (void)hipStreamDestroy(batch->capture);
+            for (int k = 0; k < kBatchBranches; ++k) {
+                if (batch->branch[k]) (void)hipStreamDestroy(batch->branch[k]);
+                if (batch->join[k]) (void)hipEventDestroy(batch->join[k]);
+            }
+            if (batch->fork) (void)hipEventDestroy(batch->fork);
         }
         int rc = TFMM_OK;
         for (tfmm_plan p : batch->plans) {
@@ -574,6 +585,11 @@ int tfmm_batch_create(int32_t n_meshes, const double *const *nodes, const int64_
     rc = guarded([&]() -> int {
         DeviceScope ds(b->device);
         tfmm::hip_check(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "hipStreamCreate");
+        tfmm::hip_check(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming), "hipEventCreate");
+        for (int k = 0; k < kBatchBranches; ++k) {
+            tfmm::hip_check(hipStreamCreateWithFlags(&b->branch[k], hipStreamNonBlocking), "hipStreamCreate");
+            tfmm::hip_check(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming), "hipEventCreate");
+        }
         return TFMM_OK;
     });
     if (rc) {
@@ -610,7 +626,28 @@ int tfmm_batch_evaluate(tfmm_batch batch, const double *const *M, double *const 
             tfmm::hip_check(hipStreamBeginCapture(batch->capture, hipStreamCaptureModeThreadLocal),
                             "hipStreamBeginCapture");
             try {
-                for (size_t i = 0; i < n; ++i) tfmm::run_evaluate(batch->plans[i]->dp, M[i], 1, u[i], batch->capture);
+                // deal the meshes to the branches: longest first, least loaded branch
+                std::vector<size_t> ord(n);
+                std::vector<double> cost(n);
+                for (size_t i = 0; i < n; ++i) {
+                    const tfmm::HostPlan &hp = batch->plans[i]->dp.hp;
+                    ord[i] = i;
+                    cost[i] = (double)hp.n_p2p_pairs + 300.0 * (double)hp.m2l_src.size() + 1e5;
+                }
+                std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+                double load[kBatchBranches] = {};
+                tfmm::hip_check(hipEventRecord(batch->fork, batch->capture), "hipEventRecord");
+                for (int k = 0; k < kBatchBranches; ++k)
+                    tfmm::hip_check(hipStreamWaitEvent(batch->branch[k], batch->fork, 0), "hipStreamWaitEvent");
+                for (size_t i : ord) {
+                    const int k = (int)(std::min_element(load, load + kBatchBranches) - load);
+                    load[k] += cost[i];
+                    tfmm::run_evaluate(batch->plans[i]->dp, M[i], 1, u[i], batch->branch[k]);
+                }
+                for (int k = 0; k < kBatchBranches; ++k) {
+                    tfmm::hip_check(hipEventRecord(batch->join[k], batch->branch[k]), "hipEventRecord");
+                    tfmm::hip_check(hipStreamWaitEvent(batch->capture, batch->join[k], 0), "hipStreamWaitEvent");
+                }
             } catch (...) {
                 hipGraph_t g = nullptr;
                 (void)hipStreamEndCapture(batch->capture, &g);
