@@ -243,6 +243,63 @@ int tfmm_batch_plan(tfmm_batch batch, int32_t i, tfmm_plan *out);
 /* Destroy the batch, its plans and its graph.  NULL is accepted. */
 int tfmm_batch_destroy(tfmm_batch batch);
 
+/*
+ * Learned near-field surrogate.  For a tet (diameter d = longest edge,
+ * centroid c, volume V) and a target x at 2 <= rho = |x - c|/d < 6 the
+ * potential is u = d * sum_{i,a} C_ia M_ia; a perceptron 12 -> H -> H -> H
+ * -> 12 (ReLU) maps s_i = (v_i - x)/|x - c| to y = 16 pi C rho^2 / (V/d^3).
+ * It is trained on the GPU (FP32, Adam; pairs drawn from the plan's tets,
+ * exact pair integrals as targets) and evaluated with BF16 weights on matrix
+ * cores.  It is an experiment beside the method: tfmm_evaluate never uses it.
+ */
+typedef struct {
+    int32_t hidden; /* hidden width: 32, 64 or 128 */
+    int32_t steps;  /* Adam steps */
+    int32_t batch;  /* fresh samples per step */
+    float lr;       /* initial learning rate (cosine decay to lr/20) */
+    uint64_t seed;
+} tfmm_train_cfg;
+
+/* Number of FP32 parameters of a network of the given width (-1 if unsupported). */
+int tfmm_surrogate_param_count(int32_t hidden);
+
+/*
+ * Train a surrogate on pairs drawn from the plan's tets, attach it to the plan
+ * and (when out_path is not NULL) write it: 8 bytes "TFMMSUR1", int32 hidden,
+ * int32 count, count FP32 parameters (W1 [12][H], b1, W2 [H][H], b2, W3, b3,
+ * W4 [H][12], b4).  *final_loss (may be NULL): mean squared error of the last
+ * 5% of the steps.  Synchronous.
+ * Errors: TFMM_EINVAL (arguments, host-only plan, unwritable path), TFMM_EDEVICE.
+ */
+int tfmm_surrogate_train(tfmm_plan plan, const tfmm_train_cfg *cfg, const char *out_path, double *final_loss);
+
+/* Attach a surrogate written by tfmm_surrogate_train.  Errors: TFMM_EINVAL, TFMM_EDEVICE. */
+int tfmm_surrogate_load(tfmm_plan plan, const char *path);
+
+/*
+ * n training samples drawn as in training (seeded): X [n][12] inputs s,
+ * Y [n][12] targets y; host arrays.  For checking the targets against an
+ * independent pair integral.  Errors: TFMM_EINVAL, TFMM_EDEVICE.
+ */
+int tfmm_surrogate_samples(tfmm_plan plan, uint64_t seed, int32_t n, float *X, float *Y);
+
+/*
+ * Mean squared error and its gradient (FP32, the training kernels) of the
+ * network with parameters params on the batch (X [batch][12], Y [batch][12]);
+ * host arrays, run on the given device.  Errors: TFMM_EINVAL, TFMM_EDEVICE.
+ */
+int tfmm_surrogate_grad(int32_t hidden, const float *params, const float *X, const float *Y, int32_t batch,
+                        float *grad, double *loss, int32_t device);
+
+/*
+ * u [n_targets] (device, written) = potential of the plan's near-field pairs
+ * with 2 <= |x - c|/d < 6 only, for one field M (device [n_nodes][3]): by the
+ * exact pair integral (use_surrogate = 0) or by the attached surrogate.
+ * Asynchronous on hip_stream.  Errors: TFMM_EINVAL (no surrogate attached,
+ * NULL arguments), TFMM_EDEVICE.
+ */
+int tfmm_band_potential(tfmm_plan plan, int32_t use_surrogate, const double *M, double *u, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,7 +19,8 @@ __all__ = [
     "tfmm_plan_destroy", "tfmm_last_error", "tfmm_simplex_rule", "tfmm_set_timing", "tfmm_kernel_times",
     "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS", "tfmm_plan_set_m2l_precision", "M2L_FP64", "M2L_FP32", "M2L_BF16X3", "M2L_BF16X6",
     "tfmm_plan_autotune", "tfmm_batch_create", "tfmm_batch_evaluate", "tfmm_batch_autotune", "tfmm_batch_plan",
-    "tfmm_batch_destroy", "Batch",
+    "tfmm_batch_destroy", "Batch", "tfmm_surrogate_param_count", "tfmm_surrogate_train", "tfmm_surrogate_load",
+    "tfmm_surrogate_samples", "tfmm_surrogate_grad", "tfmm_band_potential",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -35,8 +36,14 @@ KERNEL_NAMES = ("p2m", "m2m", "m2l", "l2l", "l2p", "p2p")
 ERRORS = {-1: "EINVAL", -2: "EINDEX", -3: "EDEGEN", -4: "ENONFINITE", -5: "ENOMEM", -6: "EDEVICE", -7: "ENOTSUP"}
 
 _dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
 _i32p = C.POINTER(C.c_int32)
 _i64p = C.POINTER(C.c_int64)
+
+
+class _TrainCfg(C.Structure):
+    _fields_ = [("hidden", C.c_int32), ("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
+                ("seed", C.c_uint64)]
 
 
 class _Params(C.Structure):
@@ -92,6 +99,12 @@ def _load():
         "tfmm_batch_autotune": (C.c_int, [C.c_void_p, C.c_void_p]),
         "tfmm_batch_plan": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
         "tfmm_batch_destroy": (C.c_int, [C.c_void_p]),
+        "tfmm_surrogate_param_count": (C.c_int, [C.c_int32]),
+        "tfmm_surrogate_train": (C.c_int, [C.c_void_p, C.POINTER(_TrainCfg), C.c_char_p, _dp]),
+        "tfmm_surrogate_load": (C.c_int, [C.c_void_p, C.c_char_p]),
+        "tfmm_surrogate_samples": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, _fp, _fp]),
+        "tfmm_surrogate_grad": (C.c_int, [C.c_int32, _fp, _fp, _fp, C.c_int32, _fp, _dp, C.c_int32]),
+        "tfmm_band_potential": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -307,6 +320,56 @@ def tfmm_batch_destroy(batch):
     if batch._h is not None:
         _check(_load().tfmm_batch_destroy(batch._h))
         batch._h = None
+
+
+def tfmm_surrogate_param_count(hidden):
+    return _check(_load().tfmm_surrogate_param_count(int(hidden)))
+
+
+def tfmm_surrogate_train(plan, hidden=128, steps=3000, batch=4096, lr=1e-3, seed=1, out_path=None):
+    """Train the near-field surrogate on pairs from the plan's tets; returns the final loss."""
+    cfg = _TrainCfg(int(hidden), int(steps), int(batch), float(lr), int(seed))
+    loss = C.c_double(0.0)
+    path = None if out_path is None else os.fsencode(out_path)
+    _check(_load().tfmm_surrogate_train(plan.handle, C.byref(cfg), path, C.byref(loss)))
+    return loss.value
+
+
+def tfmm_surrogate_load(plan, path):
+    _check(_load().tfmm_surrogate_load(plan.handle, os.fsencode(path)))
+
+
+def tfmm_surrogate_samples(plan, n, seed=7):
+    """n training samples: inputs X [n, 12] and targets Y [n, 12] (float32)."""
+    X = np.zeros((n, 12), dtype=np.float32)
+    Y = np.zeros((n, 12), dtype=np.float32)
+    _check(_load().tfmm_surrogate_samples(plan.handle, int(seed), int(n), _ptr(X, _fp), _ptr(Y, _fp)))
+    return X, Y
+
+
+def tfmm_surrogate_grad(hidden, params, X, Y, device=0):
+    """Loss and gradient of the training kernels (FP32) for one batch."""
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.ascontiguousarray(Y, dtype=np.float32)
+    g = np.zeros_like(params)
+    loss = C.c_double(0.0)
+    _check(_load().tfmm_surrogate_grad(int(hidden), _ptr(params, _fp), _ptr(X, _fp), _ptr(Y, _fp), X.shape[0],
+                                       _ptr(g, _fp), C.byref(loss), int(device)))
+    return loss.value, g
+
+
+def tfmm_band_potential(plan, M, use_surrogate, u=None, stream=None):
+    """Potential of the near-field pairs at 2 <= |x - c|/d < 6 only (one field)."""
+    import torch
+    if not (isinstance(M, torch.Tensor) and M.is_cuda and M.dtype == torch.float64 and M.is_contiguous()
+            and tuple(M.shape) == (plan.n_nodes, 3)):
+        raise ValueError("M must be a contiguous float64 CUDA tensor [n_nodes, 3]")
+    if u is None:
+        u = torch.empty(plan.n_targets, dtype=torch.float64, device=M.device)
+    _check(_load().tfmm_band_potential(plan.handle, int(bool(use_surrogate)), C.c_void_p(M.data_ptr()),
+                                       C.c_void_p(u.data_ptr()), _stream_handle(stream, M.device)))
+    return u
 
 
 def tfmm_plan_stats(plan):

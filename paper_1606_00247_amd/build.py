@@ -34,7 +34,7 @@ def build(verbose=False, jobs=4):
     plan_o = os.path.join(BUILD, "plan.o")
     cmds = [["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "plan.cpp"), "-o", plan_o]]
     objs.append(plan_o)
-    for src in ("kernels.hip", "capi.hip"):
+    for src in ("kernels.hip", "surrogate.hip", "capi.hip"):
         o = os.path.join(BUILD, src.replace(".hip", ".o"))
         cmds.append(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)

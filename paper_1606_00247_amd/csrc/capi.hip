@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -236,7 +237,7 @@ void free_plan(DevicePlan &dp)
     dp.event_pool.clear();
     void *ptrs[] = {dp.tet_xyz, dp.tet_node, dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, dp.cell_c, dp.cell_i,
                     dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.p2p_blk, dp.p2p_idx, dp.quad, dp.tet_mom, dp.Q,
-                    dp.L, dp.Qt, dp.Qtf, dp.m2l_keys, dp.m2l_D, dp.m2l_Df};
+                    dp.L, dp.Qt, dp.Qtf, dp.m2l_keys, dp.m2l_D, dp.m2l_Df, dp.sur_w, dp.sur_wb};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : dp.m2l_tiles) {
@@ -684,6 +685,102 @@ int tfmm_batch_plan(tfmm_batch batch, int32_t i, tfmm_plan *out)
     if (!batch || !out || i < 0 || (size_t)i >= batch->plans.size()) return set_error(TFMM_EINVAL, "bad batch index");
     *out = batch->plans[i];
     return TFMM_OK;
+}
+
+int tfmm_surrogate_param_count(int32_t hidden) { return tfmm::surrogate_param_count(hidden); }
+
+static int write_surrogate(const char *path, int32_t hidden, const std::vector<float> &params)
+{
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return set_error(TFMM_EINVAL, std::string("cannot write ") + path);
+    const char magic[8] = {'T', 'F', 'M', 'M', 'S', 'U', 'R', '1'};
+    const int32_t hdr[2] = {hidden, (int32_t)params.size()};
+    bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof(int32_t), 2, f) == 2 &&
+              std::fwrite(params.data(), sizeof(float), params.size(), f) == params.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? TFMM_OK : set_error(TFMM_EINVAL, std::string("write failed: ") + path);
+}
+
+int tfmm_surrogate_train(tfmm_plan plan, const tfmm_train_cfg *cfg, const char *out_path, double *final_loss)
+{
+    if (!plan || !cfg) return set_error(TFMM_EINVAL, "NULL argument");
+    if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan");
+    if ((cfg->hidden != 32 && cfg->hidden != 64 && cfg->hidden != 128) || cfg->steps < 1 || cfg->batch < 1 ||
+        !(cfg->lr > 0.f))
+        return set_error(TFMM_EINVAL, "hidden must be 32, 64 or 128; steps, batch and lr positive");
+    std::vector<float> params;
+    int rc = guarded([&]() -> int {
+        DeviceScope ds(plan->dp.device);
+        const double loss =
+            tfmm::surrogate_train(plan->dp, cfg->hidden, cfg->steps, cfg->batch, cfg->lr, cfg->seed, params);
+        if (final_loss) *final_loss = loss;
+        return TFMM_OK;
+    });
+    if (rc || !out_path) return rc;
+    return write_surrogate(out_path, cfg->hidden, params);
+}
+
+int tfmm_surrogate_load(tfmm_plan plan, const char *path)
+{
+    if (!plan || !path) return set_error(TFMM_EINVAL, "NULL argument");
+    if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return set_error(TFMM_EINVAL, std::string("cannot read ") + path);
+    char magic[8];
+    int32_t hdr[2] = {0, 0};
+    std::vector<float> params;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "TFMMSUR1", 8) == 0 &&
+              std::fread(hdr, sizeof(int32_t), 2, f) == 2 && hdr[1] == tfmm::surrogate_param_count(hdr[0]) &&
+              hdr[1] > 0;
+    if (ok) {
+        params.resize((size_t)hdr[1]);
+        ok = std::fread(params.data(), sizeof(float), params.size(), f) == params.size();
+    }
+    std::fclose(f);
+    if (!ok) return set_error(TFMM_EINVAL, std::string("not a surrogate file of a supported width: ") + path);
+    return guarded([&]() -> int {
+        DeviceScope ds(plan->dp.device);
+        tfmm::surrogate_set(plan->dp, hdr[0], params);
+        return TFMM_OK;
+    });
+}
+
+int tfmm_surrogate_samples(tfmm_plan plan, uint64_t seed, int32_t n, float *X, float *Y)
+{
+    if (!plan || !X || !Y || n < 1) return set_error(TFMM_EINVAL, "bad argument");
+    if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan");
+    return guarded([&]() -> int {
+        DeviceScope ds(plan->dp.device);
+        tfmm::surrogate_samples(plan->dp, seed, n, X, Y);
+        return TFMM_OK;
+    });
+}
+
+int tfmm_surrogate_grad(int32_t hidden, const float *params, const float *X, const float *Y, int32_t batch,
+                        float *grad, double *loss, int32_t device)
+{
+    if (!params || !X || !Y || !grad || !loss || batch < 1 || tfmm::surrogate_param_count(hidden) <= 0)
+        return set_error(TFMM_EINVAL, "bad argument");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return set_error(TFMM_EDEVICE, "no such HIP device");
+    return guarded([&]() -> int {
+        DeviceScope ds(device);
+        tfmm::surrogate_grad(hidden, params, X, Y, batch, grad, loss);
+        return TFMM_OK;
+    });
+}
+
+int tfmm_band_potential(tfmm_plan plan, int32_t use_surrogate, const double *M, double *u, void *hip_stream)
+{
+    int rc = check_eval_args(plan, M, 1, u);
+    if (rc) return rc;
+    if (use_surrogate && !plan->dp.sur_wb) return set_error(TFMM_EINVAL, "no surrogate attached to the plan");
+    return guarded([&]() -> int {
+        DeviceScope ds(plan->dp.device);
+        tfmm::run_band(plan->dp, use_surrogate != 0, M, u, (hipStream_t)hip_stream);
+        return TFMM_OK;
+    });
 }
 
 }  // extern "C"

@@ -91,6 +91,12 @@ struct DevicePlan {
     int32_t Fcap = 0;
     int32_t last_F = 0;
 
+    // near-field surrogate (optional): hidden width, FP32 parameters and their
+    // BF16 copy in the inference layout
+    int sur_hidden = 0;
+    float *sur_w = nullptr;
+    uint16_t *sur_wb = nullptr;
+
     int64_t device_bytes = 0;
 
     // timing: event pairs recorded on the evaluation stream around each phase,
@@ -131,6 +137,22 @@ void autotune(DevicePlan &dp, hipStream_t stream);
 void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t stream);
 // Queue the O(N^2) direct sum of F fields on `stream`.
 void run_direct(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t stream);
+
+// Near-field surrogate (pairs at 2 <= |x - c| / diam < 6).
+int surrogate_param_count(int hidden);
+// Train on pairs drawn from the plan's tets; attaches the result to the plan
+// and returns the mean loss of the last 5% of the steps.
+double surrogate_train(DevicePlan &dp, int hidden, int steps, int batch, float lr, uint64_t seed,
+                       std::vector<float> &params);
+void surrogate_set(DevicePlan &dp, int hidden, const std::vector<float> &params);
+// Loss and gradient of one batch (host arrays), for checking.
+void surrogate_grad(int hidden, const float *params, const float *X, const float *Y, int batch, float *grad,
+                    double *loss);
+// n training samples (inputs [n][12], targets [n][12]) to host arrays.
+void surrogate_samples(DevicePlan &dp, uint64_t seed, int n, float *X, float *Y);
+// u = potential of the plan's near-field pairs in the band only (one field),
+// exact or by the surrogate.
+void run_band(DevicePlan &dp, bool use_surrogate, const double *M, double *u, hipStream_t stream);
 
 // Collapsed Gauss-Jacobi rule on the unit simplex exact to total degree `deg`:
 // rows lambda1, lambda2, lambda3, weight (weights sum to 1/6).

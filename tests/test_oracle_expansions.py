@@ -234,3 +234,26 @@ def test_taylor_coefficients_harmonic_and_reduced_contraction(orc):
         j, c = m[2] // 2, m[2] % 2
         v = (-1) ** j * sum(math.comb(j, i) * red[(m[0] + 2 * i, m[1] + 2 * (j - i), c)] for i in range(j + 1))
         assert abs(v - full[m]) <= 1e-12 * scale, m
+
+
+def test_reference_perceptron_gradient_by_finite_differences():
+    """The oracle's surrogate network: its chain-rule gradient equals central
+    finite differences of its loss (FP64), and the packing covers every
+    parameter once."""
+    from oracle import mlp
+    H = 8
+    _, n = mlp.layout(H)
+    assert n == 12 * H + H + 2 * (H * H + H) + H * 12 + 12
+    rng = np.random.default_rng(3)
+    p = rng.standard_normal(n) * 0.5
+    X = rng.standard_normal((7, 12))
+    Tg = rng.standard_normal((7, 12))
+    loss, g = mlp.loss_and_grad(p, H, X, Tg)
+    eps = 1e-6
+    for i in rng.choice(n, 40, replace=False):
+        q = p.copy()
+        q[i] += eps
+        lp = mlp.loss_and_grad(q, H, X, Tg)[0]
+        q[i] -= 2 * eps
+        lm = mlp.loss_and_grad(q, H, X, Tg)[0]
+        assert abs((lp - lm) / (2 * eps) - g[i]) <= 1e-6 * max(1.0, abs(g[i])), i
