@@ -200,6 +200,18 @@ int tfmm_set_timing(tfmm_plan plan, int32_t on);
 int tfmm_kernel_times(tfmm_plan plan, double *ms /* [6] */, int64_t *launches /* [6] */);
 
 /*
+ * Demagnetising field and energy from nodal potentials (P1 interpolation of
+ * u on every tet): H_tet [n_tets][3] (device, input tet order, may be NULL)
+ * receives H_T = -grad u, and *energy (host) the stray-field energy over mu0,
+ *   E / mu0 = 1/2 sum_T int_T M . grad u = -1/2 int M . H,
+ * for one field M (device [n_nodes][3]) and its potential u (device
+ * [n_nodes], e.g. from tfmm_evaluate; the plan's targets must be its nodes).
+ * Synchronises hip_stream.  Errors: TFMM_EINVAL, TFMM_EDEVICE.
+ */
+int tfmm_demag_energy(tfmm_plan plan, const double *M, const double *u, double *H_tet, double *energy,
+                      void *hip_stream);
+
+/*
  * Schedule tuning.  Times evaluations of one (synthetic) field on hip_stream
  * for a few choices of the M2L work item size (keys per workgroup) and of the
  * P2P workgroup shape, and keeps the fastest; the arithmetic, and so every

@@ -20,7 +20,7 @@ __all__ = [
     "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS", "tfmm_plan_set_m2l_precision", "M2L_FP64", "M2L_FP32", "M2L_BF16X3", "M2L_BF16X6",
     "tfmm_plan_autotune", "tfmm_batch_create", "tfmm_batch_evaluate", "tfmm_batch_autotune", "tfmm_batch_plan",
     "tfmm_batch_destroy", "Batch", "tfmm_surrogate_param_count", "tfmm_surrogate_train", "tfmm_surrogate_load",
-    "tfmm_surrogate_samples", "tfmm_surrogate_grad", "tfmm_band_potential",
+    "tfmm_surrogate_samples", "tfmm_surrogate_grad", "tfmm_band_potential", "tfmm_demag_energy",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -100,6 +100,7 @@ def _load():
         "tfmm_batch_plan": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
         "tfmm_batch_destroy": (C.c_int, [C.c_void_p]),
         "tfmm_surrogate_param_count": (C.c_int, [C.c_int32]),
+        "tfmm_demag_energy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, _dp, C.c_void_p]),
         "tfmm_surrogate_train": (C.c_int, [C.c_void_p, C.POINTER(_TrainCfg), C.c_char_p, _dp]),
         "tfmm_surrogate_load": (C.c_int, [C.c_void_p, C.c_char_p]),
         "tfmm_surrogate_samples": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, _fp, _fp]),
@@ -320,6 +321,23 @@ def tfmm_batch_destroy(batch):
     if batch._h is not None:
         _check(_load().tfmm_batch_destroy(batch._h))
         batch._h = None
+
+
+def tfmm_demag_energy(plan, M, u, with_field=False, stream=None):
+    """Stray-field energy over mu0 (and H per tet [n_tets, 3] when with_field) from nodal u."""
+    import torch
+    for a, shape in ((M, (plan.n_nodes, 3)), (u, (plan.n_nodes,))):
+        if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()
+                and tuple(a.shape) == shape):
+            raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {shape}")
+    H = None
+    if with_field:
+        H = torch.empty((tfmm_plan_stats(plan)["n_tets"], 3), dtype=torch.float64, device=M.device)
+    E = C.c_double(0.0)
+    _check(_load().tfmm_demag_energy(plan.handle, C.c_void_p(M.data_ptr()), C.c_void_p(u.data_ptr()),
+                                     None if H is None else C.c_void_p(H.data_ptr()), C.byref(E),
+                                     _stream_handle(stream, M.device)))
+    return (E.value, H) if with_field else E.value
 
 
 def tfmm_surrogate_param_count(hidden):

@@ -117,6 +117,7 @@ void upload_plan(DevicePlan &dp)
             }
         dp.tet_xyz = dev_upload(xyz, B);
         dp.tet_node = dev_upload(nd, B);
+        dp.tet_perm = dev_upload(hp.tet_perm, B);
     }
     {
         std::vector<double> xyz(3 * N);
@@ -235,7 +236,7 @@ void free_plan(DevicePlan &dp)
     collect_timing(dp);
     for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
     dp.event_pool.clear();
-    void *ptrs[] = {dp.tet_xyz, dp.tet_node, dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, dp.cell_c, dp.cell_i,
+    void *ptrs[] = {dp.tet_xyz, dp.tet_node, dp.tet_perm, dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, dp.cell_c, dp.cell_i,
                     dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.p2p_blk, dp.p2p_idx, dp.quad, dp.tet_mom, dp.Q,
                     dp.L, dp.Qt, dp.Qtf, dp.m2l_keys, dp.m2l_D, dp.m2l_Df, dp.sur_w, dp.sur_wb};
     for (void *p : ptrs)
@@ -685,6 +686,19 @@ int tfmm_batch_plan(tfmm_batch batch, int32_t i, tfmm_plan *out)
     if (!batch || !out || i < 0 || (size_t)i >= batch->plans.size()) return set_error(TFMM_EINVAL, "bad batch index");
     *out = batch->plans[i];
     return TFMM_OK;
+}
+
+int tfmm_demag_energy(tfmm_plan plan, const double *M, const double *u, double *H_tet, double *energy,
+                      void *hip_stream)
+{
+    if (!plan || !M || !u || !energy) return set_error(TFMM_EINVAL, "NULL argument");
+    if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan");
+    if (!plan->dp.hp.targets_are_nodes) return set_error(TFMM_EINVAL, "the plan's targets are not its nodes");
+    return guarded([&]() -> int {
+        DeviceScope ds(plan->dp.device);
+        *energy = tfmm::run_demag(plan->dp, M, u, H_tet, (hipStream_t)hip_stream);
+        return TFMM_OK;
+    });
 }
 
 int tfmm_surrogate_param_count(int32_t hidden) { return tfmm::surrogate_param_count(hidden); }

@@ -35,6 +35,7 @@ struct DevicePlan {
     // corner node ids [4][T]
     double *tet_xyz = nullptr;
     int32_t *tet_node = nullptr;
+    int32_t *tet_perm = nullptr;  // octree order -> input tet index
     // targets in octree order: [3][N], original index, leaf cell
     double *tgt_xyz = nullptr;
     int32_t *tgt_perm = nullptr;
@@ -135,6 +136,10 @@ void prepare_evaluate(DevicePlan &dp, int32_t F);
 void autotune(DevicePlan &dp, hipStream_t stream);
 // Queue the FMM evaluation of F fields on `stream`.
 void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t stream);
+// Demagnetising field per tet (H [n_tets][3] in input order, may be null) and
+// energy E / mu0 of one field M from the nodal potentials u (targets = nodes);
+// synchronises the stream.
+double run_demag(DevicePlan &dp, const double *M, const double *u, double *H, hipStream_t stream);
 // Queue the O(N^2) direct sum of F fields on `stream`.
 void run_direct(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t stream);
 

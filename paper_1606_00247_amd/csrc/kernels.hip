@@ -1117,14 +1117,14 @@ constexpr int kP2PTets = 64;  // tets per block (direct sum)
 // consecutive tets, all targets): one wavefront for one or two fields, four
 // for more (they share the staged field coefficients).  Tets are staged in
 // LDS BT at a time, thread l preparing field l % FCH of tet l / FCH (geometry
-// 240 B + 208 B per field per tet); every thread then takes targets
+// 240 B + 208 B per field per tet; 8 tets for 32 fields); every thread then takes targets
 // ib + l, ib + l + NT, ... over the staged tets and adds its potentials
 // atomically.
 // WIDE: four wavefronts also for one or two fields (a plan's tuning choice).
 __host__ __device__ constexpr int p2p_threads(int FCH, bool wide) { return FCH <= 2 && !wide ? 64 : 256; }
 __host__ __device__ constexpr int p2p_stage(int FCH, bool wide)
 {
-    return FCH <= 2 ? (wide ? 64 / FCH : 16) : (FCH >= 16 ? 16 : (FCH >= 8 ? 32 : 64));
+    return FCH <= 2 ? (wide ? 64 / FCH : 16) : (FCH >= 32 ? 8 : (FCH >= 16 ? 16 : (FCH >= 8 ? 32 : 64)));
 }
 
 template <int FCH, bool WIDE>
@@ -1177,6 +1177,89 @@ __global__ __launch_bounds__(p2p_threads(FCH, WIDE), 2) void k_p2p(const int32_t
             for (int f = 0; f < FCH; ++f) atomicAdd(&u[(int64_t)(f0 + f) * N + o], acc[f] * kInv4Pi);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Demagnetising field and energy from nodal potentials (P1 interpolation):
+// per tet H_T = -grad u = -sum_i u_i grad lambda_i, and
+//   E / mu0 = 1/2 sum_T int_T M . grad u = 1/2 sum_T V_T (mean_i M_i) . grad u_T
+// (M affine on the tet).  One thread per tet (octree order); the block sums
+// are added in a fixed order by k_sum_blocks.
+// ---------------------------------------------------------------------------
+constexpr int kEnergyThreads = 256;
+
+__global__ __launch_bounds__(kEnergyThreads) void k_demag(const double *__restrict__ tet_xyz,
+                                                          const int32_t *__restrict__ tet_node,
+                                                          const int32_t *__restrict__ tet_perm, int64_t T,
+                                                          const double *__restrict__ M, const double *__restrict__ u,
+                                                          double *__restrict__ H, double *__restrict__ part)
+{
+    __shared__ double s_e[kEnergyThreads];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    if (t < T) {
+        double v[4][3], uc[4], mbar[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int64_t nd = tet_node[(int64_t)c * T + t];
+            uc[c] = u[nd];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                v[c][k] = tet_xyz[(int64_t)(3 * c + k) * T + t];
+                mbar[k] += 0.25 * M[3 * nd + k];
+            }
+        }
+        double e1[3], e2[3], e3[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            e1[k] = v[1][k] - v[0][k];
+            e2[k] = v[2][k] - v[0][k];
+            e3[k] = v[3][k] - v[0][k];
+        }
+        // grad u = (u1-u0) g1 + (u2-u0) g2 + (u3-u0) g3, g_i = rows of the inverse Jacobian
+        double g1[3], g2[3], g3[3];
+        g1[0] = e2[1] * e3[2] - e2[2] * e3[1];
+        g1[1] = e2[2] * e3[0] - e2[0] * e3[2];
+        g1[2] = e2[0] * e3[1] - e2[1] * e3[0];
+        g2[0] = e3[1] * e1[2] - e3[2] * e1[1];
+        g2[1] = e3[2] * e1[0] - e3[0] * e1[2];
+        g2[2] = e3[0] * e1[1] - e3[1] * e1[0];
+        g3[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        g3[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        g3[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        const double det = e1[0] * g1[0] + e1[1] * g1[1] + e1[2] * g1[2];
+        double gu[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gu[k] = ((uc[1] - uc[0]) * g1[k] + (uc[2] - uc[0]) * g2[k] + (uc[3] - uc[0]) * g3[k]) / det;
+        e = 0.5 * (fabs(det) / 6.0) * (mbar[0] * gu[0] + mbar[1] * gu[1] + mbar[2] * gu[2]);
+        if (H) {
+            const int64_t o = tet_perm[t];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) H[3 * o + k] = -gu[k];
+        }
+    }
+    s_e[threadIdx.x] = e;
+    __syncthreads();
+    for (int w = kEnergyThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s_e[threadIdx.x] += s_e[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s_e[0];
+}
+
+__global__ __launch_bounds__(kEnergyThreads) void k_sum_blocks(const double *__restrict__ part, int n,
+                                                               double *__restrict__ out)
+{
+    __shared__ double s_e[kEnergyThreads];
+    double e = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) e += part[i];
+    s_e[threadIdx.x] = e;
+    __syncthreads();
+    for (int w = kEnergyThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s_e[threadIdx.x] += s_e[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s_e[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1270,7 +1353,10 @@ void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u,
     int f = 0;
     while (f < F) {
         const int left = F - f;
-        if (left >= 16) {
+        if (left >= 32) {
+            launch_p2p<32>(dp, direct, f, M, u, st);
+            f += 32;
+        } else if (left >= 16) {
             launch_p2p<16>(dp, direct, f, M, u, st);
             f += 16;
         } else if (left >= 8) {
@@ -1627,6 +1713,28 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
         KTimer kt(dp, KT_P2P, st);
         run_p2p(dp, false, M, F, u, st);
     }
+}
+
+double run_demag(DevicePlan &dp, const double *M, const double *u, double *H, hipStream_t st)
+{
+    const HostPlan &hp = dp.hp;
+    if (!hp.targets_are_nodes) throw DeviceError{"the plan's targets are not its nodes"};
+    const int64_t T = hp.n_tets;
+    const int nb = (int)((T + kEnergyThreads - 1) / kEnergyThreads);
+    double *part = nullptr;
+    hip_check(hipMalloc(&part, sizeof(double) * (size_t)(nb + 1)), "hipMalloc energy");
+    double E = 0.0;
+    hipError_t err = hipSuccess;
+    if (T > 0) {
+        k_demag<<<nb, kEnergyThreads, 0, st>>>(dp.tet_xyz, dp.tet_node, dp.tet_perm, T, M, u, H, part);
+        k_sum_blocks<<<1, kEnergyThreads, 0, st>>>(part, nb, part + nb);
+        err = hipGetLastError();
+        if (err == hipSuccess) err = hipMemcpyAsync(&E, part + nb, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (err == hipSuccess) err = hipStreamSynchronize(st);
+    }
+    (void)hipFree(part);
+    hip_check(err, "demag energy");
+    return E;
 }
 
 void run_direct(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t st)
