@@ -234,6 +234,10 @@ void upload_plan(DevicePlan &dp)
 void free_plan(DevicePlan &dp)
 {
     collect_timing(dp);
+    if (dp.side) (void)hipStreamSynchronize(dp.side);
+    if (dp.ev_fork) (void)hipEventDestroy(dp.ev_fork);
+    if (dp.ev_join) (void)hipEventDestroy(dp.ev_join);
+    if (dp.side) (void)hipStreamDestroy(dp.side);
     for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
     dp.event_pool.clear();
     void *ptrs[] = {dp.tet_xyz, dp.tet_node, dp.tet_perm, dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, dp.cell_c, dp.cell_i,

@@ -98,6 +98,11 @@ struct DevicePlan {
     float *sur_w = nullptr;
     uint16_t *sur_wb = nullptr;
 
+    // second stream (default priority) for the near field, forked from and
+    // joined back into the evaluation stream
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
     int64_t device_bytes = 0;
 
     // timing: event pairs recorded on the evaluation stream around each phase,

@@ -6,7 +6,7 @@
 //   m2l   multipole -> local translation of the Cartesian Taylor expansion on
 //         FP64 matrix cores, target cells in tiles sharing translation keys
 //   l2l   binomial shift of a local expansion to the child centres
-//   l2p   evaluation of the local expansion at the targets (writes u)
+//   l2p   evaluation of the local expansion at the targets (adds into u)
 //   p2p   exact near-field tet-to-target potential (Sec. 2.1), source-major:
 //         one workgroup per block of <= 64 tets of a source leaf, the tets'
 //         geometry and field coefficients staged in LDS, every lane a target,
@@ -1073,7 +1073,7 @@ __global__ __launch_bounds__(64 * kM2LBWaves, 2) void k_m2l_bf16(
 }
 
 // ---------------------------------------------------------------------------
-// L2P.  One thread per target (octree order); writes u[f][perm[i]].
+// L2P.  One thread per target (octree order); adds into u[f][perm[i]].
 //   u(x) = sum_m l_m (x - c)^m
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_l2p(const double *__restrict__ tgt_xyz, const int32_t *__restrict__ tgt_perm,
@@ -1108,7 +1108,7 @@ __global__ __launch_bounds__(256) void k_l2p(const double *__restrict__ tgt_xyz,
         }
         s += Ll[m] * (px * py * pz);
     }
-    u[(int64_t)f * N + tgt_perm[i]] = s;
+    atomicAdd(&u[(int64_t)f * N + tgt_perm[i]], s);  // the near field is added concurrently
 }
 
 constexpr int kP2PTets = 64;  // tets per block (direct sum)
@@ -1561,6 +1561,11 @@ void ensure_expansions(DevicePlan &dp, int32_t F)
 void prepare_evaluate(DevicePlan &dp, int32_t F)
 {
     const int64_t C = (int64_t)dp.hp.cells.size();
+    if (!dp.side) {
+        hip_check(hipStreamCreateWithFlags(&dp.side, hipStreamNonBlocking), "hipStreamCreate");
+        hip_check(hipEventCreateWithFlags(&dp.ev_fork, hipEventDisableTiming), "hipEventCreate");
+        hip_check(hipEventCreateWithFlags(&dp.ev_join, hipEventDisableTiming), "hipEventCreate");
+    }
     ensure_expansions(dp, F);
     ensure_m2l_tiles(dp, 16 / m2l_fpt(F));
     if (dp.m2l_precision != TFMM_M2L_FP64) {
@@ -1662,6 +1667,24 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
     const int p = hp.p;
     prepare_evaluate(dp, F);
     dp.last_F = F;
+    // u = 0, then the near field (P2P, needs only M) runs on the plan's side
+    // stream while the expansions are formed; both add into u atomically.
+    // Under stream capture (batch graphs) the near field stays on st, after
+    // the far field.
+    fill(u, (int64_t)F * hp.n_targets, 0.0, st);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hip_check(hipStreamIsCapturing(st, &cap), "hipStreamIsCapturing");
+    const bool fork = cap == hipStreamCaptureStatusNone;
+    auto fork_p2p = [&]() {
+        hip_check(hipEventRecord(dp.ev_fork, st), "hipEventRecord");
+        hip_check(hipStreamWaitEvent(dp.side, dp.ev_fork, 0), "hipStreamWaitEvent");
+        {
+            KTimer kt(dp, KT_P2P, dp.side);
+            run_p2p(dp, false, M, F, u, dp.side);
+        }
+        hip_check(hipEventRecord(dp.ev_join, dp.side), "hipEventRecord");
+    };
+    if (fork) fork_p2p();
     fill(dp.Q, (int64_t)F * C * dp.ncoef, 0.0, st);
     fill(dp.L, (int64_t)F * C * dp.ncoef, 0.0, st);
     const size_t shift_lds = sizeof(double) * 2 * kShiftItems * (size_t)dp.ncoef;
@@ -1709,7 +1732,9 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
                                                  dp.L, u);
         hip_check(hipGetLastError(), "k_l2p launch");
     }
-    {
+    if (fork) {
+        hip_check(hipStreamWaitEvent(st, dp.ev_join, 0), "hipStreamWaitEvent");
+    } else {
         KTimer kt(dp, KT_P2P, st);
         run_p2p(dp, false, M, F, u, st);
     }
