@@ -69,6 +69,20 @@ def measured_traffic(kernel):
     return t["bytes_per_launch"][kernel]
 
 
+def kernel_breakdown(T, torch, plan, M, u, steps):
+    """Per-phase times (HIP event pairs on the evaluation stream) from separate
+    evaluations with timing on; the phases then run one after another, so the
+    times are not shared with the concurrent near field of the timed steps."""
+    torch.cuda.synchronize()
+    T.tfmm_set_timing(plan, True)
+    for _ in range(steps):
+        T.tfmm_evaluate(plan, M, u)
+    torch.cuda.synchronize()
+    kt = T.tfmm_kernel_times(plan)
+    T.tfmm_set_timing(plan, False)
+    return kt
+
+
 def ragged_batch(T, torch, steps):
     """32 jittered cubes with 2k-200k tets (log-uniform), one field each, p=8,
     leaf 64, theta 0.5, FP64: one eager evaluation per mesh vs the batch's
@@ -159,15 +173,12 @@ def main():
     for _ in range(args.warmup):
         T.tfmm_evaluate(plan, Md, u)
     torch.cuda.synchronize()
-    T.tfmm_set_timing(plan, True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         T.tfmm_evaluate(plan, Md, u)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    ktimes = T.tfmm_kernel_times(plan)
-    T.tfmm_set_timing(plan, False)
+    ktimes = kernel_breakdown(T, torch, plan, Md, u, args.steps)
     err = max(float(torch.linalg.norm(u[f] - ud[f]) / torch.linalg.norm(ud[f])) for f in range(W["F"]))
 
     evals = nodes.shape[0] * W["F"]
@@ -221,14 +232,12 @@ def main():
             T.tfmm_evaluate(plan, Mv, uv)
             udv = T.tfmm_direct(plan, Mv) if F > 1 else ud
             torch.cuda.synchronize()
-            T.tfmm_set_timing(plan, True)
             t1 = time.perf_counter()
             for _ in range(args.variant_steps):
                 T.tfmm_evaluate(plan, Mv, uv)
             torch.cuda.synchronize()
             dv = (time.perf_counter() - t1) / args.variant_steps
-            kv = T.tfmm_kernel_times(plan)
-            T.tfmm_set_timing(plan, False)
+            kv = kernel_breakdown(T, torch, plan, Mv, uv, 2)
             ev = max(float(torch.linalg.norm(uv[f] - udv[f]) / torch.linalg.norm(udv[f])) for f in range(F))
             variants[name] = {"value": nodes.shape[0] * F / dv, "unit": "evals/s", "ms_per_step": dv * 1e3,
                               "fields": F, "m2l": {T.M2L_FP64: "fp64", T.M2L_FP32: "fp32", T.M2L_BF16X3: "bf16x3",

@@ -208,6 +208,25 @@ void upload_plan(DevicePlan &dp)
         dp.n_p2p_idx = (int64_t)idx.size();
         dp.p2p_blk = dev_upload(blk, B);
         dp.p2p_idx = dev_upload(idx, B);
+        // shared mesh entities of the source blocks (single-field near field)
+        NearTopo tp;
+        build_near_topology(hp, blk, tp);
+        dp.n_topo_ch = (int32_t)(tp.ch_i.size() / 8);
+        dp.n_topo_edges = (int64_t)tp.ed_il.size();
+        dp.n_topo_faces = (int64_t)(tp.fc_n.size() / 3);
+        dp.topo_blk = dev_upload(tp.blk, B);
+        dp.topo_ch_i = dev_upload(tp.ch_i, B);
+        dp.topo_ch_c = dev_upload(tp.ch_c, B);
+        dp.topo_w = dev_upload(tp.nd_w, B);
+        dp.topo_ab = dev_upload(tp.ed_ab, B);
+        dp.topo_il = dev_upload(tp.ed_il, B);
+        dp.topo_pqr = dev_upload(tp.fc_pqr, B);
+        dp.topo_n = dev_upload(tp.fc_n, B);
+        dp.topo_inc = dev_upload(tp.inc, B);
+        std::vector<double> zA(4 * (size_t)std::max<int64_t>(dp.n_topo_faces, 1)),
+            zB(11 * (size_t)std::max<int64_t>(dp.n_topo_edges, 1));
+        dp.topo_A = dev_upload(zA, B);
+        dp.topo_B = dev_upload(zB, B);
     }
     {
         dp.n_m2l_keys = (int32_t)(hp.m2l_keys.size() / 4);
@@ -242,7 +261,9 @@ void free_plan(DevicePlan &dp)
     dp.event_pool.clear();
     void *ptrs[] = {dp.tet_xyz, dp.tet_node, dp.tet_perm, dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, dp.cell_c, dp.cell_i,
                     dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.p2p_blk, dp.p2p_idx, dp.quad, dp.tet_mom, dp.Q,
-                    dp.L, dp.Qt, dp.Qtf, dp.m2l_keys, dp.m2l_D, dp.m2l_Df, dp.sur_w, dp.sur_wb};
+                    dp.L, dp.Qt, dp.Qtf, dp.m2l_keys, dp.m2l_D, dp.m2l_Df, dp.sur_w, dp.sur_wb, dp.topo_blk,
+                    dp.topo_ch_i, dp.topo_ch_c, dp.topo_w, dp.topo_ab, dp.topo_il, dp.topo_pqr, dp.topo_n,
+                    dp.topo_inc, dp.topo_A, dp.topo_B};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : dp.m2l_tiles) {

@@ -1180,6 +1180,190 @@ __global__ __launch_bounds__(p2p_threads(FCH, WIDE), 2) void k_p2p(const int32_t
 }
 
 // ---------------------------------------------------------------------------
+// Single-field near field over the shared mesh entities of a source chunk.
+//
+// Summed over the tets T of a chunk, the pair formula regroups by entity:
+//   4 pi u(x) = sum_edges [ f_e il_e B_e(y) + Gamma_e g_e ] - sum_faces A_F(y) h_F Omega_F
+// with y = x - c (c the chunk's node centroid), f_e the edge log (the line
+// integral of 1/R, independent of the edge direction), g_e = R0^2 f +
+// l_b R_b - l_a R_a (also direction independent), h_F Omega_F the face's
+// height times solid angle in any fixed orientation (the product does not
+// change with it), and the field weights
+//   A_F(y)   = sum_{T, k: face k of T is F} alpha_{T,k}(y)                     (affine)
+//   B_e(y)   = sum_{T, k, e in face k} s_{k,e} alpha_{T,k}(y) n_k.(d_a x d_b)  (quadratic)
+//   Gamma_e  = sum_{T: e in T} gamma_{T,e}
+// (alpha affine in y, d = v - x).  k_topo_coef forms them once per evaluation;
+// k_p2p_topo then evaluates one square root per node, one log per edge and
+// one solid angle per face of the chunk for every target.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_topo_coef(const int32_t *__restrict__ ch_i, const double *__restrict__ ch_c,
+                                                  int nch, const int32_t *__restrict__ inc,
+                                                  const double *__restrict__ tet_xyz,
+                                                  const int32_t *__restrict__ tet_node, int64_t T,
+                                                  const double *__restrict__ M, double *__restrict__ A,
+                                                  double *__restrict__ Bc)
+{
+    __shared__ double s_A[kTopoFaces][4];
+    __shared__ double s_B[kTopoEdges][11];
+    const int ch = blockIdx.x;
+    if (ch >= nch) return;
+    const int tb = ch_i[8 * ch], nt = ch_i[8 * ch + 1], eoff = ch_i[8 * ch + 4], ne = ch_i[8 * ch + 5],
+              foff = ch_i[8 * ch + 6], nf = ch_i[8 * ch + 7];
+    const double c[3] = {ch_c[3 * ch], ch_c[3 * ch + 1], ch_c[3 * ch + 2]};
+    for (int i = threadIdx.x; i < kTopoFaces * 4; i += blockDim.x) (&s_A[0][0])[i] = 0.0;
+    for (int i = threadIdx.x; i < kTopoEdges * 11; i += blockDim.x) (&s_B[0][0])[i] = 0.0;
+    __syncthreads();
+    if ((int)threadIdx.x < nt) {
+        const int64_t t = tb + threadIdx.x;
+        TetGeom G;
+        TetField Fd;
+        tet_prepare(tet_xyz, tet_node, T, t, M, &G, Fd);
+        double w[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) w[q][k] = G.v[q][k] - c[k];
+        const int32_t *ti = inc + 10 * t;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double *n = G.n[k];
+            const int a = kFv[k][0];
+            // alpha_k(y) = a0 + a1 . y
+            const double a1[3] = {Fd.b[k][0] - Fd.c[k] * n[0], Fd.b[k][1] - Fd.c[k] * n[1], Fd.b[k][2] - Fd.c[k] * n[2]};
+            const double a0 = Fd.a[k] - (w[0][0] * Fd.b[k][0] + w[0][1] * Fd.b[k][1] + w[0][2] * Fd.b[k][2]) +
+                              Fd.c[k] * (n[0] * w[a][0] + n[1] * w[a][1] + n[2] * w[a][2]);
+            double *Af = s_A[ti[6 + k]];
+            atomicAdd(&Af[0], a0);
+            atomicAdd(&Af[1], a1[0]);
+            atomicAdd(&Af[2], a1[1]);
+            atomicAdd(&Af[3], a1[2]);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int e = kFe[k][j];
+                const double sg = kFs[k][j];
+                const int ea = kEa[e], eb = kEb[e];
+                // n . ((w_a - y) x (w_b - y)) = t0 + t1 . y
+                const double cx[3] = {w[ea][1] * w[eb][2] - w[ea][2] * w[eb][1], w[ea][2] * w[eb][0] - w[ea][0] * w[eb][2],
+                                      w[ea][0] * w[eb][1] - w[ea][1] * w[eb][0]};
+                const double t0 = n[0] * cx[0] + n[1] * cx[1] + n[2] * cx[2];
+                const double u[3] = {w[ea][0] - w[eb][0], w[ea][1] - w[eb][1], w[ea][2] - w[eb][2]};
+                const double t1[3] = {u[1] * n[2] - u[2] * n[1], u[2] * n[0] - u[0] * n[2], u[0] * n[1] - u[1] * n[0]};
+                double *Be = s_B[ti[e]];
+                atomicAdd(&Be[0], sg * a0 * t0);
+                atomicAdd(&Be[1], sg * (a0 * t1[0] + t0 * a1[0]));
+                atomicAdd(&Be[2], sg * (a0 * t1[1] + t0 * a1[1]));
+                atomicAdd(&Be[3], sg * (a0 * t1[2] + t0 * a1[2]));
+                atomicAdd(&Be[4], sg * a1[0] * t1[0]);
+                atomicAdd(&Be[5], sg * (a1[0] * t1[1] + a1[1] * t1[0]));
+                atomicAdd(&Be[6], sg * (a1[0] * t1[2] + a1[2] * t1[0]));
+                atomicAdd(&Be[7], sg * a1[1] * t1[1]);
+                atomicAdd(&Be[8], sg * (a1[1] * t1[2] + a1[2] * t1[1]));
+                atomicAdd(&Be[9], sg * a1[2] * t1[2]);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 6; ++e) atomicAdd(&s_B[ti[e]][10], Fd.g[e]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nf * 4; i += blockDim.x) A[(int64_t)foff * 4 + i] = (&s_A[0][0])[i];
+    for (int i = threadIdx.x; i < ne * 11; i += blockDim.x) Bc[(int64_t)eoff * 11 + i] = (&s_B[0][0])[i];
+}
+
+__global__ __launch_bounds__(64, 2) void k_p2p_topo(const int32_t *__restrict__ blk, int nblk,
+                                                    const int32_t *__restrict__ ch_i, const double *__restrict__ ch_c,
+                                                    const double *__restrict__ nw, const int32_t *__restrict__ eab,
+                                                    const double *__restrict__ eil, const int32_t *__restrict__ fpqr,
+                                                    const double *__restrict__ fn, const double *__restrict__ A,
+                                                    const double *__restrict__ Bc, const int32_t *__restrict__ idx,
+                                                    const double *__restrict__ tgt_xyz,
+                                                    const int32_t *__restrict__ tgt_perm, int64_t N,
+                                                    double *__restrict__ u)
+{
+    __shared__ double s_w[kTopoNodes][3];
+    __shared__ double s_R[kTopoNodes][64];
+    __shared__ int s_ea[kTopoEdges], s_eb[kTopoEdges];
+    __shared__ double s_il[kTopoEdges], s_B[kTopoEdges][11];
+    __shared__ int s_fp[kTopoFaces], s_fq[kTopoFaces], s_fr[kTopoFaces];
+    __shared__ double s_fn[kTopoFaces][3], s_A[kTopoFaces][4];
+    const int b = xcd_item(nblk);
+    if (b < 0) return;
+    const int cb = blk[4 * b], ce = blk[4 * b + 1], ib = blk[4 * b + 2], ie = blk[4 * b + 3];
+    const int lane = threadIdx.x;
+    for (int ch = cb; ch < ce; ++ch) {
+        const int noff = ch_i[8 * ch + 2], nn = ch_i[8 * ch + 3], eoff = ch_i[8 * ch + 4], ne = ch_i[8 * ch + 5],
+                  foff = ch_i[8 * ch + 6], nf = ch_i[8 * ch + 7];
+        const double c[3] = {ch_c[3 * ch], ch_c[3 * ch + 1], ch_c[3 * ch + 2]};
+        __syncthreads();
+        for (int i = lane; i < nn * 3; i += 64) (&s_w[0][0])[i] = nw[(int64_t)noff * 3 + i];
+        for (int i = lane; i < ne; i += 64) {
+            s_ea[i] = eab[2 * ((int64_t)eoff + i)];
+            s_eb[i] = eab[2 * ((int64_t)eoff + i) + 1];
+            s_il[i] = eil[eoff + i];
+        }
+        for (int i = lane; i < ne * 11; i += 64) (&s_B[0][0])[i] = Bc[(int64_t)eoff * 11 + i];
+        for (int i = lane; i < nf; i += 64) {
+            s_fp[i] = fpqr[3 * ((int64_t)foff + i)];
+            s_fq[i] = fpqr[3 * ((int64_t)foff + i) + 1];
+            s_fr[i] = fpqr[3 * ((int64_t)foff + i) + 2];
+        }
+        for (int i = lane; i < nf * 3; i += 64) (&s_fn[0][0])[i] = fn[(int64_t)foff * 3 + i];
+        for (int i = lane; i < nf * 4; i += 64) (&s_A[0][0])[i] = A[(int64_t)foff * 4 + i];
+        __syncthreads();
+        for (int i = ib + lane; i < ie; i += 64) {
+            const int s = idx[i];
+            const double y[3] = {tgt_xyz[s] - c[0], tgt_xyz[N + s] - c[1], tgt_xyz[2 * N + s] - c[2]};
+            const double m[10] = {1.0,         y[0],        y[1],        y[2],        y[0] * y[0],
+                                  y[0] * y[1], y[0] * y[2], y[1] * y[1], y[1] * y[2], y[2] * y[2]};
+#pragma unroll 1
+            for (int j = 0; j < nn; ++j) {
+                const double d0 = s_w[j][0] - y[0], d1 = s_w[j][1] - y[1], d2 = s_w[j][2] - y[2];
+                s_R[j][lane] = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
+            }
+            double acc = 0.0;
+#pragma unroll 1
+            for (int e = 0; e < ne; ++e) {
+                const int a = s_ea[e], bb = s_eb[e];
+                const double il = s_il[e];
+                const double da[3] = {s_w[a][0] - y[0], s_w[a][1] - y[1], s_w[a][2] - y[2]};
+                const double db[3] = {s_w[bb][0] - y[0], s_w[bb][1] - y[1], s_w[bb][2] - y[2]};
+                const double Ra = s_R[a][lane], Rb = s_R[bb][lane];
+                const double ev[3] = {db[0] - da[0], db[1] - da[1], db[2] - da[2]};
+                const double la = (da[0] * ev[0] + da[1] * ev[1] + da[2] * ev[2]) * il;  // (v_a - x) . e_hat
+                const double lb = (db[0] * ev[0] + db[1] * ev[1] + db[2] * ev[2]) * il;  // (v_b - x) . e_hat
+                const double cx0 = da[1] * db[2] - da[2] * db[1], cx1 = da[2] * db[0] - da[0] * db[2],
+                             cx2 = da[0] * db[1] - da[1] * db[0];
+                const double r0sq = (cx0 * cx0 + cx1 * cx1 + cx2 * cx2) * (il * il);
+                const double f = edge_log(Ra, Rb, la, lb, r0sq);
+                const double g = r0sq * f + lb * Rb - la * Ra;
+                const double *Be = s_B[e];
+                double bq = 0.0;
+#pragma unroll
+                for (int q = 0; q < 10; ++q) bq = fma(Be[q], m[q], bq);
+                acc = fma(f * il, bq, fma(Be[10], g, acc));
+            }
+#pragma unroll 1
+            for (int fi = 0; fi < nf; ++fi) {
+                const int pp = s_fp[fi], qq = s_fq[fi], rr = s_fr[fi];
+                const double dp[3] = {s_w[pp][0] - y[0], s_w[pp][1] - y[1], s_w[pp][2] - y[2]};
+                const double dq[3] = {s_w[qq][0] - y[0], s_w[qq][1] - y[1], s_w[qq][2] - y[2]};
+                const double dr[3] = {s_w[rr][0] - y[0], s_w[rr][1] - y[1], s_w[rr][2] - y[2]};
+                const double Rp = s_R[pp][lane], Rq = s_R[qq][lane], Rr = s_R[rr][lane];
+                const double Dpq = dp[0] * dq[0] + dp[1] * dq[1] + dp[2] * dq[2];
+                const double Dpr = dp[0] * dr[0] + dp[1] * dr[1] + dp[2] * dr[2];
+                const double Dqr = dq[0] * dr[0] + dq[1] * dr[1] + dq[2] * dr[2];
+                const double det = dp[0] * (dq[1] * dr[2] - dq[2] * dr[1]) + dp[1] * (dq[2] * dr[0] - dq[0] * dr[2]) +
+                                   dp[2] * (dq[0] * dr[1] - dq[1] * dr[0]);
+                const double den = Rp * Rq * Rr + Dpq * Rr + Dpr * Rq + Dqr * Rp;
+                const double h = s_fn[fi][0] * dp[0] + s_fn[fi][1] * dp[1] + s_fn[fi][2] * dp[2];
+                const double af = s_A[fi][0] + (s_A[fi][1] * y[0] + s_A[fi][2] * y[1] + s_A[fi][3] * y[2]);
+                acc = fma(-af * h, 2.0 * atan2_nr(det, den), acc);
+            }
+            atomicAdd(&u[tgt_perm[s]], acc * kInv4Pi);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Demagnetising field and energy from nodal potentials (P1 interpolation):
 // per tet H_T = -grad u = -sum_i u_i grad lambda_i, and
 //   E / mu0 = 1/2 sum_T int_T M . grad u = 1/2 sum_T V_T (mean_i M_i) . grad u_T
@@ -1350,6 +1534,19 @@ void launch_p2p(DevicePlan &dp, bool direct, int f0, const double *M, double *u,
 
 void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u, hipStream_t st)
 {
+    if (!direct && F == 1 && dp.p2p_topo && dp.n_topo_ch > 0) {
+        const HostPlan &hp = dp.hp;
+        k_topo_coef<<<dim3(dp.n_topo_ch), dim3(64), 0, st>>>(dp.topo_ch_i, dp.topo_ch_c, dp.n_topo_ch, dp.topo_inc,
+                                                             dp.tet_xyz, dp.tet_node, hp.n_tets, M, dp.topo_A,
+                                                             dp.topo_B);
+        hip_check(hipGetLastError(), "k_topo_coef launch");
+        const int nblk = dp.n_p2p_blk;
+        k_p2p_topo<<<dim3(xcd_grid(nblk)), dim3(64), 0, st>>>(
+            dp.topo_blk, nblk, dp.topo_ch_i, dp.topo_ch_c, dp.topo_w, dp.topo_ab, dp.topo_il, dp.topo_pqr, dp.topo_n,
+            dp.topo_A, dp.topo_B, dp.p2p_idx, dp.tgt_xyz, dp.tgt_perm, hp.n_targets, u);
+        hip_check(hipGetLastError(), "k_p2p_topo launch");
+        return;
+    }
     int f = 0;
     while (f < F) {
         const int left = F - f;
@@ -1674,7 +1871,8 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
     fill(u, (int64_t)F * hp.n_targets, 0.0, st);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     hip_check(hipStreamIsCapturing(st, &cap), "hipStreamIsCapturing");
-    const bool fork = cap == hipStreamCaptureStatusNone;
+    // with per-phase timing on, the phases run one after another (isolated times)
+    const bool fork = cap == hipStreamCaptureStatusNone && !dp.timing;
     auto fork_p2p = [&]() {
         hip_check(hipEventRecord(dp.ev_fork, st), "hipEventRecord");
         hip_check(hipStreamWaitEvent(dp.side, dp.ev_fork, 0), "hipStreamWaitEvent");

@@ -204,15 +204,12 @@ __device__ __forceinline__ double log_ratio(double num, double den)
 {
     int ei, ej;
     double a = frexp(num, &ei), b = frexp(den, &ej);
-    int e = ei - ej;
     const double kSqrt2 = 1.4142135623730951;
-    if (a * kSqrt2 < b) {  // a/b < 1/sqrt2
-        a += a;
-        e -= 1;
-    } else if (a > b * kSqrt2) {  // a/b > sqrt2
-        b += b;
-        e += 1;
-    }
+    const bool lo = a * kSqrt2 < b;            // a/b < 1/sqrt2
+    const bool hi = !lo && a > b * kSqrt2;     // a/b > sqrt2
+    a = lo ? a + a : a;
+    b = hi ? b + b : b;
+    const int e = ei - ej + (hi ? 1 : 0) - (lo ? 1 : 0);
     const double sv = div_nr(a - b, a + b);
     const double z = sv * sv;
     double q = 1.0 / 23.0;
@@ -230,6 +227,22 @@ __device__ __forceinline__ double log_ratio(double num, double den)
     const double kLn2Hi = 6.93147180369123816490e-01, kLn2Lo = 1.90821492927058770002e-10;
     const double de = (double)e;
     return fma(de, kLn2Hi, fma(de, kLn2Lo, t) + 2.0 * sv);
+}
+
+// The edge integral ln((R_b + l_b)/(R_a + l_a)) in a cancellation-free form:
+// as written for l_a >= 0, as ln((R_a - l_a)/(R_b - l_b)) for l_b <= 0, and
+// as ln((R_b + l_b)(R_a - l_a)/R0^2) in between.  0 when a corner coincides
+// with the target or the ratio degenerates (its factors t0 and R0^2 vanish
+// there).  Branch free: every candidate is formed and one is selected.
+__device__ __forceinline__ double edge_log(double Ra, double Rb, double la, double lb, double r0sq)
+{
+    const bool fwd = la >= 0.0, bwd = lb <= 0.0;
+    const double p = Rb + lb, q = Ra - la;
+    const double num = fwd ? p : (bwd ? q : p * q);
+    const double den = fwd ? (Ra + la) : (bwd ? (Rb - lb) : r0sq);
+    const bool ok = (Ra > 0.0) && (Rb > 0.0) && (den > 0.0) && (num > 0.0);
+    const double f = log_ratio(ok ? num : 1.0, ok ? den : 1.0);
+    return ok ? f : 0.0;
 }
 
 // atan2(y, x) in (-pi, pi], 0 for y = x = 0, with one division: with
@@ -308,11 +321,7 @@ __device__ __forceinline__ void pair_accumulate(const double x[3], const TetGeom
         const double la = (D[a][b] - R2[a]) * il;  // (v_a - x) . e_hat
         const double lb = (R2[b] - D[a][b]) * il;  // (v_b - x) . e_hat
         // f = ln((R_b + l_b)/(R_a + l_a)) in a form free of cancellation
-        const bool fwd = la >= 0.0, bwd = lb <= 0.0;
-        const double num = fwd ? (R[b] + lb) : (bwd ? (R[a] - la) : (R[b] + lb) * (R[a] - la));
-        const double den = fwd ? (R[a] + la) : (bwd ? (R[b] - lb) : r0sq);
-        const bool ok = (R[a] > 0.0) && (R[b] > 0.0) && (den > 0.0);
-        const double fe = ok ? log_ratio(num, den) : 0.0;  // factors t0 and R0^2 vanish otherwise
+        const double fe = edge_log(R[a], R[b], la, lb, r0sq);
         const double fl = fe * il;
         ge[e] = r0sq * fe + lb * R[b] - la * R[a];
 #pragma unroll

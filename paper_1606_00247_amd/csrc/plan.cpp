@@ -402,4 +402,109 @@ void build_m2l_tiles(const HostPlan &hp, int tpt, int max_ent, M2LTiles &out)
     }
 }
 
+
+void build_near_topology(const HostPlan &hp, const std::vector<int32_t> &blk, NearTopo &out)
+{
+    static const int kEa[6] = {0, 0, 0, 1, 1, 2}, kEb[6] = {1, 2, 3, 2, 3, 3};
+    static const int kFv[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
+    out = NearTopo{};
+    out.inc.assign((size_t)hp.n_tets * 10, -1);
+    const size_t nblk = blk.size() / 4;
+    std::vector<int32_t> nodes, edges, faces;  // chunk: node ids, (a,b) id pairs, (p,q,r) id triples
+    auto find = [](const std::vector<int32_t> &v, const int32_t *key, int w) -> int {
+        for (size_t i = 0; i < v.size() / w; ++i) {
+            bool eq = true;
+            for (int k = 0; k < w; ++k) eq = eq && v[i * w + k] == key[k];
+            if (eq) return (int)i;
+        }
+        return -1;
+    };
+    for (size_t b = 0; b < nblk; ++b) {
+        const int32_t tb = blk[4 * b], te = blk[4 * b + 1];
+        out.blk.push_back((int32_t)(out.ch_i.size() / 8));
+        int32_t s = tb;
+        while (s < te) {
+            nodes.clear();
+            edges.clear();
+            faces.clear();
+            int32_t t = s;
+            for (; t < te && t - s < kTopoTets; ++t) {
+                const int32_t *v = &hp.tet_nodes[4 * (size_t)t];
+                // entities this tet would add
+                std::vector<int32_t> nn, ne, nf;
+                for (int c = 0; c < 4; ++c)
+                    if (find(nodes, &v[c], 1) < 0 && find(nn, &v[c], 1) < 0) nn.push_back(v[c]);
+                for (int e = 0; e < 6; ++e) {
+                    const int32_t key[2] = {std::min(v[kEa[e]], v[kEb[e]]), std::max(v[kEa[e]], v[kEb[e]])};
+                    if (find(edges, key, 2) < 0 && find(ne, key, 2) < 0) ne.insert(ne.end(), key, key + 2);
+                }
+                for (int k = 0; k < 4; ++k) {
+                    int32_t key[3] = {v[kFv[k][0]], v[kFv[k][1]], v[kFv[k][2]]};
+                    std::sort(key, key + 3);
+                    if (find(faces, key, 3) < 0 && find(nf, key, 3) < 0) nf.insert(nf.end(), key, key + 3);
+                }
+                if (nodes.size() + nn.size() > (size_t)kTopoNodes || (edges.size() + ne.size()) / 2 > (size_t)kTopoEdges ||
+                    (faces.size() + nf.size()) / 3 > (size_t)kTopoFaces)
+                    break;
+                nodes.insert(nodes.end(), nn.begin(), nn.end());
+                edges.insert(edges.end(), ne.begin(), ne.end());
+                faces.insert(faces.end(), nf.begin(), nf.end());
+                for (int e = 0; e < 6; ++e) {
+                    const int32_t key[2] = {std::min(v[kEa[e]], v[kEb[e]]), std::max(v[kEa[e]], v[kEb[e]])};
+                    out.inc[10 * (size_t)t + e] = find(edges, key, 2);
+                }
+                for (int k = 0; k < 4; ++k) {
+                    int32_t key[3] = {v[kFv[k][0]], v[kFv[k][1]], v[kFv[k][2]]};
+                    std::sort(key, key + 3);
+                    out.inc[10 * (size_t)t + 6 + k] = find(faces, key, 3);
+                }
+            }
+            // chunk record
+            const int32_t noff = (int32_t)(out.nd_w.size() / 3), eoff = (int32_t)out.ed_il.size(),
+                          foff = (int32_t)(out.fc_n.size() / 3);
+            double c[3] = {0.0, 0.0, 0.0};
+            for (int32_t id : nodes)
+                for (int k = 0; k < 3; ++k) c[k] += hp.nodes[3 * (size_t)id + k];
+            for (int k = 0; k < 3; ++k) c[k] /= (double)nodes.size();
+            auto local = [&](int32_t id) { return find(nodes, &id, 1); };
+            auto pos = [&](int32_t id, int k) { return hp.nodes[3 * (size_t)id + k] - c[k]; };
+            for (int32_t id : nodes)
+                for (int k = 0; k < 3; ++k) out.nd_w.push_back(pos(id, k));
+            for (size_t e = 0; e < edges.size() / 2; ++e) {
+                const int32_t a = edges[2 * e], bb = edges[2 * e + 1];
+                out.ed_ab.push_back(local(a));
+                out.ed_ab.push_back(local(bb));
+                double d2 = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    const double dk = pos(bb, k) - pos(a, k);
+                    d2 += dk * dk;
+                }
+                out.ed_il.push_back(1.0 / std::sqrt(d2));
+            }
+            for (size_t f = 0; f < faces.size() / 3; ++f) {
+                const int32_t pp = faces[3 * f], qq = faces[3 * f + 1], rr = faces[3 * f + 2];
+                out.fc_pqr.push_back(local(pp));
+                out.fc_pqr.push_back(local(qq));
+                out.fc_pqr.push_back(local(rr));
+                double u[3], w[3];
+                for (int k = 0; k < 3; ++k) {
+                    u[k] = pos(qq, k) - pos(pp, k);
+                    w[k] = pos(rr, k) - pos(pp, k);
+                }
+                const double n[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+                const double il = 1.0 / std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+                for (int k = 0; k < 3; ++k) out.fc_n.push_back(n[k] * il);
+            }
+            const int32_t rec[8] = {s, t - s, noff, (int32_t)nodes.size(), eoff, (int32_t)(edges.size() / 2), foff,
+                                    (int32_t)(faces.size() / 3)};
+            out.ch_i.insert(out.ch_i.end(), rec, rec + 8);
+            out.ch_c.insert(out.ch_c.end(), c, c + 3);
+            s = t;
+        }
+        out.blk.push_back((int32_t)(out.ch_i.size() / 8));
+        out.blk.push_back(blk[4 * b + 2]);
+        out.blk.push_back(blk[4 * b + 3]);
+    }
+}
+
 }  // namespace tfmm

@@ -76,6 +76,31 @@ struct M2LTiles {
     std::vector<int32_t> ent_src;   // [nent][tpt]
 };
 
+// Mesh entities of the near-field source blocks.  Each P2P block (<= 64 tets
+// of one leaf, [tbeg, tend) in octree order) is cut into chunks of at most
+// kTopoTets tets with at most kTopoNodes distinct nodes, kTopoEdges edges and
+// kTopoFaces faces; per chunk the distinct nodes (positions relative to the
+// chunk's node centroid), edges (canonical direction: lower node id first,
+// inverse length) and faces (nodes in increasing id order, unit normal of
+// that order), and per tet the chunk-local indices of its 6 edges (corner
+// pairs (0,1),(0,2),(0,3),(1,2),(1,3),(2,3)) and 4 faces (face k opposite
+// corner k).
+constexpr int kTopoTets = 16, kTopoNodes = 16, kTopoEdges = 48, kTopoFaces = 40;
+struct NearTopo {
+    std::vector<int32_t> blk;     // [nblk][4]: chunk begin, chunk end, target begin, target end
+    std::vector<int32_t> ch_i;    // [nch][8]: tbeg, ntets, node off, nodes, edge off, edges, face off, faces
+    std::vector<double> ch_c;     // [nch][3] node centroid
+    std::vector<double> nd_w;     // [nodes][3] position - centroid
+    std::vector<int32_t> ed_ab;   // [edges][2] chunk-local nodes
+    std::vector<double> ed_il;    // [edges] 1 / length
+    std::vector<int32_t> fc_pqr;  // [faces][3] chunk-local nodes
+    std::vector<double> fc_n;     // [faces][3] unit normal of (q - p) x (r - p)
+    std::vector<int32_t> inc;     // [T][10] per tet: 6 edge, 4 face chunk-local indices
+};
+
+// Builds the chunks of the P2P blocks blk ([nblk][4]: tbeg, tend, ibeg, iend).
+void build_near_topology(const HostPlan &hp, const std::vector<int32_t> &blk, NearTopo &out);
+
 // Error raised by the plan builder: code is one of the TFMM_E* values.
 struct PlanError {
     int code;
