@@ -32,6 +32,7 @@ P2P_ARITH_FLOPS = 410
 P2P_FIELD_FLOPS = 53
 P2P_TRANS_FLOPS = 6 * 76 + 4 * 44 + 4 * 14 + 6 * 11
 FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
 METRIC = "potential evals/s at \u22641e-5 rel-L2 vs FP64 direct: plain FP64 FMM vs mixed/batched"
 
 WORKLOADS = {
@@ -224,8 +225,18 @@ def main():
     if not args.no_variants:
         # the mixed-precision and field-batched forms on the same mesh
         variants = {}
-        for name, prec, F in (("m2l_fp32", T.M2L_FP32, 1), ("fields16_fp64", T.M2L_FP64, 16),
-                              ("fields16_m2l_fp32", T.M2L_FP32, 16), ("fields16_m2l_bf16x3", T.M2L_BF16X3, 16)):
+        cases = [("m2l_fp32", T.M2L_FP32, 1, False), ("fields16_fp64", T.M2L_FP64, 16, False),
+                 ("fields16_m2l_fp32", T.M2L_FP32, 16, False), ("fields16_m2l_bf16x3", T.M2L_BF16X3, 16, False),
+                 ("near_stored", T.M2L_FP64, 1, True), ("near_stored_m2l_fp32", T.M2L_FP32, 1, True),
+                 ("near_stored_fields16_m2l_fp32", T.M2L_FP32, 16, True)]
+        for name, prec, F, stored in cases:
+            if stored and "near_store" not in out:
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                T.tfmm_plan_store_near(plan)
+                t_store = time.perf_counter() - t1
+                sn = T.tfmm_plan_stats(plan)
+                out["near_store"] = {"assembly_s": t_store, "nnz": sn["near_nnz"], "bytes": sn["near_bytes"]}
             T.tfmm_plan_set_m2l_precision(plan, prec)
             Mv = torch.from_numpy(meshgen.random_fields(nodes.shape[0], F=F, seed=1)).to(dev)
             uv = torch.empty((F, nodes.shape[0]), dtype=torch.float64, device=dev)
@@ -245,7 +256,17 @@ def main():
                               "rel_l2_vs_direct_max_over_fields": ev,
                               "speedup_vs_plain": (nodes.shape[0] * F / dv) / value,
                               "kernel_ms": {k: round(v[0], 4) for k, v in kv.items()}}
+            if stored:
+                # the near field is a sparse product: HBM bound; algorithmic bytes = the
+                # coefficient blocks and column lists once, M gathered once per field, u
+                # read and written once per field
+                nb = out["near_store"]["bytes"] + F * nodes.shape[0] * (24 + 16)
+                gbs = nb / (kv["p2p"][0] * 1e-3) / 1e9
+                variants[name]["near_roofline"] = {"kernel": "near_apply", "bound": "hbm", "achieved": round(gbs, 1),
+                                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                                   "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes": nb}
             del Mv, uv, udv
+        T.tfmm_plan_store_near(plan, False)
         T.tfmm_plan_set_m2l_precision(plan, T.M2L_FP64)
         variants["ragged32"] = ragged_batch(T, torch, args.variant_steps)
         out["variants"] = variants

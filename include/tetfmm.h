@@ -96,6 +96,8 @@ typedef struct {
     int64_t ncoef;       /* (p+1)(p+2)(p+3)/6 */
     int64_t device_bytes; /* device memory held by the plan */
     double setup_seconds; /* wall time of tfmm_plan_create */
+    int64_t near_nnz;     /* (target, node) coefficients of the stored near field, 0 if none */
+    int64_t near_bytes;   /* device bytes of the stored near field */
 } tfmm_stats;
 
 /*
@@ -131,6 +133,23 @@ int tfmm_evaluate(tfmm_plan plan, const double *M, int32_t F, double *u, void *h
  * targets and all tets, in FP64.  Same arguments and errors as tfmm_evaluate.
  */
 int tfmm_direct(tfmm_plan plan, const double *M, int32_t F, double *u, void *hip_stream);
+
+/*
+ * Stored near-field operator (Sec. 2.1 "Direct Vertex Interaction" and the
+ * storage discussion of Sec. 3: the direct part is a linear map from the
+ * nodal magnetisation to the target potentials, node-to-node vectors kept for
+ * a fixed mesh).  on != 0 assembles, once, the 3-vector coefficient of every
+ * (target, node) pair in the near field (the nodes of the tets of the P2P
+ * source leaves of the target's leaf; nnz and bytes in tfmm_stats) on
+ * `hip_stream` and synchronises it; later evaluations of the plan apply it
+ * (reading it from device memory) instead of integrating the pairs.  on == 0
+ * frees it.  The results agree with the integrating path up to rounding.
+ * Memory: 24 bytes per (target, node) coefficient plus padding, e.g. about
+ * 0.8 GB for a 40^3 Kuhn cube at leaf 64, theta 0.5.
+ * Errors: TFMM_EINVAL (NULL or host-only plan), TFMM_ENOMEM (device memory:
+ * the plan keeps integrating), TFMM_EDEVICE.
+ */
+int tfmm_plan_store_near(tfmm_plan plan, int32_t on, void *hip_stream);
 
 /* Switch the M2L arithmetic of an existing plan (one of TFMM_M2L_*). */
 int tfmm_plan_set_m2l_precision(tfmm_plan plan, int32_t m2l_precision);

@@ -21,6 +21,7 @@ __all__ = [
     "tfmm_plan_autotune", "tfmm_batch_create", "tfmm_batch_evaluate", "tfmm_batch_autotune", "tfmm_batch_plan",
     "tfmm_batch_destroy", "Batch", "tfmm_surrogate_param_count", "tfmm_surrogate_train", "tfmm_surrogate_load",
     "tfmm_surrogate_samples", "tfmm_surrogate_grad", "tfmm_band_potential", "tfmm_demag_energy",
+    "tfmm_plan_store_near",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -54,7 +55,8 @@ class _Params(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_nodes", "n_tets", "n_targets", "n_cells", "n_leaves", "depth", "n_m2l",
                                         "n_p2p", "n_p2p_pairs", "ncoef", "device_bytes")] + [("setup_seconds",
-                                                                                               C.c_double)]
+                                                                                               C.c_double)] + [
+        ("near_nnz", C.c_int64), ("near_bytes", C.c_int64)]
 
 
 class TetFMMError(RuntimeError):
@@ -88,6 +90,7 @@ def _load():
         "tfmm_plan_expansions": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
         "tfmm_plan_destroy": (C.c_int, [C.c_void_p]),
         "tfmm_plan_set_m2l_precision": (C.c_int, [C.c_void_p, C.c_int32]),
+        "tfmm_plan_store_near": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
         "tfmm_last_error": (C.c_char_p, []),
         "tfmm_simplex_rule": (C.c_int, [C.c_int32, _dp, _i32p]),
         "tfmm_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -425,6 +428,16 @@ def tfmm_plan_set_m2l_precision(plan, m2l_precision):
     """M2L arithmetic of an existing plan: M2L_FP64, M2L_FP32, M2L_BF16X3 or M2L_BF16X6."""
     _check(_load().tfmm_plan_set_m2l_precision(plan.handle, int(m2l_precision)))
     plan.params["m2l_precision"] = int(m2l_precision)
+
+
+def tfmm_plan_store_near(plan, on=True, stream=None):
+    """Assemble (on) or free (off) the plan's stored near-field operator; the
+    plan's evaluations then apply it instead of integrating the near pairs.
+    Synchronises `stream` (default: torch's current stream)."""
+    import torch
+    _check(_load().tfmm_plan_store_near(plan.handle, 1 if on else 0,
+                                        _stream_handle(stream, torch.device("cuda", plan.device))))
+    plan.params["near_stored"] = bool(on)
 
 
 def tfmm_plan_destroy(plan):

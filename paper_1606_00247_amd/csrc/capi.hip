@@ -263,7 +263,7 @@ void free_plan(DevicePlan &dp)
                     dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.p2p_blk, dp.p2p_idx, dp.quad, dp.tet_mom, dp.Q,
                     dp.L, dp.Qt, dp.Qtf, dp.m2l_keys, dp.m2l_D, dp.m2l_Df, dp.sur_w, dp.sur_wb, dp.topo_blk,
                     dp.topo_ch_i, dp.topo_ch_c, dp.topo_w, dp.topo_ab, dp.topo_il, dp.topo_pqr, dp.topo_n,
-                    dp.topo_inc, dp.topo_A, dp.topo_B};
+                    dp.topo_inc, dp.topo_A, dp.topo_B, dp.near_off, dp.near_nc, dp.near_cols, dp.near_val};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : dp.m2l_tiles) {
@@ -411,6 +411,8 @@ int tfmm_plan_stats(tfmm_plan plan, tfmm_stats *out)
                         (int64_t)(sizeof(double) * (size_t)plan->dp.Fcap * hp.cells.size() *
                                   (2 * (size_t)plan->dp.ncoef + (size_t)plan->dp.qpad));
     out->setup_seconds = hp.setup_seconds;
+    out->near_nnz = plan->dp.near_nnz;
+    out->near_bytes = plan->dp.near_bytes;
     return TFMM_OK;
 }
 
@@ -546,6 +548,20 @@ int tfmm_plan_autotune(tfmm_plan plan, void *hip_stream)
     return guarded([&]() -> int {
         DeviceScope ds(plan->dp.device);
         tfmm::autotune(plan->dp, (hipStream_t)hip_stream);
+        return TFMM_OK;
+    });
+}
+
+int tfmm_plan_store_near(tfmm_plan plan, int32_t on, void *hip_stream)
+{
+    if (!plan) return set_error(TFMM_EINVAL, "NULL plan");
+    if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan has no near-field operator");
+    return guarded([&]() -> int {
+        DeviceScope ds(plan->dp.device);
+        if (on)
+            tfmm::store_near(plan->dp, (hipStream_t)hip_stream);
+        else
+            tfmm::drop_near(plan->dp);
         return TFMM_OK;
     });
 }

@@ -92,6 +92,15 @@ struct DevicePlan {
     int32_t n_topo_ch = 0;
     int64_t n_topo_edges = 0, n_topo_faces = 0;
     bool p2p_topo = true;  // single-field near field over shared entities
+    // stored near-field operator (optional, built by store_near): per cell
+    // [C][2] column and value offsets (-1: no block), padded column counts,
+    // node columns and the coefficient blocks [nt][3][ncols] of the target
+    // leaves; evaluations then apply it instead of integrating the pairs
+    int64_t *near_off = nullptr;
+    int32_t *near_nc = nullptr, *near_cols = nullptr;
+    double *near_val = nullptr;
+    int64_t near_nvals = 0, near_ncols = 0, near_nnz = 0, near_bytes = 0;
+    bool near_stored = false;
     // geometric moments of every tet about its leaf centre: [T][ncoef]
     double *tet_mom = nullptr;
     // quadrature rule for the moments: [nq][4] = lambda1, lambda2, lambda3, weight
@@ -155,6 +164,12 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
 // energy E / mu0 of one field M from the nodal potentials u (targets = nodes);
 // synchronises the stream.
 double run_demag(DevicePlan &dp, const double *M, const double *u, double *H, hipStream_t stream);
+// Assemble the stored near-field operator on `stream` (synchronises); the
+// following evaluations apply it.  Throws PlanError(TFMM_ENOMEM) when the
+// device memory is not there.
+void store_near(DevicePlan &dp, hipStream_t stream);
+// Free the stored operator (evaluations integrate the pairs again).
+void drop_near(DevicePlan &dp);
 // Queue the O(N^2) direct sum of F fields on `stream`.
 void run_direct(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t stream);
 

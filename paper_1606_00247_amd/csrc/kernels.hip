@@ -1364,6 +1364,139 @@ __global__ __launch_bounds__(64, 2) void k_p2p_topo(const int32_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Stored near-field operator (Sec. 2.1: the direct part is linear in the
+// nodal magnetisation, so its node-to-node coefficients can be kept for a
+// fixed mesh).  u_T(x) = sum_{corners c, axes j} C_{T,c,j}(x) M_{node(T,c), j}
+// where C_{T,c,j}(x) is the potential of the field that is the unit vector e_j
+// at corner c and zero at the other corners.  k_near_assemble evaluates the
+// pair formula for these 12 unit fields (staged in LDS like the fields of
+// k_p2p) for every near (target, tet) pair and adds the coefficients into the
+// target's row of its leaf block [nt][3][ncols]; the column of a node is found
+// by binary search in the leaf's sorted column list.
+// ---------------------------------------------------------------------------
+constexpr int kNearAsmTets = 16, kNearAsmThreads = 256;
+
+__global__ __launch_bounds__(kNearAsmThreads) void k_near_assemble(
+    const int32_t *__restrict__ blk, int nblk, int64_t T, const double *__restrict__ tet_xyz,
+    const int32_t *__restrict__ tet_node, const int32_t *__restrict__ idx, const double *__restrict__ tgt_xyz,
+    int64_t N, const int32_t *__restrict__ tgt_leaf, const int32_t *__restrict__ cell_i,
+    const int64_t *__restrict__ near_off, const int32_t *__restrict__ near_nc, const int32_t *__restrict__ near_cols,
+    double *__restrict__ val)
+{
+    __shared__ TetGeom s_g[kNearAsmTets];
+    __shared__ TetField s_f[kNearAsmTets][12];
+    __shared__ int32_t s_n[kNearAsmTets][4];
+    const int b = xcd_item(nblk);
+    if (b < 0) return;
+    const int tb = blk[4 * b], te = blk[4 * b + 1], ib = blk[4 * b + 2], ie = blk[4 * b + 3];
+    const int lane = threadIdx.x;
+    for (int sb = tb; sb < te; sb += kNearAsmTets) {
+        const int nt = min(kNearAsmTets, te - sb);
+        __syncthreads();
+        {
+            const int t = lane / 12, f = lane % 12;
+            if (t < nt) {
+                TetGeom G;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) G.v[c][k] = tet_xyz[(int64_t)(3 * c + k) * T + sb + t];
+                double gl[4][3], eh[6][3];
+                tet_geometry(G, gl, eh);
+                double m[4][3];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) m[c][k] = (3 * c + k == f) ? 1.0 : 0.0;
+                tet_field(G, gl, eh, m, s_f[t][f]);
+                if (f == 0) {
+                    s_g[t] = G;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) s_n[t][c] = tet_node[(int64_t)c * T + sb + t];
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = ib + lane; i < ie; i += kNearAsmThreads) {
+            const int s = idx[i];
+            const double x[3] = {tgt_xyz[s], tgt_xyz[N + s], tgt_xyz[2 * N + s]};
+            const int32_t a = tgt_leaf[s];
+            const int64_t voff = near_off[2 * a + 1];
+            if (voff < 0) continue;
+            const int nc = near_nc[a];
+            const int32_t *cl = near_cols + near_off[2 * a];
+            double *row = val + voff + (int64_t)(s - cell_i[8 * a + 2]) * 3 * nc;
+#pragma unroll 1
+            for (int t = 0; t < nt; ++t) {
+                PairGeo P;
+                pair_geometry(x, s_g[t], P);
+#pragma unroll 1
+                for (int c = 0; c < 4; ++c) {
+                    const int32_t node = s_n[t][c];
+                    int lo = 0, hi = nc;  // first column >= node
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (cl[mid] < node) lo = mid + 1; else hi = mid;
+                    }
+                    if (lo >= nc || cl[lo] != node) continue;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        atomicAdd(&row[(int64_t)j * nc + lo], pair_contract(P, s_f[t][3 * c + j]) * kInv4Pi);
+                }
+            }
+        }
+    }
+}
+
+// Applies the stored operator: one wavefront per target row, lanes striding
+// over the columns (three coalesced coefficient streams and one gathered
+// node vector per column and field), FC fields per pass, the row sums reduced
+// across the wavefront and added into u (L2P adds concurrently).
+constexpr int kNearRowsPerBlock = 4;
+
+template <int FC>
+__global__ __launch_bounds__(64 * kNearRowsPerBlock) void k_near_apply(
+    int nrowblk, const int32_t *__restrict__ tgt_leaf, const int32_t *__restrict__ cell_i,
+    const int64_t *__restrict__ near_off, const int32_t *__restrict__ near_nc, const int32_t *__restrict__ near_cols,
+    const double *__restrict__ val, const int32_t *__restrict__ tgt_perm, int64_t N, const double *__restrict__ M,
+    int64_t n_nodes, int F, double *__restrict__ u)
+{
+    const int rb = xcd_item(nrowblk);
+    if (rb < 0) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t s = (int64_t)rb * kNearRowsPerBlock + (threadIdx.x >> 6);
+    if (s >= N) return;
+    const int32_t a = tgt_leaf[s];
+    const int64_t voff = near_off[2 * a + 1];
+    if (voff < 0) return;
+    const int nc = near_nc[a];
+    const int32_t *cl = near_cols + near_off[2 * a];
+    const double *row = val + voff + (s - cell_i[8 * a + 2]) * 3 * nc;
+    const int f0 = blockIdx.y * FC;
+    double acc[FC];
+#pragma unroll
+    for (int f = 0; f < FC; ++f) acc[f] = 0.0;
+    for (int c = lane; c < nc; c += 64) {
+        const double w0 = row[c], w1 = row[nc + c], w2 = row[2 * nc + c];
+        const int64_t n = cl[c];
+#pragma unroll
+        for (int f = 0; f < FC; ++f) {
+            if (f0 + f < F) {
+                const double *m = M + ((int64_t)(f0 + f) * n_nodes + n) * 3;
+                acc[f] = fma(w0, m[0], fma(w1, m[1], fma(w2, m[2], acc[f])));
+            }
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < FC; ++f) {
+        double v = acc[f];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0 && f0 + f < F) atomicAdd(&u[(int64_t)(f0 + f) * N + tgt_perm[s]], v);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Demagnetising field and energy from nodal potentials (P1 interpolation):
 // per tet H_T = -grad u = -sum_i u_i grad lambda_i, and
 //   E / mu0 = 1/2 sum_T int_T M . grad u = 1/2 sum_T V_T (mean_i M_i) . grad u_T
@@ -1572,6 +1705,39 @@ void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u,
     }
 }
 
+// Near field from the stored operator (F fields, FC per pass).
+void run_near_stored(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t st)
+{
+    const HostPlan &hp = dp.hp;
+    const int64_t N = hp.n_targets;
+    if (N == 0 || dp.near_nvals == 0) return;
+    const int nrb = (int)((N + kNearRowsPerBlock - 1) / kNearRowsPerBlock);
+    const int fc = F >= 8 ? 8 : (F >= 4 ? 4 : (F >= 2 ? 2 : 1));
+    const dim3 grid(xcd_grid(nrb), (unsigned)((F + fc - 1) / fc));
+    const dim3 thr(64 * kNearRowsPerBlock);
+#define TFMM_NEAR_APPLY(FCV)                                                                                     \
+    k_near_apply<FCV><<<grid, thr, 0, st>>>(nrb, dp.tgt_leaf, dp.cell_i, dp.near_off, dp.near_nc, dp.near_cols,  \
+                                            dp.near_val, dp.tgt_perm, N, M, hp.n_nodes, F, u)
+    switch (fc) {
+    case 8: TFMM_NEAR_APPLY(8); break;
+    case 4: TFMM_NEAR_APPLY(4); break;
+    case 2: TFMM_NEAR_APPLY(2); break;
+    default: TFMM_NEAR_APPLY(1); break;
+    }
+#undef TFMM_NEAR_APPLY
+    hip_check(hipGetLastError(), "k_near_apply launch");
+}
+
+// Near field of an evaluation: the stored operator when the plan holds one,
+// else the pair integrals.
+void run_near(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t st)
+{
+    if (dp.near_stored)
+        run_near_stored(dp, M, F, u, st);
+    else
+        run_p2p(dp, false, M, F, u, st);
+}
+
 template <typename T, int P>
 void launch_m2l_p(DevicePlan &dp, const DevicePlan::Tiles &tl, const T *D, const T *Qt, int fpt, int32_t F,
                   hipStream_t st)
@@ -1671,6 +1837,74 @@ void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
 }
 
 }  // namespace
+
+void store_near(DevicePlan &dp, hipStream_t st)
+{
+    if (dp.near_stored) return;
+    const HostPlan &hp = dp.hp;
+    NearOpLayout lay;
+    build_near_operator_layout(hp, lay);
+    const size_t C = hp.cells.size();
+    const size_t b_off = sizeof(int64_t) * 2 * std::max<size_t>(C, 1), b_nc = sizeof(int32_t) * std::max<size_t>(C, 1),
+                 b_cols = sizeof(int32_t) * std::max<size_t>(lay.cols.size(), 1),
+                 b_val = sizeof(double) * (size_t)std::max<int64_t>(lay.nvals, 1);
+    void *p[4] = {nullptr, nullptr, nullptr, nullptr};
+    const size_t sz[4] = {b_off, b_nc, b_cols, b_val};
+    for (int i = 0; i < 4; ++i) {
+        const hipError_t e = hipMalloc(&p[i], sz[i]);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            for (int j = 0; j < i; ++j) (void)hipFree(p[j]);
+            if (e == hipErrorOutOfMemory)
+                throw PlanError{TFMM_ENOMEM, "stored near-field operator: device memory exhausted (" +
+                                                 std::to_string(b_val >> 20) + " MiB of coefficients)"};
+            hip_check(e, "hipMalloc near operator");
+        }
+    }
+    dp.near_off = (int64_t *)p[0];
+    dp.near_nc = (int32_t *)p[1];
+    dp.near_cols = (int32_t *)p[2];
+    dp.near_val = (double *)p[3];
+    dp.near_nvals = lay.nvals;
+    dp.near_ncols = (int64_t)lay.cols.size();
+    dp.near_nnz = lay.nnz;
+    dp.near_bytes = (int64_t)(b_off + b_nc + b_cols + b_val);
+    dp.device_bytes += dp.near_bytes;
+    hip_check(hipMemcpy(dp.near_off, lay.leaf_off.data(), sizeof(int64_t) * lay.leaf_off.size(), hipMemcpyHostToDevice),
+              "hipMemcpy near offsets");
+    hip_check(hipMemcpy(dp.near_nc, lay.leaf_nc.data(), sizeof(int32_t) * lay.leaf_nc.size(), hipMemcpyHostToDevice),
+              "hipMemcpy near counts");
+    if (!lay.cols.empty())
+        hip_check(hipMemcpy(dp.near_cols, lay.cols.data(), sizeof(int32_t) * lay.cols.size(), hipMemcpyHostToDevice),
+                  "hipMemcpy near columns");
+    fill(dp.near_val, lay.nvals, 0.0, st);
+    if (dp.n_p2p_blk > 0) {
+        k_near_assemble<<<dim3(xcd_grid(dp.n_p2p_blk)), dim3(kNearAsmThreads), 0, st>>>(
+            dp.p2p_blk, dp.n_p2p_blk, hp.n_tets, dp.tet_xyz, dp.tet_node, dp.p2p_idx, dp.tgt_xyz, hp.n_targets,
+            dp.tgt_leaf, dp.cell_i, dp.near_off, dp.near_nc, dp.near_cols, dp.near_val);
+        hip_check(hipGetLastError(), "k_near_assemble launch");
+    }
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize (near operator)");
+    dp.near_stored = true;
+    ++dp.schedule_gen;
+}
+
+void drop_near(DevicePlan &dp)
+{
+    if (!dp.near_off) return;
+    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    void *p[4] = {dp.near_off, dp.near_nc, dp.near_cols, dp.near_val};
+    for (void *q : p)
+        if (q) (void)hipFree(q);
+    dp.near_off = nullptr;
+    dp.near_nc = nullptr;
+    dp.near_cols = nullptr;
+    dp.near_val = nullptr;
+    dp.device_bytes -= dp.near_bytes;
+    dp.near_bytes = dp.near_nvals = dp.near_ncols = dp.near_nnz = 0;
+    dp.near_stored = false;
+    ++dp.schedule_gen;
+}
 
 void build_tet_moments(DevicePlan &dp)
 {
@@ -1878,7 +2112,7 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
         hip_check(hipStreamWaitEvent(dp.side, dp.ev_fork, 0), "hipStreamWaitEvent");
         {
             KTimer kt(dp, KT_P2P, dp.side);
-            run_p2p(dp, false, M, F, u, dp.side);
+            run_near(dp, M, F, u, dp.side);
         }
         hip_check(hipEventRecord(dp.ev_join, dp.side), "hipEventRecord");
     };
@@ -1934,7 +2168,7 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
         hip_check(hipStreamWaitEvent(st, dp.ev_join, 0), "hipStreamWaitEvent");
     } else {
         KTimer kt(dp, KT_P2P, st);
-        run_p2p(dp, false, M, F, u, st);
+        run_near(dp, M, F, u, st);
     }
 }
 

@@ -281,13 +281,16 @@ __device__ __forceinline__ double atan2_nr(double y, double x)
     return copysign(r, y);
 }
 
-// One pair (target x, tet G with FCH fields): adds 4 pi u_T(x) of every field
-// to acc.  The edges are taken one at a time (the edges (a, b) listed first in
-// the faces give the faces' triple products for the solid angles), forming the
-// geometric integrals I0_k and g_e, which are then contracted with each field.
-template <int FCH>
-__device__ __forceinline__ void pair_accumulate(const double x[3], const TetGeom &G, const TetField *fld,
-                                                double (&acc)[FCH])
+// Geometric integrals of one pair (target x, tet G): the face integrals I0_k,
+// the edge terms g_e, the signed heights h_k and d_0 = v_0 - x; the potential
+// of a field is then the contraction pair_contract with its coefficients.
+struct PairGeo {
+    double I0[4], ge[6], h[4], d0[3];
+};
+
+// The edges are taken one at a time (the edges (a, b) listed first in the
+// faces give the faces' triple products for the solid angles).
+__device__ __forceinline__ void pair_geometry(const double x[3], const TetGeom &G, PairGeo &P)
 {
     double d[4][3], R2[4], R[4];
 #pragma unroll
@@ -302,12 +305,12 @@ __device__ __forceinline__ void pair_accumulate(const double x[3], const TetGeom
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = a + 1; b < 4; ++b) D[a][b] = D[b][a] = d[a][0] * d[b][0] + d[a][1] * d[b][1] + d[a][2] * d[b][2];
-    double h[4], I0[4], ge[6], det[4];
+    double det[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int a = kFv[k][0];
-        h[k] = G.n[k][0] * d[a][0] + G.n[k][1] * d[a][1] + G.n[k][2] * d[a][2];
-        I0[k] = 0.0;
+        P.h[k] = G.n[k][0] * d[a][0] + G.n[k][1] * d[a][1] + G.n[k][2] * d[a][2];
+        P.I0[k] = 0.0;
     }
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
@@ -323,14 +326,14 @@ __device__ __forceinline__ void pair_accumulate(const double x[3], const TetGeom
         // f = ln((R_b + l_b)/(R_a + l_a)) in a form free of cancellation
         const double fe = edge_log(R[a], R[b], la, lb, r0sq);
         const double fl = fe * il;
-        ge[e] = r0sq * fe + lb * R[b] - la * R[a];
+        P.ge[e] = r0sq * fe + lb * R[b] - la * R[a];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 if (kFe[k][j] != e) continue;
                 // t0 |e| = s n_k . (d_a x d_b)
-                I0[k] += kFs[k][j] * (G.n[k][0] * cx[0] + G.n[k][1] * cx[1] + G.n[k][2] * cx[2]) * fl;
+                P.I0[k] += kFs[k][j] * (G.n[k][0] * cx[0] + G.n[k][1] * cx[1] + G.n[k][2] * cx[2]) * fl;
                 if (j == 0) {  // det[d_a, d_b, d_c] = d_c . (d_a x d_b)
                     const int c = kFv[k][2];
                     det[k] = kFs[k][0] * (d[c][0] * cx[0] + d[c][1] * cx[1] + d[c][2] * cx[2]);
@@ -341,23 +344,38 @@ __device__ __forceinline__ void pair_accumulate(const double x[3], const TetGeom
     for (int k = 0; k < 4; ++k) {
         const int a = kFv[k][0], b = kFv[k][1], c = kFv[k][2];
         const double den = R[a] * R[b] * R[c] + D[a][b] * R[c] + D[a][c] * R[b] + D[b][c] * R[a];
-        I0[k] -= h[k] * (2.0 * atan2_nr(det[k], den));  // - h_k Omega_k
+        P.I0[k] -= P.h[k] * (2.0 * atan2_nr(det[k], den));  // - h_k Omega_k
     }
 #pragma unroll
-    for (int f = 0; f < FCH; ++f) {
-        const TetField &F1 = fld[f];
-        double v = 0.0;
+    for (int k = 0; k < 3; ++k) P.d0[k] = d[0][k];
+}
+
+// 4 pi u_T(x) of one field from the pair's geometric integrals.
+__device__ __forceinline__ double pair_contract(const PairGeo &P, const TetField &F1)
+{
+    double v = 0.0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            // alpha_k = M(x).n_k + h_k (n_k.G n_k - div M / 2)
-            const double alpha =
-                F1.a[k] - (d[0][0] * F1.b[k][0] + d[0][1] * F1.b[k][1] + d[0][2] * F1.b[k][2]) + F1.c[k] * h[k];
-            v = fma(alpha, I0[k], v);
-        }
-#pragma unroll
-        for (int e = 0; e < 6; ++e) v = fma(F1.g[e], ge[e], v);
-        acc[f] += v;
+    for (int k = 0; k < 4; ++k) {
+        // alpha_k = M(x).n_k + h_k (n_k.G n_k - div M / 2)
+        const double alpha =
+            F1.a[k] - (P.d0[0] * F1.b[k][0] + P.d0[1] * F1.b[k][1] + P.d0[2] * F1.b[k][2]) + F1.c[k] * P.h[k];
+        v = fma(alpha, P.I0[k], v);
     }
+#pragma unroll
+    for (int e = 0; e < 6; ++e) v = fma(F1.g[e], P.ge[e], v);
+    return v;
+}
+
+// One pair (target x, tet G with FCH fields): adds 4 pi u_T(x) of every field
+// to acc.
+template <int FCH>
+__device__ __forceinline__ void pair_accumulate(const double x[3], const TetGeom &G, const TetField *fld,
+                                                double (&acc)[FCH])
+{
+    PairGeo P;
+    pair_geometry(x, G, P);
+#pragma unroll
+    for (int f = 0; f < FCH; ++f) acc[f] += pair_contract(P, fld[f]);
 }
 
 }  // namespace tfmm

@@ -403,6 +403,53 @@ void build_m2l_tiles(const HostPlan &hp, int tpt, int max_ent, M2LTiles &out)
 }
 
 
+void build_near_operator_layout(const HostPlan &hp, NearOpLayout &out)
+{
+    const int64_t C = (int64_t)hp.cells.size();
+    std::vector<int32_t> cnt(C + 1, 0);
+    for (int32_t a : hp.p2p_a) cnt[a + 1]++;
+    for (int64_t c = 0; c < C; ++c) cnt[c + 1] += cnt[c];
+    std::vector<int32_t> src(hp.p2p_b.size());
+    {
+        std::vector<int32_t> fillp(cnt.begin(), cnt.end() - 1);
+        for (size_t i = 0; i < hp.p2p_a.size(); ++i) src[fillp[hp.p2p_a[i]]++] = hp.p2p_b[i];
+    }
+    out.leaf_off.assign(2 * (size_t)C, -1);
+    out.leaf_nc.assign((size_t)C, 0);
+    out.cols.clear();
+    out.nvals = 0;
+    out.nnz = 0;
+    std::vector<int64_t> stamp((size_t)hp.n_nodes, -1);
+    std::vector<int32_t> buf;
+    for (int64_t a = 0; a < C; ++a) {
+        const Cell &A = hp.cells[a];
+        const int64_t nt = A.xend - A.xbeg;
+        if (cnt[a + 1] == cnt[a] || nt == 0) continue;
+        buf.clear();
+        for (int32_t j = cnt[a]; j < cnt[a + 1]; ++j) {
+            const Cell &Bc = hp.cells[src[j]];
+            for (int32_t t = Bc.tbeg; t < Bc.tend; ++t)
+                for (int c = 0; c < 4; ++c) {
+                    const int32_t n = hp.tet_nodes[4 * (size_t)t + c];
+                    if (stamp[n] != a) {
+                        stamp[n] = a;
+                        buf.push_back(n);
+                    }
+                }
+        }
+        if (buf.empty()) continue;
+        std::sort(buf.begin(), buf.end());
+        const int64_t nc = (int64_t)buf.size(), pad = (nc + 7) / 8 * 8;
+        out.leaf_off[2 * a] = (int64_t)out.cols.size();
+        out.leaf_off[2 * a + 1] = out.nvals;
+        out.leaf_nc[a] = (int32_t)pad;
+        out.cols.insert(out.cols.end(), buf.begin(), buf.end());
+        out.cols.insert(out.cols.end(), (size_t)(pad - nc), buf.back());
+        out.nvals += nt * 3 * pad;
+        out.nnz += nt * nc;
+    }
+}
+
 void build_near_topology(const HostPlan &hp, const std::vector<int32_t> &blk, NearTopo &out)
 {
     static const int kEa[6] = {0, 0, 0, 1, 1, 2}, kEb[6] = {1, 2, 3, 2, 3, 3};

@@ -98,6 +98,21 @@ struct NearTopo {
     std::vector<int32_t> inc;     // [T][10] per tet: 6 edge, 4 face chunk-local indices
 };
 
+// Stored near-field operator (the node-to-node coefficients of the direct
+// part, Sec. 2.1, assembled once per mesh).  With the tets of the P2P source
+// leaves of a target leaf A written out by their nodes, the near potential at
+// a target x of A is sum_j C_xj . M_j over the distinct nodes j of those tets:
+// per target leaf one sorted column list (padded to a multiple of 8 by
+// repeating its last node) and one dense coefficient block [nt(A)][3][ncols].
+struct NearOpLayout {
+    std::vector<int64_t> leaf_off;  // [C][2]: column offset, value offset (-1: no block)
+    std::vector<int32_t> leaf_nc;   // [C] padded column count
+    std::vector<int32_t> cols;      // node ids, per leaf sorted
+    int64_t nvals = 0;              // doubles in all blocks
+    int64_t nnz = 0;                // (target, node) pairs before padding
+};
+void build_near_operator_layout(const HostPlan &hp, NearOpLayout &out);
+
 // Builds the chunks of the P2P blocks blk ([nblk][4]: tbeg, tend, ibeg, iend).
 void build_near_topology(const HostPlan &hp, const std::vector<int32_t> &blk, NearTopo &out);
 

@@ -116,3 +116,24 @@ def test_ragged32_batch_accuracy(torch_dev):
         torch.cuda.synchronize()
         worst = max(worst, _rel(u[i].cpu().numpy(), ud.cpu().numpy()))
     assert worst <= 1e-5, worst
+
+
+def test_batch_with_stored_near(torch_dev, orc):
+    """A plan of the batch switched to its stored near-field operator: the graph
+    is captured again and replays match the oracle."""
+    torch = torch_dev
+    meshes = _ragged(4, 31)
+    _say("batch with stored near", [m[1].shape[0] for m in meshes])
+    B = T.tfmm_batch_create(meshes, p=6, leaf_size=16, theta=0.5)
+    M = [torch.from_numpy(meshgen.random_fields(m[0].shape[0], F=1, seed=40 + i)[0]).to("cuda:0")
+         for i, m in enumerate(meshes)]
+    u0 = T.tfmm_batch_evaluate(B, M)
+    torch.cuda.synchronize()
+    T.tfmm_plan_store_near(T.tfmm_batch_plan(B, 1))
+    for r in range(2):
+        u = T.tfmm_batch_evaluate(B, M, u0 if r else None)
+        torch.cuda.synchronize()
+        for i, m in enumerate(meshes):
+            uo = orc.FMM(m[0], m[1], 6, 16, 0.5).evaluate(M[i].cpu().numpy())
+            assert _rel(u[i].cpu().numpy(), uo) <= TOL, (r, i)
+    T.tfmm_batch_destroy(B)

@@ -72,6 +72,11 @@ def test_cube40_fp64_vs_oracle_sampled_and_direct(torch_dev, orc):
     O = orc.FMM(nodes, tets, 8, 64, 0.5)
     uo = O.evaluate_sample(M, idx)
     assert _rel(u[:, idx], uo) <= FMM_TOL
+    _say("cube40 fp64 with the stored near-field operator")
+    T.tfmm_plan_store_near(P)
+    us = _eval(torch_dev, P, M)
+    assert _rel(us, u) <= FMM_TOL
+    assert _rel(us[:, idx], uo) <= FMM_TOL
 
 
 def test_film_oracle_parity_and_full_film_accuracy(torch_dev, orc):
