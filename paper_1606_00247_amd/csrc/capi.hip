@@ -204,13 +204,31 @@ void upload_plan(DevicePlan &dp)
                 blk.push_back((int32_t)ie);
             }
         }
+        // shared mesh entities of the source blocks (single-field near field)
+        NearTopo tp;
+        build_near_topology(hp, blk, tp);
+        {
+            // longest blocks (tets x targets) first in dispatch order, so that the
+            // launch ends evenly; the chunk list keeps the same block order
+            const int nb = (int)(blk.size() / 4);
+            std::vector<int32_t> ord(nb);
+            for (int i = 0; i < nb; ++i) ord[i] = i;
+            auto work = [&](int i) { return (int64_t)(blk[4 * i + 1] - blk[4 * i]) * (blk[4 * i + 3] - blk[4 * i + 2]); };
+            std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return work(x) > work(y); });
+            const std::vector<int32_t> pos = xcd_dispatch_items(nb);
+            std::vector<int32_t> b2(blk.size()), t2(tp.blk.size());
+            for (int k = 0; k < nb; ++k)
+                for (int j = 0; j < 4; ++j) {
+                    b2[4 * (size_t)pos[k] + j] = blk[4 * (size_t)ord[k] + j];
+                    t2[4 * (size_t)pos[k] + j] = tp.blk[4 * (size_t)ord[k] + j];
+                }
+            blk.swap(b2);
+            tp.blk.swap(t2);
+        }
         dp.n_p2p_blk = (int32_t)(blk.size() / 4);
         dp.n_p2p_idx = (int64_t)idx.size();
         dp.p2p_blk = dev_upload(blk, B);
         dp.p2p_idx = dev_upload(idx, B);
-        // shared mesh entities of the source blocks (single-field near field)
-        NearTopo tp;
-        build_near_topology(hp, blk, tp);
         dp.n_topo_ch = (int32_t)(tp.ch_i.size() / 8);
         dp.n_topo_edges = (int64_t)tp.ed_il.size();
         dp.n_topo_faces = (int64_t)(tp.fc_n.size() / 3);

@@ -142,6 +142,10 @@ struct DevicePlan {
 void collect_timing(DevicePlan &dp);
 void reset_timing(DevicePlan &dp);
 
+// Items of a launch of n workgroup items (xcd_grid / xcd_item mapping) in
+// the order the workgroups are dispatched.
+std::vector<int32_t> xcd_dispatch_items(int n);
+
 // Allocate and upload; hp must be built.  Throws DeviceError.
 void upload_plan(DevicePlan &dp);
 void free_plan(DevicePlan &dp);

@@ -1269,7 +1269,10 @@ __global__ __launch_bounds__(64) void k_topo_coef(const int32_t *__restrict__ ch
     for (int i = threadIdx.x; i < ne * 11; i += blockDim.x) Bc[(int64_t)eoff * 11 + i] = (&s_B[0][0])[i];
 }
 
-__global__ __launch_bounds__(64, 2) void k_p2p_topo(const int32_t *__restrict__ blk, int nblk,
+// NT = 64: one wavefront per workgroup; NT = 256: four wavefronts share the
+// staged chunk (less LDS per wavefront: 4 waves per SIMD instead of 3).
+template <int NT>
+__global__ __launch_bounds__(NT, NT == 64 ? 2 : 4) void k_p2p_topo(const int32_t *__restrict__ blk, int nblk,
                                                     const int32_t *__restrict__ ch_i, const double *__restrict__ ch_c,
                                                     const double *__restrict__ nw, const int32_t *__restrict__ eab,
                                                     const double *__restrict__ eil, const int32_t *__restrict__ fpqr,
@@ -1280,7 +1283,7 @@ __global__ __launch_bounds__(64, 2) void k_p2p_topo(const int32_t *__restrict__ 
                                                     double *__restrict__ u)
 {
     __shared__ double s_w[kTopoNodes][3];
-    __shared__ double s_R[kTopoNodes][64];
+    __shared__ double s_R[kTopoNodes][NT];
     __shared__ int s_ea[kTopoEdges], s_eb[kTopoEdges];
     __shared__ double s_il[kTopoEdges], s_B[kTopoEdges][11];
     __shared__ int s_fp[kTopoFaces], s_fq[kTopoFaces], s_fr[kTopoFaces];
@@ -1294,22 +1297,22 @@ __global__ __launch_bounds__(64, 2) void k_p2p_topo(const int32_t *__restrict__ 
                   foff = ch_i[8 * ch + 6], nf = ch_i[8 * ch + 7];
         const double c[3] = {ch_c[3 * ch], ch_c[3 * ch + 1], ch_c[3 * ch + 2]};
         __syncthreads();
-        for (int i = lane; i < nn * 3; i += 64) (&s_w[0][0])[i] = nw[(int64_t)noff * 3 + i];
-        for (int i = lane; i < ne; i += 64) {
+        for (int i = lane; i < nn * 3; i += NT) (&s_w[0][0])[i] = nw[(int64_t)noff * 3 + i];
+        for (int i = lane; i < ne; i += NT) {
             s_ea[i] = eab[2 * ((int64_t)eoff + i)];
             s_eb[i] = eab[2 * ((int64_t)eoff + i) + 1];
             s_il[i] = eil[eoff + i];
         }
-        for (int i = lane; i < ne * 11; i += 64) (&s_B[0][0])[i] = Bc[(int64_t)eoff * 11 + i];
-        for (int i = lane; i < nf; i += 64) {
+        for (int i = lane; i < ne * 11; i += NT) (&s_B[0][0])[i] = Bc[(int64_t)eoff * 11 + i];
+        for (int i = lane; i < nf; i += NT) {
             s_fp[i] = fpqr[3 * ((int64_t)foff + i)];
             s_fq[i] = fpqr[3 * ((int64_t)foff + i) + 1];
             s_fr[i] = fpqr[3 * ((int64_t)foff + i) + 2];
         }
-        for (int i = lane; i < nf * 3; i += 64) (&s_fn[0][0])[i] = fn[(int64_t)foff * 3 + i];
-        for (int i = lane; i < nf * 4; i += 64) (&s_A[0][0])[i] = A[(int64_t)foff * 4 + i];
+        for (int i = lane; i < nf * 3; i += NT) (&s_fn[0][0])[i] = fn[(int64_t)foff * 3 + i];
+        for (int i = lane; i < nf * 4; i += NT) (&s_A[0][0])[i] = A[(int64_t)foff * 4 + i];
         __syncthreads();
-        for (int i = ib + lane; i < ie; i += 64) {
+        for (int i = ib + lane; i < ie; i += NT) {
             const int s = idx[i];
             const double y[3] = {tgt_xyz[s] - c[0], tgt_xyz[N + s] - c[1], tgt_xyz[2 * N + s] - c[2]};
             const double m[10] = {1.0,         y[0],        y[1],        y[2],        y[0] * y[0],
@@ -1327,9 +1330,9 @@ __global__ __launch_bounds__(64, 2) void k_p2p_topo(const int32_t *__restrict__ 
                 const double da[3] = {s_w[a][0] - y[0], s_w[a][1] - y[1], s_w[a][2] - y[2]};
                 const double db[3] = {s_w[bb][0] - y[0], s_w[bb][1] - y[1], s_w[bb][2] - y[2]};
                 const double Ra = s_R[a][lane], Rb = s_R[bb][lane];
-                const double ev[3] = {db[0] - da[0], db[1] - da[1], db[2] - da[2]};
-                const double la = (da[0] * ev[0] + da[1] * ev[1] + da[2] * ev[2]) * il;  // (v_a - x) . e_hat
-                const double lb = (db[0] * ev[0] + db[1] * ev[1] + db[2] * ev[2]) * il;  // (v_b - x) . e_hat
+                const double Dab = da[0] * db[0] + da[1] * db[1] + da[2] * db[2];
+                const double la = fma(-Ra, Ra, Dab) * il;  // (v_a - x) . e_hat
+                const double lb = fma(Rb, Rb, -Dab) * il;  // (v_b - x) . e_hat
                 const double cx0 = da[1] * db[2] - da[2] * db[1], cx1 = da[2] * db[0] - da[0] * db[2],
                              cx2 = da[0] * db[1] - da[1] * db[0];
                 const double r0sq = (cx0 * cx0 + cx1 * cx1 + cx2 * cx2) * (il * il);
@@ -1582,6 +1585,18 @@ __global__ __launch_bounds__(kEnergyThreads) void k_sum_blocks(const double *__r
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+std::vector<int32_t> xcd_dispatch_items(int n)
+{
+    std::vector<int32_t> out;
+    out.reserve(n > 0 ? n : 0);
+    const int per = (n + kXcds - 1) / kXcds;
+    for (int w = 0; w < kXcds * per; ++w) {
+        const int item = (w % kXcds) * per + w / kXcds;
+        if (item < n) out.push_back(item);
+    }
+    return out;
+}
+
 void hip_check(hipError_t e, const char *what)
 {
     if (e != hipSuccess) throw DeviceError{std::string(what) + ": " + hipGetErrorString(e)};
@@ -1674,9 +1689,14 @@ void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u,
                                                              dp.topo_B);
         hip_check(hipGetLastError(), "k_topo_coef launch");
         const int nblk = dp.n_p2p_blk;
-        k_p2p_topo<<<dim3(xcd_grid(nblk)), dim3(64), 0, st>>>(
-            dp.topo_blk, nblk, dp.topo_ch_i, dp.topo_ch_c, dp.topo_w, dp.topo_ab, dp.topo_il, dp.topo_pqr, dp.topo_n,
-            dp.topo_A, dp.topo_B, dp.p2p_idx, dp.tgt_xyz, dp.tgt_perm, hp.n_targets, u);
+        if (dp.p2p_wide)
+            k_p2p_topo<256><<<dim3(xcd_grid(nblk)), dim3(256), 0, st>>>(
+                dp.topo_blk, nblk, dp.topo_ch_i, dp.topo_ch_c, dp.topo_w, dp.topo_ab, dp.topo_il, dp.topo_pqr,
+                dp.topo_n, dp.topo_A, dp.topo_B, dp.p2p_idx, dp.tgt_xyz, dp.tgt_perm, hp.n_targets, u);
+        else
+            k_p2p_topo<64><<<dim3(xcd_grid(nblk)), dim3(64), 0, st>>>(
+                dp.topo_blk, nblk, dp.topo_ch_i, dp.topo_ch_c, dp.topo_w, dp.topo_ab, dp.topo_il, dp.topo_pqr,
+                dp.topo_n, dp.topo_A, dp.topo_B, dp.p2p_idx, dp.tgt_xyz, dp.tgt_perm, hp.n_targets, u);
         hip_check(hipGetLastError(), "k_p2p_topo launch");
         return;
     }
