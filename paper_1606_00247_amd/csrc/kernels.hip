@@ -697,11 +697,13 @@ struct M2LCols {
 // key e+1 are loaded into registers and stored to the other buffer; one
 // barrier per key.  Thread tid stages column tid/16, coefficients
 // n = tid%16 + 16 j.
+constexpr int kM2LSeg = 128;  // M2L entries whose metadata is staged in LDS at once
+
 template <typename T, int P, int W>
 __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_rng, const int32_t *__restrict__ ent_key,
                                          const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys,
                                          const T *__restrict__ Dtab, const T *__restrict__ Qr, int qpad, int64_t C,
-                                         M2LCols cols, int tile, T *s_D, T *s_Q,
+                                         M2LCols cols, int tile, T *s_D, T *s_Q, int32_t *s_src, int32_t *s_kk,
                                          typename Mfma<T>::v4 (&acc)[m2l_nrt(P)])
 {
     using v4 = typename Mfma<T>::v4;
@@ -720,20 +722,43 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_rng, c
     int pdl = 0, qdeg[QREG];
 #pragma unroll
     for (int j = 0; j < QREG; ++j) qdeg[j] = rdeg(tn + 16 * j);
+    // Entry metadata (key id, its level difference, the source cell of every
+    // tile slot) is staged in LDS a segment of kM2LSeg entries (plus one
+    // lookahead entry) at a time, so the loop issues no global load whose
+    // address depends on another global load: the table row and multipoles of
+    // entry e + 1 are loaded while the MFMAs of entry e run.  Loads go to
+    // clamped, in-bounds addresses unconditionally and are masked when stored
+    // (exec-masked loads make the compiler wait for every outstanding load
+    // where the branches join).
+    const bool active = field < cols.F;
+    const T *qf = Qr + (int64_t)(active ? field : 0) * C * qpad;
+    int seg = e0;
+    auto stage_seg = [&]() {
+        const int ne = min(e1 - seg, kM2LSeg + 1);
+        for (int i = tid; i < ne * cols.tpt; i += NT) s_src[i] = ent_src[(int64_t)seg * cols.tpt + i];
+        for (int i = tid; i < ne; i += NT) {
+            const int key = ent_key[seg + i];
+            s_kk[2 * i] = key;
+            s_kk[2 * i + 1] = keys[4 * key];
+        }
+    };
+    bool qok = false;
     auto fetch = [&](int e) {
-        const int key = ent_key[e];
-        pdl = keys[4 * key];
+        const int r = e - seg;
+        const int key = s_kk[2 * r];
+        pdl = s_kk[2 * r + 1];
+        const int src = s_src[r * cols.tpt + tslot];
 #pragma unroll
         for (int j = 0; j < DREG; ++j) {
             const int k = tid + NT * j;
-            pd[j] = k < ND ? Dtab[(int64_t)key * ND + k] : (T)0;
+            pd[j] = Dtab[(int64_t)key * ND + (k < ND ? k : ND - 1)];
         }
-        const int src = field < cols.F ? ent_src[(int64_t)e * cols.tpt + tslot] : -1;
-        const T *q = Qr + ((int64_t)(src >= 0 ? field : 0) * C + (src >= 0 ? src : 0)) * qpad;
+        qok = active && src >= 0;
+        const T *q = qf + (int64_t)(qok ? src : 0) * qpad;
 #pragma unroll
         for (int j = 0; j < QREG; ++j) {
             const int n = tn + 16 * j;
-            pq[j] = (src >= 0 && n < NR) ? q[n] : (T)0;
+            pq[j] = q[n < NR ? n : NR - 1];
         }
     };
     auto store = [&](int buf) {
@@ -747,10 +772,12 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_rng, c
 #pragma unroll
         for (int j = 0; j < QREG; ++j) {
             const int n = tn + 16 * j;
-            if (n < NR) Qb[n] = ldexp(pq[j], -pdl * qdeg[j]);  // 2^(-dl |n|), exact
+            if (n < NR) Qb[n] = qok ? ldexp(pq[j], -pdl * qdeg[j]) : (T)0;  // 2^(-dl |n|), exact
         }
     };
     if (e0 >= e1) return;
+    stage_seg();
+    __syncthreads();
     fetch(e0);
     store(0);
     __syncthreads();
@@ -760,6 +787,11 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_rng, c
         m2l_wave_mfma<T, P, W>(acc, acc0, s_D + buf * DSTR, s_Q + buf * 16 * KSTR, didx, lane);
         if (e + 1 < e1) store(buf ^ 1);
         __syncthreads();
+        if (e + 1 - seg == kM2LSeg && e + 1 < e1) {  // the next fetch leaves the segment
+            seg = e + 1;
+            stage_seg();
+            __syncthreads();
+        }
     }
     acc[0] += acc0[0] + acc0[1];
 }
@@ -801,6 +833,7 @@ __global__ __launch_bounds__(64 * kM2LWaves, 2) void k_m2l_mfma(
     static_assert(2 * sizeof(T) >= sizeof(double), "reduction buffer fits in the staging buffers");
     __shared__ T s_D[2 * (ND + 1)];
     __shared__ __align__(16) T s_Q[2 * 16 * KSTR];
+    __shared__ int32_t s_src[(kM2LSeg + 1) * 16], s_kk[2 * (kM2LSeg + 1)];
     const int tile = blockIdx.x;
     if (tile >= ntiles) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -812,10 +845,10 @@ __global__ __launch_bounds__(64 * kM2LWaves, 2) void k_m2l_mfma(
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt) acc[rt] = v4{0, 0, 0, 0};
     switch (wave) {
-    case 0: m2l_tile<T, P, 0>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
-    case 1: m2l_tile<T, P, 1>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
-    case 2: m2l_tile<T, P, 2>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
-    default: m2l_tile<T, P, 3>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc); break;
+    case 0: m2l_tile<T, P, 0>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, s_src, s_kk, acc); break;
+    case 1: m2l_tile<T, P, 1>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, s_src, s_kk, acc); break;
+    case 2: m2l_tile<T, P, 2>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, s_src, s_kk, acc); break;
+    default: m2l_tile<T, P, 3>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, s_src, s_kk, acc); break;
     }
     // sum the waves' partial accumulators in LDS (FP64): red[c][m], c = column
     __syncthreads();
@@ -917,7 +950,7 @@ __device__ __forceinline__ void m2lb_tile(const int32_t *__restrict__ tile_rng, 
                                           const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys,
                                           const float *__restrict__ Dtab, const float *__restrict__ Qr, int qpad,
                                           int64_t C, M2LCols cols, int tile, __bf16 *s_D, __bf16 *s_Q,
-                                          Mfma<float>::v4 (&acc)[m2l_nrt(P)])
+                                          int32_t *s_src, int32_t *s_kk, Mfma<float>::v4 (&acc)[m2l_nrt(P)])
 {
     constexpr int NR = nr_of(P), NROW = m2l_nrows(P), ND = nd_of(P), KSTR = m2lb_kstr(P), DSTR = ND + 1;
     constexpr int NT = 64 * kM2LBWaves, NS = m2lb_wave_steps(P, W);
@@ -947,20 +980,36 @@ __device__ __forceinline__ void m2lb_tile(const int32_t *__restrict__ tile_rng, 
     int pdl = 0, qdeg[QREG];
 #pragma unroll
     for (int j = 0; j < QREG; ++j) qdeg[j] = rdeg(tn + TPC * j);
+    // entry metadata staged in LDS by segments, loads as in m2l_tile
+    const bool active = field < cols.F;
+    const float *qf = Qr + (int64_t)(active ? field : 0) * C * qpad;
+    int seg = e0;
+    auto stage_seg = [&]() {
+        const int ne = min(e1 - seg, kM2LSeg + 1);
+        for (int i = tid; i < ne * cols.tpt; i += NT) s_src[i] = ent_src[(int64_t)seg * cols.tpt + i];
+        for (int i = tid; i < ne; i += NT) {
+            const int key = ent_key[seg + i];
+            s_kk[2 * i] = key;
+            s_kk[2 * i + 1] = keys[4 * key];
+        }
+    };
+    bool qok = false;
     auto fetch = [&](int e) {
-        const int key = ent_key[e];
-        pdl = keys[4 * key];
+        const int r = e - seg;
+        const int key = s_kk[2 * r];
+        pdl = s_kk[2 * r + 1];
+        const int src = s_src[r * cols.tpt + tslot];
 #pragma unroll
         for (int j = 0; j < DREG; ++j) {
             const int k = tid + NT * j;
-            pd[j] = k < ND ? Dtab[(int64_t)key * ND + k] : 0.0f;
+            pd[j] = Dtab[(int64_t)key * ND + (k < ND ? k : ND - 1)];
         }
-        const int src = field < cols.F ? ent_src[(int64_t)e * cols.tpt + tslot] : -1;
-        const float *q = Qr + ((int64_t)(src >= 0 ? field : 0) * C + (src >= 0 ? src : 0)) * qpad;
+        qok = active && src >= 0;
+        const float *q = qf + (int64_t)(qok ? src : 0) * qpad;
 #pragma unroll
         for (int j = 0; j < QREG; ++j) {
             const int n = tn + TPC * j;
-            pq[j] = (src >= 0 && n < NR) ? q[n] : 0.0f;
+            pq[j] = q[n < NR ? n : NR - 1];
         }
     };
     auto store = [&](int buf) {
@@ -975,10 +1024,13 @@ __device__ __forceinline__ void m2lb_tile(const int32_t *__restrict__ tile_rng, 
         for (int j = 0; j < QREG; ++j) {
             const int n = tn + TPC * j;
             if (n >= 1 && n < NR)  // column n is stored at n - 1
-                bf16_split3(ldexpf(pq[j], -pdl * qdeg[j]), Qb[n - 1], Qb[16 * KSTR + n - 1], Qb[32 * KSTR + n - 1]);
+                bf16_split3(qok ? ldexpf(pq[j], -pdl * qdeg[j]) : 0.0f, Qb[n - 1], Qb[16 * KSTR + n - 1],
+                            Qb[32 * KSTR + n - 1]);
         }
     };
     if (e0 >= e1) return;
+    stage_seg();
+    __syncthreads();
     fetch(e0);
     store(0);
     __syncthreads();
@@ -1009,6 +1061,11 @@ __device__ __forceinline__ void m2lb_tile(const int32_t *__restrict__ tile_rng, 
         }
         if (e + 1 < e1) store(buf ^ 1);
         __syncthreads();
+        if (e + 1 - seg == kM2LSeg && e + 1 < e1) {
+            seg = e + 1;
+            stage_seg();
+            __syncthreads();
+        }
     }
 }
 
@@ -1026,6 +1083,7 @@ __global__ __launch_bounds__(64 * kM2LBWaves, 2) void k_m2l_bf16(
     static_assert(16 * RSTR * sizeof(double) <= 2 * 3 * 16 * KSTR * sizeof(__bf16), "reduction buffer fits");
     __shared__ __bf16 s_D[2 * 3 * (ND + 1)];
     __shared__ __align__(16) __bf16 s_Q[2 * 3 * 16 * KSTR];
+    __shared__ int32_t s_src[(kM2LSeg + 1) * 16], s_kk[2 * (kM2LSeg + 1)];
     const int tile = blockIdx.x;
     if (tile >= ntiles) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1037,9 +1095,11 @@ __global__ __launch_bounds__(64 * kM2LBWaves, 2) void k_m2l_bf16(
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt) acc[rt] = v4{0, 0, 0, 0};
     if (wave == 0)
-        m2lb_tile<P, NP, 0>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc);
+        m2lb_tile<P, NP, 0>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, s_src, s_kk,
+                            acc);
     else
-        m2lb_tile<P, NP, 1>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, acc);
+        m2lb_tile<P, NP, 1>(tile_rng, ent_key, ent_src, keys, Dtab, Qr, qpad, C, cols, tile, s_D, s_Q, s_src, s_kk,
+                            acc);
     __syncthreads();
     double *red = reinterpret_cast<double *>(s_Q);
     for (int i = tid; i < 16 * RSTR; i += blockDim.x) red[i] = 0.0;
