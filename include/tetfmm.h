@@ -151,6 +151,40 @@ int tfmm_direct(tfmm_plan plan, const double *M, int32_t F, double *u, void *hip
  */
 int tfmm_plan_store_near(tfmm_plan plan, int32_t on, void *hip_stream);
 
+/*
+ * Choice of expansion order and opening angle for an accuracy target (the
+ * two knobs of Sec. 2.2 and Sec. 3.2 that trade accuracy for work).
+ * For every p of p_list (ascending) the opening angles of theta_list are
+ * tried from the largest down; each candidate plan (leaf_size,
+ * m2l_precision, device from *base) evaluates the probe field M and its
+ * relative L2 error is measured against the FP64 direct sum at n_sample
+ * nodes drawn with `seed` (SplitMix64, without replacement).  The first
+ * theta whose sampled error is at most tol / 2 (a margin for the sampling)
+ * is timed (best of 3 evaluations) and the smaller thetas of that p are
+ * skipped; the fastest timed candidate is returned.
+ *  M      host, [n_nodes][3] double, the probe magnetisation
+ *  out    p, theta, sampled error and ms of the choice; met = 0 when no
+ *         candidate met the tolerance (out then holds the most accurate one,
+ *         ms = -1)
+ *  table  host [n_p * n_theta][4] (p, theta, error, ms; -1 where not
+ *         measured), or NULL
+ * Synchronous; builds and frees one plan per candidate.
+ * Errors: TFMM_EINVAL (NULL pointers, tol <= 0, empty lists, p or theta out
+ *         of range, host-only device), the errors of tfmm_plan_create.
+ */
+typedef struct {
+    int32_t p;
+    double theta;
+    double err;     /* sampled relative L2 error vs the FP64 direct sum */
+    double ms;      /* ms per evaluation of one field */
+    int32_t n_tried;
+    int32_t met;
+} tfmm_tune_result;
+int tfmm_tune_accuracy(const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
+                       const tfmm_params *base, const double *M, double tol, int32_t n_sample, uint64_t seed,
+                       const int32_t *p_list, int32_t n_p, const double *theta_list, int32_t n_theta,
+                       tfmm_tune_result *out, double *table);
+
 /* Switch the M2L arithmetic of an existing plan (one of TFMM_M2L_*). */
 int tfmm_plan_set_m2l_precision(tfmm_plan plan, int32_t m2l_precision);
 

@@ -21,7 +21,7 @@ __all__ = [
     "tfmm_plan_autotune", "tfmm_batch_create", "tfmm_batch_evaluate", "tfmm_batch_autotune", "tfmm_batch_plan",
     "tfmm_batch_destroy", "Batch", "tfmm_surrogate_param_count", "tfmm_surrogate_train", "tfmm_surrogate_load",
     "tfmm_surrogate_samples", "tfmm_surrogate_grad", "tfmm_band_potential", "tfmm_demag_energy",
-    "tfmm_plan_store_near",
+    "tfmm_plan_store_near", "tfmm_tune_accuracy",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -50,6 +50,11 @@ class _TrainCfg(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("p", C.c_int32), ("leaf_size", C.c_int32), ("theta", C.c_double), ("m2l_precision", C.c_int32),
                 ("device", C.c_int32)]
+
+
+class _TuneResult(C.Structure):
+    _fields_ = [("p", C.c_int32), ("theta", C.c_double), ("err", C.c_double), ("ms", C.c_double),
+                ("n_tried", C.c_int32), ("met", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -91,6 +96,8 @@ def _load():
         "tfmm_plan_destroy": (C.c_int, [C.c_void_p]),
         "tfmm_plan_set_m2l_precision": (C.c_int, [C.c_void_p, C.c_int32]),
         "tfmm_plan_store_near": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+        "tfmm_tune_accuracy": (C.c_int, [_dp, C.c_int64, _i32p, C.c_int64, C.c_void_p, _dp, C.c_double, C.c_int32,
+                                         C.c_uint64, _i32p, C.c_int32, _dp, C.c_int32, C.POINTER(_TuneResult), _dp]),
         "tfmm_last_error": (C.c_char_p, []),
         "tfmm_simplex_rule": (C.c_int, [C.c_int32, _dp, _i32p]),
         "tfmm_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -428,6 +435,32 @@ def tfmm_plan_set_m2l_precision(plan, m2l_precision):
     """M2L arithmetic of an existing plan: M2L_FP64, M2L_FP32, M2L_BF16X3 or M2L_BF16X6."""
     _check(_load().tfmm_plan_set_m2l_precision(plan.handle, int(m2l_precision)))
     plan.params["m2l_precision"] = int(m2l_precision)
+
+
+def tfmm_tune_accuracy(nodes, tets, tol, M=None, leaf_size=64, m2l_precision=M2L_FP64, device=0, n_sample=512,
+                       seed=1, p_list=(4, 5, 6, 7, 8, 9, 10), theta_list=(0.3, 0.35, 0.4, 0.45, 0.5, 0.55, 0.6, 0.7)):
+    """Fastest (p, theta) whose sampled error against the FP64 direct sum is at
+    most tol / 2.  M: host [n_nodes, 3] probe field (default: seeded random unit
+    vectors).  Returns dict(p, theta, err, ms, met, n_tried, table[n_p*n_theta, 4])."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    if M is None:
+        g = np.random.default_rng(seed).standard_normal((nodes.shape[0], 3))
+        M = g / np.linalg.norm(g, axis=1, keepdims=True)
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    if M.shape != (nodes.shape[0], 3):
+        raise ValueError("M must be [n_nodes, 3]")
+    pl = np.ascontiguousarray(p_list, dtype=np.int32)
+    tl = np.ascontiguousarray(theta_list, dtype=np.float64)
+    table = np.zeros((pl.size * tl.size, 4))
+    prm = _Params(8, int(leaf_size), 0.5, int(m2l_precision), int(device))
+    res = _TuneResult()
+    _check(_load().tfmm_tune_accuracy(_ptr(nodes, _dp), nodes.shape[0], _ptr(tets, _i32p), tets.shape[0],
+                                      C.byref(prm), _ptr(M, _dp), float(tol), int(n_sample), int(seed),
+                                      _ptr(pl, _i32p), pl.size, _ptr(tl, _dp), tl.size, C.byref(res),
+                                      _ptr(table, _dp)))
+    return dict(p=res.p, theta=res.theta, err=res.err, ms=res.ms, met=bool(res.met), n_tried=res.n_tried,
+                table=table)
 
 
 def tfmm_plan_store_near(plan, on=True, stream=None):

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <cstdio>
 #include <cstring>
@@ -582,6 +583,161 @@ int tfmm_plan_store_near(tfmm_plan plan, int32_t on, void *hip_stream)
             tfmm::drop_near(plan->dp);
         return TFMM_OK;
     });
+}
+
+// Seeded choice of k distinct indices of [0, n) (partial Fisher-Yates driven
+// by SplitMix64), sorted.
+static std::vector<int64_t> tune_sample(int64_t n, int64_t k, uint64_t seed)
+{
+    std::vector<int64_t> idx((size_t)n);
+    for (int64_t i = 0; i < n; ++i) idx[(size_t)i] = i;
+    uint64_t x = seed;
+    auto next = [&]() {
+        uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    for (int64_t i = 0; i < k; ++i) {
+        const int64_t j = i + (int64_t)(next() % (uint64_t)(n - i));
+        std::swap(idx[(size_t)i], idx[(size_t)j]);
+    }
+    idx.resize((size_t)k);
+    std::sort(idx.begin(), idx.end());
+    return idx;
+}
+
+int tfmm_tune_accuracy(const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
+                       const tfmm_params *base, const double *M, double tol, int32_t n_sample, uint64_t seed,
+                       const int32_t *p_list, int32_t n_p, const double *theta_list, int32_t n_theta,
+                       tfmm_tune_result *out, double *table)
+{
+    if (!nodes || !tets || !base || !M || !out || !p_list || !theta_list)
+        return set_error(TFMM_EINVAL, "NULL argument");
+    if (!(tol > 0.0) || n_sample < 1 || n_p < 1 || n_theta < 1 || n_nodes < 1)
+        return set_error(TFMM_EINVAL, "tol > 0, n_sample >= 1 and non-empty candidate lists required");
+    if (base->device < 0) return set_error(TFMM_EINVAL, "tuning needs a device");
+    for (int32_t i = 0; i < n_p; ++i)
+        if (p_list[i] < 1 || p_list[i] > TFMM_PMAX) return set_error(TFMM_EINVAL, "p out of range");
+    for (int32_t i = 0; i < n_theta; ++i)
+        if (!(theta_list[i] > 0.0 && theta_list[i] < 1.0)) return set_error(TFMM_EINVAL, "theta out of (0, 1)");
+    std::memset(out, 0, sizeof(*out));
+    if (table)
+        for (int64_t i = 0; i < (int64_t)n_p * n_theta; ++i) {
+            table[4 * i] = p_list[i / n_theta];
+            table[4 * i + 1] = theta_list[i % n_theta];
+            table[4 * i + 2] = table[4 * i + 3] = -1.0;
+        }
+    const int64_t ns = std::min<int64_t>(n_sample, n_nodes);
+    const std::vector<int64_t> sample = tune_sample(n_nodes, ns, seed);
+    std::vector<double> xs(3 * (size_t)ns);
+    for (int64_t i = 0; i < ns; ++i)
+        for (int k = 0; k < 3; ++k) xs[3 * (size_t)i + k] = nodes[3 * sample[(size_t)i] + k];
+    double *dM = nullptr, *du = nullptr, *dref = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    tfmm_plan ref = nullptr, cand = nullptr;
+    auto cleanup = [&]() {
+        if (cand) tfmm_plan_destroy(cand);
+        if (ref) tfmm_plan_destroy(ref);
+        if (st) (void)hipStreamSynchronize(st);
+        if (dM) (void)hipFree(dM);
+        if (du) (void)hipFree(du);
+        if (dref) (void)hipFree(dref);
+        if (ea) (void)hipEventDestroy(ea);
+        if (eb) (void)hipEventDestroy(eb);
+        if (st) (void)hipStreamDestroy(st);
+    };
+    int rc = guarded([&]() -> int {
+        DeviceScope ds(base->device);
+        tfmm::hip_check(hipStreamCreate(&st), "hipStreamCreate");
+        tfmm::hip_check(hipEventCreate(&ea), "hipEventCreate");
+        tfmm::hip_check(hipEventCreate(&eb), "hipEventCreate");
+        tfmm::hip_check(hipMalloc(&dM, sizeof(double) * 3 * (size_t)n_nodes), "hipMalloc M");
+        tfmm::hip_check(hipMalloc(&du, sizeof(double) * (size_t)n_nodes), "hipMalloc u");
+        tfmm::hip_check(hipMalloc(&dref, sizeof(double) * (size_t)ns), "hipMalloc reference");
+        tfmm::hip_check(hipMemcpy(dM, M, sizeof(double) * 3 * (size_t)n_nodes, hipMemcpyHostToDevice), "hipMemcpy M");
+        // reference: FP64 direct sum at the sampled nodes
+        tfmm_params rp = *base;
+        rp.p = 2;
+        rp.theta = 0.5;
+        int r = tfmm_plan_create(nodes, n_nodes, tets, n_tets, xs.data(), ns, &rp, &ref);
+        if (r) return r;
+        if ((r = tfmm_direct(ref, dM, 1, dref, st))) return r;
+        std::vector<double> uref((size_t)ns), u((size_t)n_nodes);
+        tfmm::hip_check(hipMemcpyAsync(uref.data(), dref, sizeof(double) * (size_t)ns, hipMemcpyDeviceToHost, st),
+                        "hipMemcpy reference");
+        tfmm::hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        tfmm_plan_destroy(ref);
+        ref = nullptr;
+        double nref = 0.0;
+        for (double v : uref) nref += v * v;
+        nref = std::sqrt(nref);
+        bool any = false;
+        double best_err = -1.0;
+        // p ascending; per p the largest theta first (the cheapest); the first
+        // theta whose sampled error is within half the tolerance is timed and
+        // the smaller thetas of that p (more work) are skipped
+        for (int32_t ip = 0; ip < n_p; ++ip) {
+            std::vector<int32_t> order((size_t)n_theta);
+            for (int32_t i = 0; i < n_theta; ++i) order[(size_t)i] = i;
+            std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return theta_list[a] > theta_list[b]; });
+            for (int32_t it : order) {
+                tfmm_params cp = *base;
+                cp.p = p_list[ip];
+                cp.theta = theta_list[it];
+                if ((r = tfmm_plan_create(nodes, n_nodes, tets, n_tets, nullptr, 0, &cp, &cand))) return r;
+                if ((r = tfmm_evaluate(cand, dM, 1, du, st))) return r;
+                tfmm::hip_check(hipMemcpyAsync(u.data(), du, sizeof(double) * (size_t)n_nodes, hipMemcpyDeviceToHost, st),
+                                "hipMemcpy u");
+                tfmm::hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+                double e2 = 0.0;
+                for (int64_t i = 0; i < ns; ++i) {
+                    const double d = u[(size_t)sample[(size_t)i]] - uref[(size_t)i];
+                    e2 += d * d;
+                }
+                const double err = nref > 0.0 ? std::sqrt(e2) / nref : std::sqrt(e2);
+                ++out->n_tried;
+                double *row = table ? table + 4 * ((int64_t)ip * n_theta + it) : nullptr;
+                if (row) row[2] = err;
+                const bool ok = err <= 0.5 * tol;
+                if (ok) {
+                    float best_ms = -1.f;
+                    for (int rep = 0; rep < 3; ++rep) {
+                        tfmm::hip_check(hipEventRecord(ea, st), "hipEventRecord");
+                        if ((r = tfmm_evaluate(cand, dM, 1, du, st))) return r;
+                        tfmm::hip_check(hipEventRecord(eb, st), "hipEventRecord");
+                        tfmm::hip_check(hipEventSynchronize(eb), "hipEventSynchronize");
+                        float ms = 0.f;
+                        tfmm::hip_check(hipEventElapsedTime(&ms, ea, eb), "hipEventElapsedTime");
+                        if (best_ms < 0.f || ms < best_ms) best_ms = ms;
+                    }
+                    if (row) row[3] = best_ms;
+                    if (!any || best_ms < out->ms) {
+                        out->p = cp.p;
+                        out->theta = cp.theta;
+                        out->err = err;
+                        out->ms = best_ms;
+                    }
+                    any = true;
+                } else if (!any && (best_err < 0.0 || err < best_err)) {
+                    // the most accurate candidate so far stands in until one meets the tolerance
+                    best_err = err;
+                    out->p = cp.p;
+                    out->theta = cp.theta;
+                    out->err = err;
+                    out->ms = -1.0;
+                }
+                tfmm_plan_destroy(cand);
+                cand = nullptr;
+                if (ok) break;
+            }
+        }
+        out->met = any ? 1 : 0;
+        return TFMM_OK;
+    });
+    cleanup();
+    return rc;
 }
 
 static void batch_drop_graph(tfmm_batch b)
