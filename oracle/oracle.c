@@ -531,6 +531,74 @@ int orc_p2m_tet(const double *v, const double *M, const double *c, int p, double
     return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Point dipoles, the second source kind of the paper (its "Mag FMM" for      */
+/* point-like dipole clouds, Sec. 4).  A dipole of moment m at y is the       */
+/* magnetisation m delta(r' - y) in eq. approx1, so                           */
+/*   u(x) = m . (x - y) / (4 pi |x - y|^3)   (0 at x = y: no self term)       */
+/* and its multipole coefficients (the integral of M . grad'(r' - c)^n) are   */
+/*   Q_n = sum_k n_k m_k (y - c)^(n - e_k).                                   */
+/* ------------------------------------------------------------------------- */
+double orc_dipole_potential(const double *x, const double *y, const double *m)
+{
+    double d[3];
+    sub3(x, y, d);
+    const double r2 = dot3(d, d);
+    if (r2 == 0.0) return 0.0;
+    return ORC_INV4PI * dot3(m, d) / (r2 * sqrt(r2));
+}
+
+static void orc_p2m_dipole_acc(const orc_basis *B, const double *y, const double *m, const double *c, double *Q)
+{
+    double yc[3];
+    sub3(y, c, yc);
+    double mono[(ORC_MAXP + 1) * (ORC_MAXP + 2) * (ORC_MAXP + 3) / 6];
+    orc_monomials(B, yc, mono);
+    for (int k = 1; k < B->ncoef; ++k) {
+        const int *n = B->mi[k];
+        double s = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            if (n[i] == 0) continue;
+            int q[3] = {n[0], n[1], n[2]};
+            q[i] -= 1;
+            s += n[i] * m[i] * mono[B->idx[q[0]][q[1]][q[2]]];
+        }
+        Q[k] += s;
+    }
+}
+
+int orc_p2m_dipole(const double *y, const double *m, const double *c, int p, double *Q)
+{
+    if (p < 0 || p > ORC_MAXP) return -1;
+    orc_basis B;
+    orc_basis_init(&B, p);
+    memset(Q, 0, sizeof(double) * (size_t)B.ncoef);
+    orc_p2m_dipole_acc(&B, y, m, c, Q);
+    orc_basis_free(&B);
+    return 0;
+}
+
+/* O(N^2) dipole sum: pts [n][3], M [F][n][3] moments, targets [nt][3] (NULL: */
+/* the points), u [F][nt].                                                     */
+int orc_dipole_direct(const double *pts, int64_t n, const double *M, int32_t F, const double *targets, int64_t nt,
+                      double *u)
+{
+    if (!targets) {
+        targets = pts;
+        nt = n;
+    }
+    for (int32_t f = 0; f < F; ++f) {
+        const double *Mf = M + (size_t)f * n * 3;
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t i = 0; i < nt; ++i) {
+            double s = 0.0;
+            for (int64_t j = 0; j < n; ++j) s += orc_dipole_potential(targets + 3 * i, pts + 3 * j, Mf + 3 * j);
+            u[(size_t)f * nt + i] = s;
+        }
+    }
+    return 0;
+}
+
 int orc_m2m(const double *Qc, const double *delta, int p, double *Qp)
 {
     if (p < 0 || p > ORC_MAXP) return -1;
@@ -613,6 +681,7 @@ typedef struct {
     orc_basis B;
     orc_rule R;
     double *Q, *L; /* [ncells][ncoef] for the last evaluated field */
+    int points;    /* sources are point dipoles at the nodes (orc_fmm_build_points) */
 } orc_fmm;
 
 static uint32_t orc_key1(double xd, double o, double S)
@@ -883,6 +952,22 @@ void *orc_fmm_build(const double *nodes, int64_t n_nodes, const int32_t *tets, i
     return T;
 }
 
+/* Tree and lists over point dipoles: source i is the point pts[i], entered  */
+/* as a tet whose four corners are that point (centroid and farthest corner   */
+/* are the point itself).                                                      */
+void *orc_fmm_build_points(const double *pts, int64_t n, const double *targets, int64_t n_targets, int32_t p,
+                           int32_t leaf, double theta)
+{
+    if (n < 1) return NULL;
+    int32_t *tv = malloc(sizeof(int32_t) * 4 * (size_t)n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < 4; ++c) tv[4 * i + c] = (int32_t)i;
+    orc_fmm *T = orc_fmm_build(pts, n, tv, n, targets, n_targets, p, leaf, theta);
+    free(tv);
+    if (T) T->points = 1;
+    return T;
+}
+
 void orc_fmm_free(void *h)
 {
     orc_fmm *T = h;
@@ -984,6 +1069,12 @@ static void orc_upward(orc_fmm *T, const double *Mf)
         orc_cell *C = &T->cells[ci];
         if (C->nchild != 0) continue;
         for (int64_t i = 0; i < C->ntets; ++i) {
+            if (T->points) {
+                const int32_t nd = T->tetv[4 * C->tets[i]];
+                orc_p2m_dipole_acc(&T->B, T->nodes + 3 * (size_t)nd, Mf + 3 * (size_t)nd, C->c,
+                                   T->Q + (size_t)ci * nc);
+                continue;
+            }
             double v[12], m[12];
             for (int c = 0; c < 4; ++c) {
                 int32_t nd = T->tetv[4 * C->tets[i] + c];
@@ -1025,6 +1116,11 @@ static double orc_target_near(const orc_fmm *T, const orc_cell *A, int64_t ti, c
     for (int j = 0; j < A->np2p; ++j) {
         const orc_cell *Bc = &T->cells[A->p2p[j]];
         for (int64_t i = 0; i < Bc->ntets; ++i) {
+            if (T->points) {
+                const int32_t nd = T->tetv[4 * Bc->tets[i]];
+                s += orc_dipole_potential(x, T->nodes + 3 * (size_t)nd, Mf + 3 * (size_t)nd);
+                continue;
+            }
             double v[12], m[12];
             for (int c = 0; c < 4; ++c) {
                 int32_t nd = T->tetv[4 * Bc->tets[i] + c];

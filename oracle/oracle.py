@@ -64,6 +64,14 @@ def _load():
     lib.orc_fmm_evaluate_sample.argtypes = [C.c_void_p, _dp, C.c_int32, _i64p, C.c_int64, _dp]
     lib.orc_fmm_expansions.restype = C.c_int
     lib.orc_fmm_expansions.argtypes = [C.c_void_p, C.c_int32, _dp]
+    lib.orc_dipole_potential.restype = C.c_double
+    lib.orc_dipole_potential.argtypes = [_dp, _dp, _dp]
+    lib.orc_p2m_dipole.restype = C.c_int
+    lib.orc_p2m_dipole.argtypes = [_dp, _dp, _dp, C.c_int, _dp]
+    lib.orc_dipole_direct.restype = C.c_int
+    lib.orc_dipole_direct.argtypes = [_dp, C.c_int64, _dp, C.c_int32, _dp, C.c_int64, _dp]
+    lib.orc_fmm_build_points.restype = C.c_void_p
+    lib.orc_fmm_build_points.argtypes = [_dp, C.c_int64, _dp, C.c_int64, C.c_int32, C.c_int32, C.c_double]
     lib.orc_num_threads.restype = C.c_int
     lib.orc_set_num_threads.restype = None
     lib.orc_set_num_threads.argtypes = [C.c_int]
@@ -241,3 +249,59 @@ class FMM:
         out = np.zeros((st["ncells"], st["ncoef"]))
         assert _load().orc_fmm_expansions(self._h, 0 if which == "Q" else 1, _ptr(out, _dp)) == 0
         return out
+
+
+# ---------------------------------------------------------------------------
+# Point dipoles (the paper's second source kind, its "Mag FMM", Sec. 4)
+# ---------------------------------------------------------------------------
+def dipole_potential(x, y, m):
+    """m . (x - y) / (4 pi |x - y|^3); 0 at x = y."""
+    x, y, m = _d(x), _d(y), _d(m)
+    return _load().orc_dipole_potential(_ptr(x, _dp), _ptr(y, _dp), _ptr(m, _dp))
+
+
+def p2m_dipole(y, m, c, p):
+    """Multipole coefficients of one dipole about c: Q_n = sum_k n_k m_k (y - c)^(n - e_k)."""
+    Q = np.zeros(ncoef(p))
+    y, m, c = _d(y), _d(m), _d(c)
+    assert _load().orc_p2m_dipole(_ptr(y, _dp), _ptr(m, _dp), _ptr(c, _dp), p, _ptr(Q, _dp)) == 0
+    return Q
+
+
+def dipole_direct(points, M, targets=None):
+    """O(N^2) dipole sum.  M [F, n, 3] or [n, 3] moments -> u [F, nt] or [nt]."""
+    points = _d(points)
+    M = _d(M)
+    squeeze = M.ndim == 2
+    if squeeze:
+        M = M[None]
+    F = M.shape[0]
+    if targets is None:
+        tp, nt, nu = None, 0, points.shape[0]
+    else:
+        tgt = _d(targets)
+        tp, nt, nu = _ptr(tgt, _dp), tgt.shape[0], tgt.shape[0]
+    u = np.zeros((F, nu))
+    assert _load().orc_dipole_direct(_ptr(points, _dp), points.shape[0], _ptr(M, _dp), F, tp, nt, _ptr(u, _dp)) == 0
+    return u[0] if squeeze else u
+
+
+class DipoleFMM(FMM):
+    """Oracle FMM over point dipoles at `points` (same tree, lists and
+    translations as FMM; dipole P2M and near field).  evaluate(M) takes the
+    moments M [F, n, 3] or [n, 3]."""
+
+    def __init__(self, points, p, leaf, theta, targets=None):
+        self.nodes = _d(points)
+        self.tets = None
+        self.targets = None if targets is None else _d(targets)
+        self.p = int(p)
+        lib = _load()
+        tp = _ptr(self.targets, _dp) if self.targets is not None else None
+        nt = self.targets.shape[0] if self.targets is not None else 0
+        h = lib.orc_fmm_build_points(_ptr(self.nodes, _dp), self.nodes.shape[0], tp, nt, int(p), int(leaf),
+                                     float(theta))
+        if not h:
+            raise ValueError("orc_fmm_build_points: bad input")
+        self._h = C.c_void_p(h)
+        self.n_targets = self.stats()["n_targets"]
