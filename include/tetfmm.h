@@ -119,6 +119,24 @@ int tfmm_plan_create(const double *nodes, int64_t n_nodes, const int32_t *tets, 
                      const double *targets, int64_t n_targets, const tfmm_params *prm, tfmm_plan *out);
 
 /*
+ * Plan for point dipoles (the paper's second source kind, the "Mag FMM" of
+ * Sec. 4: point-like dipole clouds).  Source i is a dipole at points[i]; the
+ * tree, radii, lists and translations are those of tfmm_plan_create with each
+ * source's centroid and farthest point being the point itself; P2M is the
+ * dipole expansion Q_n = sum_i sum_k n_k m_ik (y_i - c)^(n - e_k) and the
+ * near field the dipole potential m . (x - y)/(4 pi |x - y|^3), a target at
+ * a dipole's own position taking nothing from that dipole.
+ *  points   host, [n_points][3] double
+ *  targets  host, [n_targets][3] double, or NULL for the points themselves
+ * tfmm_evaluate / tfmm_direct then take M = the dipole moments, device
+ * [F][n_points][3], and write u [F][n_targets].  The stored near field, the
+ * demagnetising energy and the surrogate return TFMM_ENOTSUP on such plans.
+ * Errors: as tfmm_plan_create (TFMM_EINVAL also when all points coincide).
+ */
+int tfmm_plan_create_points(const double *points, int64_t n_points, const double *targets, int64_t n_targets,
+                            const tfmm_params *prm, tfmm_plan *out);
+
+/*
  * FMM evaluation (Secs. 2-3: P2M, M2M, M2L, L2L, L2P plus the exact
  * near-field P2P of Sec. 2.1) of F fields.
  *  M  device, [F][n_nodes][3] double: nodal magnetisation, affine per tet

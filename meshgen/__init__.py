@@ -68,6 +68,18 @@ def random_fields(n_nodes, F=1, seed=1):
     return np.stack([unit_vectors(n_nodes, seed + f) for f in range(F)])
 
 
+def lumped_volumes(nodes, tets):
+    """Per node a quarter of the volume of every tet around it (sums to the
+    mesh volume): the weights that turn nodal magnetisation into the moments
+    of a point-dipole cloud on the same nodes."""
+    v = nodes[tets]
+    vol = np.abs(np.einsum("ij,ij->i", v[:, 1] - v[:, 0], np.cross(v[:, 2] - v[:, 0], v[:, 3] - v[:, 0]))) / 6.0
+    w = np.zeros(nodes.shape[0])
+    for c in range(4):
+        np.add.at(w, tets[:, c], vol / 4.0)
+    return w
+
+
 def uniform_field(n_nodes, direction):
     d = np.asarray(direction, dtype=np.float64)
     return np.tile(d, (n_nodes, 1))

@@ -21,7 +21,7 @@ __all__ = [
     "tfmm_plan_autotune", "tfmm_batch_create", "tfmm_batch_evaluate", "tfmm_batch_autotune", "tfmm_batch_plan",
     "tfmm_batch_destroy", "Batch", "tfmm_surrogate_param_count", "tfmm_surrogate_train", "tfmm_surrogate_load",
     "tfmm_surrogate_samples", "tfmm_surrogate_grad", "tfmm_band_potential", "tfmm_demag_energy",
-    "tfmm_plan_store_near", "tfmm_tune_accuracy",
+    "tfmm_plan_store_near", "tfmm_tune_accuracy", "tfmm_plan_create_points",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -96,6 +96,7 @@ def _load():
         "tfmm_plan_destroy": (C.c_int, [C.c_void_p]),
         "tfmm_plan_set_m2l_precision": (C.c_int, [C.c_void_p, C.c_int32]),
         "tfmm_plan_store_near": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+        "tfmm_plan_create_points": (C.c_int, [_dp, C.c_int64, _dp, C.c_int64, C.c_void_p, C.POINTER(C.c_void_p)]),
         "tfmm_tune_accuracy": (C.c_int, [_dp, C.c_int64, _i32p, C.c_int64, C.c_void_p, _dp, C.c_double, C.c_int32,
                                          C.c_uint64, _i32p, C.c_int32, _dp, C.c_int32, C.POINTER(_TuneResult), _dp]),
         "tfmm_last_error": (C.c_char_p, []),
@@ -181,6 +182,28 @@ def tfmm_plan_create(nodes, tets, targets=None, p=8, leaf_size=64, theta=0.5, m2
                                 C.byref(prm), C.byref(h)))
     return Plan(h.value, int(device), nodes.shape[0], nt if targets is not None else nodes.shape[0],
                 dict(p=int(p), leaf_size=int(leaf_size), theta=float(theta), m2l_precision=int(m2l_precision)))
+
+
+def tfmm_plan_create_points(points, targets=None, p=8, leaf_size=64, theta=0.5, m2l_precision=0, device=0):
+    """Plan for point dipoles at `points` [n, 3]; evaluations take the dipole
+    moments as M [F, n, 3] (device) and give u at the targets (default: the
+    points, each excluding its own dipole)."""
+    lib = _load()
+    points = np.ascontiguousarray(points, dtype=np.float64)
+    if points.ndim != 2 or points.shape[1] != 3:
+        raise ValueError("points must be [n,3]")
+    tp, nt = None, 0
+    if targets is not None:
+        targets = np.ascontiguousarray(targets, dtype=np.float64)
+        if targets.ndim != 2 or targets.shape[1] != 3:
+            raise ValueError("targets must be [n,3]")
+        tp, nt = _ptr(targets, _dp), targets.shape[0]
+    prm = _Params(int(p), int(leaf_size), float(theta), int(m2l_precision), int(device))
+    h = C.c_void_p()
+    _check(lib.tfmm_plan_create_points(_ptr(points, _dp), points.shape[0], tp, nt, C.byref(prm), C.byref(h)))
+    return Plan(h.value, int(device), points.shape[0], nt if targets is not None else points.shape[0],
+                dict(p=int(p), leaf_size=int(leaf_size), theta=float(theta), m2l_precision=int(m2l_precision),
+                     points=True))
 
 
 def _stream_handle(stream, device):

@@ -207,7 +207,7 @@ void upload_plan(DevicePlan &dp)
         }
         // shared mesh entities of the source blocks (single-field near field)
         NearTopo tp;
-        build_near_topology(hp, blk, tp);
+        if (!hp.points) build_near_topology(hp, blk, tp);  // point sources have no mesh entities
         {
             // longest blocks (tets x targets) first in dispatch order, so that the
             // launch ends evenly; the chunk list keeps the same block order
@@ -218,10 +218,11 @@ void upload_plan(DevicePlan &dp)
             std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return work(x) > work(y); });
             const std::vector<int32_t> pos = xcd_dispatch_items(nb);
             std::vector<int32_t> b2(blk.size()), t2(tp.blk.size());
+            const bool has_topo = !tp.blk.empty();
             for (int k = 0; k < nb; ++k)
                 for (int j = 0; j < 4; ++j) {
                     b2[4 * (size_t)pos[k] + j] = blk[4 * (size_t)ord[k] + j];
-                    t2[4 * (size_t)pos[k] + j] = tp.blk[4 * (size_t)ord[k] + j];
+                    if (has_topo) t2[4 * (size_t)pos[k] + j] = tp.blk[4 * (size_t)ord[k] + j];
                 }
             blk.swap(b2);
             tp.blk.swap(t2);
@@ -298,8 +299,23 @@ extern "C" {
 
 const char *tfmm_last_error(void) { return g_last_error.c_str(); }
 
+static int plan_create(const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
+                       const double *targets, int64_t n_targets, const tfmm_params *prm, tfmm_plan *out, bool points);
+
 int tfmm_plan_create(const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
                      const double *targets, int64_t n_targets, const tfmm_params *prm, tfmm_plan *out)
+{
+    return plan_create(nodes, n_nodes, tets, n_tets, targets, n_targets, prm, out, false);
+}
+
+int tfmm_plan_create_points(const double *points, int64_t n_points, const double *targets, int64_t n_targets,
+                            const tfmm_params *prm, tfmm_plan *out)
+{
+    return plan_create(points, n_points, nullptr, n_points, targets, n_targets, prm, out, true);
+}
+
+static int plan_create(const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
+                       const double *targets, int64_t n_targets, const tfmm_params *prm, tfmm_plan *out, bool points)
 {
     if (out) *out = nullptr;
     if (!prm || !out) return set_error(TFMM_EINVAL, "prm and out must not be NULL");
@@ -309,7 +325,7 @@ int tfmm_plan_create(const double *nodes, int64_t n_nodes, const int32_t *tets, 
         auto t0 = std::chrono::steady_clock::now();
         std::unique_ptr<tfmm_plan_s> P(new tfmm_plan_s());
         tfmm::build_host_plan(P->dp.hp, nodes, n_nodes, tets, n_tets, targets, n_targets, prm->p, prm->leaf_size,
-                              prm->theta);
+                              prm->theta, points);
         P->dp.ncoef = (prm->p + 1) * (prm->p + 2) * (prm->p + 3) / 6;
         P->dp.m2l_precision = prm->m2l_precision;
         if (prm->device >= 0) {
@@ -575,6 +591,7 @@ int tfmm_plan_store_near(tfmm_plan plan, int32_t on, void *hip_stream)
 {
     if (!plan) return set_error(TFMM_EINVAL, "NULL plan");
     if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan has no near-field operator");
+    if (plan->dp.hp.points) return set_error(TFMM_ENOTSUP, "not available for point-dipole plans");
     return guarded([&]() -> int {
         DeviceScope ds(plan->dp.device);
         if (on)
@@ -908,6 +925,7 @@ int tfmm_demag_energy(tfmm_plan plan, const double *M, const double *u, double *
 {
     if (!plan || !M || !u || !energy) return set_error(TFMM_EINVAL, "NULL argument");
     if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan");
+    if (plan->dp.hp.points) return set_error(TFMM_ENOTSUP, "not available for point-dipole plans");
     if (!plan->dp.hp.targets_are_nodes) return set_error(TFMM_EINVAL, "the plan's targets are not its nodes");
     return guarded([&]() -> int {
         DeviceScope ds(plan->dp.device);
@@ -934,6 +952,7 @@ int tfmm_surrogate_train(tfmm_plan plan, const tfmm_train_cfg *cfg, const char *
 {
     if (!plan || !cfg) return set_error(TFMM_EINVAL, "NULL argument");
     if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan");
+    if (plan->dp.hp.points) return set_error(TFMM_ENOTSUP, "not available for point-dipole plans");
     if ((cfg->hidden != 32 && cfg->hidden != 64 && cfg->hidden != 128) || cfg->steps < 1 || cfg->batch < 1 ||
         !(cfg->lr > 0.f))
         return set_error(TFMM_EINVAL, "hidden must be 32, 64 or 128; steps, batch and lr positive");
@@ -953,6 +972,7 @@ int tfmm_surrogate_load(tfmm_plan plan, const char *path)
 {
     if (!plan || !path) return set_error(TFMM_EINVAL, "NULL argument");
     if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan");
+    if (plan->dp.hp.points) return set_error(TFMM_ENOTSUP, "not available for point-dipole plans");
     FILE *f = std::fopen(path, "rb");
     if (!f) return set_error(TFMM_EINVAL, std::string("cannot read ") + path);
     char magic[8];
@@ -978,6 +998,7 @@ int tfmm_surrogate_samples(tfmm_plan plan, uint64_t seed, int32_t n, float *X, f
 {
     if (!plan || !X || !Y || n < 1) return set_error(TFMM_EINVAL, "bad argument");
     if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan");
+    if (plan->dp.hp.points) return set_error(TFMM_ENOTSUP, "not available for point-dipole plans");
     return guarded([&]() -> int {
         DeviceScope ds(plan->dp.device);
         tfmm::surrogate_samples(plan->dp, seed, n, X, Y);
@@ -1004,6 +1025,7 @@ int tfmm_band_potential(tfmm_plan plan, int32_t use_surrogate, const double *M, 
 {
     int rc = check_eval_args(plan, M, 1, u);
     if (rc) return rc;
+    if (plan->dp.hp.points) return set_error(TFMM_ENOTSUP, "not available for point-dipole plans");
     if (use_surrogate && !plan->dp.sur_wb) return set_error(TFMM_EINVAL, "no surrogate attached to the plan");
     return guarded([&]() -> int {
         DeviceScope ds(plan->dp.device);

@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kMomThreads) void k_tet_moments(const int32_t *__re
                                                              const double *__restrict__ cell_c, int64_t C,
                                                              const double *__restrict__ tet_xyz, int64_t T,
                                                              const double *__restrict__ quad, int nq, int p,
-                                                             double *__restrict__ mom)
+                                                             int points, double *__restrict__ mom)
 {
     __shared__ double s_pw[kMomChunk][3][kPmax + 1];  // powers 0..p of (y - c)
     __shared__ double s_w[kMomChunk];
@@ -137,6 +137,19 @@ __global__ __launch_bounds__(kMomThreads) void k_tet_moments(const int32_t *__re
     const double cc[3] = {cell_c[cell], cell_c[C + cell], cell_c[2 * C + cell]};
     const int ncoef = ncoef_of(p);
     const int tid = threadIdx.x;
+    if (points) {  // point sources: S_m = (y - c)^m at the point
+        for (int i = tid; i < (tend - tbeg) * ncoef; i += kMomThreads) {
+            const int t = tbeg + i / ncoef, m = i % ncoef;
+            double r = 1.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double y = tet_xyz[(int64_t)k * T + t] - cc[k];
+                for (int j = 0; j < c_mi.v[m][k]; ++j) r *= y;
+            }
+            mom[(int64_t)t * ncoef + m] = r;
+        }
+        return;
+    }
     for (int t = tbeg; t < tend; ++t) {
         double v[4][3];
 #pragma unroll
@@ -263,7 +276,7 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m(const int32_t *__restrict__
                                                      const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node,
                                                      int64_t T, const double *__restrict__ mom,
                                                      const double *__restrict__ M, int64_t n_nodes, int F, int p,
-                                                     int ncells, double *__restrict__ Q)
+                                                     int ncells, int points, double *__restrict__ Q)
 {
     extern __shared__ double s_dyn[];
     const int ncoef = ncoef_of(p);
@@ -287,7 +300,11 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m(const int32_t *__restrict__
         for (int i = tid; i < nt * ncoef; i += blockDim.x) s_S[i] = mom[(int64_t)sb * ncoef + i];
         for (int i = tid; i < nt * FC; i += blockDim.x) {
             const int t = i / FC, j = i - t * FC;
-            if (f0 + j < F)
+            if (f0 + j < F && points) {  // a dipole: M(c) = its moment, no gradient
+                const double *m = M + ((int64_t)(f0 + j) * n_nodes + tet_node[sb + t]) * 3;
+                double *w = s_W + (t * FC + j) * 12;
+                for (int q = 0; q < 12; ++q) w[q] = q < 3 ? m[q] : 0.0;
+            } else if (f0 + j < F)
                 tet_affine_field(tet_xyz, tet_node, T, sb + t, M + (int64_t)(f0 + j) * n_nodes * 3, cc,
                                  s_W + (t * FC + j) * 12);
             else
@@ -1240,6 +1257,76 @@ __global__ __launch_bounds__(p2p_threads(FCH, WIDE), 2) void k_p2p(const int32_t
 }
 
 // ---------------------------------------------------------------------------
+// Point dipoles (the second source kind): u(x) = 1/(4 pi) sum_i m_i . (x - y_i)
+// / |x - y_i|^3 over the sources of the near leaves (or all, direct sum); a
+// target at a source's own position takes nothing from it.  Blocks as in
+// k_p2p; the positions and the FCH moments of kPtStage sources are staged in
+// LDS, every thread takes targets ib + l, ib + l + 256, ...
+// ---------------------------------------------------------------------------
+constexpr int kPtStage = 128, kPtThreads = 256;
+
+template <int FCH>
+__global__ __launch_bounds__(kPtThreads) void k_p2p_points(const int32_t *__restrict__ blk, int nblk, int direct_src,
+                                                           int64_t T, const double *__restrict__ src_xyz,
+                                                           const int32_t *__restrict__ src_node,
+                                                           const int32_t *__restrict__ idx,
+                                                           const double *__restrict__ tgt_xyz,
+                                                           const int32_t *__restrict__ tgt_perm, int64_t N,
+                                                           const double *__restrict__ M, int64_t n_nodes, int f0,
+                                                           double *__restrict__ u)
+{
+    __shared__ double s_y[kPtStage][3];
+    __shared__ double s_m[kPtStage][FCH][3];
+    const int b = xcd_item(nblk);
+    if (b < 0) return;
+    int tb, te, ib, ie;
+    if (direct_src) {
+        tb = b * kP2PTets;
+        te = min<int64_t>(T, tb + kP2PTets);
+        ib = 0;
+        ie = (int)N;
+    } else {
+        tb = blk[4 * b];
+        te = blk[4 * b + 1];
+        ib = blk[4 * b + 2];
+        ie = blk[4 * b + 3];
+    }
+    const int lane = threadIdx.x;
+    for (int sb = tb; sb < te; sb += kPtStage) {
+        const int ns = min(kPtStage, te - sb);
+        __syncthreads();
+        for (int i = lane; i < ns; i += kPtThreads) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s_y[i][k] = src_xyz[(int64_t)k * T + sb + i];
+            const int64_t nd = src_node[sb + i];
+#pragma unroll
+            for (int f = 0; f < FCH; ++f)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) s_m[i][f][k] = M[((int64_t)(f0 + f) * n_nodes + nd) * 3 + k];
+        }
+        __syncthreads();
+        for (int i = ib + lane; i < ie; i += kPtThreads) {
+            const int s = direct_src ? i : idx[i];
+            const double x[3] = {tgt_xyz[s], tgt_xyz[N + s], tgt_xyz[2 * N + s]};
+            double acc[FCH];
+#pragma unroll
+            for (int f = 0; f < FCH; ++f) acc[f] = 0.0;
+            for (int j = 0; j < ns; ++j) {
+                const double d0 = x[0] - s_y[j][0], d1 = x[1] - s_y[j][1], d2 = x[2] - s_y[j][2];
+                const double r2 = (d0 * d0 + d1 * d1) + d2 * d2;
+                const double w = r2 > 0.0 ? 1.0 / (r2 * sqrt(r2)) : 0.0;
+#pragma unroll
+                for (int f = 0; f < FCH; ++f)
+                    acc[f] = fma(w, (s_m[j][f][0] * d0 + s_m[j][f][1] * d1) + s_m[j][f][2] * d2, acc[f]);
+            }
+            const int64_t o = tgt_perm[s];
+#pragma unroll
+            for (int f = 0; f < FCH; ++f) atomicAdd(&u[(int64_t)(f0 + f) * N + o], acc[f] * kInv4Pi);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Single-field near field over the shared mesh entities of a source chunk.
 //
 // Summed over the tets T of a chunk, the pair formula regroups by entity:
@@ -1740,8 +1827,41 @@ void launch_p2p(DevicePlan &dp, bool direct, int f0, const double *M, double *u,
     launch_p2p_w<FCH, false>(dp, direct, f0, M, u, st);
 }
 
+void run_p2p_points(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u, hipStream_t st)
+{
+    const HostPlan &hp = dp.hp;
+    const unsigned nblk = direct ? (unsigned)((hp.n_tets + kP2PTets - 1) / kP2PTets) : (unsigned)dp.n_p2p_blk;
+    if (nblk == 0) return;
+    for (int f = 0; f < F;) {
+        const int left = F - f;
+#define TFMM_P2P_POINTS(FCV)                                                                                       \
+    k_p2p_points<FCV><<<dim3(xcd_grid((int)nblk)), dim3(kPtThreads), 0, st>>>(                                      \
+        dp.p2p_blk, (int)nblk, direct ? 1 : 0, hp.n_tets, dp.tet_xyz, dp.tet_node, dp.p2p_idx, dp.tgt_xyz,            \
+        dp.tgt_perm, hp.n_targets, M, hp.n_nodes, f, u)
+        if (left >= 8) {
+            TFMM_P2P_POINTS(8);
+            f += 8;
+        } else if (left >= 4) {
+            TFMM_P2P_POINTS(4);
+            f += 4;
+        } else if (left >= 2) {
+            TFMM_P2P_POINTS(2);
+            f += 2;
+        } else {
+            TFMM_P2P_POINTS(1);
+            f += 1;
+        }
+#undef TFMM_P2P_POINTS
+        hip_check(hipGetLastError(), "k_p2p_points launch");
+    }
+}
+
 void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u, hipStream_t st)
 {
+    if (dp.hp.points) {
+        run_p2p_points(dp, direct, M, F, u, st);
+        return;
+    }
     if (!direct && F == 1 && dp.p2p_topo && dp.n_topo_ch > 0) {
         const HostPlan &hp = dp.hp;
         k_topo_coef<<<dim3(dp.n_topo_ch), dim3(64), 0, st>>>(dp.topo_ch_i, dp.topo_ch_c, dp.n_topo_ch, dp.topo_inc,
@@ -1991,7 +2111,8 @@ void build_tet_moments(DevicePlan &dp)
     if (dp.n_p2m_cells == 0) return;
     k_tet_moments<<<dim3(dp.n_p2m_cells), dim3(kMomThreads)>>>(dp.p2m_cells, dp.cell_i, dp.cell_c,
                                                                (int64_t)dp.hp.cells.size(), dp.tet_xyz, dp.hp.n_tets,
-                                                               dp.quad, dp.nq, dp.hp.p, dp.tet_mom);
+                                                               dp.quad, dp.nq, dp.hp.p, dp.hp.points ? 1 : 0,
+                                                               dp.tet_mom);
     hip_check(hipGetLastError(), "k_tet_moments launch");
     hip_check(hipDeviceSynchronize(), "k_tet_moments");
 }
@@ -2207,7 +2328,7 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
             const size_t lds = sizeof(double) * (size_t)kP2MStage * (dp.ncoef + 12 * FC);
             k_p2m<FC><<<dim3(xcd_grid(dp.n_p2m_cells), (F + FC - 1) / FC), dim3(kP2MThreads), lds, st>>>(
                 dp.p2m_cells, dp.cell_i, dp.cell_c, C, dp.tet_xyz, dp.tet_node, hp.n_tets, dp.tet_mom, M, hp.n_nodes, F,
-                p, dp.n_p2m_cells, dp.Q);
+                p, dp.n_p2m_cells, hp.points ? 1 : 0, dp.Q);
             hip_check(hipGetLastError(), "k_p2m launch");
         });
     }

@@ -68,11 +68,25 @@ std::vector<int32_t> sorted_order(const std::vector<uint64_t> &codes)
 }  // namespace
 
 void build_host_plan(HostPlan &hp, const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
-                     const double *targets, int64_t n_targets, int p, int leaf, double theta)
+                     const double *targets, int64_t n_targets, int p, int leaf, double theta, bool points)
 {
     auto t0 = std::chrono::steady_clock::now();
+    // point sources: source i is the point nodes[i], written as a tet whose
+    // four corners are that node (its centroid and farthest corner are the
+    // point), so the tree, radii and lists below serve both kinds
+    std::vector<int32_t> ptv;
+    if (points) {
+        if (!nodes) fail(TFMM_EINVAL, "points must not be NULL");
+        if (n_nodes < 1 || n_nodes > INT32_MAX / 4) fail(TFMM_EINVAL, "bad number of points");
+        ptv.resize(4 * (size_t)n_nodes);
+        for (int64_t i = 0; i < n_nodes; ++i)
+            for (int c = 0; c < 4; ++c) ptv[4 * (size_t)i + c] = (int32_t)i;
+        tets = ptv.data();
+        n_tets = n_nodes;
+    }
+    hp.points = points;
     if (!nodes || !tets) fail(TFMM_EINVAL, "nodes and tets must not be NULL");
-    if (n_nodes < 4 || n_tets < 1) fail(TFMM_EINVAL, "need at least 4 nodes and 1 tet");
+    if (!points && (n_nodes < 4 || n_tets < 1)) fail(TFMM_EINVAL, "need at least 4 nodes and 1 tet");
     if (n_nodes > INT32_MAX || n_tets > INT32_MAX / 4) fail(TFMM_EINVAL, "mesh too large for 32-bit indices");
     if (targets && (n_targets < 1 || n_targets > INT32_MAX)) fail(TFMM_EINVAL, "bad number of targets");
     if (p < 1 || p > TFMM_PMAX) fail(TFMM_EINVAL, "expansion order p out of range");
@@ -101,7 +115,7 @@ void build_host_plan(HostPlan &hp, const double *nodes, int64_t n_nodes, const i
 
     // orientation and degeneracy
     std::vector<int32_t> tv(tets, tets + 4 * n_tets);
-    for (int64_t t = 0; t < n_tets; ++t) {
+    for (int64_t t = 0; t < (points ? 0 : n_tets); ++t) {
         int32_t *q = &tv[4 * t];
         const double *a = nodes + 3 * (int64_t)q[0], *b = nodes + 3 * (int64_t)q[1];
         const double *c = nodes + 3 * (int64_t)q[2], *d = nodes + 3 * (int64_t)q[3];
@@ -136,6 +150,7 @@ void build_host_plan(HostPlan &hp, const double *nodes, int64_t n_nodes, const i
     grow(targets, n_targets);
     double ext = 0.0;
     for (int k = 0; k < 3; ++k) ext = std::max(ext, hi[k] - lo[k]);
+    if (!(ext > 0.0)) fail(TFMM_EINVAL, "sources and targets must not all coincide");
     hp.side = ext * (1.0 + std::ldexp(1.0, -20));
     for (int k = 0; k < 3; ++k) hp.origin[k] = (lo[k] + hi[k]) * 0.5 - 0.5 * hp.side;
 

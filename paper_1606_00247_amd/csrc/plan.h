@@ -27,6 +27,7 @@ struct HostPlan {
     double theta = 0.0;
     int64_t n_nodes = 0, n_tets = 0, n_targets = 0;
     bool targets_are_nodes = true;
+    bool points = false;  // sources are point dipoles at the nodes (see build_host_plan)
 
     // bounding cube
     double origin[3] = {0, 0, 0};
@@ -126,8 +127,9 @@ struct PlanError {
 // work items of at most max_ent entries.
 void build_m2l_tiles(const HostPlan &hp, int tpt, int max_ent, M2LTiles &out);
 
-// Builds the plan.  Throws PlanError on invalid input.
+// Builds the plan.  Throws PlanError on invalid input.  With points = true
+// the sources are the n_nodes points `nodes` (tets is ignored).
 void build_host_plan(HostPlan &hp, const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
-                     const double *targets, int64_t n_targets, int p, int leaf, double theta);
+                     const double *targets, int64_t n_targets, int p, int leaf, double theta, bool points = false);
 
 }  // namespace tfmm
