@@ -303,6 +303,29 @@ def main():
         else:
             variants["tuned_tol1e-5"] = {"met": False, "tune_s": t_tune, "closest": [tr["p"], tr["theta"], tr["err"]]}
         variants["ragged32"] = ragged_batch(T, torch, args.variant_steps)
+        # point-dipole cloud on the same nodes (moments M_i V_i, V_i the lumped volume)
+        md = torch.from_numpy(M[0] * meshgen.lumped_volumes(nodes, tets)[:, None]).to(dev)
+        pd = T.tfmm_plan_create_points(nodes, p=W["p"], leaf_size=W["leaf"], theta=0.5, device=0)
+        udd = T.tfmm_direct(pd, md)
+        torch.cuda.synchronize()
+        del pd
+        for th in (0.5, 0.4):
+            pd = T.tfmm_plan_create_points(nodes, p=W["p"], leaf_size=W["leaf"], theta=th, device=0)
+            uv = torch.empty(nodes.shape[0], dtype=torch.float64, device=dev)
+            T.tfmm_evaluate(pd, md, uv)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.variant_steps):
+                T.tfmm_evaluate(pd, md, uv)
+            torch.cuda.synchronize()
+            dv = (time.perf_counter() - t1) / args.variant_steps
+            kv = kernel_breakdown(T, torch, pd, md, uv, 2)
+            variants[f"dipoles_theta{th}"] = {
+                "value": nodes.shape[0] / dv, "unit": "evals/s", "ms_per_step": dv * 1e3, "sources": "point dipoles",
+                "p": W["p"], "theta": th, "m2l": "fp64",
+                "rel_l2_vs_direct": float(torch.linalg.norm(uv - udd) / torch.linalg.norm(udd)),
+                "kernel_ms": {k: round(v[0], 4) for k, v in kv.items()}}
+            del pd, uv
         out["variants"] = variants
 
     if not args.no_cpu_baseline:
