@@ -283,7 +283,7 @@ void free_plan(DevicePlan &dp)
                     dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.p2p_blk, dp.p2p_idx, dp.quad, dp.tet_mom, dp.Q,
                     dp.L, dp.Qt, dp.Qtf, dp.m2l_keys, dp.m2l_D, dp.m2l_Df, dp.sur_w, dp.sur_wb, dp.topo_blk,
                     dp.topo_ch_i, dp.topo_ch_c, dp.topo_w, dp.topo_ab, dp.topo_il, dp.topo_pqr, dp.topo_n,
-                    dp.topo_inc, dp.topo_A, dp.topo_B, dp.near_off, dp.near_nc, dp.near_cols, dp.near_val};
+                    dp.topo_inc, dp.topo_A, dp.topo_B, dp.near_off, dp.near_nc, dp.near_cols, dp.near_val, dp.near_items};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : dp.m2l_tiles) {

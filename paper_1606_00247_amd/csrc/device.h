@@ -99,6 +99,8 @@ struct DevicePlan {
     int64_t *near_off = nullptr;
     int32_t *near_nc = nullptr, *near_cols = nullptr;
     double *near_val = nullptr;
+    int32_t *near_items = nullptr;  // [n][2]: leaf, first row of up to 4 rows (apply work items)
+    int32_t near_nitems = 0;
     int64_t near_nvals = 0, near_ncols = 0, near_nnz = 0, near_bytes = 0;
     bool near_stored = false;
     // geometric moments of every tet about its leaf centre: [T][ncoef]

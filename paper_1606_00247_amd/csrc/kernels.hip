@@ -1598,52 +1598,66 @@ __global__ __launch_bounds__(kNearAsmThreads) void k_near_assemble(
     }
 }
 
-// Applies the stored operator: one wavefront per target row, lanes striding
-// over the columns (three coalesced coefficient streams and one gathered
-// node vector per column and field), FC fields per pass, the row sums reduced
-// across the wavefront and added into u (L2P adds concurrently).
-constexpr int kNearRowsPerBlock = 4;
+// Applies the stored operator.  Work item = up to kNearRows consecutive target
+// rows of one leaf (they share the leaf's column list): one wavefront per
+// item, lanes striding the columns; per column the node's M is gathered once
+// for FC fields and applied to every row of the item (three coalesced
+// coefficient streams per row).  Row sums are reduced across the wavefront
+// and added into u (L2P adds concurrently).
+constexpr int kNearRows = 4, kNearItemsPerBlock = 4;
 
 template <int FC>
-__global__ __launch_bounds__(64 * kNearRowsPerBlock) void k_near_apply(
-    int nrowblk, const int32_t *__restrict__ tgt_leaf, const int32_t *__restrict__ cell_i,
+__global__ __launch_bounds__(64 * kNearItemsPerBlock) void k_near_apply(
+    int nitems, const int32_t *__restrict__ items, const int32_t *__restrict__ cell_i,
     const int64_t *__restrict__ near_off, const int32_t *__restrict__ near_nc, const int32_t *__restrict__ near_cols,
     const double *__restrict__ val, const int32_t *__restrict__ tgt_perm, int64_t N, const double *__restrict__ M,
     int64_t n_nodes, int F, double *__restrict__ u)
 {
-    const int rb = xcd_item(nrowblk);
-    if (rb < 0) return;
+    const int blk = xcd_item((nitems + kNearItemsPerBlock - 1) / kNearItemsPerBlock);
+    if (blk < 0) return;
     const int lane = threadIdx.x & 63;
-    const int64_t s = (int64_t)rb * kNearRowsPerBlock + (threadIdx.x >> 6);
-    if (s >= N) return;
-    const int32_t a = tgt_leaf[s];
+    const int it = blk * kNearItemsPerBlock + (threadIdx.x >> 6);
+    if (it >= nitems) return;
+    const int32_t a = items[2 * it], r0 = items[2 * it + 1];
+    const int xb = cell_i[8 * a + 2];
+    const int nr = min(kNearRows, cell_i[8 * a + 3] - xb - r0);
     const int64_t voff = near_off[2 * a + 1];
-    if (voff < 0) return;
     const int nc = near_nc[a];
     const int32_t *cl = near_cols + near_off[2 * a];
-    const double *row = val + voff + (s - cell_i[8 * a + 2]) * 3 * nc;
+    const double *row = val + voff + (int64_t)r0 * 3 * nc;
     const int f0 = blockIdx.y * FC;
-    double acc[FC];
+    double acc[kNearRows][FC];
 #pragma unroll
-    for (int f = 0; f < FC; ++f) acc[f] = 0.0;
+    for (int r = 0; r < kNearRows; ++r)
+#pragma unroll
+        for (int f = 0; f < FC; ++f) acc[r][f] = 0.0;
     for (int c = lane; c < nc; c += 64) {
-        const double w0 = row[c], w1 = row[nc + c], w2 = row[2 * nc + c];
         const int64_t n = cl[c];
+        double w[kNearRows][3];
+#pragma unroll
+        for (int r = 0; r < kNearRows; ++r)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) w[r][k] = r < nr ? row[((int64_t)r * 3 + k) * nc + c] : 0.0;
 #pragma unroll
         for (int f = 0; f < FC; ++f) {
             if (f0 + f < F) {
                 const double *m = M + ((int64_t)(f0 + f) * n_nodes + n) * 3;
-                acc[f] = fma(w0, m[0], fma(w1, m[1], fma(w2, m[2], acc[f])));
+                const double m0 = m[0], m1 = m[1], m2 = m[2];
+#pragma unroll
+                for (int r = 0; r < kNearRows; ++r)
+                    acc[r][f] = fma(w[r][0], m0, fma(w[r][1], m1, fma(w[r][2], m2, acc[r][f])));
             }
         }
     }
 #pragma unroll
-    for (int f = 0; f < FC; ++f) {
-        double v = acc[f];
+    for (int r = 0; r < kNearRows; ++r)
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        if (lane == 0 && f0 + f < F) atomicAdd(&u[(int64_t)(f0 + f) * N + tgt_perm[s]], v);
-    }
+        for (int f = 0; f < FC; ++f) {
+            double v = acc[r][f];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0 && r < nr && f0 + f < F) atomicAdd(&u[(int64_t)(f0 + f) * N + tgt_perm[xb + r0 + r]], v);
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -1911,12 +1925,14 @@ void run_near_stored(DevicePlan &dp, const double *M, int32_t F, double *u, hipS
     const HostPlan &hp = dp.hp;
     const int64_t N = hp.n_targets;
     if (N == 0 || dp.near_nvals == 0) return;
-    const int nrb = (int)((N + kNearRowsPerBlock - 1) / kNearRowsPerBlock);
+    const int ni = dp.near_nitems;
+    if (ni == 0) return;
+    const int nblk = (ni + kNearItemsPerBlock - 1) / kNearItemsPerBlock;
     const int fc = F >= 8 ? 8 : (F >= 4 ? 4 : (F >= 2 ? 2 : 1));
-    const dim3 grid(xcd_grid(nrb), (unsigned)((F + fc - 1) / fc));
-    const dim3 thr(64 * kNearRowsPerBlock);
-#define TFMM_NEAR_APPLY(FCV)                                                                                     \
-    k_near_apply<FCV><<<grid, thr, 0, st>>>(nrb, dp.tgt_leaf, dp.cell_i, dp.near_off, dp.near_nc, dp.near_cols,  \
+    const dim3 grid(xcd_grid(nblk), (unsigned)((F + fc - 1) / fc));
+    const dim3 thr(64 * kNearItemsPerBlock);
+#define TFMM_NEAR_APPLY(FCV)                                                                                       \
+    k_near_apply<FCV><<<grid, thr, 0, st>>>(ni, dp.near_items, dp.cell_i, dp.near_off, dp.near_nc, dp.near_cols,    \
                                             dp.near_val, dp.tgt_perm, N, M, hp.n_nodes, F, u)
     switch (fc) {
     case 8: TFMM_NEAR_APPLY(8); break;
@@ -2048,9 +2064,20 @@ void store_near(DevicePlan &dp, hipStream_t st)
     const size_t b_off = sizeof(int64_t) * 2 * std::max<size_t>(C, 1), b_nc = sizeof(int32_t) * std::max<size_t>(C, 1),
                  b_cols = sizeof(int32_t) * std::max<size_t>(lay.cols.size(), 1),
                  b_val = sizeof(double) * (size_t)std::max<int64_t>(lay.nvals, 1);
-    void *p[4] = {nullptr, nullptr, nullptr, nullptr};
-    const size_t sz[4] = {b_off, b_nc, b_cols, b_val};
-    for (int i = 0; i < 4; ++i) {
+    // apply work items: (leaf, first row) per kNearRows rows of a leaf block
+    std::vector<int32_t> items;
+    for (size_t a = 0; a < C; ++a) {
+        if (lay.leaf_off[2 * a + 1] < 0) continue;
+        const Cell &K = hp.cells[a];
+        for (int32_t r = 0; r < K.xend - K.xbeg; r += kNearRows) {
+            items.push_back((int32_t)a);
+            items.push_back(r);
+        }
+    }
+    const size_t b_items = sizeof(int32_t) * std::max<size_t>(items.size(), 1);
+    void *p[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    const size_t sz[5] = {b_off, b_nc, b_cols, b_val, b_items};
+    for (int i = 0; i < 5; ++i) {
         const hipError_t e = hipMalloc(&p[i], sz[i]);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -2065,10 +2092,15 @@ void store_near(DevicePlan &dp, hipStream_t st)
     dp.near_nc = (int32_t *)p[1];
     dp.near_cols = (int32_t *)p[2];
     dp.near_val = (double *)p[3];
+    dp.near_items = (int32_t *)p[4];
+    dp.near_nitems = (int32_t)(items.size() / 2);
+    if (!items.empty())
+        hip_check(hipMemcpy(dp.near_items, items.data(), sizeof(int32_t) * items.size(), hipMemcpyHostToDevice),
+                  "hipMemcpy near items");
     dp.near_nvals = lay.nvals;
     dp.near_ncols = (int64_t)lay.cols.size();
     dp.near_nnz = lay.nnz;
-    dp.near_bytes = (int64_t)(b_off + b_nc + b_cols + b_val);
+    dp.near_bytes = (int64_t)(b_off + b_nc + b_cols + b_val + b_items);
     dp.device_bytes += dp.near_bytes;
     hip_check(hipMemcpy(dp.near_off, lay.leaf_off.data(), sizeof(int64_t) * lay.leaf_off.size(), hipMemcpyHostToDevice),
               "hipMemcpy near offsets");
@@ -2093,9 +2125,11 @@ void drop_near(DevicePlan &dp)
 {
     if (!dp.near_off) return;
     hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
-    void *p[4] = {dp.near_off, dp.near_nc, dp.near_cols, dp.near_val};
+    void *p[5] = {dp.near_off, dp.near_nc, dp.near_cols, dp.near_val, dp.near_items};
     for (void *q : p)
         if (q) (void)hipFree(q);
+    dp.near_items = nullptr;
+    dp.near_nitems = 0;
     dp.near_off = nullptr;
     dp.near_nc = nullptr;
     dp.near_cols = nullptr;
