@@ -74,6 +74,11 @@ constexpr BinomTable make_binom()
     return t;
 }
 __constant__ MiTable c_mi = make_mi();
+// compile-time view of the same table (loops unrolled over a template order)
+constexpr MiTable kMi = make_mi();
+__host__ __device__ constexpr int mi_x(int m) { return kMi.v[m][0]; }
+__host__ __device__ constexpr int mi_y(int m) { return kMi.v[m][1]; }
+__host__ __device__ constexpr int mi_z(int m) { return kMi.v[m][2]; }
 __constant__ BinomTable c_bin = make_binom();
 
 __device__ __forceinline__ int mi_index(int nx, int ny, int nz)
@@ -1150,41 +1155,36 @@ __global__ __launch_bounds__(64 * kM2LBWaves, 2) void k_m2l_bf16(
 }
 
 // ---------------------------------------------------------------------------
-// L2P.  One thread per target (octree order); adds into u[f][perm[i]].
+// L2P.  One thread per target (octree order) and field (blockIdx.y); adds
+// into u[f][perm[i]].
 //   u(x) = sum_m l_m (x - c)^m
+// The order is a template parameter, so the loop over m unrolls and every
+// monomial is a product of three powers held in registers.
 // ---------------------------------------------------------------------------
+template <int P>
 __global__ __launch_bounds__(256) void k_l2p(const double *__restrict__ tgt_xyz, const int32_t *__restrict__ tgt_perm,
                                              const int32_t *__restrict__ tgt_leaf, int64_t N,
-                                             const double *__restrict__ cell_c, int64_t C, int p,
+                                             const double *__restrict__ cell_c, int64_t C,
                                              const double *__restrict__ L, double *__restrict__ u)
 {
+    constexpr int NC = ncoef_of(P);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int f = blockIdx.y;
     if (i >= N) return;
     const int leaf = tgt_leaf[i];
-    const int ncoef = ncoef_of(p);
     const double y[3] = {tgt_xyz[i] - cell_c[leaf], tgt_xyz[N + i] - cell_c[C + leaf],
                          tgt_xyz[2 * N + i] - cell_c[2 * C + leaf]};
-    double pw[3][kPmax + 1];
+    double pw[3][P + 1];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         pw[k][0] = 1.0;
 #pragma unroll
-        for (int j = 1; j <= kPmax; ++j) pw[k][j] = pw[k][j - 1] * y[k];
+        for (int j = 1; j <= P; ++j) pw[k][j] = pw[k][j - 1] * y[k];
     }
-    const double *Ll = L + ((int64_t)f * C + leaf) * ncoef;
+    const double *Ll = L + ((int64_t)f * C + leaf) * NC;
     double s = 0.0;
-    for (int m = 0; m < ncoef; ++m) {
-        const int a = c_mi.v[m][0], b = c_mi.v[m][1], c = c_mi.v[m][2];
-        double px = 1.0, py = 1.0, pz = 1.0;
 #pragma unroll
-        for (int j = 1; j <= kPmax; ++j) {
-            px = (j == a) ? pw[0][j] : px;
-            py = (j == b) ? pw[1][j] : py;
-            pz = (j == c) ? pw[2][j] : pz;
-        }
-        s += Ll[m] * (px * py * pz);
-    }
+    for (int m = 0; m < NC; ++m) s = fma(Ll[m], pw[0][mi_x(m)] * pw[1][mi_y(m)] * pw[2][mi_z(m)], s);
     atomicAdd(&u[(int64_t)f * N + tgt_perm[i]], s);  // the near field is added concurrently
 }
 
@@ -1766,6 +1766,24 @@ void hip_check(hipError_t e, const char *what)
 namespace {
 
 // Calls fn with std::integral_constant<int, field_chunk(F)>.
+// Calls fn with std::integral_constant<int, p> for 1 <= p <= kPmax.
+template <class Fn>
+void with_order(int p, Fn &&fn)
+{
+    switch (p) {
+    case 1: fn(std::integral_constant<int, 1>{}); break;
+    case 2: fn(std::integral_constant<int, 2>{}); break;
+    case 3: fn(std::integral_constant<int, 3>{}); break;
+    case 4: fn(std::integral_constant<int, 4>{}); break;
+    case 5: fn(std::integral_constant<int, 5>{}); break;
+    case 6: fn(std::integral_constant<int, 6>{}); break;
+    case 7: fn(std::integral_constant<int, 7>{}); break;
+    case 8: fn(std::integral_constant<int, 8>{}); break;
+    case 9: fn(std::integral_constant<int, 9>{}); break;
+    default: fn(std::integral_constant<int, 10>{}); break;
+    }
+}
+
 template <class Fn>
 void launch_fc(int F, Fn &&fn)
 {
@@ -2395,8 +2413,11 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
     {
         KTimer kt(dp, KT_L2P, st);
         const unsigned nb = (unsigned)((hp.n_targets + 255) / 256);
-        k_l2p<<<dim3(nb, F), dim3(256), 0, st>>>(dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, hp.n_targets, dp.cell_c, C, p,
-                                                 dp.L, u);
+        with_order(p, [&](auto pc) {
+            constexpr int PP = decltype(pc)::value;
+            k_l2p<PP><<<dim3(nb, F), dim3(256), 0, st>>>(dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, hp.n_targets, dp.cell_c,
+                                                         C, dp.L, u);
+        });
         hip_check(hipGetLastError(), "k_l2p launch");
     }
     if (fork) {
