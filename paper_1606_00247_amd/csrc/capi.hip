@@ -242,6 +242,7 @@ void upload_plan(DevicePlan &dp)
         dp.topo_il = dev_upload(tp.ed_il, B);
         dp.topo_pqr = dev_upload(tp.fc_pqr, B);
         dp.topo_n = dev_upload(tp.fc_n, B);
+        dp.topo_a2 = dev_upload(tp.fc_a2, B);
         dp.topo_inc = dev_upload(tp.inc, B);
         std::vector<double> zA(4 * (size_t)std::max<int64_t>(dp.n_topo_faces, 1)),
             zB(11 * (size_t)std::max<int64_t>(dp.n_topo_edges, 1));
@@ -282,7 +283,7 @@ void free_plan(DevicePlan &dp)
     void *ptrs[] = {dp.tet_xyz, dp.tet_node, dp.tet_perm, dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, dp.cell_c, dp.cell_i,
                     dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.p2p_blk, dp.p2p_idx, dp.quad, dp.tet_mom, dp.Q,
                     dp.L, dp.Qt, dp.Qtf, dp.m2l_keys, dp.m2l_D, dp.m2l_Df, dp.sur_w, dp.sur_wb, dp.topo_blk,
-                    dp.topo_ch_i, dp.topo_ch_c, dp.topo_w, dp.topo_ab, dp.topo_il, dp.topo_pqr, dp.topo_n,
+                    dp.topo_ch_i, dp.topo_ch_c, dp.topo_w, dp.topo_ab, dp.topo_il, dp.topo_pqr, dp.topo_n, dp.topo_a2,
                     dp.topo_inc, dp.topo_A, dp.topo_B, dp.near_off, dp.near_nc, dp.near_cols, dp.near_val, dp.near_items};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);

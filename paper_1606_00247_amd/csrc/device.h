@@ -87,7 +87,7 @@ struct DevicePlan {
     // y = x - chunk centroid), edges B [ne][11] (quadratic in y: 1, y0, y1,
     // y2, y0y0, y0y1, y0y2, y1y1, y1y2, y2y2; then the constant g weight)
     int32_t *topo_blk = nullptr, *topo_ch_i = nullptr, *topo_ab = nullptr, *topo_pqr = nullptr, *topo_inc = nullptr;
-    double *topo_ch_c = nullptr, *topo_w = nullptr, *topo_il = nullptr, *topo_n = nullptr;
+    double *topo_ch_c = nullptr, *topo_w = nullptr, *topo_il = nullptr, *topo_n = nullptr, *topo_a2 = nullptr;
     double *topo_A = nullptr, *topo_B = nullptr;
     int32_t n_topo_ch = 0;
     int64_t n_topo_edges = 0, n_topo_faces = 0;

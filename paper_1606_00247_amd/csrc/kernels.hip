@@ -1423,7 +1423,8 @@ __global__ __launch_bounds__(NT, NT == 64 ? 2 : 4) void k_p2p_topo(const int32_t
                                                     const int32_t *__restrict__ ch_i, const double *__restrict__ ch_c,
                                                     const double *__restrict__ nw, const int32_t *__restrict__ eab,
                                                     const double *__restrict__ eil, const int32_t *__restrict__ fpqr,
-                                                    const double *__restrict__ fn, const double *__restrict__ A,
+                                                    const double *__restrict__ fn, const double *__restrict__ fa2,
+                                                    const double *__restrict__ A,
                                                     const double *__restrict__ Bc, const int32_t *__restrict__ idx,
                                                     const double *__restrict__ tgt_xyz,
                                                     const int32_t *__restrict__ tgt_perm, int64_t N,
@@ -1434,7 +1435,7 @@ __global__ __launch_bounds__(NT, NT == 64 ? 2 : 4) void k_p2p_topo(const int32_t
     __shared__ int s_ea[kTopoEdges], s_eb[kTopoEdges];
     __shared__ double s_il[kTopoEdges], s_B[kTopoEdges][11];
     __shared__ int s_fp[kTopoFaces], s_fq[kTopoFaces], s_fr[kTopoFaces];
-    __shared__ double s_fn[kTopoFaces][3], s_A[kTopoFaces][4];
+    __shared__ double s_fn[kTopoFaces][3], s_fa[kTopoFaces], s_A[kTopoFaces][4];
     const int b = xcd_item(nblk);
     if (b < 0) return;
     const int cb = blk[4 * b], ce = blk[4 * b + 1], ib = blk[4 * b + 2], ie = blk[4 * b + 3];
@@ -1457,6 +1458,7 @@ __global__ __launch_bounds__(NT, NT == 64 ? 2 : 4) void k_p2p_topo(const int32_t
             s_fr[i] = fpqr[3 * ((int64_t)foff + i) + 2];
         }
         for (int i = lane; i < nf * 3; i += NT) (&s_fn[0][0])[i] = fn[(int64_t)foff * 3 + i];
+        for (int i = lane; i < nf; i += NT) s_fa[i] = fa2[foff + i];
         for (int i = lane; i < nf * 4; i += NT) (&s_A[0][0])[i] = A[(int64_t)foff * 4 + i];
         __syncthreads();
         for (int i = ib + lane; i < ie; i += NT) {
@@ -1501,10 +1503,10 @@ __global__ __launch_bounds__(NT, NT == 64 ? 2 : 4) void k_p2p_topo(const int32_t
                 const double Dpq = dp[0] * dq[0] + dp[1] * dq[1] + dp[2] * dq[2];
                 const double Dpr = dp[0] * dr[0] + dp[1] * dr[1] + dp[2] * dr[2];
                 const double Dqr = dq[0] * dr[0] + dq[1] * dr[1] + dq[2] * dr[2];
-                const double det = dp[0] * (dq[1] * dr[2] - dq[2] * dr[1]) + dp[1] * (dq[2] * dr[0] - dq[0] * dr[2]) +
-                                   dp[2] * (dq[0] * dr[1] - dq[1] * dr[0]);
                 const double den = Rp * Rq * Rr + Dpq * Rr + Dpr * Rq + Dqr * Rp;
                 const double h = s_fn[fi][0] * dp[0] + s_fn[fi][1] * dp[1] + s_fn[fi][2] * dp[2];
+                // [d_p, d_q, d_r] = d_p . ((q - p) x (r - p)) = h |(q - p) x (r - p)|
+                const double det = h * s_fa[fi];
                 const double af = s_A[fi][0] + (s_A[fi][1] * y[0] + s_A[fi][2] * y[1] + s_A[fi][3] * y[2]);
                 acc = fma(-af * h, 2.0 * atan2_nr(det, den), acc);
             }
@@ -1904,11 +1906,11 @@ void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u,
         if (dp.p2p_wide)
             k_p2p_topo<256><<<dim3(xcd_grid(nblk)), dim3(256), 0, st>>>(
                 dp.topo_blk, nblk, dp.topo_ch_i, dp.topo_ch_c, dp.topo_w, dp.topo_ab, dp.topo_il, dp.topo_pqr,
-                dp.topo_n, dp.topo_A, dp.topo_B, dp.p2p_idx, dp.tgt_xyz, dp.tgt_perm, hp.n_targets, u);
+                dp.topo_n, dp.topo_a2, dp.topo_A, dp.topo_B, dp.p2p_idx, dp.tgt_xyz, dp.tgt_perm, hp.n_targets, u);
         else
             k_p2p_topo<64><<<dim3(xcd_grid(nblk)), dim3(64), 0, st>>>(
                 dp.topo_blk, nblk, dp.topo_ch_i, dp.topo_ch_c, dp.topo_w, dp.topo_ab, dp.topo_il, dp.topo_pqr,
-                dp.topo_n, dp.topo_A, dp.topo_B, dp.p2p_idx, dp.tgt_xyz, dp.tgt_perm, hp.n_targets, u);
+                dp.topo_n, dp.topo_a2, dp.topo_A, dp.topo_B, dp.p2p_idx, dp.tgt_xyz, dp.tgt_perm, hp.n_targets, u);
         hip_check(hipGetLastError(), "k_p2p_topo launch");
         return;
     }

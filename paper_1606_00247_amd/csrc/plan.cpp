@@ -556,6 +556,7 @@ void build_near_topology(const HostPlan &hp, const std::vector<int32_t> &blk, Ne
                 const double n[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
                 const double il = 1.0 / std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
                 for (int k = 0; k < 3; ++k) out.fc_n.push_back(n[k] * il);
+                out.fc_a2.push_back(1.0 / il);
             }
             const int32_t rec[8] = {s, t - s, noff, (int32_t)nodes.size(), eoff, (int32_t)(edges.size() / 2), foff,
                                     (int32_t)(faces.size() / 3)};

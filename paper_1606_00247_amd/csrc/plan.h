@@ -96,6 +96,7 @@ struct NearTopo {
     std::vector<double> ed_il;    // [edges] 1 / length
     std::vector<int32_t> fc_pqr;  // [faces][3] chunk-local nodes
     std::vector<double> fc_n;     // [faces][3] unit normal of (q - p) x (r - p)
+    std::vector<double> fc_a2;    // [faces] |(q - p) x (r - p)| (twice the area)
     std::vector<int32_t> inc;     // [T][10] per tet: 6 edge, 4 face chunk-local indices
 };
 
