@@ -50,6 +50,28 @@ def m2l_terms(p):
     return sum((2 * dm + 1) * (2 * dn + 1) for dm in range(p) for dn in range(1, p - dm + 1))
 
 
+def path_roofline(st, p, F, ms_per_step, n_targets):
+    """Whole-path bound: per phase the time its algorithmic work takes at the
+    peak of the unit that bounds it (FP64 vector for the near field, P2M, the
+    shifts and L2P; FP64 matrix cores for M2L), summed and divided by the
+    measured time per evaluation.  The compulsory HBM traffic (M, the mesh, u:
+    ~150 B per target) is far below any of these and is left out."""
+    nc = (p + 1) * (p + 2) * (p + 3) // 6
+    mi = [(a, b, d - a - b) for d in range(p + 1) for a in range(d, -1, -1) for b in range(d - a, -1, -1)]
+    shift_terms = 3 * sum(n[0] + 1 for n in mi)  # one axis pass ~ sum (n_ax + 1) terms, three passes
+    flops = {
+        "p2p": st["n_p2p_pairs"] * (P2P_ARITH_FLOPS + P2P_TRANS_FLOPS + F * P2P_FIELD_FLOPS),
+        "m2l": st["n_m2l"] * F * 2 * m2l_terms(p),
+        "p2m": st["n_tets"] * F * 24 * nc,
+        "m2m_l2l": 2 * st["n_cells"] * F * 2 * shift_terms,
+        "l2p": n_targets * F * 2 * nc,
+    }
+    t = {k: v / (FP64_PEAK_TFLOPS * 1e12) * 1e3 for k, v in flops.items()}
+    return {"phase_bound_ms": {k: round(v, 4) for k, v in t.items()}, "bound_ms": round(sum(t.values()), 4),
+            "frac": round(sum(t.values()) / ms_per_step, 4),
+            "note": "sum over phases of algorithmic flops / FP64 peak (78.6 TFLOP/s vector and matrix)"}
+
+
 def kernel_source_hash():
     import hashlib
     with open(os.path.join(ROOT, "paper_1606_00247_amd", "csrc", "kernels.hip"), "rb") as f:
@@ -220,6 +242,7 @@ def main():
         "kernel_ms": {k: round(v[0], 4) for k, v in ktimes.items()},
         "counts": {"n_p2p_pairs": st["n_p2p_pairs"], "n_m2l": st["n_m2l"], "n_cells": st["n_cells"]},
         "roofline": roof,
+        "path_roofline": path_roofline(st, W["p"], W["F"], dt * 1e3, nodes.shape[0]),
     }
 
     if not args.no_variants:
@@ -343,12 +366,25 @@ def main():
         per_target = max(t_s - t_up, 0.0) / len(sample)
         t_full = t_up + per_target * nodes.shape[0]
         ucheck = float(np.linalg.norm(us - u[:, sample].cpu().numpy()) / np.linalg.norm(us))
+        # the same on one core (a smaller sample)
+        oracle.set_num_threads(1)
+        t1 = time.perf_counter()
+        O.evaluate_sample(M, sample[:1])
+        t_up1 = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        O.evaluate_sample(M, sample[:64])
+        per1 = max(time.perf_counter() - t1 - t_up1, 0.0) / 64
+        oracle.set_num_threads(ncores)
+        t_full1 = t_up1 + per1 * nodes.shape[0]
         out["cpu_baseline"] = {
             "value": evals / t_full, "unit": "evals/s", "cores": ncores, "kind": "oracle",
             "sample": f"oracle FMM on {len(sample)} seeded targets of {nodes.shape[0]} (full upward pass, "
                       f"{t_up:.1f}s; downward+near per target {per_target * 1e3:.2f} ms), extrapolated to all "
                       f"targets: {t_full:.1f}s per evaluation",
             "gpu_vs_oracle_rel_l2_on_sample": ucheck,
+            "single_core": {"value": evals / t_full1, "cores": 1,
+                            "sample": f"64 targets (upward pass {t_up1:.1f}s, {per1 * 1e3:.2f} ms per target), "
+                                      f"extrapolated: {t_full1:.1f}s per evaluation"},
         }
     print(json.dumps(out), flush=True)
 
