@@ -2114,29 +2114,34 @@ void store_near(DevicePlan &dp, hipStream_t st)
     dp.near_val = (double *)p[3];
     dp.near_items = (int32_t *)p[4];
     dp.near_nitems = (int32_t)(items.size() / 2);
-    if (!items.empty())
-        hip_check(hipMemcpy(dp.near_items, items.data(), sizeof(int32_t) * items.size(), hipMemcpyHostToDevice),
-                  "hipMemcpy near items");
     dp.near_nvals = lay.nvals;
     dp.near_ncols = (int64_t)lay.cols.size();
     dp.near_nnz = lay.nnz;
     dp.near_bytes = (int64_t)(b_off + b_nc + b_cols + b_val + b_items);
     dp.device_bytes += dp.near_bytes;
-    hip_check(hipMemcpy(dp.near_off, lay.leaf_off.data(), sizeof(int64_t) * lay.leaf_off.size(), hipMemcpyHostToDevice),
-              "hipMemcpy near offsets");
-    hip_check(hipMemcpy(dp.near_nc, lay.leaf_nc.data(), sizeof(int32_t) * lay.leaf_nc.size(), hipMemcpyHostToDevice),
-              "hipMemcpy near counts");
-    if (!lay.cols.empty())
-        hip_check(hipMemcpy(dp.near_cols, lay.cols.data(), sizeof(int32_t) * lay.cols.size(), hipMemcpyHostToDevice),
-                  "hipMemcpy near columns");
-    fill(dp.near_val, lay.nvals, 0.0, st);
-    if (dp.n_p2p_blk > 0) {
-        k_near_assemble<<<dim3(xcd_grid(dp.n_p2p_blk)), dim3(kNearAsmThreads), 0, st>>>(
-            dp.p2p_blk, dp.n_p2p_blk, hp.n_tets, dp.tet_xyz, dp.tet_node, dp.p2p_idx, dp.tgt_xyz, hp.n_targets,
-            dp.tgt_leaf, dp.cell_i, dp.near_off, dp.near_nc, dp.near_cols, dp.near_val);
-        hip_check(hipGetLastError(), "k_near_assemble launch");
+    try {
+        if (!items.empty())
+            hip_check(hipMemcpy(dp.near_items, items.data(), sizeof(int32_t) * items.size(), hipMemcpyHostToDevice),
+                      "hipMemcpy near items");
+        hip_check(hipMemcpy(dp.near_off, lay.leaf_off.data(), sizeof(int64_t) * lay.leaf_off.size(), hipMemcpyHostToDevice),
+                  "hipMemcpy near offsets");
+        hip_check(hipMemcpy(dp.near_nc, lay.leaf_nc.data(), sizeof(int32_t) * lay.leaf_nc.size(), hipMemcpyHostToDevice),
+                  "hipMemcpy near counts");
+        if (!lay.cols.empty())
+            hip_check(hipMemcpy(dp.near_cols, lay.cols.data(), sizeof(int32_t) * lay.cols.size(), hipMemcpyHostToDevice),
+                      "hipMemcpy near columns");
+        fill(dp.near_val, lay.nvals, 0.0, st);
+        if (dp.n_p2p_blk > 0) {
+            k_near_assemble<<<dim3(xcd_grid(dp.n_p2p_blk)), dim3(kNearAsmThreads), 0, st>>>(
+                dp.p2p_blk, dp.n_p2p_blk, hp.n_tets, dp.tet_xyz, dp.tet_node, dp.p2p_idx, dp.tgt_xyz, hp.n_targets,
+                dp.tgt_leaf, dp.cell_i, dp.near_off, dp.near_nc, dp.near_cols, dp.near_val);
+            hip_check(hipGetLastError(), "k_near_assemble launch");
+        }
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize (near operator)");
+    } catch (...) {
+        drop_near(dp);  // a failed assembly leaves no operator behind
+        throw;
     }
-    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize (near operator)");
     dp.near_stored = true;
     ++dp.schedule_gen;
 }
@@ -2144,7 +2149,7 @@ void store_near(DevicePlan &dp, hipStream_t st)
 void drop_near(DevicePlan &dp)
 {
     if (!dp.near_off) return;
-    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    (void)hipDeviceSynchronize();  // also called on a failure path: freeing must not throw
     void *p[5] = {dp.near_off, dp.near_nc, dp.near_cols, dp.near_val, dp.near_items};
     for (void *q : p)
         if (q) (void)hipFree(q);
