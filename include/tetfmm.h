@@ -202,6 +202,12 @@ int tfmm_tune_accuracy(const double *nodes, int64_t n_nodes, const int32_t *tets
                        const tfmm_params *base, const double *M, double tol, int32_t n_sample, uint64_t seed,
                        const int32_t *p_list, int32_t n_p, const double *theta_list, int32_t n_theta,
                        tfmm_tune_result *out, double *table);
+/* The same search for a point-dipole plan (see tfmm_plan_create_points):
+ * M holds the probe dipole moments [n_points][3]; the reference is the
+ * dipole direct sum at the sampled points. */
+int tfmm_tune_accuracy_points(const double *points, int64_t n_points, const tfmm_params *base, const double *M,
+                              double tol, int32_t n_sample, uint64_t seed, const int32_t *p_list, int32_t n_p,
+                              const double *theta_list, int32_t n_theta, tfmm_tune_result *out, double *table);
 
 /* Switch the M2L arithmetic of an existing plan (one of TFMM_M2L_*). */
 int tfmm_plan_set_m2l_precision(tfmm_plan plan, int32_t m2l_precision);

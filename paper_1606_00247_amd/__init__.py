@@ -99,6 +99,8 @@ def _load():
         "tfmm_plan_create_points": (C.c_int, [_dp, C.c_int64, _dp, C.c_int64, C.c_void_p, C.POINTER(C.c_void_p)]),
         "tfmm_tune_accuracy": (C.c_int, [_dp, C.c_int64, _i32p, C.c_int64, C.c_void_p, _dp, C.c_double, C.c_int32,
                                          C.c_uint64, _i32p, C.c_int32, _dp, C.c_int32, C.POINTER(_TuneResult), _dp]),
+        "tfmm_tune_accuracy_points": (C.c_int, [_dp, C.c_int64, C.c_void_p, _dp, C.c_double, C.c_int32, C.c_uint64,
+                                                _i32p, C.c_int32, _dp, C.c_int32, C.POINTER(_TuneResult), _dp]),
         "tfmm_last_error": (C.c_char_p, []),
         "tfmm_simplex_rule": (C.c_int, [C.c_int32, _dp, _i32p]),
         "tfmm_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -464,9 +466,11 @@ def tfmm_tune_accuracy(nodes, tets, tol, M=None, leaf_size=64, m2l_precision=M2L
                        seed=1, p_list=(4, 5, 6, 7, 8, 9, 10), theta_list=(0.3, 0.35, 0.4, 0.45, 0.5, 0.55, 0.6, 0.7)):
     """Fastest (p, theta) whose sampled error against the FP64 direct sum is at
     most tol / 2.  M: host [n_nodes, 3] probe field (default: seeded random unit
-    vectors).  Returns dict(p, theta, err, ms, met, n_tried, table[n_p*n_theta, 4])."""
+    vectors).  tets=None tunes a point-dipole plan at `nodes` (M = moments).
+    Returns dict(p, theta, err, ms, met, n_tried, table[n_p*n_theta, 4])."""
     nodes = np.ascontiguousarray(nodes, dtype=np.float64)
-    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    if tets is not None:
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
     if M is None:
         g = np.random.default_rng(seed).standard_normal((nodes.shape[0], 3))
         M = g / np.linalg.norm(g, axis=1, keepdims=True)
@@ -478,10 +482,15 @@ def tfmm_tune_accuracy(nodes, tets, tol, M=None, leaf_size=64, m2l_precision=M2L
     table = np.zeros((pl.size * tl.size, 4))
     prm = _Params(8, int(leaf_size), 0.5, int(m2l_precision), int(device))
     res = _TuneResult()
-    _check(_load().tfmm_tune_accuracy(_ptr(nodes, _dp), nodes.shape[0], _ptr(tets, _i32p), tets.shape[0],
-                                      C.byref(prm), _ptr(M, _dp), float(tol), int(n_sample), int(seed),
-                                      _ptr(pl, _i32p), pl.size, _ptr(tl, _dp), tl.size, C.byref(res),
-                                      _ptr(table, _dp)))
+    if tets is None:
+        _check(_load().tfmm_tune_accuracy_points(_ptr(nodes, _dp), nodes.shape[0], C.byref(prm), _ptr(M, _dp),
+                                                 float(tol), int(n_sample), int(seed), _ptr(pl, _i32p), pl.size,
+                                                 _ptr(tl, _dp), tl.size, C.byref(res), _ptr(table, _dp)))
+    else:
+        _check(_load().tfmm_tune_accuracy(_ptr(nodes, _dp), nodes.shape[0], _ptr(tets, _i32p), tets.shape[0],
+                                          C.byref(prm), _ptr(M, _dp), float(tol), int(n_sample), int(seed),
+                                          _ptr(pl, _i32p), pl.size, _ptr(tl, _dp), tl.size, C.byref(res),
+                                          _ptr(table, _dp)))
     return dict(p=res.p, theta=res.theta, err=res.err, ms=res.ms, met=bool(res.met), n_tried=res.n_tried,
                 table=table)
 

@@ -625,13 +625,19 @@ static std::vector<int64_t> tune_sample(int64_t n, int64_t k, uint64_t seed)
     return idx;
 }
 
-int tfmm_tune_accuracy(const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
-                       const tfmm_params *base, const double *M, double tol, int32_t n_sample, uint64_t seed,
-                       const int32_t *p_list, int32_t n_p, const double *theta_list, int32_t n_theta,
-                       tfmm_tune_result *out, double *table)
+// The (p, theta) search of tfmm_tune_accuracy for tets (tets != NULL) or for
+// point dipoles at the nodes (tets == NULL).
+static int tune_accuracy(const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
+                         const tfmm_params *base, const double *M, double tol, int32_t n_sample, uint64_t seed,
+                         const int32_t *p_list, int32_t n_p, const double *theta_list, int32_t n_theta,
+                         tfmm_tune_result *out, double *table)
 {
-    if (!nodes || !tets || !base || !M || !out || !p_list || !theta_list)
-        return set_error(TFMM_EINVAL, "NULL argument");
+    if (!nodes || !base || !M || !out || !p_list || !theta_list) return set_error(TFMM_EINVAL, "NULL argument");
+    const bool points = tets == nullptr;
+    auto create = [&](const double *tg, int64_t ntg, const tfmm_params *prm, tfmm_plan *pl) {
+        return points ? tfmm_plan_create_points(nodes, n_nodes, tg, ntg, prm, pl)
+                      : tfmm_plan_create(nodes, n_nodes, tets, n_tets, tg, ntg, prm, pl);
+    };
     if (!(tol > 0.0) || n_sample < 1 || n_p < 1 || n_theta < 1 || n_nodes < 1)
         return set_error(TFMM_EINVAL, "tol > 0, n_sample >= 1 and non-empty candidate lists required");
     if (base->device < 0) return set_error(TFMM_EINVAL, "tuning needs a device");
@@ -679,7 +685,7 @@ int tfmm_tune_accuracy(const double *nodes, int64_t n_nodes, const int32_t *tets
         tfmm_params rp = *base;
         rp.p = 2;
         rp.theta = 0.5;
-        int r = tfmm_plan_create(nodes, n_nodes, tets, n_tets, xs.data(), ns, &rp, &ref);
+        int r = create(xs.data(), ns, &rp, &ref);
         if (r) return r;
         if ((r = tfmm_direct(ref, dM, 1, dref, st))) return r;
         std::vector<double> uref((size_t)ns), u((size_t)n_nodes);
@@ -704,7 +710,7 @@ int tfmm_tune_accuracy(const double *nodes, int64_t n_nodes, const int32_t *tets
                 tfmm_params cp = *base;
                 cp.p = p_list[ip];
                 cp.theta = theta_list[it];
-                if ((r = tfmm_plan_create(nodes, n_nodes, tets, n_tets, nullptr, 0, &cp, &cand))) return r;
+                if ((r = create(nullptr, 0, &cp, &cand))) return r;
                 if ((r = tfmm_evaluate(cand, dM, 1, du, st))) return r;
                 tfmm::hip_check(hipMemcpyAsync(u.data(), du, sizeof(double) * (size_t)n_nodes, hipMemcpyDeviceToHost, st),
                                 "hipMemcpy u");
@@ -756,6 +762,24 @@ int tfmm_tune_accuracy(const double *nodes, int64_t n_nodes, const int32_t *tets
     });
     cleanup();
     return rc;
+}
+
+int tfmm_tune_accuracy(const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
+                       const tfmm_params *base, const double *M, double tol, int32_t n_sample, uint64_t seed,
+                       const int32_t *p_list, int32_t n_p, const double *theta_list, int32_t n_theta,
+                       tfmm_tune_result *out, double *table)
+{
+    if (!tets) return set_error(TFMM_EINVAL, "NULL argument");
+    return tune_accuracy(nodes, n_nodes, tets, n_tets, base, M, tol, n_sample, seed, p_list, n_p, theta_list, n_theta,
+                         out, table);
+}
+
+int tfmm_tune_accuracy_points(const double *points, int64_t n_points, const tfmm_params *base, const double *M,
+                              double tol, int32_t n_sample, uint64_t seed, const int32_t *p_list, int32_t n_p,
+                              const double *theta_list, int32_t n_theta, tfmm_tune_result *out, double *table)
+{
+    return tune_accuracy(points, n_points, nullptr, n_points, base, M, tol, n_sample, seed, p_list, n_p, theta_list,
+                         n_theta, out, table);
 }
 
 static void batch_drop_graph(tfmm_batch b)

@@ -65,3 +65,18 @@ def test_unreachable_tolerance_reports_the_most_accurate(torch_dev):
     assert r["err"] == pytest.approx(tried[:, 2].min())
     with pytest.raises(T.TetFMMError):
         T.tfmm_tune_accuracy(nodes, tets, -1.0, leaf_size=8)
+
+
+def test_tuned_dipole_configuration(torch_dev, orc):
+    """Point dipoles: the returned (p, theta) meets the tolerance in the
+    oracle's dipole FMM against the oracle's dipole sum."""
+    rng = np.random.default_rng(12)
+    pts = rng.uniform(-1, 1, (1200, 3)) * [1.0, 0.8, 0.5]
+    m = rng.standard_normal((pts.shape[0], 3))
+    tol = 1e-4
+    _say("tune dipoles tol", tol)
+    r = T.tfmm_tune_accuracy(pts, None, tol, M=m, leaf_size=16, n_sample=256, seed=2,
+                             p_list=(4, 6, 8), theta_list=(0.35, 0.5, 0.65))
+    assert r["met"] and r["err"] <= tol / 2, r
+    u = orc.DipoleFMM(pts, r["p"], 16, r["theta"]).evaluate(m)
+    assert _rel(u, orc.dipole_direct(pts, m)) <= tol, (r["p"], r["theta"])
