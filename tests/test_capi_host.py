@@ -153,3 +153,43 @@ def test_batch_errors_without_device():
         T.tfmm_batch_create([meshes[0], (meshes[1][0], bad)], p=4, leaf_size=8, device=0)
     assert e.value.code in (-2, -6)
     assert lib.tfmm_batch_destroy(None) == 0
+
+
+@pytest.mark.parametrize("n,p,leaf,theta", [(1500, 6, 16, 0.5), (400, 4, 4, 0.6), (60, 3, 1, 0.45)])
+def test_point_plan_matches_oracle_exactly(orc, n, p, leaf, theta):
+    """Point-dipole plans: the same tree, radii and lists as the oracle's
+    dipole FMM, bit for bit (host-only plan, no device)."""
+    rng = np.random.default_rng(n)
+    pts = rng.uniform(-1, 1, (n, 3)) * [1.0, 0.6, 0.3]
+    P = T.tfmm_plan_create_points(pts, p=p, leaf_size=leaf, theta=theta, device=-1)
+    F = orc.DipoleFMM(pts, p, leaf, theta)
+    st, so = T.tfmm_plan_stats(P), F.stats()
+    for a, b in (("n_cells", "ncells"), ("depth", "depth"), ("n_m2l", "n_m2l"), ("n_p2p", "n_p2p"),
+                 ("n_p2p_pairs", "n_p2p_pairs")):
+        assert st[a] == so[b], a
+    for kind in ("m2l", "p2p"):
+        assert {tuple(r) for r in T.tfmm_plan_lists(P, kind)} == {tuple(r) for r in F.lists(kind)}
+    cg, rg = T.tfmm_plan_cells(P)
+    co, ro = F.cells()
+    assert {tuple(c[:4]): (tuple(c[4:]), tuple(r)) for c, r in zip(cg, rg)} == \
+        {tuple(c[:4]): (tuple(c[4:]), tuple(r)) for c, r in zip(co, ro)}
+
+
+def test_point_plan_and_tuner_errors():
+    with pytest.raises(T.TetFMMError) as e:
+        T.tfmm_plan_create_points(np.ones((4, 3)), device=-1)  # all points coincide
+    assert e.value.code == -1
+    pts = np.random.default_rng(1).standard_normal((10, 3))
+    pts[3, 0] = np.inf
+    with pytest.raises(T.TetFMMError) as e:
+        T.tfmm_plan_create_points(pts, device=-1)
+    assert e.value.code == -4
+    nodes, tets = meshgen.box_mesh(2)
+    for kw in (dict(tol=0.0), dict(tol=1e-3, n_sample=0), dict(tol=1e-3, p_list=(0,)),
+               dict(tol=1e-3, theta_list=(1.0,)), dict(tol=1e-3, device=-1)):
+        args = dict(leaf_size=8)
+        args.update(kw)
+        tol = args.pop("tol")
+        with pytest.raises(T.TetFMMError) as e:
+            T.tfmm_tune_accuracy(nodes, tets, tol, **args)
+        assert e.value.code == -1, kw
