@@ -46,6 +46,7 @@ def _cloud(n, seed):
 
 
 @pytest.mark.parametrize("n,p,leaf,theta,F", [(2000, 6, 16, 0.5, 1), (3000, 8, 32, 0.45, 3), (700, 4, 4, 0.6, 9),
+                                              (900, 8, 16, 0.5, 18),
                                               (64, 3, 1, 0.5, 2)])
 def test_dipole_fmm_matches_oracle(torch_dev, orc, n, p, leaf, theta, F):
     pts = _cloud(n, 5)
