@@ -96,6 +96,26 @@ def test_fmm_field_batches_match_oracle(torch_dev, orc, F):
         assert _rel(u[f], ref[f]) <= TOL, f
 
 
+def test_highest_order_many_fields(torch_dev, orc):
+    """p = 10 (the largest order: 286 coefficients) with 17 fields (one tile
+    group of 16 plus one field): FP64 against the oracle, and the FP32 and
+    split-BF16 translations close to FP64 (largest LDS and register shapes of
+    P2M, M2L and the shifts)."""
+    nodes, tets = meshgen.box_mesh((7, 6, 5), seed=21)
+    F = 17
+    M = meshgen.random_fields(nodes.shape[0], F=F, seed=22)
+    _say("p=10 with 17 fields")
+    P = T.tfmm_plan_create(nodes, tets, p=10, leaf_size=8, theta=0.5)
+    u = _run(torch_dev, P, M)
+    ref = orc.FMM(nodes, tets, 10, 8, 0.5).evaluate(M)
+    for f in range(F):
+        assert _rel(u[f], ref[f]) <= TOL, f
+    for prec, tol in ((T.M2L_FP32, 1e-5), (T.M2L_BF16X3, 1e-5), (T.M2L_BF16X6, 1e-5)):
+        T.tfmm_plan_set_m2l_precision(P, prec)
+        ul = _run(torch_dev, P, M)
+        assert max(_rel(ul[f], u[f]) for f in range(F)) <= tol, prec
+
+
 def test_fp32_m2l_accuracy(torch_dev, orc):
     """FP32 matrix-core M2L on level-scaled expansions: close to the FP64 FMM,
     and its error against the direct sum stays at the FMM's own level."""
