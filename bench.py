@@ -109,7 +109,8 @@ def kernel_breakdown(T, torch, plan, M, u, steps):
 def ragged_batch(T, torch, steps):
     """32 jittered cubes with 2k-200k tets (log-uniform), one field each, p=8,
     leaf 64, theta 0.5, FP64: one eager evaluation per mesh vs the batch's
-    captured graph, before and after schedule tuning."""
+    captured graph, before and after schedule tuning; then the tuned graph
+    with split-BF16 and FP32 translations and with the stored near field."""
     import meshgen
     ns = meshgen.ragged_sizes(32)
     meshes = [meshgen.box_mesh(int(n), seed=i) for i, n in enumerate(ns)]
@@ -133,15 +134,29 @@ def ragged_batch(T, torch, steps):
     t_graph = timed(lambda: T.tfmm_batch_evaluate(B, M, u))
     T.tfmm_batch_autotune(B)
     t_tuned = timed(lambda: T.tfmm_batch_evaluate(B, M, u))
-    err = 0.0
-    for p, m, x in zip(plans, M, u):
-        ud = T.tfmm_direct(p, m)
-        err = max(err, float(torch.linalg.norm(x - ud) / torch.linalg.norm(ud)))
+    uds = [T.tfmm_direct(p, m) for p, m in zip(plans, M)]
+
+    def max_err():
+        torch.cuda.synchronize()
+        return max(float(torch.linalg.norm(x - ud) / torch.linalg.norm(ud)) for x, ud in zip(u, uds))
+
+    err = max_err()
+    # the same graph with mixed-precision translations, then with the stored near field
+    forms = {}
+    for name, prec, store in (("bf16x3", T.M2L_BF16X3, False), ("fp32", T.M2L_FP32, False),
+                              ("fp32_near_stored", T.M2L_FP32, True)):
+        for pl in plans:
+            T.tfmm_plan_set_m2l_precision(pl, prec)
+            if store:
+                T.tfmm_plan_store_near(pl)
+        t = timed(lambda: T.tfmm_batch_evaluate(B, M, u))
+        forms[name] = {"value": evals / t, "ms_per_step": t * 1e3, "rel_l2_vs_direct_max_over_meshes": max_err(),
+                       "speedup_vs_fp64_graph": t_tuned / t}
     T.tfmm_batch_destroy(B)
     return {"meshes": len(meshes), "tets": int(sum(m[1].shape[0] for m in meshes)), "targets": int(evals),
             "value": evals / t_tuned, "unit": "evals/s", "ms_per_step": t_tuned * 1e3,
             "ms_eager_per_mesh_launches": t_eager * 1e3, "ms_graph": t_graph * 1e3, "ms_graph_tuned": t_tuned * 1e3,
-            "m2l": "fp64", "rel_l2_vs_direct_max_over_meshes": err}
+            "m2l": "fp64", "rel_l2_vs_direct_max_over_meshes": err, "forms": forms}
 
 
 def main():
