@@ -221,7 +221,9 @@ int tfmm_plan_stats(tfmm_plan plan, tfmm_stats *out);
 
 /*
  * Interaction lists as integer cell coordinates, for verification.
- *  kind 0 = M2L pairs, 1 = P2P pairs.
+ *  kind 0 = M2L pairs, 1 = P2P pairs, 2 = the M2L pairs in the order the
+ *  matrix-core tiles (16 target cells) schedule them: the same set as
+ *  kind 0, each pair once.
  *  out  host, [n][8] int32: levelA, ixA, iyA, izA, levelB, ixB, iyB, izB
  *       (A target cell, B source cell; a cell at level L covers
  *       [origin + i s, origin + (i+1) s) per axis with s = side / 2^L), or

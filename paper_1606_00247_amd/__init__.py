@@ -432,8 +432,9 @@ def tfmm_plan_stats(plan):
 
 
 def tfmm_plan_lists(plan, kind):
-    """kind 'm2l' or 'p2p' -> int32 [n, 8] (levA, ixA, iyA, izA, levB, ixB, iyB, izB)."""
-    k = {"m2l": 0, "p2p": 1}[kind]
+    """kind 'm2l', 'p2p' or 'm2l_tiles' (the M2L pairs as the matrix-core
+    tiles schedule them) -> int32 [n, 8] (levA, ixA, iyA, izA, levB, ixB, iyB, izB)."""
+    k = {"m2l": 0, "p2p": 1, "m2l_tiles": 2}[kind]
     n = _check(_load().tfmm_plan_lists(plan.handle, k, None))
     out = np.zeros((n, 8), dtype=np.int32)
     _check(_load().tfmm_plan_lists(plan.handle, k, _ptr(out, _i32p)))

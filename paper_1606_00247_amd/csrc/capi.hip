@@ -455,7 +455,7 @@ int tfmm_plan_stats(tfmm_plan plan, tfmm_stats *out)
 int64_t tfmm_plan_lists(tfmm_plan plan, int32_t kind, int32_t *out)
 {
     if (!plan) return set_error(TFMM_EINVAL, "NULL plan");
-    if (kind != 0 && kind != 1) return set_error(TFMM_EINVAL, "kind must be 0 (M2L) or 1 (P2P)");
+    if (kind < 0 || kind > 2) return set_error(TFMM_EINVAL, "kind must be 0 (M2L), 1 (P2P) or 2 (M2L tile schedule)");
     const tfmm::HostPlan &hp = plan->dp.hp;
     auto put = [&](int64_t k, int32_t a, int32_t b) {
         const tfmm::Cell &A = hp.cells[a], &B = hp.cells[b];
@@ -477,6 +477,24 @@ int64_t tfmm_plan_lists(tfmm_plan plan, int32_t kind, int32_t *out)
                 for (int32_t j = hp.m2l_ptr[a]; j < hp.m2l_ptr[a + 1]; ++j) put(k++, (int32_t)a, hp.m2l_src[j]);
         }
         return n;
+    }
+    if (kind == 2) {  // the pairs as the matrix-core tiles of 16 target cells schedule them
+        tfmm::M2LTiles t;
+        try {
+            tfmm::build_m2l_tiles(hp, 16, plan->dp.m2l_max_ent, t);
+        } catch (const tfmm::PlanError &e) {
+            return set_error(e.code, e.msg);
+        }
+        int64_t k = 0;
+        for (size_t i = 0; 2 * i < t.tile_rng.size(); ++i)
+            for (int32_t e = t.tile_rng[2 * i]; e < t.tile_rng[2 * i + 1]; ++e)
+                for (int s = 0; s < t.tpt; ++s) {
+                    const int32_t a = t.tile_tgt[i * t.tpt + s], b = t.ent_src[(size_t)e * t.tpt + s];
+                    if (a < 0 || b < 0) continue;
+                    if (out) put(k, a, b);
+                    ++k;
+                }
+        return k;
     }
     int64_t n = (int64_t)hp.p2p_a.size();
     if (out)

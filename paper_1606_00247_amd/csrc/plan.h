@@ -68,7 +68,10 @@ struct HostPlan {
 // (sorted by level difference, then key), with the source cell of each tile
 // slot (-1: none).  A tile's entries are cut into work items of at most
 // max_ent entries (each adds its part to the tiles' local expansions), and
-// the work items are ordered longest first.
+// the work items are ordered for dispatch over the XCDs: each XCD takes a
+// spatially contiguous share of every level, longest items first (empty
+// items, tile_rng {0, 0}, pad the XCDs with fewer).
+constexpr int kM2LXcds = 8;
 struct M2LTiles {
     int tpt = 0;
     std::vector<int32_t> tile_tgt;  // [nitems][tpt] target cells (-1: empty slot)

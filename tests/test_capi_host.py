@@ -52,6 +52,21 @@ def test_plan_matches_oracle_exactly(orc, n, p, leaf, theta):
     assert dg == do  # radii bit for bit
 
 
+@pytest.mark.parametrize("n,leaf,theta", [(10, 8, 0.5), ((14, 6, 9), 16, 0.4), (6, 2, 0.6)])
+def test_m2l_tile_schedule_covers_every_pair_once(orc, n, leaf, theta):
+    """The matrix-core schedule (tiles of 16 target cells, entries per key,
+    work items spread over the XCDs) translates every M2L pair of the
+    oracle's list exactly once."""
+    nodes, tets = meshgen.box_mesh(n, jitter=0.15, seed=3)
+    P = T.tfmm_plan_create(nodes, tets, p=4, leaf_size=leaf, theta=theta, device=-1)
+    sched = T.tfmm_plan_lists(P, "m2l_tiles")
+    ref = orc.FMM(nodes, tets, 4, leaf, theta).lists("m2l")
+    assert sched.shape == ref.shape
+    a = np.unique(sched, axis=0, return_counts=True)
+    assert a[1].max() == 1 and a[0].shape[0] == ref.shape[0]
+    assert {tuple(r) for r in a[0]} == {tuple(r) for r in ref}
+
+
 def test_plan_explicit_targets_and_unjittered(orc):
     nodes, tets = meshgen.box_mesh((6, 6, 2), lo=(-3, -3, 0), hi=(3, 3, 1), jitter=0.0)
     rng = np.random.default_rng(3)
