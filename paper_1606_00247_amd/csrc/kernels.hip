@@ -720,6 +720,7 @@ struct M2LCols {
 // barrier per key.  Thread tid stages column tid/16, coefficients
 // n = tid%16 + 16 j.
 constexpr int kM2LSeg = 128;  // M2L entries whose metadata is staged in LDS at once
+constexpr int kM2LAhead = 2;  // lookahead entries staged with a segment (matrix-core form)
 
 template <typename T, int P, int W>
 __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_rng, const int32_t *__restrict__ ent_key,
@@ -740,23 +741,24 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_rng, c
     m2l_wave_index<P, W>(lane, didx);
     v4 acc0[2] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
     const int e0 = tile_rng[2 * tile], e1 = tile_rng[2 * tile + 1];
-    T pq[QREG], pd[DREG];
-    int pdl = 0, qdeg[QREG];
+    int qdeg[QREG];
 #pragma unroll
     for (int j = 0; j < QREG; ++j) qdeg[j] = rdeg(tn + 16 * j);
     // Entry metadata (key id, its level difference, the source cell of every
-    // tile slot) is staged in LDS a segment of kM2LSeg entries (plus one
-    // lookahead entry) at a time, so the loop issues no global load whose
-    // address depends on another global load: the table row and multipoles of
-    // entry e + 1 are loaded while the MFMAs of entry e run.  Loads go to
-    // clamped, in-bounds addresses unconditionally and are masked when stored
-    // (exec-masked loads make the compiler wait for every outstanding load
-    // where the branches join).
+    // tile slot) is staged in LDS a segment of kM2LSeg entries (plus
+    // kM2LAhead lookahead entries) at a time, so the loop issues no global
+    // load whose address depends on another global load.  The table row and
+    // multipoles of an entry are loaded two entries ahead, into one of two
+    // register sets: those of entry e + 2 are in flight while the MFMAs of
+    // entry e run and entry e + 1 is stored to LDS, so a load has two entries
+    // of matrix work to arrive in.  Loads go to clamped, in-bounds addresses
+    // unconditionally and are masked when stored (exec-masked loads make the
+    // compiler wait for every outstanding load where the branches join).
     const bool active = field < cols.F;
     const T *qf = Qr + (int64_t)(active ? field : 0) * C * qpad;
     int seg = e0;
     auto stage_seg = [&]() {
-        const int ne = min(e1 - seg, kM2LSeg + 1);
+        const int ne = min(e1 - seg, kM2LSeg + kM2LAhead);
         for (int i = tid; i < ne * cols.tpt; i += NT) s_src[i] = ent_src[(int64_t)seg * cols.tpt + i];
         for (int i = tid; i < ne; i += NT) {
             const int key = ent_key[seg + i];
@@ -764,56 +766,68 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_rng, c
             s_kk[2 * i + 1] = keys[4 * key];
         }
     };
-    bool qok = false;
-    auto fetch = [&](int e) {
+    struct Ops {
+        T q[QREG], d[DREG];
+        int dl;
+        bool ok;
+    };
+    auto fetch = [&](Ops &o, int e) {
         const int r = e - seg;
         const int key = s_kk[2 * r];
-        pdl = s_kk[2 * r + 1];
+        o.dl = s_kk[2 * r + 1];
         const int src = s_src[r * cols.tpt + tslot];
 #pragma unroll
         for (int j = 0; j < DREG; ++j) {
             const int k = tid + NT * j;
-            pd[j] = Dtab[(int64_t)key * ND + (k < ND ? k : ND - 1)];
+            o.d[j] = Dtab[(int64_t)key * ND + (k < ND ? k : ND - 1)];
         }
-        qok = active && src >= 0;
-        const T *q = qf + (int64_t)(qok ? src : 0) * qpad;
+        o.ok = active && src >= 0;
+        const T *q = qf + (int64_t)(o.ok ? src : 0) * qpad;
 #pragma unroll
         for (int j = 0; j < QREG; ++j) {
             const int n = tn + 16 * j;
-            pq[j] = q[n < NR ? n : NR - 1];
+            o.q[j] = q[n < NR ? n : NR - 1];
         }
     };
-    auto store = [&](int buf) {
+    auto store = [&](const Ops &o, int buf) {
         T *D = s_D + buf * DSTR;
         T *Qb = s_Q + buf * 16 * KSTR + tcol * KSTR;
 #pragma unroll
         for (int j = 0; j < DREG; ++j) {
             const int k = tid + NT * j;
-            if (k < ND) D[k] = pd[j];
+            if (k < ND) D[k] = o.d[j];
         }
 #pragma unroll
         for (int j = 0; j < QREG; ++j) {
             const int n = tn + 16 * j;
-            if (n < NR) Qb[n] = qok ? ldexp(pq[j], -pdl * qdeg[j]) : (T)0;  // 2^(-dl |n|), exact
+            if (n < NR) Qb[n] = o.ok ? ldexp(o.q[j], -o.dl * qdeg[j]) : (T)0;  // 2^(-dl |n|), exact
         }
     };
     if (e0 >= e1) return;
     stage_seg();
     __syncthreads();
-    fetch(e0);
-    store(0);
+    Ops oa, ob;
+    fetch(oa, e0);
+    store(oa, 0);
+    if (e0 + 1 < e1) fetch(oa, e0 + 1);
     __syncthreads();
-    for (int e = e0; e < e1; ++e) {
+    // Entry e is in LDS buffer (e - e0) & 1, `cur` holds the loads of entry
+    // e + 1 and `nxt` takes those of entry e + 2.
+    auto step = [&](Ops &cur, Ops &nxt, int e) {
         const int buf = (e - e0) & 1;
-        if (e + 1 < e1) fetch(e + 1);
+        if (e + 2 < e1) fetch(nxt, e + 2);
         m2l_wave_mfma<T, P, W>(acc, acc0, s_D + buf * DSTR, s_Q + buf * 16 * KSTR, didx, lane);
-        if (e + 1 < e1) store(buf ^ 1);
+        if (e + 1 < e1) store(cur, buf ^ 1);
         __syncthreads();
-        if (e + 1 - seg == kM2LSeg && e + 1 < e1) {  // the next fetch leaves the segment
-            seg = e + 1;
+        if (e + 3 < e1 && e + 3 - seg == kM2LSeg + kM2LAhead) {  // the next fetch leaves the segment
+            seg = e + 3;
             stage_seg();
             __syncthreads();
         }
+    };
+    for (int e = e0; e < e1; e += 2) {
+        step(oa, ob, e);
+        if (e + 1 < e1) step(ob, oa, e + 1);
     }
     acc[0] += acc0[0] + acc0[1];
 }
@@ -855,7 +869,7 @@ __global__ __launch_bounds__(64 * kM2LWaves, 2) void k_m2l_mfma(
     static_assert(2 * sizeof(T) >= sizeof(double), "reduction buffer fits in the staging buffers");
     __shared__ T s_D[2 * (ND + 1)];
     __shared__ __align__(16) T s_Q[2 * 16 * KSTR];
-    __shared__ int32_t s_src[(kM2LSeg + 1) * 16], s_kk[2 * (kM2LSeg + 1)];
+    __shared__ int32_t s_src[(kM2LSeg + kM2LAhead) * 16], s_kk[2 * (kM2LSeg + kM2LAhead)];
     const int tile = blockIdx.x;
     if (tile >= ntiles) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
