@@ -98,6 +98,8 @@ typedef struct {
     double setup_seconds; /* wall time of tfmm_plan_create */
     int64_t near_nnz;     /* (target, node) coefficients of the stored near field, 0 if none */
     int64_t near_bytes;   /* device bytes of the stored near field */
+    int32_t m2l_keys_per_item; /* schedule: M2L keys per workgroup item (tfmm_plan_autotune) */
+    int32_t p2p_wide;          /* schedule: 1 if one-field P2P blocks run four wavefronts */
 } tfmm_stats;
 
 /*

@@ -61,7 +61,8 @@ class _Stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_nodes", "n_tets", "n_targets", "n_cells", "n_leaves", "depth", "n_m2l",
                                         "n_p2p", "n_p2p_pairs", "ncoef", "device_bytes")] + [("setup_seconds",
                                                                                                C.c_double)] + [
-        ("near_nnz", C.c_int64), ("near_bytes", C.c_int64)]
+        ("near_nnz", C.c_int64), ("near_bytes", C.c_int64),
+        ("m2l_keys_per_item", C.c_int32), ("p2p_wide", C.c_int32)]
 
 
 class TetFMMError(RuntimeError):

@@ -449,6 +449,8 @@ int tfmm_plan_stats(tfmm_plan plan, tfmm_stats *out)
     out->setup_seconds = hp.setup_seconds;
     out->near_nnz = plan->dp.near_nnz;
     out->near_bytes = plan->dp.near_bytes;
+    out->m2l_keys_per_item = plan->dp.m2l_max_ent;
+    out->p2p_wide = plan->dp.p2p_wide ? 1 : 0;
     return TFMM_OK;
 }
 

@@ -40,6 +40,7 @@ def test_plan_matches_oracle_exactly(orc, n, p, leaf, theta):
     for a, b in (("n_cells", "ncells"), ("n_leaves", "nleaves"), ("depth", "depth"), ("n_m2l", "n_m2l"),
                  ("n_p2p", "n_p2p"), ("n_p2p_pairs", "n_p2p_pairs"), ("ncoef", "ncoef")):
         assert st[a] == so[b], a
+    assert st["m2l_keys_per_item"] == 256 and st["p2p_wide"] == 0  # default schedule, untuned
     for kind in ("m2l", "p2p"):
         a = T.tfmm_plan_lists(P, kind)
         b = F.lists(kind)

@@ -81,7 +81,11 @@ def test_autotune_keeps_results(torch_dev, orc):
     M = meshgen.random_fields(nodes.shape[0], F=1, seed=6)[0]
     _say("autotune cube10")
     P = T.tfmm_plan_create(nodes, tets, p=7, leaf_size=16, theta=0.5)
+    st = T.tfmm_plan_stats(P)
+    assert st["m2l_keys_per_item"] == 256 and st["p2p_wide"] == 0  # the default schedule
     T.tfmm_plan_autotune(P)
+    st = T.tfmm_plan_stats(P)
+    assert st["m2l_keys_per_item"] in (128, 256, 512, 1024) and st["p2p_wide"] in (0, 1)
     u = T.tfmm_evaluate(P, torch.from_numpy(M).to("cuda:0"))
     torch.cuda.synchronize()
     uo = orc.FMM(nodes, tets, 7, 16, 0.5).evaluate(M)
