@@ -185,6 +185,10 @@ def test_point_plan_matches_oracle_exactly(orc, n, p, leaf, theta):
         assert st[a] == so[b], a
     for kind in ("m2l", "p2p"):
         assert {tuple(r) for r in T.tfmm_plan_lists(P, kind)} == {tuple(r) for r in F.lists(kind)}
+    # the matrix-core schedule translates every M2L pair once
+    sched = T.tfmm_plan_lists(P, "m2l_tiles")
+    assert sched.shape[0] == so["n_m2l"] and np.unique(sched, axis=0).shape[0] == so["n_m2l"]
+    assert {tuple(r) for r in sched} == {tuple(r) for r in F.lists("m2l")}
     cg, rg = T.tfmm_plan_cells(P)
     co, ro = F.cells()
     assert {tuple(c[:4]): (tuple(c[4:]), tuple(r)) for c, r in zip(cg, rg)} == \
