@@ -32,6 +32,14 @@ def _load():
     lib = C.CDLL(_LIB)
     lib.orc_tet_potential.restype = C.c_double
     lib.orc_tet_potential.argtypes = [_dp, _dp, _dp]
+    lib.orc_tet_potential_gauss.restype = C.c_double
+    lib.orc_tet_potential_gauss.argtypes = [_dp, _dp, _dp, C.c_int]
+    lib.orc_gauss_legendre01_rule.restype = C.c_int
+    lib.orc_gauss_legendre01_rule.argtypes = [C.c_int, _dp, _dp]
+    lib.orc_tet_potential_direct.restype = C.c_double
+    lib.orc_tet_potential_direct.argtypes = [_dp, _dp, _dp]
+    lib.orc_tet_distance_ratio.restype = C.c_double
+    lib.orc_tet_distance_ratio.argtypes = [_dp, _dp]
     lib.orc_direct.restype = C.c_int
     lib.orc_direct.argtypes = [_dp, C.c_int64, _i32p, C.c_int64, _dp, C.c_int32, _dp, C.c_int64, _dp]
     lib.orc_ncoef.restype = C.c_int
@@ -112,8 +120,36 @@ def tet_potential(x, v, M):
     return _load().orc_tet_potential(_ptr(x, _dp), _ptr(v, _dp), _ptr(M, _dp))
 
 
+def tet_potential_gauss(x, v, M, n=8):
+    """u_T(x) by the n^3-point collapsed Gauss-Legendre product rule (exact for
+    integrands of total degree 2n - 3); accurate only for targets far from the tet."""
+    x, v, M = _d(x), _d(v), _d(M)
+    return _load().orc_tet_potential_gauss(_ptr(x, _dp), _ptr(v, _dp), _ptr(M, _dp), int(n))
+
+
+def gauss_legendre01(n):
+    """The oracle's n-point Gauss-Legendre rule on [0, 1]: nodes, weights."""
+    t, w = np.zeros(n), np.zeros(n)
+    if _load().orc_gauss_legendre01_rule(int(n), _ptr(t, _dp), _ptr(w, _dp)) != 0:
+        raise ValueError("1 <= n <= 24")
+    return t, w
+
+
+def tet_potential_direct(x, v, M):
+    """u_T(x) as the direct sum takes it: closed form within 4 diameters, Gauss beyond."""
+    x, v, M = _d(x), _d(v), _d(M)
+    return _load().orc_tet_potential_direct(_ptr(x, _dp), _ptr(v, _dp), _ptr(M, _dp))
+
+
+def tet_distance_ratio(x, v):
+    """|x - centroid| / longest edge."""
+    x, v = _d(x), _d(v)
+    return _load().orc_tet_distance_ratio(_ptr(x, _dp), _ptr(v, _dp))
+
+
 def direct(nodes, tets, M, targets=None):
-    """O(N^2) direct sum.  M [F, n_nodes, 3] or [n_nodes, 3] -> u [F, nt] or [nt]."""
+    """O(N^2) direct sum (closed form within 4 tet diameters, a degree-13 Gauss
+    rule beyond).  M [F, n_nodes, 3] or [n_nodes, 3] -> u [F, nt] or [nt]."""
     nodes = _d(nodes)
     tets = np.ascontiguousarray(tets, dtype=np.int32)
     M = _d(M)
