@@ -1381,6 +1381,73 @@ int orc_fmm_expansions(void *h, int32_t which, double *out)
     return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Demagnetising field and energy from nodal potentials (the paper's reported */
+/* quantity, Sec. 4.1: the stray-field energy of the magnetised box).  With u */
+/* interpolated linearly on every tet (P1):                                   */
+/*   H_T = -grad u_T = -sum_i u_i grad lambda_i              (per tet)        */
+/*   E / mu0 = 1/2 sum_T int_T M . grad u_T = 1/2 sum_T V_T Mbar_T . grad u_T  */
+/* (M affine on T, so int_T M = V_T times the mean of its nodal values), and  */
+/* the nodal field by mass lumping, the lumped L2 projection of H onto P1:    */
+/*   H_j = sum_{T ni j} (V_T / 4) H_T / sum_{T ni j} (V_T / 4).                */
+/* nodes [n][3], tets [T][4], M [n][3], u [n]; H_tet [T][3] and H_node [n][3] */
+/* may be NULL.  Returns 0, or -1 on a bad index.                             */
+/* ------------------------------------------------------------------------- */
+int orc_demag(const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets, const double *M,
+              const double *u, double *H_tet, double *H_node, double *energy)
+{
+    for (int64_t t = 0; t < 4 * n_tets; ++t)
+        if (tets[t] < 0 || tets[t] >= n_nodes) return -1;
+    double *wsum = NULL;
+    if (H_node) {
+        wsum = calloc((size_t)(n_nodes > 0 ? n_nodes : 1), sizeof(double));
+        for (int64_t j = 0; j < 3 * n_nodes; ++j) H_node[j] = 0.0;
+    }
+    double E = 0.0;
+    for (int64_t t = 0; t < n_tets; ++t) {
+        const int32_t *tv = tets + 4 * t;
+        const double *V[4] = {nodes + 3 * (size_t)tv[0], nodes + 3 * (size_t)tv[1], nodes + 3 * (size_t)tv[2],
+                              nodes + 3 * (size_t)tv[3]};
+        double e1[3], e2[3], e3[3], c23[3], c31[3], c12[3];
+        sub3(V[1], V[0], e1);
+        sub3(V[2], V[0], e2);
+        sub3(V[3], V[0], e3);
+        cross3(e2, e3, c23);
+        cross3(e3, e1, c31);
+        cross3(e1, e2, c12);
+        const double det = dot3(e1, c23);
+        double g[4][3], gu[3] = {0.0, 0.0, 0.0}, mbar[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < 3; ++d) {
+            g[1][d] = c23[d] / det;
+            g[2][d] = c31[d] / det;
+            g[3][d] = c12[d] / det;
+            g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+        }
+        for (int i = 0; i < 4; ++i)
+            for (int d = 0; d < 3; ++d) {
+                gu[d] += u[tv[i]] * g[i][d];
+                mbar[d] += 0.25 * M[3 * (size_t)tv[i] + d];
+            }
+        const double vol = fabs(det) / 6.0;
+        E += 0.5 * vol * dot3(mbar, gu);
+        if (H_tet)
+            for (int d = 0; d < 3; ++d) H_tet[3 * t + d] = -gu[d];
+        if (H_node)
+            for (int i = 0; i < 4; ++i) {
+                wsum[tv[i]] += 0.25 * vol;
+                for (int d = 0; d < 3; ++d) H_node[3 * (size_t)tv[i] + d] -= 0.25 * vol * gu[d];
+            }
+    }
+    if (H_node) {
+        for (int64_t j = 0; j < n_nodes; ++j)
+            if (wsum[j] > 0.0)
+                for (int d = 0; d < 3; ++d) H_node[3 * j + d] /= wsum[j];
+        free(wsum);
+    }
+    *energy = E;
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

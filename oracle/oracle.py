@@ -80,6 +80,8 @@ def _load():
     lib.orc_dipole_direct.argtypes = [_dp, C.c_int64, _dp, C.c_int32, _dp, C.c_int64, _dp]
     lib.orc_fmm_build_points.restype = C.c_void_p
     lib.orc_fmm_build_points.argtypes = [_dp, C.c_int64, _dp, C.c_int64, C.c_int32, C.c_int32, C.c_double]
+    lib.orc_demag.restype = C.c_int
+    lib.orc_demag.argtypes = [_dp, C.c_int64, _i32p, C.c_int64, _dp, _dp, _dp, _dp, _dp]
     lib.orc_num_threads.restype = C.c_int
     lib.orc_set_num_threads.restype = None
     lib.orc_set_num_threads.argtypes = [C.c_int]
@@ -164,6 +166,24 @@ def direct(nodes, tets, M, targets=None):
     if rc != 0:
         raise ValueError("orc_direct: bad input")
     return u[0] if squeeze else u
+
+
+def demag(nodes, tets, M, u):
+    """P1 demagnetising field and energy from nodal potentials u [n]:
+    returns (E / mu0, H per tet [T, 3], lumped nodal H [n, 3])."""
+    nodes = _d(nodes)
+    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    M = _d(M)
+    u = _d(u)
+    if M.shape != (nodes.shape[0], 3) or u.shape != (nodes.shape[0],):
+        raise ValueError("M must be [n, 3] and u [n]")
+    Ht = np.zeros((tets.shape[0], 3))
+    Hn = np.zeros((nodes.shape[0], 3))
+    E = C.c_double(0.0)
+    if _load().orc_demag(_ptr(nodes, _dp), nodes.shape[0], _ptr(tets, _i32p), tets.shape[0], _ptr(M, _dp),
+                         _ptr(u, _dp), _ptr(Ht, _dp), _ptr(Hn, _dp), C.byref(E)) != 0:
+        raise ValueError("orc_demag: bad input")
+    return E.value, Ht, Hn
 
 
 def taylor_coeffs(x, p):
