@@ -322,12 +322,12 @@ double orc_tet_distance_ratio(const double *x, const double *v)
     return norm3(d) / diam;
 }
 
-/* The pair as the direct sum takes it: the closed form within 4 diameters,  */
+/* The pair as the direct sum takes it: the closed form within 3 diameters,  */
 /* the 8-point (degree 13) Gauss product rule beyond.  Measured on random    */
 /* tets (error relative to |M| V / (4 pi d^2)): the closed form loses about  */
-/* (d/diam)^4 eps, ~1e-12 at 4 diameters and ~1e-9 at 10, while the rule is  */
-/* at ~1e-13 from 2 diameters and at round-off from 3.                        */
-#define ORC_FAR_RATIO 4.0
+/* (d/diam)^4 eps, ~1e-12 at 3 diameters, up to 1e-10 at 4 and ~1e-9 at 10,  */
+/* while the rule is at ~1e-13 from 2 diameters and at round-off from 3.     */
+#define ORC_FAR_RATIO 3.0
 #define ORC_FAR_POINTS 8
 static double orc_pair_direct(const double *x, const double *v, const double *M, const double *t, const double *w)
 {

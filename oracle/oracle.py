@@ -138,7 +138,7 @@ def gauss_legendre01(n):
 
 
 def tet_potential_direct(x, v, M):
-    """u_T(x) as the direct sum takes it: closed form within 4 diameters, Gauss beyond."""
+    """u_T(x) as the direct sum takes it: closed form within 3 diameters, Gauss beyond."""
     x, v, M = _d(x), _d(v), _d(M)
     return _load().orc_tet_potential_direct(_ptr(x, _dp), _ptr(v, _dp), _ptr(M, _dp))
 
@@ -150,7 +150,7 @@ def tet_distance_ratio(x, v):
 
 
 def direct(nodes, tets, M, targets=None):
-    """O(N^2) direct sum (closed form within 4 tet diameters, a degree-13 Gauss
+    """O(N^2) direct sum (closed form within 3 tet diameters, a degree-13 Gauss
     rule beyond).  M [F, n_nodes, 3] or [n_nodes, 3] -> u [F, nt] or [nt]."""
     nodes = _d(nodes)
     tets = np.ascontiguousarray(tets, dtype=np.int32)

@@ -2,7 +2,7 @@
 
 Far from a tet the closed-form pair integral (Sec. 2.1) adds face and edge
 terms much larger than their sum, so the direct sum switches to a Gauss
-product rule on the collapsed cube beyond 4 tet diameters.  The rule is
+product rule on the collapsed cube beyond 3 tet diameters.  The rule is
 pinned by
  - its 1-D Gauss-Legendre nodes and weights against numpy's;
  - the independent cone-decomposition quadrature of Sec. 2.1.1 at 2-10
@@ -96,7 +96,7 @@ def test_direct_pair_switch(orc):
     rng = np.random.default_rng(10)
     v, L = _well_shaped_tet(rng)
     M = rng.standard_normal((4, 3))
-    for ratio, far in ((3.9, False), (4.1, True), (50.0, True)):
+    for ratio, far in ((2.9, False), (3.1, True), (50.0, True)):
         x = _target(rng, v, L, ratio)
         want = orc.tet_potential_gauss(x, v, M, 8) if far else orc.tet_potential(x, v, M)
         assert orc.tet_potential_direct(x, v, M) == want
