@@ -150,7 +150,12 @@ int tfmm_evaluate(tfmm_plan plan, const double *M, int32_t F, double *u, void *h
 
 /*
  * O(N^2) direct sum of the exact tet-to-target integrals (Sec. 2.1) over all
- * targets and all tets, in FP64.  Same arguments and errors as tfmm_evaluate.
+ * targets and all tets, in FP64.  Pairs within 3 tet diameters (longest edge)
+ * of the tet's centroid take the closed form; farther pairs, where the closed
+ * form cancels, a collapsed Gauss-Jacobi rule of degree 13, 11, 9 or 7 by
+ * distance band (3-6, 6-12, 12-24, >= 24 diameters; rule error below ~1e-14
+ * of the pair's size).  Point-dipole plans sum the dipole potentials.  Same
+ * arguments and errors as tfmm_evaluate.
  */
 int tfmm_direct(tfmm_plan plan, const double *M, int32_t F, double *u, void *hip_stream);
 
@@ -293,6 +298,19 @@ int tfmm_demag_energy(tfmm_plan plan, const double *M, const double *u, double *
                       void *hip_stream);
 
 /*
+ * Mass-lumped nodal demagnetising field (the lumped L2 projection of the P1
+ * field -grad u onto the nodes, as used for nodal effective fields in
+ * micromagnetics next to the stray-field energy of Sec. 4.1):
+ *   H_j = sum_{T ni j} (V_T / 4) H_T / sum_{T ni j} (V_T / 4).
+ *  u       device [n_nodes] double, nodal potential (targets must be the nodes)
+ *  H_node  device [n_nodes][3] double, written (input node order)
+ * Asynchronous on hip_stream.  The first call on a plan allocates and builds
+ * the lumped node volumes (kept with the plan).
+ * Errors: TFMM_EINVAL, TFMM_ENOTSUP (point-dipole plans), TFMM_EDEVICE.
+ */
+int tfmm_demag_field_nodes(tfmm_plan plan, const double *u, double *H_node, void *hip_stream);
+
+/*
  * Schedule tuning.  Times evaluations of one (synthetic) field on hip_stream
  * for a few choices of the M2L work item size (keys per workgroup) and of the
  * P2P workgroup shape, and keeps the fastest; the arithmetic, and so every
@@ -301,6 +319,31 @@ int tfmm_demag_energy(tfmm_plan plan, const double *M, const double *u, double *
  * Errors: TFMM_EINVAL (NULL or host-only plan), TFMM_EDEVICE.
  */
 int tfmm_plan_autotune(tfmm_plan plan, void *hip_stream);
+
+/*
+ * Set the schedule knobs that tfmm_plan_autotune picks: M2L keys per
+ * workgroup item (16..4096) and the P2P workgroup shape for one or two fields
+ * (p2p_wide 1: four wavefronts per block; 0: one).  Every choice computes the
+ * same arithmetic; the point is to run a given schedule (for instance the one
+ * a benchmark timed) under test.  Builds the M2L tiles of the new item size
+ * (synchronous).  Errors: TFMM_EINVAL (NULL or host-only plan, values out of
+ * range), TFMM_EDEVICE.
+ */
+int tfmm_plan_set_schedule(tfmm_plan plan, int32_t m2l_keys_per_item, int32_t p2p_wide);
+
+/*
+ * The elementary functions of the exact near-field integral (Sec. 2.1: its
+ * edge logarithms and face solid angles), evaluated on the device one element
+ * at a time, for checking them against an independent implementation:
+ *  fn 0: ln(a/b) for positive finite a, b (one division, atanh series)
+ *  fn 1: atan2(a, b) in (-pi, pi] (one division, polynomial on [0, tan(pi/8)])
+ *  fn 2: a / b for finite nonzero b of moderate range (reciprocal estimate and
+ *        Newton-Raphson steps)
+ *  fn 3: 1/sqrt(a) for positive finite normal a (b ignored)
+ * a, b, out: host arrays of n doubles.  Synchronous on `device`.
+ * Errors: TFMM_EINVAL (fn, n, NULL arrays), TFMM_EDEVICE.
+ */
+int tfmm_elementary(int32_t fn, const double *a, const double *b, double *out, int64_t n, int32_t device);
 
 /*
  * Ragged batches of meshes (one field each).  tfmm_batch_create builds one

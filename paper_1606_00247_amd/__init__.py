@@ -18,9 +18,9 @@ __all__ = [
     "tfmm_direct_host", "tfmm_plan_stats", "tfmm_plan_lists", "tfmm_plan_cells", "tfmm_plan_expansions",
     "tfmm_plan_destroy", "tfmm_last_error", "tfmm_simplex_rule", "tfmm_set_timing", "tfmm_kernel_times",
     "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS", "tfmm_plan_set_m2l_precision", "M2L_FP64", "M2L_FP32", "M2L_BF16X3", "M2L_BF16X6",
-    "tfmm_plan_autotune", "tfmm_batch_create", "tfmm_batch_evaluate", "tfmm_batch_autotune", "tfmm_batch_plan",
+    "tfmm_plan_autotune", "tfmm_plan_set_schedule", "tfmm_elementary", "ELEMENTARY", "tfmm_batch_create", "tfmm_batch_evaluate", "tfmm_batch_autotune", "tfmm_batch_plan",
     "tfmm_batch_destroy", "Batch", "tfmm_surrogate_param_count", "tfmm_surrogate_train", "tfmm_surrogate_load",
-    "tfmm_surrogate_samples", "tfmm_surrogate_grad", "tfmm_band_potential", "tfmm_demag_energy",
+    "tfmm_surrogate_samples", "tfmm_surrogate_grad", "tfmm_band_potential", "tfmm_demag_energy", "tfmm_demag_field_nodes",
     "tfmm_plan_store_near", "tfmm_tune_accuracy", "tfmm_plan_create_points",
 ]
 
@@ -107,6 +107,9 @@ def _load():
         "tfmm_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
         "tfmm_kernel_times": (C.c_int, [C.c_void_p, _dp, _i64p]),
         "tfmm_plan_autotune": (C.c_int, [C.c_void_p, C.c_void_p]),
+        "tfmm_plan_set_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+        "tfmm_elementary": (C.c_int, [C.c_int32, _dp, _dp, _dp, C.c_int64, C.c_int32]),
+        "tfmm_demag_field_nodes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
         "tfmm_batch_create": (C.c_int, [C.c_int32, C.POINTER(_dp), _i64p, C.POINTER(_i32p), _i64p,
                                         C.POINTER(_Params), C.POINTER(C.c_void_p)]),
         "tfmm_batch_evaluate": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
@@ -271,6 +274,25 @@ def tfmm_plan_autotune(plan, stream=None):
     _check(_load().tfmm_plan_autotune(plan.handle, _stream_handle(stream, dev)))
 
 
+def tfmm_plan_set_schedule(plan, m2l_keys_per_item, p2p_wide):
+    """Set the schedule knobs tfmm_plan_autotune picks (same results, other launch shapes)."""
+    _check(_load().tfmm_plan_set_schedule(plan.handle, int(m2l_keys_per_item), int(p2p_wide)))
+
+
+ELEMENTARY = {"log_ratio": 0, "atan2": 1, "div": 2, "rsqrt": 3}
+
+
+def tfmm_elementary(fn, a, b=None, device=0):
+    """The near field's elementary function `fn` (a key of ELEMENTARY) on host arrays."""
+    a = np.ascontiguousarray(a, dtype=np.float64).ravel()
+    b = np.zeros_like(a) if b is None else np.ascontiguousarray(b, dtype=np.float64).ravel()
+    if a.shape != b.shape:
+        raise ValueError("a and b must have the same size")
+    out = np.zeros_like(a)
+    _check(_load().tfmm_elementary(ELEMENTARY[fn], _ptr(a, _dp), _ptr(b, _dp), _ptr(out, _dp), a.size, int(device)))
+    return out
+
+
 class _BorrowedPlan(Plan):
     """A plan owned by a batch (not destroyed with this object)."""
 
@@ -374,6 +396,21 @@ def tfmm_demag_energy(plan, M, u, with_field=False, stream=None):
                                      None if H is None else C.c_void_p(H.data_ptr()), C.byref(E),
                                      _stream_handle(stream, M.device)))
     return (E.value, H) if with_field else E.value
+
+
+def tfmm_demag_field_nodes(plan, u, H=None, stream=None):
+    """Mass-lumped nodal field H [n_nodes, 3] from the nodal potential u (device)."""
+    import torch
+    if not (isinstance(u, torch.Tensor) and u.is_cuda and u.dtype == torch.float64 and u.is_contiguous()
+            and tuple(u.shape) == (plan.n_nodes,)):
+        raise ValueError(f"u must be a contiguous float64 CUDA tensor of shape ({plan.n_nodes},)")
+    if H is None:
+        H = torch.empty((plan.n_nodes, 3), dtype=torch.float64, device=u.device)
+    elif not (H.is_cuda and H.dtype == torch.float64 and H.is_contiguous() and tuple(H.shape) == (plan.n_nodes, 3)):
+        raise ValueError("H must be a contiguous float64 CUDA tensor [n_nodes, 3]")
+    _check(_load().tfmm_demag_field_nodes(plan.handle, C.c_void_p(u.data_ptr()), C.c_void_p(H.data_ptr()),
+                                          _stream_handle(stream, u.device)))
+    return H
 
 
 def tfmm_surrogate_param_count(hidden):

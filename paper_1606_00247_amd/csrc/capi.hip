@@ -264,6 +264,13 @@ void upload_plan(DevicePlan &dp)
         std::vector<double> q = simplex_rule(hp.p, &np);
         dp.nq = np;
         dp.quad = dev_upload(q, B);
+        std::vector<double> far;
+        for (int deg : kFarDeg) {
+            int nf = 0;
+            std::vector<double> r = simplex_rule(deg, &nf);
+            far.insert(far.end(), r.begin(), r.end());
+        }
+        dp.far_rule = dev_upload(far, B);
         const size_t mb = sizeof(double) * std::max<size_t>(1, (size_t)T * dp.ncoef);
         hip_check(hipMalloc(&dp.tet_mom, mb), "hipMalloc tet moments");
         B += (int64_t)mb;
@@ -281,7 +288,7 @@ void free_plan(DevicePlan &dp)
     for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
     dp.event_pool.clear();
     void *ptrs[] = {dp.tet_xyz, dp.tet_node, dp.tet_perm, dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, dp.cell_c, dp.cell_i,
-                    dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.p2p_blk, dp.p2p_idx, dp.quad, dp.tet_mom, dp.Q,
+                    dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.p2p_blk, dp.p2p_idx, dp.quad, dp.far_rule, dp.node_lump, dp.tet_mom, dp.Q,
                     dp.L, dp.Qt, dp.Qtf, dp.m2l_keys, dp.m2l_D, dp.m2l_Df, dp.sur_w, dp.sur_wb, dp.topo_blk,
                     dp.topo_ch_i, dp.topo_ch_c, dp.topo_w, dp.topo_ab, dp.topo_il, dp.topo_pqr, dp.topo_n, dp.topo_a2,
                     dp.topo_inc, dp.topo_A, dp.topo_B, dp.near_off, dp.near_nc, dp.near_cols, dp.near_val, dp.near_items};
@@ -604,6 +611,47 @@ int tfmm_plan_autotune(tfmm_plan plan, void *hip_stream)
     return guarded([&]() -> int {
         DeviceScope ds(plan->dp.device);
         tfmm::autotune(plan->dp, (hipStream_t)hip_stream);
+        return TFMM_OK;
+    });
+}
+
+int tfmm_demag_field_nodes(tfmm_plan plan, const double *u, double *H_node, void *hip_stream)
+{
+    if (!plan || !u || !H_node) return set_error(TFMM_EINVAL, "NULL argument");
+    if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan");
+    if (plan->dp.hp.points) return set_error(TFMM_ENOTSUP, "not available for point-dipole plans");
+    if (!plan->dp.hp.targets_are_nodes) return set_error(TFMM_EINVAL, "the plan's targets are not its nodes");
+    return guarded([&]() -> int {
+        DeviceScope ds(plan->dp.device);
+        tfmm::run_demag_nodes(plan->dp, u, H_node, (hipStream_t)hip_stream);
+        return TFMM_OK;
+    });
+}
+
+int tfmm_elementary(int32_t fn, const double *a, const double *b, double *out, int64_t n, int32_t device)
+{
+    if (fn < 0 || fn > 3 || n < 0 || (n > 0 && (!a || !b || !out)) || device < 0)
+        return set_error(TFMM_EINVAL, "fn in 0..3, n >= 0, non-NULL arrays and a device required");
+    if (n == 0) return TFMM_OK;
+    return guarded([&]() -> int {
+        DeviceScope ds(device);
+        tfmm::run_elementary(fn, a, b, n, out);
+        return TFMM_OK;
+    });
+}
+
+int tfmm_plan_set_schedule(tfmm_plan plan, int32_t m2l_keys_per_item, int32_t p2p_wide)
+{
+    if (!plan) return set_error(TFMM_EINVAL, "NULL plan");
+    if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan");
+    if (m2l_keys_per_item < 16 || m2l_keys_per_item > 4096 || (p2p_wide != 0 && p2p_wide != 1))
+        return set_error(TFMM_EINVAL, "m2l_keys_per_item must be in [16, 4096] and p2p_wide 0 or 1");
+    return guarded([&]() -> int {
+        DeviceScope ds(plan->dp.device);
+        plan->dp.m2l_max_ent = m2l_keys_per_item;
+        plan->dp.p2p_wide = p2p_wide != 0;
+        ++plan->dp.schedule_gen;
+        tfmm::prepare_evaluate(plan->dp, 1);  // the tiles of the new work item size
         return TFMM_OK;
     });
 }
@@ -937,6 +985,9 @@ int tfmm_batch_evaluate(tfmm_batch batch, const double *const *M, double *const 
             tfmm::hip_check(hipGraphInstantiate(&batch->exec, batch->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
             batch->keyM.assign(M, M + n);
             batch->keyU.assign(u, u + n);
+            // prepare_evaluate above may have reallocated buffers (and bumped
+            // the generations); the graph holds the buffers of now
+            for (size_t i = 0; i < n; ++i) gen[i] = batch->plans[i]->dp.schedule_gen;
             batch->keyGen = gen;
         }
         tfmm::hip_check(hipGraphLaunch(batch->exec, st), "hipGraphLaunch");

@@ -16,6 +16,16 @@ namespace tfmm {
 inline int m2l_reduced_width(int p) { return (p + 1) * (p + 1); }
 inline int m2l_table_width(int p) { return 1 + 3 * p * (p + 1) / 2; }
 
+// Far pairs of the direct sum (targets at least kFarRatio[0] longest edges
+// from a tet's centroid) are integrated by collapsed Gauss-Jacobi rules of
+// degree 13, 11, 9 and 7 (7^3, 6^3, 5^3 and 4^3 points, concatenated at
+// kFarOff) for the distance bands [3, 6), [6, 12), [12, 24) and [24, inf)
+// diameters.
+constexpr int kFarBands = 4;
+constexpr int kFarDeg[kFarBands] = {13, 11, 9, 7};
+constexpr int kFarOff[kFarBands + 1] = {0, 343, 559, 684, 748};
+constexpr double kFarRatio[kFarBands] = {3.0, 6.0, 12.0, 24.0};
+
 // Thrown by launchers on HIP failures (converted to TFMM_EDEVICE at the ABI).
 struct DeviceError {
     std::string msg;
@@ -70,7 +80,9 @@ struct DevicePlan {
     int m2l_max_ent = 256;
     bool p2p_wide = false;
     // bumped whenever the launch sequence of an evaluation may change
-    // (precision, schedule), so that captured graphs are rebuilt
+    // (precision, schedule) or a buffer its launches use is reallocated
+    // (expansions, scaled multipoles, M2L tiles), so that captured graphs
+    // are rebuilt instead of replaying on freed memory
     uint64_t schedule_gen = 0;
     // scaled multipoles Qt_n = (-1)^|n| Q_n / (n! s^|n|): [Fcap][C][qpad] (FP64 or FP32)
     double *Qt = nullptr;
@@ -108,6 +120,11 @@ struct DevicePlan {
     // quadrature rule for the moments: [nq][4] = lambda1, lambda2, lambda3, weight
     double *quad = nullptr;
     int32_t nq = 0;
+    // far-pair rules of the direct sum (degrees 11, 9, 7 concatenated, rows as quad)
+    double *far_rule = nullptr;
+    // lumped node volumes (sum of V_T / 4 over the tets of a node), built on
+    // the first nodal-field request
+    double *node_lump = nullptr;
     // expansions [Fcap][C][ncoef]
     double *Q = nullptr, *L = nullptr;
     int32_t Fcap = 0;
@@ -118,6 +135,15 @@ struct DevicePlan {
     int sur_hidden = 0;
     float *sur_w = nullptr;
     uint16_t *sur_wb = nullptr;
+    // near-field pairs of the surrogate's band (built on first use): (sorted
+    // target index, tet) per pair, target-major within each P2P block; the
+    // 27-point rule of the Gauss control; the band's mode in evaluations
+    int32_t *band_pairs = nullptr;
+    int64_t n_band_pairs = 0;
+    bool band_built = false;
+    double *band_rule = nullptr;
+    int32_t n_band_rule = 0;
+    int sur_mode = 0;  // TFMM_SUR_*
 
     // second stream (default priority) for the near field, forked from and
     // joined back into the evaluation stream
@@ -170,12 +196,18 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
 // energy E / mu0 of one field M from the nodal potentials u (targets = nodes);
 // synchronises the stream.
 double run_demag(DevicePlan &dp, const double *M, const double *u, double *H, hipStream_t stream);
+// Mass-lumped nodal field H [n_nodes][3] (input node order) from nodal u;
+// queued on the stream (the first call also builds the lumped volumes).
+void run_demag_nodes(DevicePlan &dp, const double *u, double *Hn, hipStream_t stream);
 // Assemble the stored near-field operator on `stream` (synchronises); the
 // following evaluations apply it.  Throws PlanError(TFMM_ENOMEM) when the
 // device memory is not there.
 void store_near(DevicePlan &dp, hipStream_t stream);
 // Free the stored operator (evaluations integrate the pairs again).
 void drop_near(DevicePlan &dp);
+// The near field's elementary functions on host arrays (fn 0 log_ratio(a, b),
+// 1 atan2_nr(a, b), 2 div_nr(a, b), 3 rsqrt_nr(a)); synchronous, current device.
+void run_elementary(int fn, const double *a, const double *b, int64_t n, double *out);
 // Queue the O(N^2) direct sum of F fields on `stream`.
 void run_direct(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t stream);
 
@@ -194,6 +226,11 @@ void surrogate_samples(DevicePlan &dp, uint64_t seed, int n, float *X, float *Y)
 // u = potential of the plan's near-field pairs in the band only (one field),
 // exact or by the surrogate.
 void run_band(DevicePlan &dp, bool use_surrogate, const double *M, double *u, hipStream_t stream);
+// The list of the near-field pairs of the band (once per plan; synchronises).
+void build_band_list(DevicePlan &dp, hipStream_t stream);
+// Adds the band pairs' potential of F fields into u: mode TFMM_SUR_MLP (the
+// network), TFMM_SUR_GAUSS, TFMM_SUR_QUAD, or TFMM_SUR_OFF (exact integral).
+void run_band_pairs(DevicePlan &dp, int mode, const double *M, int32_t F, double *u, hipStream_t stream);
 
 // Collapsed Gauss-Jacobi rule on the unit simplex exact to total degree `deg`:
 // rows lambda1, lambda2, lambda3, weight (weights sum to 1/6).

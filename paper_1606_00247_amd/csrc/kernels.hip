@@ -1271,6 +1271,148 @@ __global__ __launch_bounds__(p2p_threads(FCH, WIDE), 2) void k_p2p(const int32_t
 }
 
 // ---------------------------------------------------------------------------
+// Direct sum: every target against every tet.  Far from a tet the closed form
+// of pair_accumulate adds terms much larger than their sum and loses about
+// (d/diam)^4 eps (d = |x - centroid|, diam = the longest edge).  From 3
+// diameters on the pair is instead integrated by a collapsed Gauss-Jacobi
+// rule of the integrand of eq. approx1,
+//   4 pi u_T(x) = 6|V| sum_q w_q M(y_q) . (x - y_q) / |x - y_q|^3
+//               = 6|V| sum_i M_i . K_i,
+//   K_i = sum_q w_q lambda_i(q) (x - y_q) / |x - y_q|^3,
+// K independent of the field, with the rules of degree 13, 11, 9 and 7 for
+// the bands [3, 6), [6, 12), [12, 24) and [24, inf) diameters (rule error
+// below ~1e-14 of |M| V / (4 pi d^2)).  One workgroup of 256 threads per DT consecutive tets
+// staged in LDS; every thread takes targets lane, lane + 256, ... and adds
+// its sums over the staged tets atomically.
+// ---------------------------------------------------------------------------
+struct FarTet {
+    double c[3];     // centroid
+    double id2;      // 1 / diam^2
+    double e[3][3];  // v_1 - v_0, v_2 - v_0, v_3 - v_0
+    double vol6;     // 6 |V|
+};
+__host__ __device__ constexpr int direct_stage(int FCH) { return FCH >= 32 ? 4 : (FCH >= 16 ? 8 : 16); }
+
+template <int FCH>
+__global__ __launch_bounds__(256, 2) void k_direct(int nblk, int64_t T, const double *__restrict__ tet_xyz,
+                                                const int32_t *__restrict__ tet_node,
+                                                const double *__restrict__ tgt_xyz,
+                                                const int32_t *__restrict__ tgt_perm, int64_t N,
+                                                const double *__restrict__ M, int64_t n_nodes, int f0,
+                                                const double *__restrict__ rule, double *__restrict__ u)
+{
+    constexpr int DT = direct_stage(FCH);
+    static_assert(DT * FCH <= 256, "one thread per staged tet and field");
+    __shared__ TetGeom s_g[DT];
+    __shared__ TetField s_f[DT][FCH];
+    __shared__ FarTet s_t[DT];
+    __shared__ double s_m[DT][FCH][12];
+    const int b = xcd_item(nblk);
+    if (b < 0) return;
+    const int64_t tb = (int64_t)b * DT;
+    const int nt = (int)min<int64_t>(DT, T - tb);
+    const int lane = threadIdx.x;
+    {
+        const int t = lane / FCH, f = lane % FCH;
+        if (t < nt) {
+            const int64_t tt = tb + t;
+            const double *Mf = M + (int64_t)(f0 + f) * n_nodes * 3;
+            tet_prepare(tet_xyz, tet_node, T, tt, Mf, f == 0 ? &s_g[t] : nullptr, s_f[t][f]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int64_t nd = tet_node[(int64_t)c * T + tt];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) s_m[t][f][3 * c + k] = Mf[3 * nd + k];
+            }
+            if (f == 0) {
+                double v[4][3];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) v[c][k] = tet_xyz[(int64_t)(3 * c + k) * T + tt];
+                FarTet &F = s_t[t];
+                double l2 = 0.0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int q = a + 1; q < 4; ++q) {
+                        const double dx = v[q][0] - v[a][0], dy = v[q][1] - v[a][1], dz = v[q][2] - v[a][2];
+                        l2 = fmax(l2, dx * dx + dy * dy + dz * dz);
+                    }
+                F.id2 = 1.0 / l2;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    F.c[k] = 0.25 * ((v[0][k] + v[1][k]) + (v[2][k] + v[3][k]));
+                    F.e[0][k] = v[1][k] - v[0][k];
+                    F.e[1][k] = v[2][k] - v[0][k];
+                    F.e[2][k] = v[3][k] - v[0][k];
+                }
+                const double det = F.e[0][0] * (F.e[1][1] * F.e[2][2] - F.e[1][2] * F.e[2][1]) -
+                                   F.e[0][1] * (F.e[1][0] * F.e[2][2] - F.e[1][2] * F.e[2][0]) +
+                                   F.e[0][2] * (F.e[1][0] * F.e[2][1] - F.e[1][1] * F.e[2][0]);
+                F.vol6 = fabs(det);
+            }
+        }
+    }
+    __syncthreads();
+    const double r2b[kFarBands] = {kFarRatio[0] * kFarRatio[0], kFarRatio[1] * kFarRatio[1],
+                                   kFarRatio[2] * kFarRatio[2], kFarRatio[3] * kFarRatio[3]};
+    for (int64_t i = lane; i < N; i += 256) {
+        const double x[3] = {tgt_xyz[i], tgt_xyz[N + i], tgt_xyz[2 * N + i]};
+        double acc[FCH];
+#pragma unroll
+        for (int f = 0; f < FCH; ++f) acc[f] = 0.0;
+#pragma unroll 1
+        for (int t = 0; t < nt; ++t) {
+            const FarTet &F = s_t[t];
+            const double dc0 = x[0] - F.c[0], dc1 = x[1] - F.c[1], dc2 = x[2] - F.c[2];
+            const double rat2 = (dc0 * dc0 + dc1 * dc1 + dc2 * dc2) * F.id2;
+            if (rat2 < r2b[0]) {
+                pair_accumulate<FCH>(x, s_g[t], s_f[t], acc);
+                continue;
+            }
+            const int band = rat2 < r2b[1] ? 0 : (rat2 < r2b[2] ? 1 : (rat2 < r2b[3] ? 2 : 3));
+            const int q0 = band == 0 ? kFarOff[0] : (band == 1 ? kFarOff[1] : (band == 2 ? kFarOff[2] : kFarOff[3]));
+            const int q1 = band == 0 ? kFarOff[1] : (band == 1 ? kFarOff[2] : (band == 2 ? kFarOff[3] : kFarOff[4]));
+            const double xv[3] = {x[0] - s_g[t].v[0][0], x[1] - s_g[t].v[0][1], x[2] - s_g[t].v[0][2]};
+            double S[3] = {0.0, 0.0, 0.0}, K[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+#pragma unroll 2
+            for (int q = q0; q < q1; ++q) {
+                const double l1 = rule[4 * q], l2 = rule[4 * q + 1], l3 = rule[4 * q + 2], w = rule[4 * q + 3];
+                double d[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) d[k] = xv[k] - (l1 * F.e[0][k] + l2 * F.e[1][k] + l3 * F.e[2][k]);
+                const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                const double ri = rsqrt_nr(r2);
+                const double wr = w * ri * ri * ri;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double kk = wr * d[k];
+                    S[k] += kk;
+                    K[0][k] = fma(l1, kk, K[0][k]);
+                    K[1][k] = fma(l2, kk, K[1][k]);
+                    K[2][k] = fma(l3, kk, K[2][k]);
+                }
+            }
+            // K_0 = S - K_1 - K_2 - K_3 (lambda_0 = 1 - lambda_1 - lambda_2 - lambda_3)
+#pragma unroll
+            for (int f = 0; f < FCH; ++f) {
+                const double *m = s_m[t][f];
+                double v = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    v += m[k] * (S[k] - K[0][k] - K[1][k] - K[2][k]) + m[3 + k] * K[0][k] + m[6 + k] * K[1][k] +
+                         m[9 + k] * K[2][k];
+                acc[f] = fma(F.vol6, v, acc[f]);
+            }
+        }
+        const int64_t o = tgt_perm[i];
+#pragma unroll
+        for (int f = 0; f < FCH; ++f) atomicAdd(&u[(int64_t)(f0 + f) * N + o], acc[f] * kInv4Pi);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Point dipoles (the second source kind): u(x) = 1/(4 pi) sum_i m_i . (x - y_i)
 // / |x - y_i|^3 over the sources of the near leaves (or all, direct sum); a
 // target at a source's own position takes nothing from it.  Blocks as in
@@ -1685,6 +1827,49 @@ __global__ __launch_bounds__(64 * kNearItemsPerBlock) void k_near_apply(
 // ---------------------------------------------------------------------------
 constexpr int kEnergyThreads = 256;
 
+// grad u of the P1 interpolant on tet t (octree order) of the nodal values u,
+// with its corner node ids, 6|V| and the mean nodal M (when M is not null).
+__device__ inline void p1_gradient(const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node, int64_t T,
+                                   int64_t t, const double *__restrict__ u, const double *__restrict__ M,
+                                   double gu[3], int64_t nd[4], double &vol6, double mbar[3])
+{
+    double v[4][3], uc[4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) mbar[k] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        nd[c] = tet_node[(int64_t)c * T + t];
+        uc[c] = u[nd[c]];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            v[c][k] = tet_xyz[(int64_t)(3 * c + k) * T + t];
+            if (M) mbar[k] += 0.25 * M[3 * nd[c] + k];
+        }
+    }
+    double e1[3], e2[3], e3[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = v[1][k] - v[0][k];
+        e2[k] = v[2][k] - v[0][k];
+        e3[k] = v[3][k] - v[0][k];
+    }
+    // grad u = (u1-u0) g1 + (u2-u0) g2 + (u3-u0) g3, g_i = rows of the inverse Jacobian
+    double g1[3], g2[3], g3[3];
+    g1[0] = e2[1] * e3[2] - e2[2] * e3[1];
+    g1[1] = e2[2] * e3[0] - e2[0] * e3[2];
+    g1[2] = e2[0] * e3[1] - e2[1] * e3[0];
+    g2[0] = e3[1] * e1[2] - e3[2] * e1[1];
+    g2[1] = e3[2] * e1[0] - e3[0] * e1[2];
+    g2[2] = e3[0] * e1[1] - e3[1] * e1[0];
+    g3[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    g3[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    g3[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    const double det = e1[0] * g1[0] + e1[1] * g1[1] + e1[2] * g1[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gu[k] = ((uc[1] - uc[0]) * g1[k] + (uc[2] - uc[0]) * g2[k] + (uc[3] - uc[0]) * g3[k]) / det;
+    vol6 = fabs(det);
+}
+
 __global__ __launch_bounds__(kEnergyThreads) void k_demag(const double *__restrict__ tet_xyz,
                                                           const int32_t *__restrict__ tet_node,
                                                           const int32_t *__restrict__ tet_perm, int64_t T,
@@ -1695,40 +1880,10 @@ __global__ __launch_bounds__(kEnergyThreads) void k_demag(const double *__restri
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double e = 0.0;
     if (t < T) {
-        double v[4][3], uc[4], mbar[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int64_t nd = tet_node[(int64_t)c * T + t];
-            uc[c] = u[nd];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                v[c][k] = tet_xyz[(int64_t)(3 * c + k) * T + t];
-                mbar[k] += 0.25 * M[3 * nd + k];
-            }
-        }
-        double e1[3], e2[3], e3[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            e1[k] = v[1][k] - v[0][k];
-            e2[k] = v[2][k] - v[0][k];
-            e3[k] = v[3][k] - v[0][k];
-        }
-        // grad u = (u1-u0) g1 + (u2-u0) g2 + (u3-u0) g3, g_i = rows of the inverse Jacobian
-        double g1[3], g2[3], g3[3];
-        g1[0] = e2[1] * e3[2] - e2[2] * e3[1];
-        g1[1] = e2[2] * e3[0] - e2[0] * e3[2];
-        g1[2] = e2[0] * e3[1] - e2[1] * e3[0];
-        g2[0] = e3[1] * e1[2] - e3[2] * e1[1];
-        g2[1] = e3[2] * e1[0] - e3[0] * e1[2];
-        g2[2] = e3[0] * e1[1] - e3[1] * e1[0];
-        g3[0] = e1[1] * e2[2] - e1[2] * e2[1];
-        g3[1] = e1[2] * e2[0] - e1[0] * e2[2];
-        g3[2] = e1[0] * e2[1] - e1[1] * e2[0];
-        const double det = e1[0] * g1[0] + e1[1] * g1[1] + e1[2] * g1[2];
-        double gu[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) gu[k] = ((uc[1] - uc[0]) * g1[k] + (uc[2] - uc[0]) * g2[k] + (uc[3] - uc[0]) * g3[k]) / det;
-        e = 0.5 * (fabs(det) / 6.0) * (mbar[0] * gu[0] + mbar[1] * gu[1] + mbar[2] * gu[2]);
+        double gu[3], vol6, mbar[3];
+        int64_t nd[4];
+        p1_gradient(tet_xyz, tet_node, T, t, u, M, gu, nd, vol6, mbar);
+        e = 0.5 * (vol6 / 6.0) * (mbar[0] * gu[0] + mbar[1] * gu[1] + mbar[2] * gu[2]);
         if (H) {
             const int64_t o = tet_perm[t];
 #pragma unroll
@@ -1744,6 +1899,39 @@ __global__ __launch_bounds__(kEnergyThreads) void k_demag(const double *__restri
     if (threadIdx.x == 0) part[blockIdx.x] = s_e[0];
 }
 
+// Mass-lumped nodal field (the lumped L2 projection of the P1 field onto the
+// nodes): H_j = sum_{T ni j} (V_T / 4) H_T / w_j, w_j = sum_{T ni j} V_T / 4.
+// k_demag_scatter adds (V_T / 4) H_T of every tet to its corners (and, when w
+// is not null, V_T / 4 to the weights); k_lump_divide divides by w.
+__global__ __launch_bounds__(kEnergyThreads) void k_demag_scatter(const double *__restrict__ tet_xyz,
+                                                                  const int32_t *__restrict__ tet_node, int64_t T,
+                                                                  const double *__restrict__ u, double *__restrict__ Hn,
+                                                                  double *__restrict__ w)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    double gu[3], vol6, mbar[3];
+    int64_t nd[4];
+    p1_gradient(tet_xyz, tet_node, T, t, u, nullptr, gu, nd, vol6, mbar);
+    const double q = vol6 / 24.0;  // V_T / 4
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) atomicAdd(&Hn[3 * nd[c] + k], -q * gu[k]);
+        if (w) atomicAdd(&w[nd[c]], q);
+    }
+}
+
+__global__ void k_lump_divide(double *__restrict__ Hn, const double *__restrict__ w, int64_t n)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double wj = w[j];
+    const double r = wj > 0.0 ? 1.0 / wj : 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Hn[3 * j + k] *= r;
+}
+
 __global__ __launch_bounds__(kEnergyThreads) void k_sum_blocks(const double *__restrict__ part, int n,
                                                                double *__restrict__ out)
 {
@@ -1757,6 +1945,26 @@ __global__ __launch_bounds__(kEnergyThreads) void k_sum_blocks(const double *__r
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = s_e[0];
+}
+
+// ---------------------------------------------------------------------------
+// The near field's own elementary functions, one call per element (for
+// checking them against an independent implementation).
+// ---------------------------------------------------------------------------
+__global__ void k_elementary(int fn, const double *__restrict__ a, const double *__restrict__ b, int64_t n,
+                             double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = a[i], y = b[i];
+    double r;
+    switch (fn) {
+    case 0: r = log_ratio(x, y); break;
+    case 1: r = atan2_nr(x, y); break;
+    case 2: r = div_nr(x, y); break;
+    default: r = rsqrt_nr(x); break;
+    }
+    out[i] = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -2205,6 +2413,8 @@ DevicePlan::Tiles &ensure_m2l_tiles(DevicePlan &dp, int tpt)
     if ((16 >> slot) != tpt) throw DeviceError{"bad M2L tile width"};
     DevicePlan::Tiles &t = dp.m2l_tiles[slot];
     if (t.tpt == tpt && t.max_ent == dp.m2l_max_ent) return t;
+    // a captured graph may hold the old tile pointers
+    ++dp.schedule_gen;
     for (int32_t *q : {t.tile_tgt, t.tile_rng, t.ent_key, t.ent_src})
         if (q) (void)hipFree(q);
     t = DevicePlan::Tiles{};
@@ -2253,6 +2463,7 @@ void reset_timing(DevicePlan &dp)
 void ensure_expansions(DevicePlan &dp, int32_t F)
 {
     if (F <= dp.Fcap) return;
+    ++dp.schedule_gen;  // a captured graph may hold the old Q and L
     if (dp.Q) (void)hipFree(dp.Q);
     if (dp.L) (void)hipFree(dp.L);
     dp.Q = dp.L = nullptr;
@@ -2275,6 +2486,7 @@ void prepare_evaluate(DevicePlan &dp, int32_t F)
     ensure_m2l_tiles(dp, 16 / m2l_fpt(F));
     if (dp.m2l_precision != TFMM_M2L_FP64) {
         if (!dp.m2l_Df) {
+            ++dp.schedule_gen;
             const int64_t n = (int64_t)dp.n_m2l_keys * nd_of(dp.hp.p);
             hip_check(hipMalloc(&dp.m2l_Df, sizeof(float) * std::max<int64_t>(n, 1)), "hipMalloc M2L table f32");
             k_to_float<<<dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536))), dim3(256)>>>(
@@ -2283,6 +2495,7 @@ void prepare_evaluate(DevicePlan &dp, int32_t F)
             hip_check(hipDeviceSynchronize(), "k_to_float");
         }
         if (dp.qtf_cap < F) {
+            ++dp.schedule_gen;
             if (dp.Qtf) (void)hipFree(dp.Qtf);
             dp.Qtf = nullptr;
             dp.qtf_cap = 0;
@@ -2290,6 +2503,7 @@ void prepare_evaluate(DevicePlan &dp, int32_t F)
             dp.qtf_cap = F;
         }
     } else if (dp.qt_cap < F) {
+        ++dp.schedule_gen;
         if (dp.Qt) (void)hipFree(dp.Qt);
         dp.Qt = nullptr;
         dp.qt_cap = 0;
@@ -2471,10 +2685,71 @@ double run_demag(DevicePlan &dp, const double *M, const double *u, double *H, hi
     return E;
 }
 
+void run_elementary(int fn, const double *a, const double *b, int64_t n, double *out)
+{
+    double *d = nullptr;
+    hip_check(hipMalloc(&d, sizeof(double) * 3 * (size_t)n), "hipMalloc elementary");
+    hipError_t e = hipMemcpy(d, a, sizeof(double) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d + n, b, sizeof(double) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        k_elementary<<<(unsigned)((n + 255) / 256), 256>>>(fn, d, d + n, n, d + 2 * n);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(out, d + 2 * n, sizeof(double) * n, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    hip_check(e, "elementary functions");
+}
+
+void run_demag_nodes(DevicePlan &dp, const double *u, double *Hn, hipStream_t st)
+{
+    const HostPlan &hp = dp.hp;
+    if (!hp.targets_are_nodes) throw DeviceError{"the plan's targets are not its nodes"};
+    const int64_t T = hp.n_tets, N = hp.n_nodes;
+    const unsigned nb = (unsigned)((T + kEnergyThreads - 1) / kEnergyThreads);
+    fill(Hn, 3 * N, 0.0, st);
+    if (!dp.node_lump) {  // lumped volumes, once per plan
+        hip_check(hipMalloc(&dp.node_lump, sizeof(double) * (size_t)std::max<int64_t>(N, 1)), "hipMalloc lumped volumes");
+        dp.device_bytes += (int64_t)(sizeof(double) * (size_t)std::max<int64_t>(N, 1));
+        fill(dp.node_lump, N, 0.0, st);
+        if (T > 0)
+            k_demag_scatter<<<nb, kEnergyThreads, 0, st>>>(dp.tet_xyz, dp.tet_node, T, u, Hn, dp.node_lump);
+    } else if (T > 0) {
+        k_demag_scatter<<<nb, kEnergyThreads, 0, st>>>(dp.tet_xyz, dp.tet_node, T, u, Hn, nullptr);
+    }
+    if (N > 0) k_lump_divide<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(Hn, dp.node_lump, N);
+    hip_check(hipGetLastError(), "lumped field launch");
+}
+
 void run_direct(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t st)
 {
-    fill(u, (int64_t)F * dp.hp.n_targets, 0.0, st);
-    run_p2p(dp, true, M, F, u, st);
+    const HostPlan &hp = dp.hp;
+    fill(u, (int64_t)F * hp.n_targets, 0.0, st);
+    if (hp.points) {
+        run_p2p(dp, true, M, F, u, st);
+        return;
+    }
+    if (hp.n_tets == 0 || hp.n_targets == 0) return;
+    for (int f = 0; f < F;) {
+        const int left = F - f;
+        const int fch = left >= 32 ? 32 : (left >= 16 ? 16 : (left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1))));
+        auto go = [&](auto fc) {
+            constexpr int FC = decltype(fc)::value;
+            const int nblk = (int)((hp.n_tets + direct_stage(FC) - 1) / direct_stage(FC));
+            k_direct<FC><<<dim3(xcd_grid(nblk)), dim3(256), 0, st>>>(nblk, hp.n_tets, dp.tet_xyz, dp.tet_node,
+                                                                     dp.tgt_xyz, dp.tgt_perm, hp.n_targets, M,
+                                                                     hp.n_nodes, f, dp.far_rule, u);
+        };
+        switch (fch) {
+        case 32: go(std::integral_constant<int, 32>{}); break;
+        case 16: go(std::integral_constant<int, 16>{}); break;
+        case 8: go(std::integral_constant<int, 8>{}); break;
+        case 4: go(std::integral_constant<int, 4>{}); break;
+        case 2: go(std::integral_constant<int, 2>{}); break;
+        default: go(std::integral_constant<int, 1>{}); break;
+        }
+        hip_check(hipGetLastError(), "k_direct launch");
+        f += fch;
+    }
 }
 
 // ---------------------------------------------------------------------------

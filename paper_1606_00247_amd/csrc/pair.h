@@ -179,6 +179,32 @@ __device__ inline void tet_prepare(const double *__restrict__ tet_xyz, const int
     tet_field(G, gl, eh, m, F1);
 }
 
+// The distance band of the near-field surrogate: 2 <= |x - c| / diam < 6
+// (c the centroid, diam the longest edge).  band_geom and in_band are the only
+// place the band is decided, with explicit fused operations, so that every
+// kernel that splits pairs by it rounds identically.
+constexpr double kBandLo = 2.0, kBandHi = 6.0;
+__device__ __forceinline__ void band_geom(const double v[4][3], double c[3], double &id2)
+{
+    double l2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a + 1; b < 4; ++b) {
+            const double dx = v[b][0] - v[a][0], dy = v[b][1] - v[a][1], dz = v[b][2] - v[a][2];
+            l2 = fmax(l2, fma(dx, dx, fma(dy, dy, dz * dz)));
+        }
+    id2 = 1.0 / l2;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c[k] = 0.25 * ((v[0][k] + v[1][k]) + (v[2][k] + v[3][k]));
+}
+__device__ __forceinline__ bool in_band(const double x[3], const double c[3], double id2)
+{
+    const double dx = x[0] - c[0], dy = x[1] - c[1], dz = x[2] - c[2];
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz)) * id2;
+    return r2 >= kBandLo * kBandLo && r2 < kBandHi * kBandHi;
+}
+
 // n / d for finite nonzero d of moderate range: the hardware reciprocal
 // estimate, two Newton-Raphson steps r <- r + r (1 - d r), then the quotient
 // with one residual correction q <- q + r (n - d q).
@@ -191,6 +217,23 @@ __device__ __forceinline__ double div_nr(double n, double d)
     r = fma(r, e, r);
     const double q = n * r;
     return fma(r, fma(-d, q, n), q);
+}
+
+// 1/sqrt(a) for positive finite normal a: the hardware estimate and two
+// Newton-Raphson steps r <- r + r (1 - a r^2) / 2, then one more on the
+// residual (the estimate's ~2^-23 relative error squares per step).
+__device__ __forceinline__ double rsqrt_nr(double a)
+{
+    double r = __builtin_amdgcn_rsq(a);
+    double h = a * r;
+    double e = fma(-h, r, 1.0);
+    r = fma(0.5 * r, e, r);
+    h = a * r;
+    e = fma(-h, r, 1.0);
+    r = fma(0.5 * r, e, r);
+    h = a * r;
+    e = fma(-h, r, 1.0);
+    return fma(0.5 * r, e, r);
 }
 
 // ln(num / den) for positive finite num, den, with one division: writing

@@ -141,3 +141,31 @@ def test_batch_with_stored_near(torch_dev, orc):
             uo = orc.FMM(m[0], m[1], 6, 16, 0.5).evaluate(M[i].cpu().numpy())
             assert _rel(u[i].cpu().numpy(), uo) <= TOL, (r, i)
     T.tfmm_batch_destroy(B)
+
+
+def test_batch_graph_after_plan_buffers_regrow(torch_dev, orc):
+    """A batch plan evaluated on its own with 4 fields regrows its expansion
+    and scaled-multipole buffers; the next batch evaluation must capture a new
+    graph on the new buffers (not replay the old one on freed memory)."""
+    torch = torch_dev
+    meshes = _ragged(3, 51)
+    _say("batch regrow", [m[1].shape[0] for m in meshes])
+    B = T.tfmm_batch_create(meshes, p=6, leaf_size=16, theta=0.5)
+    M = [torch.from_numpy(meshgen.random_fields(m[0].shape[0], F=1, seed=60 + i)[0]).to("cuda:0")
+         for i, m in enumerate(meshes)]
+    u = T.tfmm_batch_evaluate(B, M)
+    torch.cuda.synchronize()
+    P1 = T.tfmm_batch_plan(B, 1)
+    M4 = torch.from_numpy(meshgen.random_fields(meshes[1][0].shape[0], F=4, seed=70)).to("cuda:0")
+    u4 = T.tfmm_evaluate(P1, M4)
+    torch.cuda.synchronize()
+    u4o = orc.FMM(meshes[1][0], meshes[1][1], 6, 16, 0.5).evaluate(M4.cpu().numpy())
+    for f in range(4):
+        assert _rel(u4[f].cpu().numpy(), u4o[f]) <= TOL, f
+    for r in range(2):
+        T.tfmm_batch_evaluate(B, M, u)
+        torch.cuda.synchronize()
+        for i, m in enumerate(meshes):
+            uo = orc.FMM(m[0], m[1], 6, 16, 0.5).evaluate(M[i].cpu().numpy())
+            assert _rel(u[i].cpu().numpy(), uo) <= TOL, (r, i)
+    T.tfmm_batch_destroy(B)

@@ -60,23 +60,59 @@ def _sample(n, k, seed):
     return np.sort(np.random.default_rng(seed).choice(n, k, replace=False))
 
 
-def test_cube40_fp64_vs_oracle_sampled_and_direct(torch_dev, orc):
+# the schedules the plan's autotune chooses between (M2L keys per work item,
+# four-wavefront one-field P2P blocks); the benchmark times the tuned one
+SCHEDULES = [(k, w) for k in (128, 256, 512, 1024) for w in (0, 1)]
+
+
+def test_cube40_fp64_vs_oracle_all_targets_every_schedule(torch_dev, orc):
+    """The 40^3 cube (384,000 tets, 68,921 targets, p=8, leaf 64, theta 0.5):
+    the FP64 FMM against the oracle FMM on every target, element by element,
+    under every schedule the autotune can pick (the benchmark's among them)."""
     nodes, tets = meshgen.box_mesh(40, seed=0)
     M = meshgen.random_fields(nodes.shape[0], F=1, seed=1)
-    _say("cube40 fp64 vs oracle (sampled) and direct")
     P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=64, theta=0.5)
+    _say("cube40 oracle FMM on all targets")
+    uo = orc.FMM(nodes, tets, 8, 64, 0.5).evaluate(M)
+    scale = np.abs(uo).max()
+    for keys, wide in SCHEDULES:
+        _say("cube40 fp64 schedule", keys, wide)
+        T.tfmm_plan_set_schedule(P, keys, wide)
+        st = T.tfmm_plan_stats(P)
+        assert (st["m2l_keys_per_item"], st["p2p_wide"]) == (keys, wide)
+        u = _eval(torch_dev, P, M)
+        assert _rel(u, uo) <= FMM_TOL, (keys, wide)
+        assert np.abs(u - uo).max() <= 1e-11 * scale, (keys, wide)
+    _say("cube40 autotuned schedule")
+    T.tfmm_plan_autotune(P)
     u = _eval(torch_dev, P, M)
-    ud = _eval(torch_dev, P, M, direct=True)
-    assert _rel(u[0], ud[0]) <= ACC_TOL
-    idx = _sample(nodes.shape[0], 96, 7)
-    O = orc.FMM(nodes, tets, 8, 64, 0.5)
-    uo = O.evaluate_sample(M, idx)
-    assert _rel(u[:, idx], uo) <= FMM_TOL
+    assert _rel(u, uo) <= FMM_TOL
     _say("cube40 fp64 with the stored near-field operator")
     T.tfmm_plan_store_near(P)
     us = _eval(torch_dev, P, M)
-    assert _rel(us, u) <= FMM_TOL
-    assert _rel(us[:, idx], uo) <= FMM_TOL
+    assert _rel(us, uo) <= FMM_TOL
+    assert np.abs(us - uo).max() <= 1e-11 * scale
+
+
+def test_cube40_direct_vs_oracle_direct(torch_dev, orc):
+    """The FP64 direct sum (closed form within 3 tet diameters, Gauss rules
+    beyond) against the oracle's direct sum on 64 seeded targets of the 40^3
+    cube (the oracle takes ~4 core-seconds per target), and the FMM's
+    accuracy against the GPU direct sum on every target."""
+    nodes, tets = meshgen.box_mesh(40, seed=0)
+    M = meshgen.random_fields(nodes.shape[0], F=1, seed=1)
+    idx = _sample(nodes.shape[0], 64, 7)
+    _say("cube40 direct at 64 targets vs oracle direct")
+    ud = _direct_at(torch_dev, nodes, tets, M, idx)
+    ref = orc.direct(nodes, tets, M, targets=nodes[idx])
+    assert _rel(ud, ref) <= FMM_TOL
+    assert np.abs(ud - ref).max() <= 1e-11 * np.abs(ref).max()
+    _say("cube40 fmm vs direct, all targets")
+    P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=64, theta=0.5)
+    u = _eval(torch_dev, P, M)
+    uda = _eval(torch_dev, P, M, direct=True)
+    assert _rel(uda[:, idx], ud) <= 1e-13
+    assert _rel(u, uda) <= ACC_TOL
 
 
 def test_film_oracle_parity_and_full_film_accuracy(torch_dev, orc):

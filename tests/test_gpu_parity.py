@@ -52,6 +52,32 @@ def test_direct_small_all_targets(torch_dev, orc):
         assert _rel(u[f], ref[f]) <= TOL
 
 
+def test_direct_far_bands_single_tet(torch_dev, orc):
+    """One tet, targets on both sides of every distance band of the direct
+    sum's far rules (3, 6, 12, 24 diameters) and far beyond: against the
+    oracle's 20^3-point Gauss rule (converged to round-off there from 2
+    diameters) and, closer, its closed form."""
+    v = np.array([[0.1, 0.0, 0.0], [1.0, 0.2, 0.1], [0.3, 1.1, 0.0], [0.2, 0.3, 0.9]])
+    t = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    rng = np.random.default_rng(12)
+    M = rng.standard_normal((4, 3))
+    c = v.mean(0)
+    L = max(np.linalg.norm(v[a] - v[b]) for a in range(4) for b in range(a + 1, 4))
+    vol = abs(np.linalg.det(np.stack([v[1] - v[0], v[2] - v[0], v[3] - v[0]]))) / 6.0
+    ratios = [1.5, 2.5, 2.99, 3.01, 4.0, 5.99, 6.01, 11.99, 12.01, 23.99, 24.01, 40.0, 300.0]
+    d = rng.standard_normal((len(ratios), 3))
+    tg = c + (np.array(ratios) * L)[:, None] * d / np.linalg.norm(d, axis=1, keepdims=True)
+    _say("direct far bands")
+    P = T.tfmm_plan_create(v, t, targets=tg, p=3, leaf_size=4, theta=0.5)
+    ud = _run(torch_dev, P, M, direct=True)
+    for k, r in enumerate(ratios):
+        ref = orc.tet_potential(tg[k], v, M) if r < 2.0 else orc.tet_potential_gauss(tg[k], v, M, 20)
+        scale = np.abs(M).max() * vol / (4 * np.pi * (r * L) ** 2)
+        # below 3 diameters the closed form (it keeps ~1e-12 of the scale there), the rules beyond
+        tol = 1e-11 if r < 3.0 else 1e-13
+        assert abs(ud[k] - ref) <= tol * scale, (r, ud[k], ref)
+
+
 def test_direct_uniform_box_closed_form(torch_dev):
     """Independent of the oracle: the GPU direct sum reproduces the box closed form."""
     from tests import closed_forms as cf
@@ -231,10 +257,11 @@ def test_device_argument_errors(torch_dev):
         T._check(T._load().tfmm_evaluate(P.handle, None, 1, None, None))
 
 
-def test_demag_energy_and_field(torch_dev):
-    """P1 field and energy from the GPU potentials: equal to the plain
-    definition written out in numpy on the same u, and for the uniformly
-    magnetised cube close to the analytic E = mu0 Ms^2 / 6 (Sec. 4.1)."""
+def test_demag_energy_and_field(torch_dev, orc):
+    """P1 field per tet, lumped nodal field and energy from the GPU potentials:
+    equal to the oracle's orc_demag on the same u, and for the uniformly
+    magnetised cube close to the analytic E = mu0 Ms^2 / 6 (Sec. 4.1); a
+    random affine field on a jittered box checks the general case."""
     import json
     import os
     torch = torch_dev
@@ -242,19 +269,18 @@ def test_demag_energy_and_field(torch_dev):
     nodes, tets = meshgen.box_mesh(12, seed=0)
     _say("demag energy cube12")
     P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=32, theta=0.4)
-    M = meshgen.uniform_field(nodes.shape[0], (0.0, 0.0, 1.0))
-    Md = torch.from_numpy(M).to("cuda:0")
-    u = T.tfmm_evaluate(P, Md)
-    E, H = T.tfmm_demag_energy(P, Md, u, with_field=True)
-    torch.cuda.synchronize()
-    un = u.cpu().numpy()
-    v = nodes[tets]
-    J = np.stack([v[:, 1] - v[:, 0], v[:, 2] - v[:, 0], v[:, 3] - v[:, 0]], axis=2)
-    vol = np.abs(np.linalg.det(J)) / 6.0
-    Ji = np.linalg.inv(J)
-    gl = np.concatenate([-Ji.sum(1, keepdims=True), Ji], axis=1)
-    gradu = np.einsum("tij,ti->tj", gl, un[tets])
-    Eref = 0.5 * np.sum(vol * np.einsum("tj,tj->t", M[tets].mean(1), gradu))
-    assert abs(E - Eref) <= 1e-12 * abs(Eref)
-    assert np.abs(H.cpu().numpy() + gradu).max() <= 1e-10 * np.abs(gradu).max()
-    assert abs(E - g["cube_energy_over_mu0_ms2"]["value"]) <= 5e-3
+    for k, M in enumerate([meshgen.uniform_field(nodes.shape[0], (0.0, 0.0, 1.0)),
+                           meshgen.random_fields(nodes.shape[0], F=1, seed=9)[0]]):
+        Md = torch.from_numpy(np.ascontiguousarray(M)).to("cuda:0")
+        u = T.tfmm_evaluate(P, Md)
+        E, H = T.tfmm_demag_energy(P, Md, u, with_field=True)
+        Hn = T.tfmm_demag_field_nodes(P, u)
+        Hn2 = T.tfmm_demag_field_nodes(P, u)  # second call: lumped volumes already built
+        torch.cuda.synchronize()
+        Eo, Hto, Hno = orc.demag(nodes, tets, M, u.cpu().numpy())
+        assert abs(E - Eo) <= 1e-12 * abs(Eo), k
+        assert np.abs(H.cpu().numpy() - Hto).max() <= 1e-12 * np.abs(Hto).max(), k
+        assert np.abs(Hn.cpu().numpy() - Hno).max() <= 1e-12 * np.abs(Hno).max(), k
+        assert np.abs(Hn2.cpu().numpy() - Hno).max() <= 1e-12 * np.abs(Hno).max(), k
+        if k == 0:
+            assert abs(E - g["cube_energy_over_mu0_ms2"]["value"]) <= 5e-3
