@@ -298,6 +298,27 @@ int tfmm_demag_energy(tfmm_plan plan, const double *M, const double *u, double *
                       void *hip_stream);
 
 /*
+ * tfmm_demag_energy without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arithmetic and H_tet as
+ * tfmm_demag_energy, but the energy E / mu0 goes to a device double (energy,
+ * caller-owned) and nothing is synchronised or copied to the host: the call
+ * only queues two kernels on hip_stream.  The per-block partial sums live in
+ * a library-owned static device array of 65,536 doubles (512 KiB), one per
+ * device the library runs on, held until the process ends; hence at most
+ * TFMM_NOALLOC_MAX_TETS tets.  Every call on a device shares that array:
+ * calls that overlap on one device (several streams or threads) race and
+ * give wrong energies; serialise them.  The first call on a device takes the
+ * array's device address (hipGetSymbolAddress) and keeps it.
+ * Errors: TFMM_EINVAL (NULL arguments, host-only plan, targets not the nodes,
+ * more than TFMM_NOALLOC_MAX_TETS tets), TFMM_ENOTSUP (point-dipole plans),
+ * TFMM_EDEVICE.
+ */
+#define TFMM_NOALLOC_MAX_TETS (65535LL * 256LL)
+int tfmm_demag_energy_noalloc(tfmm_plan plan, const double *M, const double *u, double *H_tet, double *energy,
+                              void *hip_stream);
+
+/*
  * Mass-lumped nodal demagnetising field (the lumped L2 projection of the P1
  * field -grad u onto the nodes, as used for nodal effective fields in
  * micromagnetics next to the stray-field energy of Sec. 4.1):

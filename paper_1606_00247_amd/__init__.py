@@ -20,7 +20,7 @@ __all__ = [
     "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS", "tfmm_plan_set_m2l_precision", "M2L_FP64", "M2L_FP32", "M2L_BF16X3", "M2L_BF16X6",
     "tfmm_plan_autotune", "tfmm_plan_set_schedule", "tfmm_elementary", "ELEMENTARY", "tfmm_batch_create", "tfmm_batch_evaluate", "tfmm_batch_autotune", "tfmm_batch_plan",
     "tfmm_batch_destroy", "Batch", "tfmm_surrogate_param_count", "tfmm_surrogate_train", "tfmm_surrogate_load",
-    "tfmm_surrogate_samples", "tfmm_surrogate_grad", "tfmm_band_potential", "tfmm_demag_energy", "tfmm_demag_field_nodes",
+    "tfmm_surrogate_samples", "tfmm_surrogate_grad", "tfmm_band_potential", "tfmm_demag_energy", "tfmm_demag_energy_noalloc", "NOALLOC_MAX_TETS", "tfmm_demag_field_nodes",
     "tfmm_plan_store_near", "tfmm_tune_accuracy", "tfmm_plan_create_points",
 ]
 
@@ -110,6 +110,8 @@ def _load():
         "tfmm_plan_set_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
         "tfmm_elementary": (C.c_int, [C.c_int32, _dp, _dp, _dp, C.c_int64, C.c_int32]),
         "tfmm_demag_field_nodes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+        "tfmm_demag_energy_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                                C.c_void_p]),
         "tfmm_batch_create": (C.c_int, [C.c_int32, C.POINTER(_dp), _i64p, C.POINTER(_i32p), _i64p,
                                         C.POINTER(_Params), C.POINTER(C.c_void_p)]),
         "tfmm_batch_evaluate": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
@@ -396,6 +398,27 @@ def tfmm_demag_energy(plan, M, u, with_field=False, stream=None):
                                      None if H is None else C.c_void_p(H.data_ptr()), C.byref(E),
                                      _stream_handle(stream, M.device)))
     return (E.value, H) if with_field else E.value
+
+
+NOALLOC_MAX_TETS = 65535 * 256
+
+
+def tfmm_demag_energy_noalloc(plan, M, u, energy, H=None, stream=None):
+    """tfmm_demag_energy without allocation: E / mu0 into the device tensor
+    `energy` (float64, one element) and, when H is given, H per tet into H
+    [n_tets, 3]; asynchronous, nothing allocated (the caller's tensors only)."""
+    import torch
+    for a, shape in ((M, (plan.n_nodes, 3)), (u, (plan.n_nodes,)), (energy, (1,))):
+        if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()
+                and tuple(a.shape) == shape):
+            raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {shape}")
+    if H is not None and not (H.is_cuda and H.dtype == torch.float64 and H.is_contiguous() and H.dim() == 2
+                              and H.shape[1] == 3):
+        raise ValueError("H must be a contiguous float64 CUDA tensor [n_tets, 3]")
+    _check(_load().tfmm_demag_energy_noalloc(plan.handle, C.c_void_p(M.data_ptr()), C.c_void_p(u.data_ptr()),
+                                             None if H is None else C.c_void_p(H.data_ptr()),
+                                             C.c_void_p(energy.data_ptr()), _stream_handle(stream, M.device)))
+    return energy
 
 
 def tfmm_demag_field_nodes(plan, u, H=None, stream=None):

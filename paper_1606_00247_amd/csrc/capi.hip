@@ -615,6 +615,22 @@ int tfmm_plan_autotune(tfmm_plan plan, void *hip_stream)
     });
 }
 
+int tfmm_demag_energy_noalloc(tfmm_plan plan, const double *M, const double *u, double *H_tet, double *energy,
+                              void *hip_stream)
+{
+    if (!plan || !M || !u || !energy) return set_error(TFMM_EINVAL, "NULL argument");
+    if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan");
+    if (plan->dp.hp.points) return set_error(TFMM_ENOTSUP, "not available for point-dipole plans");
+    if (!plan->dp.hp.targets_are_nodes) return set_error(TFMM_EINVAL, "the plan's targets are not its nodes");
+    if (plan->dp.hp.n_tets > (int64_t)TFMM_NOALLOC_MAX_TETS)
+        return set_error(TFMM_EINVAL, "more than TFMM_NOALLOC_MAX_TETS tets");
+    return guarded([&]() -> int {
+        DeviceScope ds(plan->dp.device);
+        tfmm::run_demag_noalloc(plan->dp, M, u, H_tet, energy, (hipStream_t)hip_stream);
+        return TFMM_OK;
+    });
+}
+
 int tfmm_demag_field_nodes(tfmm_plan plan, const double *u, double *H_node, void *hip_stream)
 {
     if (!plan || !u || !H_node) return set_error(TFMM_EINVAL, "NULL argument");

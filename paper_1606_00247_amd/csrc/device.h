@@ -196,6 +196,15 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
 // energy E / mu0 of one field M from the nodal potentials u (targets = nodes);
 // synchronises the stream.
 double run_demag(DevicePlan &dp, const double *M, const double *u, double *H, hipStream_t stream);
+// Doubles of the scratch array of the allocation-free entry point (block
+// partial sums of the energy: TFMM_NOALLOC_MAX_TETS / 256 + 1).
+constexpr int64_t kNoAllocScratchDoubles = 65536;
+// run_demag without any allocation: the block partials go to the device's
+// scratch array, the energy to energy_dev (device); queued on the stream,
+// no synchronisation.  Throws PlanError(TFMM_EINVAL) beyond
+// TFMM_NOALLOC_MAX_TETS tets.
+void run_demag_noalloc(DevicePlan &dp, const double *M, const double *u, double *H, double *energy_dev,
+                       hipStream_t stream);
 // Mass-lumped nodal field H [n_nodes][3] (input node order) from nodal u;
 // queued on the stream (the first call also builds the lumped volumes).
 void run_demag_nodes(DevicePlan &dp, const double *u, double *Hn, hipStream_t stream);

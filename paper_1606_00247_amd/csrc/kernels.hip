@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -2698,6 +2699,58 @@ void run_elementary(int fn, const double *a, const double *b, int64_t n, double 
     if (e == hipSuccess) e = hipMemcpy(out, d + 2 * n, sizeof(double) * n, hipMemcpyDeviceToHost);
     (void)hipFree(d);
     hip_check(e, "elementary functions");
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point: one file-scope device array of
+// kNoAllocScratchDoubles doubles; every device the library runs on holds its
+// own copy until the process ends.  In host code the array's name is only a
+// stand-in (not a device address), so host code reaches it through the
+// address hipGetSymbolAddress returns on each device, taken once per device
+// with that device current and kept.  Every call on a device shares that
+// device's array (it keeps the last call's contents): calls that overlap on
+// one device race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+static double *scratch_address(int device)
+{
+    static std::mutex mu;
+    static std::vector<double *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0) throw DeviceError{"no device"};
+    if ((int)addr.size() <= device) addr.resize((size_t)device + 1, nullptr);
+    if (!addr[device]) {
+        int cur = -1;
+        hip_check(hipGetDevice(&cur), "hipGetDevice");
+        if (cur != device) throw DeviceError{"scratch address requested for a device that is not current"};
+        void *p = nullptr;
+        hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        addr[device] = static_cast<double *>(p);
+    }
+    return addr[device];
+}
+
+void run_demag_noalloc(DevicePlan &dp, const double *M, const double *u, double *H, double *energy_dev,
+                       hipStream_t st)
+{
+    const HostPlan &hp = dp.hp;
+    if (!hp.targets_are_nodes) throw DeviceError{"the plan's targets are not its nodes"};
+    const int64_t T = hp.n_tets;
+    const int64_t nb = (T + kEnergyThreads - 1) / kEnergyThreads;
+    if (nb + 1 > kNoAllocScratchDoubles)
+        throw PlanError{TFMM_EINVAL, "tfmm_demag_energy_noalloc: " + std::to_string(T) + " tets exceed the limit of " +
+                                         std::to_string((int64_t)TFMM_NOALLOC_MAX_TETS)};
+    double *part = scratch_address(dp.device);
+    // every slot read below is written first in this call (block partials,
+    // then their sum): nothing has to start at zero
+    if (T > 0) {
+        k_demag<<<(unsigned)nb, kEnergyThreads, 0, st>>>(dp.tet_xyz, dp.tet_node, dp.tet_perm, T, M, u, H, part);
+        k_sum_blocks<<<1, kEnergyThreads, 0, st>>>(part, (int)nb, energy_dev);
+    } else {
+        k_sum_blocks<<<1, kEnergyThreads, 0, st>>>(part, 0, energy_dev);
+    }
+    hip_check(hipGetLastError(), "demag energy (no allocation) launch");
 }
 
 void run_demag_nodes(DevicePlan &dp, const double *u, double *Hn, hipStream_t st)
