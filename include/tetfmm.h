@@ -55,6 +55,13 @@ extern "C" {
 #define TFMM_M2L_BF16X3 2 /* FP32 operands split into BF16 parts, 3 part products, FP32 accumulation */
 #define TFMM_M2L_BF16X6 3 /* as BF16X3 with 6 part products (about FP32 accuracy) */
 
+/* Near-field pairs 2 <= |x - centroid| / diameter < 6 (Sec. 2.1's exact
+ * integral elsewhere; the diameter is the tet's longest edge) */
+#define TFMM_SUR_OFF 0   /* exact integral for every near pair */
+#define TFMM_SUR_MLP 1   /* the attached network (quadrupole expansion + learned residual) */
+#define TFMM_SUR_GAUSS 2 /* control: 27-point collapsed Gauss-Jacobi rule (degree 5) */
+#define TFMM_SUR_QUAD 3  /* control: the tet's quadrupole expansion alone (the network's base) */
+
 typedef struct tfmm_plan_s *tfmm_plan; /* opaque, owned by the library */
 typedef struct tfmm_batch_s *tfmm_batch; /* opaque, owned by the library */
 
@@ -74,6 +81,13 @@ typedef struct tfmm_batch_s *tfmm_batch; /* opaque, owned by the library */
  *             operands into three BF16 parts and sum 3 or 6 of the part
  *             products in FP32; the local expansions are accumulated and
  *             stored in FP64).
+ *  surrogate  TFMM_SUR_OFF, or how the near-field pairs 2 to 6 tet diameters
+ *             apart are evaluated: TFMM_SUR_MLP (the learned surrogate; a
+ *             network must be attached by tfmm_surrogate_train or
+ *             tfmm_surrogate_load before the first evaluation), or one of the
+ *             controls TFMM_SUR_GAUSS, TFMM_SUR_QUAD.  Closer pairs always
+ *             take the exact integral.  Ignored by point-dipole plans and
+ *             while the stored near field is on.
  *  device     HIP device ordinal; -1 builds a host-only plan (tree and lists
  *             without any device allocation: only tfmm_plan_stats,
  *             tfmm_plan_lists and tfmm_plan_cells work on it).
@@ -83,6 +97,7 @@ typedef struct {
     int32_t leaf_size;
     double theta;
     int32_t m2l_precision;
+    int32_t surrogate;
     int32_t device;
 } tfmm_params;
 
@@ -100,6 +115,13 @@ typedef struct {
     int64_t near_bytes;   /* device bytes of the stored near field */
     int32_t m2l_keys_per_item; /* schedule: M2L keys per workgroup item (tfmm_plan_autotune) */
     int32_t p2p_wide;          /* schedule: 1 if one-field P2P blocks run four wavefronts */
+    /* one-field near field over shared mesh entities: (target, entity)
+       evaluations per evaluation (nodes: a distance, edges: a logarithm,
+       faces: a solid angle) */
+    int64_t p2p_node_evals, p2p_edge_evals, p2p_face_evals;
+    int64_t n_band_pairs; /* near pairs of the surrogate's band (0 until first used) */
+    int32_t surrogate;    /* TFMM_SUR_* of the plan */
+    int32_t surrogate_hidden; /* width of the attached network, 0 if none */
 } tfmm_stats;
 
 /*
@@ -215,6 +237,12 @@ int tfmm_tune_accuracy(const double *nodes, int64_t n_nodes, const int32_t *tets
 int tfmm_tune_accuracy_points(const double *points, int64_t n_points, const tfmm_params *base, const double *M,
                               double tol, int32_t n_sample, uint64_t seed, const int32_t *p_list, int32_t n_p,
                               const double *theta_list, int32_t n_theta, tfmm_tune_result *out, double *table);
+
+/* Switch the near-field surrogate of an existing plan (one of TFMM_SUR_*;
+ * TFMM_SUR_MLP needs an attached network by the next evaluation).  The first
+ * evaluation with a mode other than TFMM_SUR_OFF lists the band's pairs once
+ * (8 bytes per pair, synchronising).  Errors: TFMM_EINVAL. */
+int tfmm_plan_set_surrogate(tfmm_plan plan, int32_t mode);
 
 /* Switch the M2L arithmetic of an existing plan (one of TFMM_M2L_*). */
 int tfmm_plan_set_m2l_precision(tfmm_plan plan, int32_t m2l_precision);
@@ -401,13 +429,22 @@ int tfmm_batch_plan(tfmm_batch batch, int32_t i, tfmm_plan *out);
 int tfmm_batch_destroy(tfmm_batch batch);
 
 /*
- * Learned near-field surrogate.  For a tet (diameter d = longest edge,
- * centroid c, volume V) and a target x at 2 <= rho = |x - c|/d < 6 the
- * potential is u = d * sum_{i,a} C_ia M_ia; a perceptron 12 -> H -> H -> H
- * -> 12 (ReLU) maps s_i = (v_i - x)/|x - c| to y = 16 pi C rho^2 / (V/d^3).
- * It is trained on the GPU (FP32, Adam; pairs drawn from the plan's tets,
- * exact pair integrals as targets) and evaluated with BF16 weights on matrix
- * cores.  It is an experiment beside the method: tfmm_evaluate never uses it.
+ * Learned near-field surrogate of the pair integral of Sec. 2.1 at
+ * intermediate distance.  For a tet (diameter d = longest edge, centroid c,
+ * volume V) and a target x at 2 <= rho = |x - c|/d < 6 the potential is
+ * u = d * sum_{i,a} C_ia M_ia.  The tet's own multipole expansion about c
+ * truncated at |n| <= 2 (dipole and quadrupole, Sec. 2.2) gives Cq in closed
+ * form; a perceptron 16 -> H -> H -> H -> 12 (ReLU) maps the tet's corners
+ * seen from the target (as 16 scale-free numbers: the unit direction
+ * (x - c)/|x - c|, the corners about c in units of d, and 1/rho) to the
+ * residual y = 2048 (C - Cq) rho^4 / (V/d^3), and the 12 coefficients are
+ * contracted with the 4 nodal M exactly.  It is trained on
+ * the GPU (FP32, Adam; pairs drawn from the plan's own band pairs, the exact
+ * pair integrals as targets) and evaluated with BF16 weights and activations on
+ * matrix cores (FP32 accumulation; inputs as two BF16 parts; the quadrupole
+ * part and the contraction in FP64).  Evaluations use it for the band's
+ * pairs when the plan's surrogate mode is TFMM_SUR_MLP (tfmm_params,
+ * tfmm_plan_set_surrogate); the exact integral takes the closer pairs.
  */
 typedef struct {
     int32_t hidden; /* hidden width: 32, 64 or 128 */
@@ -434,7 +471,7 @@ int tfmm_surrogate_train(tfmm_plan plan, const tfmm_train_cfg *cfg, const char *
 int tfmm_surrogate_load(tfmm_plan plan, const char *path);
 
 /*
- * n training samples drawn as in training (seeded): X [n][12] inputs s,
+ * n training samples drawn as in training (seeded): X [n][16] inputs,
  * Y [n][12] targets y; host arrays.  For checking the targets against an
  * independent pair integral.  Errors: TFMM_EINVAL, TFMM_EDEVICE.
  */
@@ -451,7 +488,8 @@ int tfmm_surrogate_grad(int32_t hidden, const float *params, const float *X, con
 /*
  * u [n_targets] (device, written) = potential of the plan's near-field pairs
  * with 2 <= |x - c|/d < 6 only, for one field M (device [n_nodes][3]): by the
- * exact pair integral (use_surrogate = 0) or by the attached surrogate.
+ * exact pair integral (use_surrogate = 0) or by the attached surrogate.  The
+ * first call lists the band's pairs (synchronising).
  * Asynchronous on hip_stream.  Errors: TFMM_EINVAL (no surrogate attached,
  * NULL arguments), TFMM_EDEVICE.
  */

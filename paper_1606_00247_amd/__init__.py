@@ -17,7 +17,7 @@ __all__ = [
     "TetFMMError", "Plan", "tfmm_plan_create", "tfmm_evaluate", "tfmm_direct", "tfmm_evaluate_host",
     "tfmm_direct_host", "tfmm_plan_stats", "tfmm_plan_lists", "tfmm_plan_cells", "tfmm_plan_expansions",
     "tfmm_plan_destroy", "tfmm_last_error", "tfmm_simplex_rule", "tfmm_set_timing", "tfmm_kernel_times",
-    "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS", "tfmm_plan_set_m2l_precision", "M2L_FP64", "M2L_FP32", "M2L_BF16X3", "M2L_BF16X6",
+    "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS", "tfmm_plan_set_m2l_precision", "tfmm_plan_set_surrogate", "SUR_OFF", "SUR_MLP", "SUR_GAUSS", "SUR_QUAD", "M2L_FP64", "M2L_FP32", "M2L_BF16X3", "M2L_BF16X6",
     "tfmm_plan_autotune", "tfmm_plan_set_schedule", "tfmm_elementary", "ELEMENTARY", "tfmm_batch_create", "tfmm_batch_evaluate", "tfmm_batch_autotune", "tfmm_batch_plan",
     "tfmm_batch_destroy", "Batch", "tfmm_surrogate_param_count", "tfmm_surrogate_train", "tfmm_surrogate_load",
     "tfmm_surrogate_samples", "tfmm_surrogate_grad", "tfmm_band_potential", "tfmm_demag_energy", "tfmm_demag_energy_noalloc", "NOALLOC_MAX_TETS", "tfmm_demag_field_nodes",
@@ -33,6 +33,10 @@ M2L_FP64 = 0
 M2L_FP32 = 1
 M2L_BF16X3 = 2
 M2L_BF16X6 = 3
+SUR_OFF = 0
+SUR_MLP = 1
+SUR_GAUSS = 2
+SUR_QUAD = 3
 KERNEL_NAMES = ("p2m", "m2m", "m2l", "l2l", "l2p", "p2p")
 ERRORS = {-1: "EINVAL", -2: "EINDEX", -3: "EDEGEN", -4: "ENONFINITE", -5: "ENOMEM", -6: "EDEVICE", -7: "ENOTSUP"}
 
@@ -49,7 +53,7 @@ class _TrainCfg(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("p", C.c_int32), ("leaf_size", C.c_int32), ("theta", C.c_double), ("m2l_precision", C.c_int32),
-                ("device", C.c_int32)]
+                ("surrogate", C.c_int32), ("device", C.c_int32)]
 
 
 class _TuneResult(C.Structure):
@@ -62,7 +66,9 @@ class _Stats(C.Structure):
                                         "n_p2p", "n_p2p_pairs", "ncoef", "device_bytes")] + [("setup_seconds",
                                                                                                C.c_double)] + [
         ("near_nnz", C.c_int64), ("near_bytes", C.c_int64),
-        ("m2l_keys_per_item", C.c_int32), ("p2p_wide", C.c_int32)]
+        ("m2l_keys_per_item", C.c_int32), ("p2p_wide", C.c_int32),
+        ("p2p_node_evals", C.c_int64), ("p2p_edge_evals", C.c_int64), ("p2p_face_evals", C.c_int64),
+        ("n_band_pairs", C.c_int64), ("surrogate", C.c_int32), ("surrogate_hidden", C.c_int32)]
 
 
 class TetFMMError(RuntimeError):
@@ -96,6 +102,7 @@ def _load():
         "tfmm_plan_expansions": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
         "tfmm_plan_destroy": (C.c_int, [C.c_void_p]),
         "tfmm_plan_set_m2l_precision": (C.c_int, [C.c_void_p, C.c_int32]),
+        "tfmm_plan_set_surrogate": (C.c_int, [C.c_void_p, C.c_int32]),
         "tfmm_plan_store_near": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
         "tfmm_plan_create_points": (C.c_int, [_dp, C.c_int64, _dp, C.c_int64, C.c_void_p, C.POINTER(C.c_void_p)]),
         "tfmm_tune_accuracy": (C.c_int, [_dp, C.c_int64, _i32p, C.c_int64, C.c_void_p, _dp, C.c_double, C.c_int32,
@@ -171,7 +178,8 @@ class Plan:
             self._h = None
 
 
-def tfmm_plan_create(nodes, tets, targets=None, p=8, leaf_size=64, theta=0.5, m2l_precision=0, device=0):
+def tfmm_plan_create(nodes, tets, targets=None, p=8, leaf_size=64, theta=0.5, m2l_precision=0, device=0,
+                     surrogate=0):
     """Build the octree, lists and device data of a mesh (copies the host arrays)."""
     lib = _load()
     nodes = np.ascontiguousarray(nodes, dtype=np.float64)
@@ -184,7 +192,7 @@ def tfmm_plan_create(nodes, tets, targets=None, p=8, leaf_size=64, theta=0.5, m2
         if targets.ndim != 2 or targets.shape[1] != 3:
             raise ValueError("targets must be [n,3]")
         tp, nt = _ptr(targets, _dp), targets.shape[0]
-    prm = _Params(int(p), int(leaf_size), float(theta), int(m2l_precision), int(device))
+    prm = _Params(int(p), int(leaf_size), float(theta), int(m2l_precision), int(surrogate), int(device))
     h = C.c_void_p()
     _check(lib.tfmm_plan_create(_ptr(nodes, _dp), nodes.shape[0], _ptr(tets, _i32p), tets.shape[0], tp, nt,
                                 C.byref(prm), C.byref(h)))
@@ -192,7 +200,8 @@ def tfmm_plan_create(nodes, tets, targets=None, p=8, leaf_size=64, theta=0.5, m2
                 dict(p=int(p), leaf_size=int(leaf_size), theta=float(theta), m2l_precision=int(m2l_precision)))
 
 
-def tfmm_plan_create_points(points, targets=None, p=8, leaf_size=64, theta=0.5, m2l_precision=0, device=0):
+def tfmm_plan_create_points(points, targets=None, p=8, leaf_size=64, theta=0.5, m2l_precision=0, device=0,
+                            surrogate=0):
     """Plan for point dipoles at `points` [n, 3]; evaluations take the dipole
     moments as M [F, n, 3] (device) and give u at the targets (default: the
     points, each excluding its own dipole)."""
@@ -206,7 +215,7 @@ def tfmm_plan_create_points(points, targets=None, p=8, leaf_size=64, theta=0.5, 
         if targets.ndim != 2 or targets.shape[1] != 3:
             raise ValueError("targets must be [n,3]")
         tp, nt = _ptr(targets, _dp), targets.shape[0]
-    prm = _Params(int(p), int(leaf_size), float(theta), int(m2l_precision), int(device))
+    prm = _Params(int(p), int(leaf_size), float(theta), int(m2l_precision), int(surrogate), int(device))
     h = C.c_void_p()
     _check(lib.tfmm_plan_create_points(_ptr(points, _dp), points.shape[0], tp, nt, C.byref(prm), C.byref(h)))
     return Plan(h.value, int(device), points.shape[0], nt if targets is not None else points.shape[0],
@@ -327,7 +336,7 @@ class Batch:
             self._h = None
 
 
-def tfmm_batch_create(meshes, p=8, leaf_size=64, theta=0.5, m2l_precision=0, device=0):
+def tfmm_batch_create(meshes, p=8, leaf_size=64, theta=0.5, m2l_precision=0, device=0, surrogate=0):
     """meshes: sequence of (nodes [N_i, 3], tets [T_i, 4]) host arrays."""
     lib = _load()
     nodes = [np.ascontiguousarray(m[0], dtype=np.float64) for m in meshes]
@@ -337,7 +346,7 @@ def tfmm_batch_create(meshes, p=8, leaf_size=64, theta=0.5, m2l_precision=0, dev
     TP = (_i32p * n)(*[_ptr(a, _i32p) for a in tets])
     nn = np.array([a.shape[0] for a in nodes], dtype=np.int64)
     nt = np.array([a.shape[0] for a in tets], dtype=np.int64)
-    prm = _Params(int(p), int(leaf_size), float(theta), int(m2l_precision), int(device))
+    prm = _Params(int(p), int(leaf_size), float(theta), int(m2l_precision), int(surrogate), int(device))
     h = C.c_void_p()
     _check(lib.tfmm_batch_create(n, NP, _ptr(nn, _i64p), TP, _ptr(nt, _i64p), C.byref(prm), C.byref(h)))
     return Batch(h.value, int(device), list(zip(nn.tolist(), nt.tolist())),
@@ -454,8 +463,8 @@ def tfmm_surrogate_load(plan, path):
 
 
 def tfmm_surrogate_samples(plan, n, seed=7):
-    """n training samples: inputs X [n, 12] and targets Y [n, 12] (float32)."""
-    X = np.zeros((n, 12), dtype=np.float32)
+    """n training samples: inputs X [n, 16] and targets Y [n, 12] (float32)."""
+    X = np.zeros((n, 16), dtype=np.float32)
     Y = np.zeros((n, 12), dtype=np.float32)
     _check(_load().tfmm_surrogate_samples(plan.handle, int(seed), int(n), _ptr(X, _fp), _ptr(Y, _fp)))
     return X, Y
@@ -518,6 +527,13 @@ def tfmm_plan_expansions(plan, which):
     return out
 
 
+def tfmm_plan_set_surrogate(plan, mode):
+    """How the near-field pairs 2-6 tet diameters apart are evaluated: SUR_OFF
+    (exact), SUR_MLP (the attached network), SUR_GAUSS or SUR_QUAD (controls)."""
+    _check(_load().tfmm_plan_set_surrogate(plan.handle, int(mode)))
+    plan.params["surrogate"] = int(mode)
+
+
 def tfmm_plan_set_m2l_precision(plan, m2l_precision):
     """M2L arithmetic of an existing plan: M2L_FP64, M2L_FP32, M2L_BF16X3 or M2L_BF16X6."""
     _check(_load().tfmm_plan_set_m2l_precision(plan.handle, int(m2l_precision)))
@@ -542,7 +558,7 @@ def tfmm_tune_accuracy(nodes, tets, tol, M=None, leaf_size=64, m2l_precision=M2L
     pl = np.ascontiguousarray(p_list, dtype=np.int32)
     tl = np.ascontiguousarray(theta_list, dtype=np.float64)
     table = np.zeros((pl.size * tl.size, 4))
-    prm = _Params(8, int(leaf_size), 0.5, int(m2l_precision), int(device))
+    prm = _Params(8, int(leaf_size), 0.5, int(m2l_precision), SUR_OFF, int(device))
     res = _TuneResult()
     if tets is None:
         _check(_load().tfmm_tune_accuracy_points(_ptr(nodes, _dp), nodes.shape[0], C.byref(prm), _ptr(M, _dp),

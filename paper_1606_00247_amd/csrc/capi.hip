@@ -231,6 +231,15 @@ void upload_plan(DevicePlan &dp)
         dp.n_p2p_idx = (int64_t)idx.size();
         dp.p2p_blk = dev_upload(blk, B);
         dp.p2p_idx = dev_upload(idx, B);
+        // (target, entity) evaluations of the one-field near field per evaluation
+        for (size_t k = 0; k + 3 < tp.blk.size(); k += 4) {
+            const int64_t nt = (int64_t)tp.blk[k + 3] - tp.blk[k + 2];
+            for (int32_t ch = tp.blk[k]; ch < tp.blk[k + 1]; ++ch) {
+                dp.topo_evals[0] += nt * tp.ch_i[8 * (size_t)ch + 3];
+                dp.topo_evals[1] += nt * tp.ch_i[8 * (size_t)ch + 5];
+                dp.topo_evals[2] += nt * tp.ch_i[8 * (size_t)ch + 7];
+            }
+        }
         dp.n_topo_ch = (int32_t)(tp.ch_i.size() / 8);
         dp.n_topo_edges = (int64_t)tp.ed_il.size();
         dp.n_topo_faces = (int64_t)(tp.fc_n.size() / 3);
@@ -289,7 +298,7 @@ void free_plan(DevicePlan &dp)
     dp.event_pool.clear();
     void *ptrs[] = {dp.tet_xyz, dp.tet_node, dp.tet_perm, dp.tgt_xyz, dp.tgt_perm, dp.tgt_leaf, dp.cell_c, dp.cell_i,
                     dp.p2m_cells, dp.m2m_cells, dp.l2l_cells, dp.p2p_blk, dp.p2p_idx, dp.quad, dp.far_rule, dp.node_lump, dp.tet_mom, dp.Q,
-                    dp.L, dp.Qt, dp.Qtf, dp.m2l_keys, dp.m2l_D, dp.m2l_Df, dp.sur_w, dp.sur_wb, dp.topo_blk,
+                    dp.L, dp.Qt, dp.Qtf, dp.m2l_keys, dp.m2l_D, dp.m2l_Df, dp.sur_w, dp.sur_wb, dp.band_pairs, dp.band_rule, dp.topo_blk,
                     dp.topo_ch_i, dp.topo_ch_c, dp.topo_w, dp.topo_ab, dp.topo_il, dp.topo_pqr, dp.topo_n, dp.topo_a2,
                     dp.topo_inc, dp.topo_A, dp.topo_B, dp.near_off, dp.near_nc, dp.near_cols, dp.near_val, dp.near_items};
     for (void *p : ptrs)
@@ -327,6 +336,8 @@ static int plan_create(const double *nodes, int64_t n_nodes, const int32_t *tets
 {
     if (out) *out = nullptr;
     if (!prm || !out) return set_error(TFMM_EINVAL, "prm and out must not be NULL");
+    if (prm->surrogate < TFMM_SUR_OFF || prm->surrogate > TFMM_SUR_QUAD)
+        return set_error(TFMM_EINVAL, "surrogate must be one of TFMM_SUR_*");
     if (prm->m2l_precision < TFMM_M2L_FP64 || prm->m2l_precision > TFMM_M2L_BF16X6)
         return set_error(TFMM_ENOTSUP, "unsupported m2l_precision");
     return guarded([&]() -> int {
@@ -336,6 +347,7 @@ static int plan_create(const double *nodes, int64_t n_nodes, const int32_t *tets
                               prm->theta, points);
         P->dp.ncoef = (prm->p + 1) * (prm->p + 2) * (prm->p + 3) / 6;
         P->dp.m2l_precision = prm->m2l_precision;
+        P->dp.sur_mode = prm->surrogate;
         if (prm->device >= 0) {
             int ndev = 0;
             if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
@@ -458,6 +470,12 @@ int tfmm_plan_stats(tfmm_plan plan, tfmm_stats *out)
     out->near_bytes = plan->dp.near_bytes;
     out->m2l_keys_per_item = plan->dp.m2l_max_ent;
     out->p2p_wide = plan->dp.p2p_wide ? 1 : 0;
+    out->p2p_node_evals = plan->dp.topo_evals[0];
+    out->p2p_edge_evals = plan->dp.topo_evals[1];
+    out->p2p_face_evals = plan->dp.topo_evals[2];
+    out->n_band_pairs = plan->dp.n_band_pairs;
+    out->surrogate = plan->dp.sur_mode;
+    out->surrogate_hidden = plan->dp.sur_hidden;
     return TFMM_OK;
 }
 
@@ -548,6 +566,15 @@ int tfmm_plan_expansions(tfmm_plan plan, int32_t which, double *out)
         tfmm::hip_check(hipMemcpy(out, src, per * sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy expansions");
         return TFMM_OK;
     });
+}
+
+int tfmm_plan_set_surrogate(tfmm_plan plan, int32_t mode)
+{
+    if (!plan) return set_error(TFMM_EINVAL, "NULL plan");
+    if (mode < TFMM_SUR_OFF || mode > TFMM_SUR_QUAD) return set_error(TFMM_EINVAL, "mode must be one of TFMM_SUR_*");
+    plan->dp.sur_mode = mode;
+    ++plan->dp.schedule_gen;
+    return TFMM_OK;
 }
 
 int tfmm_plan_set_m2l_precision(tfmm_plan plan, int32_t m2l_precision)
@@ -767,6 +794,7 @@ static int tune_accuracy(const double *nodes, int64_t n_nodes, const int32_t *te
         tfmm::hip_check(hipMemcpy(dM, M, sizeof(double) * 3 * (size_t)n_nodes, hipMemcpyHostToDevice), "hipMemcpy M");
         // reference: FP64 direct sum at the sampled nodes
         tfmm_params rp = *base;
+        rp.surrogate = TFMM_SUR_OFF;
         rp.p = 2;
         rp.theta = 0.5;
         int r = create(xs.data(), ns, &rp, &ref);
@@ -792,6 +820,7 @@ static int tune_accuracy(const double *nodes, int64_t n_nodes, const int32_t *te
             std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return theta_list[a] > theta_list[b]; });
             for (int32_t it : order) {
                 tfmm_params cp = *base;
+                cp.surrogate = TFMM_SUR_OFF;  // the search is over the exact method's knobs
                 cp.p = p_list[ip];
                 cp.theta = theta_list[it];
                 if ((r = create(nullptr, 0, &cp, &cand))) return r;

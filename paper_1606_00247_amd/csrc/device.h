@@ -103,6 +103,7 @@ struct DevicePlan {
     double *topo_A = nullptr, *topo_B = nullptr;
     int32_t n_topo_ch = 0;
     int64_t n_topo_edges = 0, n_topo_faces = 0;
+    int64_t topo_evals[3] = {0, 0, 0};  // (target, node / edge / face) evaluations per one-field evaluation
     bool p2p_topo = true;  // single-field near field over shared entities
     // stored near-field operator (optional, built by store_near): per cell
     // [C][2] column and value offsets (-1: no block), padded column counts,

@@ -1203,15 +1203,14 @@ __global__ __launch_bounds__(256) void k_l2p(const double *__restrict__ tgt_xyz,
     atomicAdd(&u[(int64_t)f * N + tgt_perm[i]], s);  // the near field is added concurrently
 }
 
-constexpr int kP2PTets = 64;  // tets per block (direct sum)
-
-// One workgroup per block of <= 64 tets of a source leaf (direct sum: 64
-// consecutive tets, all targets): one wavefront for one or two fields, four
-// for more (they share the staged field coefficients).  Tets are staged in
-// LDS BT at a time, thread l preparing field l % FCH of tet l / FCH (geometry
-// 240 B + 208 B per field per tet; 8 tets for 32 fields); every thread then takes targets
+// One workgroup per P2P block (<= 64 tets of a source leaf and the targets of
+// its near target leaves): one wavefront for one or two fields, four for more
+// (they share the staged field coefficients).  Tets are staged in LDS BT at a
+// time, thread l preparing field l % FCH of tet l / FCH (geometry 240 B + 208
+// B per field per tet; 8 tets for 32 fields); every thread then takes targets
 // ib + l, ib + l + NT, ... over the staged tets and adds its potentials
-// atomically.
+// atomically.  With band_skip the pairs of the surrogate's distance band
+// (in_band) are left out: they are evaluated from the band pair list.
 // WIDE: four wavefronts also for one or two fields (a plan's tuning choice).
 __host__ __device__ constexpr int p2p_threads(int FCH, bool wide) { return FCH <= 2 && !wide ? 64 : 256; }
 __host__ __device__ constexpr int p2p_stage(int FCH, bool wide)
@@ -1220,7 +1219,7 @@ __host__ __device__ constexpr int p2p_stage(int FCH, bool wide)
 }
 
 template <int FCH, bool WIDE>
-__global__ __launch_bounds__(p2p_threads(FCH, WIDE), 2) void k_p2p(const int32_t *__restrict__ blk, int nblk, int direct_tets, int64_t T,
+__global__ __launch_bounds__(p2p_threads(FCH, WIDE), 2) void k_p2p(const int32_t *__restrict__ blk, int nblk, int band_skip, int64_t T,
                                                      const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node,
                                                      const int32_t *__restrict__ idx, const double *__restrict__ tgt_xyz,
                                                      const int32_t *__restrict__ tgt_perm, int64_t N,
@@ -1231,39 +1230,41 @@ __global__ __launch_bounds__(p2p_threads(FCH, WIDE), 2) void k_p2p(const int32_t
     static_assert(BT * FCH <= NT, "one thread per staged tet and field");
     __shared__ TetGeom s_g[BT];
     __shared__ TetField s_f[BT][FCH];
+    __shared__ double s_bc[BT][4];  // band test: centroid, 1 / diam^2
     const int b = xcd_item(nblk);
     if (b < 0) return;
-    int tb, te, ib, ie;
-    if (direct_tets) {  // direct sum: consecutive tets, all targets
-        tb = b * kP2PTets;
-        te = min<int64_t>(T, tb + kP2PTets);
-        ib = 0;
-        ie = (int)N;
-    } else {
-        tb = blk[4 * b];
-        te = blk[4 * b + 1];
-        ib = blk[4 * b + 2];
-        ie = blk[4 * b + 3];
-    }
+    const int tb = blk[4 * b], te = blk[4 * b + 1], ib = blk[4 * b + 2], ie = blk[4 * b + 3];
     const int lane = threadIdx.x;
     for (int sb = tb; sb < te; sb += BT) {
         const int nt = min(BT, te - sb);
         __syncthreads();
         {
             const int t = lane / FCH, f = lane % FCH;
-            if (t < nt)
+            if (t < nt) {
                 tet_prepare(tet_xyz, tet_node, T, sb + t, M + (int64_t)(f0 + f) * n_nodes * 3, f == 0 ? &s_g[t] : nullptr,
                             s_f[t][f]);
+                if (band_skip && f == 0) {
+                    double v[4][3];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) v[q][k] = tet_xyz[(int64_t)(3 * q + k) * T + sb + t];
+                    band_geom(v, s_bc[t], s_bc[t][3]);
+                }
+            }
         }
         __syncthreads();
         for (int i = ib + lane; i < ie; i += NT) {
-            const int s = direct_tets ? i : idx[i];
+            const int s = idx[i];
             const double x[3] = {tgt_xyz[s], tgt_xyz[N + s], tgt_xyz[2 * N + s]};
             double acc[FCH];
 #pragma unroll
             for (int f = 0; f < FCH; ++f) acc[f] = 0.0;
 #pragma unroll 1
-            for (int t = 0; t < nt; ++t) pair_accumulate<FCH>(x, s_g[t], s_f[t], acc);
+            for (int t = 0; t < nt; ++t) {
+                if (band_skip && in_band(x, s_bc[t], s_bc[t][3])) continue;
+                pair_accumulate<FCH>(x, s_g[t], s_f[t], acc);
+            }
             const int64_t o = tgt_perm[s];
 #pragma unroll
             for (int f = 0; f < FCH; ++f) atomicAdd(&u[(int64_t)(f0 + f) * N + o], acc[f] * kInv4Pi);
@@ -1421,6 +1422,7 @@ __global__ __launch_bounds__(256, 2) void k_direct(int nblk, int64_t T, const do
 // LDS, every thread takes targets ib + l, ib + l + 256, ...
 // ---------------------------------------------------------------------------
 constexpr int kPtStage = 128, kPtThreads = 256;
+constexpr int kP2PTets = 64;  // sources per block of the dipole direct sum
 
 template <int FCH>
 __global__ __launch_bounds__(kPtThreads) void k_p2p_points(const int32_t *__restrict__ blk, int nblk, int direct_src,
@@ -2061,27 +2063,27 @@ void fill(double *a, int64_t n, double v, hipStream_t st)
 }
 
 template <int FCH, bool WIDE>
-void launch_p2p_w(DevicePlan &dp, bool direct, int f0, const double *M, double *u, hipStream_t st)
+void launch_p2p_w(DevicePlan &dp, bool band_skip, int f0, const double *M, double *u, hipStream_t st)
 {
     const HostPlan &hp = dp.hp;
-    unsigned nblk = direct ? (unsigned)((hp.n_tets + kP2PTets - 1) / kP2PTets) : (unsigned)dp.n_p2p_blk;
+    const unsigned nblk = (unsigned)dp.n_p2p_blk;
     if (nblk == 0) return;
     k_p2p<FCH, WIDE><<<dim3(xcd_grid((int)nblk)), dim3(p2p_threads(FCH, WIDE)), 0, st>>>(
-        dp.p2p_blk, (int)nblk, direct ? 1 : 0, hp.n_tets, dp.tet_xyz, dp.tet_node, dp.p2p_idx, dp.tgt_xyz, dp.tgt_perm,
-        hp.n_targets, M, hp.n_nodes, f0, u);
+        dp.p2p_blk, (int)nblk, band_skip ? 1 : 0, hp.n_tets, dp.tet_xyz, dp.tet_node, dp.p2p_idx, dp.tgt_xyz,
+        dp.tgt_perm, hp.n_targets, M, hp.n_nodes, f0, u);
     hip_check(hipGetLastError(), "k_p2p launch");
 }
 
 template <int FCH>
-void launch_p2p(DevicePlan &dp, bool direct, int f0, const double *M, double *u, hipStream_t st)
+void launch_p2p(DevicePlan &dp, bool band_skip, int f0, const double *M, double *u, hipStream_t st)
 {
     if constexpr (FCH <= 2) {
         if (dp.p2p_wide) {
-            launch_p2p_w<FCH, true>(dp, direct, f0, M, u, st);
+            launch_p2p_w<FCH, true>(dp, band_skip, f0, M, u, st);
             return;
         }
     }
-    launch_p2p_w<FCH, false>(dp, direct, f0, M, u, st);
+    launch_p2p_w<FCH, false>(dp, band_skip, f0, M, u, st);
 }
 
 void run_p2p_points(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u, hipStream_t st)
@@ -2113,13 +2115,17 @@ void run_p2p_points(DevicePlan &dp, bool direct, const double *M, int32_t F, dou
     }
 }
 
-void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u, hipStream_t st)
+// Near field by the pair integrals: point dipoles (or, direct, the dipole
+// sum); one field of tets over the shared mesh entities; otherwise the
+// per-tet kernel, without the band's pairs when band_skip.
+void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u, hipStream_t st, bool band_skip = false)
 {
     if (dp.hp.points) {
         run_p2p_points(dp, direct, M, F, u, st);
         return;
     }
-    if (!direct && F == 1 && dp.p2p_topo && dp.n_topo_ch > 0) {
+    if (direct) throw DeviceError{"the tet direct sum runs in k_direct"};
+    if (!band_skip && F == 1 && dp.p2p_topo && dp.n_topo_ch > 0) {
         const HostPlan &hp = dp.hp;
         k_topo_coef<<<dim3(dp.n_topo_ch), dim3(64), 0, st>>>(dp.topo_ch_i, dp.topo_ch_c, dp.n_topo_ch, dp.topo_inc,
                                                              dp.tet_xyz, dp.tet_node, hp.n_tets, M, dp.topo_A,
@@ -2141,22 +2147,22 @@ void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u,
     while (f < F) {
         const int left = F - f;
         if (left >= 32) {
-            launch_p2p<32>(dp, direct, f, M, u, st);
+            launch_p2p<32>(dp, band_skip, f, M, u, st);
             f += 32;
         } else if (left >= 16) {
-            launch_p2p<16>(dp, direct, f, M, u, st);
+            launch_p2p<16>(dp, band_skip, f, M, u, st);
             f += 16;
         } else if (left >= 8) {
-            launch_p2p<8>(dp, direct, f, M, u, st);
+            launch_p2p<8>(dp, band_skip, f, M, u, st);
             f += 8;
         } else if (left >= 4) {
-            launch_p2p<4>(dp, direct, f, M, u, st);
+            launch_p2p<4>(dp, band_skip, f, M, u, st);
             f += 4;
         } else if (left >= 2) {
-            launch_p2p<2>(dp, direct, f, M, u, st);
+            launch_p2p<2>(dp, band_skip, f, M, u, st);
             f += 2;
         } else {
-            launch_p2p<1>(dp, direct, f, M, u, st);
+            launch_p2p<1>(dp, band_skip, f, M, u, st);
             f += 1;
         }
     }
@@ -2187,14 +2193,19 @@ void run_near_stored(DevicePlan &dp, const double *M, int32_t F, double *u, hipS
     hip_check(hipGetLastError(), "k_near_apply launch");
 }
 
-// Near field of an evaluation: the stored operator when the plan holds one,
-// else the pair integrals.
+// Near field of an evaluation: the stored operator when the plan holds one;
+// with the surrogate switched on, the exact integrals outside the band and
+// the band's pairs by the network (or a control); else the pair integrals.
 void run_near(DevicePlan &dp, const double *M, int32_t F, double *u, hipStream_t st)
 {
-    if (dp.near_stored)
+    if (dp.near_stored) {
         run_near_stored(dp, M, F, u, st);
-    else
+    } else if (dp.sur_mode != TFMM_SUR_OFF && !dp.hp.points) {
+        run_p2p(dp, false, M, F, u, st, true);
+        run_band_pairs(dp, dp.sur_mode, M, F, u, st);
+    } else {
         run_p2p(dp, false, M, F, u, st);
+    }
 }
 
 template <typename T, int P>
@@ -2478,6 +2489,11 @@ void ensure_expansions(DevicePlan &dp, int32_t F)
 void prepare_evaluate(DevicePlan &dp, int32_t F)
 {
     const int64_t C = (int64_t)dp.hp.cells.size();
+    if (dp.sur_mode != TFMM_SUR_OFF && !dp.hp.points && !dp.near_stored) {
+        if (dp.sur_mode == TFMM_SUR_MLP && !dp.sur_wb)
+            throw PlanError{TFMM_EINVAL, "the surrogate is switched on but no network is attached"};
+        build_band_list(dp, nullptr);
+    }
     if (!dp.side) {
         hip_check(hipStreamCreateWithFlags(&dp.side, hipStreamNonBlocking), "hipStreamCreate");
         hip_check(hipEventCreateWithFlags(&dp.ev_fork, hipEventDisableTiming), "hipEventCreate");

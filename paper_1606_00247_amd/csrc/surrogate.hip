@@ -4,16 +4,27 @@
 // a target x with 2 <= rho = |x - c| / diam < 6 the potential is linear in the
 // nodal magnetisation and homogeneous of degree one in length:
 //   u_T(x) = diam * sum_{i,a} C_ia M_ia,
-// C a function of the corners seen from the target.  A multilayer perceptron
-// maps the 12 inputs s_i = (v_i - x) / |x - c| (scale free, O(1)) to
-// y = 16 pi C rho^2 / Vh (Vh = V / diam^3; the dipole term of y is the unit
-// vector from c to x, so y is O(1)); the 12 outputs are contracted with the
-// 4 nodal M exactly.  Layers 12 -> H -> H -> H -> 12
-// with ReLU.  Training pairs are drawn from the plan's tets with uniform
-// directions and rho uniform in [2, 6); their targets come from the exact
-// pair integral (unit nodal fields).  Training runs in FP32 (Adam);
-// inference uses BF16 weights and activations on matrix cores with FP32
-// accumulation.
+// C a function of the corners seen from the target.  The tet's own multipole
+// expansion about c truncated at |n| <= 2 (the dipole and quadrupole terms of
+// the Taylor expansion of Sec. 2.2) gives most of it in closed form,
+//   4 pi diam Cq_ia = (V / R^3) [R_a / 4 + (3 R_a (R . w_i) / R^2 - w_ia) / 20],
+// R = x - c, w_i = v_i - c; a multilayer perceptron predicts the rest: it maps
+// the tet's corners seen from the target, as 16 scale-free O(1) numbers (the
+// unit direction R / |R|, w_i / diam and 1 / rho), to
+// y = kYScale (C - Cq) rho^4 / Vh (Vh = V / diam^3; the residual falls like
+// rho^-4, so y is O(1) over the band), and the 12 coefficients are contracted
+// with the 4 nodal M exactly.  Layers 16 -> H -> H -> H -> 12 with ReLU.
+// Training pairs are drawn from the plan's own band pairs (the pairs the
+// evaluation hands to the network); their targets come from the exact pair
+// integral (unit nodal fields).  Training runs in FP32 (Adam); inference uses BF16
+// weights and activations on matrix cores with FP32 accumulation, the
+// quadrupole part and the contraction in FP64.
+//
+// In an evaluation with the surrogate on, the near-field pairs of the band
+// are taken out of the exact near-field kernel and evaluated from a list of
+// band pairs (built once per plan, ordered by target within each P2P block)
+// by the network, or by one of two controls: the quadrupole part alone (the
+// network's base) or a 27-point Gauss-Jacobi rule (degree 5) of the integrand.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,9 +41,8 @@ namespace tfmm {
 
 namespace {
 
-constexpr double kBandLo = 2.0, kBandHi = 6.0;
-constexpr int kIn = 12, kOut = 12;
-constexpr double kYScale = 16.0 * 3.141592653589793;  // y = kYScale C rho^2 / Vh
+constexpr int kIn = 16, kOut = 12;
+constexpr double kYScale = 2048.0;  // y = kYScale (C - Cq) rho^4 / Vh
 
 // splitmix64 (Steele, Lea and Flood 2014): the counter-based generator of the
 // training samples.
@@ -88,26 +98,91 @@ __device__ inline void tet_scales(const double v[4][3], double c[3], double &dia
     vh = fabs(det) / 6.0 / (l2 * diam);
 }
 
-// One training sample per thread: inputs X [n][12], targets Y [n][12].
-__global__ void k_sur_gen(const double *__restrict__ tet_xyz, int64_t T, uint64_t seed, int n, float *__restrict__ X,
-                          float *__restrict__ Y)
+// 4 pi diam Cq_j of the 12 unit fields j = 3 i + a (component a at corner i):
+// the tet's multipole expansion about its centroid c truncated at |n| <= 2,
+//   q_{3i+a} = (V / R^3) [R_a / 4 + (3 R_a (R . w_i) / R^2 - w_ia) / 20],
+// R = x - c, w_i = v_i - c (the moments int_T lambda_i = V/4 and
+// int_T lambda_i (y - c) = V w_i / 20 of the barycentric field lambda_i e_a).
+__device__ inline void quad_coeffs(const double x[3], const double v[4][3], const double c[3], double q[12])
+{
+    const double R[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+    const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+    const double ir = rsqrt_nr(r2);
+    const double ir2 = ir * ir;
+    const double e1[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
+    const double e2[3] = {v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2]};
+    const double e3[3] = {v[3][0] - v[0][0], v[3][1] - v[0][1], v[3][2] - v[0][2]};
+    const double V = fabs(e1[0] * (e2[1] * e3[2] - e2[2] * e3[1]) - e1[1] * (e2[0] * e3[2] - e2[2] * e3[0]) +
+                          e1[2] * (e2[0] * e3[1] - e2[1] * e3[0])) / 6.0;
+    const double f = V * ir * ir2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double w[3] = {v[i][0] - c[0], v[i][1] - c[1], v[i][2] - c[2]};
+        const double rw = 3.0 * (R[0] * w[0] + R[1] * w[1] + R[2] * w[2]) * ir2;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) q[3 * i + a] = f * (0.25 * R[a] + 0.05 * (R[a] * rw - w[a]));
+    }
+}
+
+// The network's 16 inputs for target x and a tet (corners v, centroid c,
+// longest edge diam), all O(1) and scale free: the unit direction
+// R / |R| (R = x - c), the corners about the centroid in units of the
+// diameter (v_i - c) / diam, and 1 / rho = diam / |R|.
+__device__ inline void sur_features(const double x[3], const double v[4][3], const double c[3], double diam,
+                                    double f[kIn])
+{
+    const double R[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+    const double ir = rsqrt_nr(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+    const double id = 1.0 / diam;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[k] = R[k] * ir;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) f[3 + 3 * i + k] = (v[i][k] - c[k]) * id;
+    f[15] = diam * ir;
+}
+
+// One training sample per thread: inputs X [n][16], targets Y [n][12].  The
+// pair is drawn from the plan's list of band pairs (the near-field pairs the
+// evaluation hands to the network) when given, else a tet of the plan with a
+// target at a uniform direction and rho uniform in [2, 6).
+__global__ void k_sur_gen(const double *__restrict__ tet_xyz, int64_t T, const int32_t *__restrict__ pairs,
+                          int64_t npairs, const double *__restrict__ tgt_xyz, int64_t N, uint64_t seed, int n,
+                          float *__restrict__ X, float *__restrict__ Y)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const uint64_t h0 = splitmix64(seed ^ splitmix64((uint64_t)s));
     const uint64_t h1 = splitmix64(h0), h2 = splitmix64(h1), h3 = splitmix64(h2);
-    const int64_t t = (int64_t)(h0 % (uint64_t)T);
+    int64_t t;
+    double x[3];
     TetGeom G;
+    double c[3], diam, vh;
+    if (pairs && npairs > 0) {
+        const int64_t k = (int64_t)(h0 % (uint64_t)npairs);
+        const int64_t tg = pairs[2 * k];
+        t = pairs[2 * k + 1];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) x[d] = tgt_xyz[d * N + tg];
+    } else {
+        t = (int64_t)(h0 % (uint64_t)T);
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int k = 0; k < 3; ++k) G.v[q][k] = tet_xyz[(int64_t)(3 * q + k) * T + t];
-    double c[3], diam, vh;
     tet_scales(G.v, c, diam, vh);
-    const double zc = 2.0 * u01(h1) - 1.0, ph = 6.283185307179586 * u01(h2);
-    const double sr = sqrt(fmax(0.0, 1.0 - zc * zc));
-    const double rho = kBandLo + (kBandHi - kBandLo) * u01(h3);
-    const double x[3] = {c[0] + rho * diam * sr * cos(ph), c[1] + rho * diam * sr * sin(ph), c[2] + rho * diam * zc};
+    if (!(pairs && npairs > 0)) {
+        const double zc = 2.0 * u01(h1) - 1.0, ph = 6.283185307179586 * u01(h2);
+        const double sr = sqrt(fmax(0.0, 1.0 - zc * zc));
+        const double rho = kBandLo + (kBandHi - kBandLo) * u01(h3);
+        x[0] = c[0] + rho * diam * sr * cos(ph);
+        x[1] = c[1] + rho * diam * sr * sin(ph);
+        x[2] = c[2] + rho * diam * zc;
+    }
+    const double dist = sqrt((x[0] - c[0]) * (x[0] - c[0]) + (x[1] - c[1]) * (x[1] - c[1]) + (x[2] - c[2]) * (x[2] - c[2]));
+    const double rho = dist / diam;
     double gl[4][3], eh[6][3];
     tet_geometry(G, gl, eh);
     TetField fld[kOut];
@@ -121,13 +196,16 @@ __global__ void k_sur_gen(const double *__restrict__ tet_xyz, int64_t T, uint64_
 #pragma unroll
     for (int j = 0; j < kOut; ++j) acc[j] = 0.0;
     pair_accumulate<kOut>(x, G, fld, acc);
-    const double scale = kYScale * kInv4Pi / diam * rho * rho / vh;
-    const double dist = rho * diam;
+    double q[kOut];
+    quad_coeffs(x, G.v, c, q);
+    const double rho2 = rho * rho;
+    const double scale = kYScale * kInv4Pi / diam * rho2 * rho2 / vh;
+    double f[kIn];
+    sur_features(x, G.v, c, diam, f);
 #pragma unroll
-    for (int j = 0; j < kOut; ++j) {
-        X[(int64_t)s * kIn + j] = (float)((G.v[j / 3][j % 3] - x[j % 3]) / dist);
-        Y[(int64_t)s * kOut + j] = (float)(acc[j] * scale);
-    }
+    for (int j = 0; j < kIn; ++j) X[(int64_t)s * kIn + j] = (float)f[j];
+#pragma unroll
+    for (int j = 0; j < kOut; ++j) Y[(int64_t)s * kOut + j] = (float)((acc[j] - q[j]) * scale);
 }
 
 // Z [B][N] = A [B][K] W [K][N] + b; out = relu(Z) (relu) or Z.
@@ -226,12 +304,15 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
 }
 
-__global__ void k_f32_to_bf16_t(const float *__restrict__ W, int K, int N, int KP, int NP, __bf16 *__restrict__ out)
+__global__ void k_f32_to_bf16_t(const float *__restrict__ W, int K, int N, int KP, int NP, int dup,
+                                __bf16 *__restrict__ out)
 {
-    // out [NP][KP] = W^T, zero padded
+    // out [NP][KP] = W^T, zero padded; with dup the K rows are repeated once
+    // (columns K .. 2K - 1 take the weights of the low parts of the inputs)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NP * KP) return;
-    const int n = i / KP, k = i % KP;
+    const int n = i / KP, k0 = i % KP;
+    const int k = (dup && k0 >= K && k0 < 2 * K) ? k0 - K : k0;
     out[i] = (__bf16)((n < N && k < K) ? W[(int64_t)k * N + n] : 0.f);
 }
 
@@ -293,26 +374,121 @@ void forward_backward(const Layout &L, const float *P, Work &w, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-// Band potential over the near-field pairs of a plan (one field): pairs with
-// 2 <= rho < 6 only, by the exact integral (SUR = false) or by the network
-// (SUR = true).  One wavefront per P2P block; tets staged 16 at a time.
+// Band pairs: the (target, tet) pairs of the near field with
+// 2 <= |x - c| / diam < 6 (in_band), listed once per plan per P2P block (the
+// block's tets x its target list), target-major, so that the pairs of a
+// wavefront come in runs of one target.  k_band_count counts them per block;
+// k_band_fill writes them at the block's offset as (sorted target index, tet).
 // ---------------------------------------------------------------------------
-constexpr int kBandStage = 16;
+constexpr int kBandThreads = 256;
+constexpr int kBandMaxTets = 64;  // tets per P2P block
 
-__global__ void k_zero(double *__restrict__ a, int64_t n)
+struct BandTetG {
+    double c[3];
+    double id2;
+};
+
+__device__ inline int stage_band_tets(const int32_t *__restrict__ blk, int b, int64_t T,
+                                      const double *__restrict__ tet_xyz, BandTetG *s_b, int &ib, int &ie, int &tb)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        a[i] = 0.0;
+    tb = blk[4 * b];
+    const int te = blk[4 * b + 1];
+    ib = blk[4 * b + 2];
+    ie = blk[4 * b + 3];
+    const int nt = min(te - tb, kBandMaxTets);
+    if ((int)threadIdx.x < nt) {
+        double v[4][3];
+        const int64_t t = tb + threadIdx.x;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v[q][k] = tet_xyz[(int64_t)(3 * q + k) * T + t];
+        band_geom(v, s_b[threadIdx.x].c, s_b[threadIdx.x].id2);
+    }
+    return nt;
 }
+
+__global__ __launch_bounds__(kBandThreads) void k_band_count(const int32_t *__restrict__ blk, int nblk, int64_t T,
+                                                            const double *__restrict__ tet_xyz,
+                                                            const int32_t *__restrict__ idx,
+                                                            const double *__restrict__ tgt_xyz, int64_t N,
+                                                            int64_t *__restrict__ cnt)
+{
+    __shared__ BandTetG s_b[kBandMaxTets];
+    __shared__ int64_t s_n[kBandThreads / 64];
+    const int b = blockIdx.x;
+    if (b >= nblk) return;
+    int ib, ie, tb;
+    const int nt = stage_band_tets(blk, b, T, tet_xyz, s_b, ib, ie, tb);
+    __syncthreads();
+    int64_t n = 0;
+    for (int i = ib + threadIdx.x; i < ie; i += kBandThreads) {
+        const int s = idx[i];
+        const double x[3] = {tgt_xyz[s], tgt_xyz[N + s], tgt_xyz[2 * N + s]};
+        for (int t = 0; t < nt; ++t) n += in_band(x, s_b[t].c, s_b[t].id2) ? 1 : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_down(n, o);
+    if ((threadIdx.x & 63) == 0) s_n[threadIdx.x >> 6] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t tot = 0;
+        for (int w = 0; w < kBandThreads / 64; ++w) tot += s_n[w];
+        cnt[b] = tot;
+    }
+}
+
+__global__ __launch_bounds__(kBandThreads) void k_band_fill(const int32_t *__restrict__ blk, int nblk, int64_t T,
+                                                           const double *__restrict__ tet_xyz,
+                                                           const int32_t *__restrict__ idx,
+                                                           const double *__restrict__ tgt_xyz, int64_t N,
+                                                           const int64_t *__restrict__ off,
+                                                           int32_t *__restrict__ pairs)
+{
+    __shared__ BandTetG s_b[kBandMaxTets];
+    __shared__ int s_scan[kBandThreads];
+    const int b = blockIdx.x;
+    if (b >= nblk) return;
+    int ib, ie, tb;
+    const int nt = stage_band_tets(blk, b, T, tet_xyz, s_b, ib, ie, tb);
+    __syncthreads();
+    int64_t base = off[b];
+    for (int i0 = ib; i0 < ie; i0 += kBandThreads) {
+        const int i = i0 + threadIdx.x;
+        int s = 0, n = 0;
+        double x[3] = {0.0, 0.0, 0.0};
+        if (i < ie) {
+            s = idx[i];
+            x[0] = tgt_xyz[s];
+            x[1] = tgt_xyz[N + s];
+            x[2] = tgt_xyz[2 * N + s];
+            for (int t = 0; t < nt; ++t) n += in_band(x, s_b[t].c, s_b[t].id2) ? 1 : 0;
+        }
+        // inclusive scan of n over the block (Hillis-Steele)
+        s_scan[threadIdx.x] = n;
+        __syncthreads();
+        for (int o = 1; o < kBandThreads; o <<= 1) {
+            const int add = (int)threadIdx.x >= o ? s_scan[threadIdx.x - o] : 0;
+            __syncthreads();
+            s_scan[threadIdx.x] += add;
+            __syncthreads();
+        }
+        const int incl = s_scan[threadIdx.x], total = s_scan[kBandThreads - 1];
+        if (i < ie && n > 0) {
+            int64_t k = base + incl - n;
+            for (int t = 0; t < nt; ++t)
+                if (in_band(x, s_b[t].c, s_b[t].id2)) {
+                    pairs[2 * k] = s;
+                    pairs[2 * k + 1] = tb + t;
+                    ++k;
+                }
+        }
+        base += total;
+        __syncthreads();
+    }
+}
+
 using bf16x8 = __bf16 __attribute__((ext_vector_type(8)));
 using f32x4 = float __attribute__((ext_vector_type(4)));
-
-struct BandTet {
-    double v[4][3];
-    double m[4][3];
-    double c[3];
-    double diam, vh;
-};
 
 // One dense layer of the network for the 64 rows (pairs) of a wavefront:
 // out [64][NP] = act(in [64][KP] W + b), W as [NP][KP] BF16 (transposed,
@@ -323,7 +499,7 @@ __device__ __forceinline__ void mlp_layer(const __bf16 *in, const __bf16 *__rest
 {
 #pragma unroll 1
     for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
+#pragma unroll 1
         for (int nb = 0; nb < NP / 16; ++nb) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -346,87 +522,161 @@ __device__ __forceinline__ void mlp_layer(const __bf16 *in, const __bf16 *__rest
         }
 }
 
-template <bool SUR, int H>
-__global__ __launch_bounds__(64) void k_band(const int32_t *__restrict__ blk, int nblk, int64_t T,
-                                            const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node,
-                                            const int32_t *__restrict__ idx, const double *__restrict__ tgt_xyz,
-                                            const int32_t *__restrict__ tgt_perm, int64_t N,
-                                            const double *__restrict__ M, const __bf16 *__restrict__ Wt,
-                                            const float *__restrict__ P, double *__restrict__ u)
+// ---------------------------------------------------------------------------
+// Band pairs of an evaluation: one wavefront per 64 listed pairs.  Every pair
+// gets the 12 coefficients q_j = 4 pi u_T(x) of the unit nodal fields j by
+//   kBandExact  the exact pair integral (pair_geometry / pair_contract),
+//   kBandMLP    the quadrupole part plus the network's residual,
+//   kBandGauss  the 27-point collapsed Gauss-Jacobi rule (degree 5),
+//   kBandQuad   the quadrupole part alone,
+// contracted with each field's nodal M in FP64; the lanes of one target are
+// summed by a segmented scan across the wavefront and the last lane of each
+// run adds the sum into u.  The network's first layer takes every input as
+// two BF16 parts, hi = bf16(s), lo = bf16(s - hi), against the same weights
+// (24 of the 32 columns of the padded matrix-core step), so the inputs enter
+// with ~16 significant bits.
+// ---------------------------------------------------------------------------
+enum { kBandExact = 0, kBandMLP = 1, kBandGauss = 2, kBandQuad = 3 };
+
+template <int MODE, int H>
+__global__ __launch_bounds__(64, 3) void k_band_eval(const int32_t *__restrict__ pairs, int64_t npairs, int64_t T,
+                                                 const double *__restrict__ tet_xyz,
+                                                 const int32_t *__restrict__ tet_node,
+                                                 const double *__restrict__ tgt_xyz,
+                                                 const int32_t *__restrict__ tgt_perm, int64_t N,
+                                                 const double *__restrict__ M, int64_t n_nodes, int F,
+                                                 const __bf16 *__restrict__ Wt, const float *__restrict__ P,
+                                                 const double *__restrict__ rule, int nrule, double *__restrict__ u)
 {
+    constexpr bool NET = MODE == kBandMLP;
     constexpr int KP0 = 32, NPL = 16;  // padded input and output widths
-    __shared__ BandTet s_t[kBandStage];
-    __shared__ TetGeom s_g[SUR ? 1 : kBandStage];
-    __shared__ TetField s_f[SUR ? 1 : kBandStage];
-    __shared__ __align__(16) __bf16 s_a[SUR ? 64 * H : 8];
-    __shared__ __align__(16) __bf16 s_b[SUR ? 64 * H : 8];
-    __shared__ float s_y[SUR ? 64 * NPL : 1];
-    const int b = blockIdx.x;
-    if (b >= nblk) return;
-    const int tb = blk[4 * b], te = blk[4 * b + 1], ib = blk[4 * b + 2], ie = blk[4 * b + 3];
+    __shared__ __align__(16) __bf16 s_a[NET ? 64 * H : 8];
+    __shared__ __align__(16) __bf16 s_b[NET ? 64 * H : 8];
+    __shared__ float s_y[NET ? 64 * NPL : 1];
     const int lane = threadIdx.x;
-    const Layout L(H);
-    for (int sb = tb; sb < te; sb += kBandStage) {
-        const int nt = min(kBandStage, te - sb);
-        __syncthreads();
-        if (lane < nt) {
-            const int64_t t = sb + lane;
-            BandTet &B = s_t[lane];
-            for (int q = 0; q < 4; ++q) {
-                const int64_t nd = tet_node[(int64_t)q * T + t];
-                for (int k = 0; k < 3; ++k) {
-                    B.v[q][k] = tet_xyz[(int64_t)(3 * q + k) * T + t];
-                    B.m[q][k] = M[3 * nd + k];
-                }
-            }
-            tet_scales(B.v, B.c, B.diam, B.vh);
-            if constexpr (!SUR) tet_prepare(tet_xyz, tet_node, T, t, M, &s_g[lane], s_f[lane]);
-        }
-        __syncthreads();
-        // every lane of the wavefront takes part in every round (matrix cores)
-        for (int i0 = ib; i0 < ie; i0 += 64) {
-            const int i = i0 + lane;
-            const bool valid = i < ie;
-            const int s = valid ? idx[i] : idx[ib];
-            const double x[3] = {tgt_xyz[s], tgt_xyz[N + s], tgt_xyz[2 * N + s]};
-            double acc = 0.0;
-            for (int t = 0; t < nt; ++t) {
-                const BandTet &B = s_t[t];
-                const double dx = x[0] - B.c[0], dy = x[1] - B.c[1], dz = x[2] - B.c[2];
-                const double rho = sqrt(dx * dx + dy * dy + dz * dz) / B.diam;
-                const bool band = valid && rho >= kBandLo && rho < kBandHi;
-                if constexpr (!SUR) {
-                    if (band) {
-                        double a1[1] = {0.0};
-                        pair_accumulate<1>(x, s_g[t], &s_f[t], a1);
-                        acc += a1[0] * kInv4Pi;
-                    }
-                } else {
-                    __bf16 *row = s_a + lane * KP0;
-                    const double dist = rho * B.diam;
+    const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+    const bool valid = p < npairs;
+    const int64_t pp = valid ? p : npairs - 1;
+    const int s = pairs[2 * pp];
+    const int64_t t = pairs[2 * pp + 1];
+    const double x[3] = {tgt_xyz[s], tgt_xyz[N + s], tgt_xyz[2 * N + s]};
+    double v[4][3];
+    int64_t nd[4];
 #pragma unroll
-                    for (int j = 0; j < KP0; ++j)
-                        row[j] = (__bf16)(j < kIn ? (float)((B.v[j / 3][j % 3] - x[j % 3]) / dist) : 0.f);
-                    __syncthreads();
-                    mlp_layer<KP0, H, false>(s_a, Wt, P + L.b[0], H, s_b, nullptr, lane);
-                    __syncthreads();
-                    mlp_layer<H, H, false>(s_b, Wt + H * KP0, P + L.b[1], H, s_a, nullptr, lane);
-                    __syncthreads();
-                    mlp_layer<H, H, false>(s_a, Wt + H * KP0 + H * H, P + L.b[2], H, s_b, nullptr, lane);
-                    __syncthreads();
-                    mlp_layer<H, NPL, true>(s_b, Wt + H * KP0 + 2 * H * H, P + L.b[3], kOut, nullptr, s_y, lane);
-                    __syncthreads();
-                    if (band) {
-                        double v = 0.0;
+    for (int q = 0; q < 4; ++q) {
+        nd[q] = tet_node[(int64_t)q * T + t];
 #pragma unroll
-                        for (int j = 0; j < kOut; ++j) v += (double)s_y[lane * NPL + j] * B.m[j / 3][j % 3];
-                        acc += v * B.diam * B.vh / (kYScale * rho * rho);
-                    }
-                    __syncthreads();
-                }
-            }
-            if (valid && acc != 0.0) atomicAdd(&u[tgt_perm[s]], acc);
+        for (int k = 0; k < 3; ++k) v[q][k] = tet_xyz[(int64_t)(3 * q + k) * T + t];
+    }
+    double coef[kOut];
+    if constexpr (MODE == kBandExact) {
+        TetGeom G;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) G.v[q][k] = v[q][k];
+        double gl[4][3], eh[6][3];
+        tet_geometry(G, gl, eh);
+        PairGeo PG;
+        pair_geometry(x, G, PG);
+#pragma unroll 1
+        for (int j = 0; j < kOut; ++j) {
+            double m[4][3] = {};
+            m[j / 3][j % 3] = 1.0;
+            TetField F1;
+            tet_field(G, gl, eh, m, F1);
+            coef[j] = pair_contract(PG, F1);
         }
+    } else if constexpr (MODE == kBandGauss) {
+        const double e[3][3] = {{v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]},
+                                {v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2]},
+                                {v[3][0] - v[0][0], v[3][1] - v[0][1], v[3][2] - v[0][2]}};
+        const double vol6 = fabs(e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                                 e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                                 e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]));
+        const double xv[3] = {x[0] - v[0][0], x[1] - v[0][1], x[2] - v[0][2]};
+        double S[3] = {0.0, 0.0, 0.0}, K[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+        for (int q = 0; q < nrule; ++q) {
+            const double l1 = rule[4 * q], l2 = rule[4 * q + 1], l3 = rule[4 * q + 2], w = rule[4 * q + 3];
+            double d[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) d[k] = xv[k] - (l1 * e[0][k] + l2 * e[1][k] + l3 * e[2][k]);
+            const double ri = rsqrt_nr(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            const double wr = w * ri * ri * ri;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double kk = wr * d[k];
+                S[k] += kk;
+                K[0][k] = fma(l1, kk, K[0][k]);
+                K[1][k] = fma(l2, kk, K[1][k]);
+                K[2][k] = fma(l3, kk, K[2][k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            coef[k] = vol6 * (S[k] - K[0][k] - K[1][k] - K[2][k]);
+            coef[3 + k] = vol6 * K[0][k];
+            coef[6 + k] = vol6 * K[1][k];
+            coef[9 + k] = vol6 * K[2][k];
+        }
+    } else {
+        double c[3], diam, vh;
+        tet_scales(v, c, diam, vh);
+        quad_coeffs(x, v, c, coef);
+        if constexpr (NET) {
+            const Layout L(H);
+            const double dist =
+                sqrt((x[0] - c[0]) * (x[0] - c[0]) + (x[1] - c[1]) * (x[1] - c[1]) + (x[2] - c[2]) * (x[2] - c[2]));
+            const double rho = dist / diam;
+            __bf16 *row = s_a + lane * KP0;
+            double fin[kIn];
+            sur_features(x, v, c, diam, fin);
+            static_assert(2 * kIn <= KP0, "hi and lo parts of every input fit one matrix-core step");
+#pragma unroll
+            for (int j = 0; j < kIn; ++j) {
+                const float sj = (float)fin[j];
+                const __bf16 hi = (__bf16)sj;
+                row[j] = hi;
+                row[kIn + j] = (__bf16)(sj - (float)hi);
+            }
+#pragma unroll
+            for (int j = 2 * kIn; j < KP0; ++j) row[j] = (__bf16)0.f;
+            __syncthreads();
+            mlp_layer<KP0, H, false>(s_a, Wt, P + L.b[0], H, s_b, nullptr, lane);
+            __syncthreads();
+            mlp_layer<H, H, false>(s_b, Wt + H * KP0, P + L.b[1], H, s_a, nullptr, lane);
+            __syncthreads();
+            mlp_layer<H, H, false>(s_a, Wt + H * KP0 + H * H, P + L.b[2], H, s_b, nullptr, lane);
+            __syncthreads();
+            mlp_layer<H, NPL, true>(s_b, Wt + H * KP0 + 2 * H * H, P + L.b[3], kOut, nullptr, s_y, lane);
+            __syncthreads();
+            const double rho2 = rho * rho;
+            const double g = 4.0 * 3.141592653589793 * diam * vh / (kYScale * rho2 * rho2);
+#pragma unroll
+            for (int j = 0; j < kOut; ++j) coef[j] = fma(g, (double)s_y[lane * NPL + j], coef[j]);
+        }
+    }
+    // contraction with every field, one sum per run of equal targets
+    const int key = valid ? s : -1 - lane;
+    const int knext = __shfl_down(key, 1);
+    const bool tail = valid && (lane == 63 || knext != key);
+    const int64_t o = tgt_perm[s];
+#pragma unroll 1
+    for (int f = 0; f < F; ++f) {
+        const double *Mf = M + (int64_t)f * n_nodes * 3;
+        double val = 0.0;
+        if (valid) {
+#pragma unroll
+            for (int j = 0; j < kOut; ++j) val = fma(coef[j], Mf[3 * nd[j / 3] + j % 3], val);
+            val *= kInv4Pi;
+        }
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double vo = __shfl_up(val, d);
+            const int ko = __shfl_up(key, d);
+            if (lane >= d && ko == key) val += vo;
+        }
+        if (tail) atomicAdd(&u[(int64_t)f * N + o], val);
     }
 }
 
@@ -452,12 +702,13 @@ void surrogate_set(DevicePlan &dp, int H, const std::vector<float> &params)
     const int KP[4] = {32, H, H, H}, NP[4] = {H, H, H, 16};
     for (int l = 0; l < 4; ++l) {
         const int n = NP[l] * KP[l];
-        k_f32_to_bf16_t<<<(n + 255) / 256, 256>>>(dp.sur_w + L.w[l], L.K(l), L.N(l), KP[l], NP[l], o);
+        k_f32_to_bf16_t<<<(n + 255) / 256, 256>>>(dp.sur_w + L.w[l], L.K(l), L.N(l), KP[l], NP[l], l == 0 ? 1 : 0, o);
         o += n;
     }
     hip_check(hipGetLastError(), "surrogate upload launch");
     hip_check(hipDeviceSynchronize(), "surrogate upload");
     dp.sur_hidden = H;
+    ++dp.schedule_gen;  // a captured graph may hold the old weights
 }
 
 void surrogate_grad(int H, const float *params, const float *X, const float *Y, int B, float *grad, double *loss)
@@ -484,13 +735,15 @@ void surrogate_grad(int H, const float *params, const float *X, const float *Y, 
 
 void surrogate_samples(DevicePlan &dp, uint64_t seed, int n, float *X, float *Y)
 {
+    build_band_list(dp, nullptr);
     float *dX = nullptr, *dY = nullptr;
     hip_check(hipMalloc(&dX, sizeof(float) * n * kIn), "hipMalloc");
     if (hipMalloc(&dY, sizeof(float) * n * kOut) != hipSuccess) {
         (void)hipFree(dX);
         throw DeviceError{"hipMalloc failed"};
     }
-    k_sur_gen<<<(n + 63) / 64, 64>>>(dp.tet_xyz, dp.hp.n_tets, seed, n, dX, dY);
+    k_sur_gen<<<(n + 63) / 64, 64>>>(dp.tet_xyz, dp.hp.n_tets, dp.band_pairs, dp.n_band_pairs, dp.tgt_xyz,
+                                     dp.hp.n_targets, seed, n, dX, dY);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpy(X, dX, sizeof(float) * n * kIn, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(Y, dY, sizeof(float) * n * kOut, hipMemcpyDeviceToHost);
@@ -502,6 +755,7 @@ void surrogate_samples(DevicePlan &dp, uint64_t seed, int n, float *X, float *Y)
 double surrogate_train(DevicePlan &dp, int H, int steps, int B, float lr, uint64_t seed, std::vector<float> &params)
 {
     const Layout L(H);
+    build_band_list(dp, nullptr);  // training pairs: the plan's own band pairs
     // He initialisation, biases zero
     params.assign(L.n, 0.f);
     std::mt19937_64 rng(seed);
@@ -530,7 +784,8 @@ double surrogate_train(DevicePlan &dp, int H, int steps, int B, float lr, uint64
             if (it == steps - tail) {
                 hip_check(hipMemset(w.loss, 0, sizeof(double)), "hipMemset");
             }
-            k_sur_gen<<<(B + 63) / 64, 64>>>(dp.tet_xyz, dp.hp.n_tets, splitmix64(seed + 1 + (uint64_t)it), B, w.X, w.Yt);
+            k_sur_gen<<<(B + 63) / 64, 64>>>(dp.tet_xyz, dp.hp.n_tets, dp.band_pairs, dp.n_band_pairs, dp.tgt_xyz,
+                                             dp.hp.n_targets, splitmix64(seed + 1 + (uint64_t)it), B, w.X, w.Yt);
             forward_backward(L, P, w, nullptr);
             const float b1 = 0.9f, b2 = 0.999f;
             const float c1 = 1.f - std::pow(b1, (float)(it + 1)), c2 = 1.f - std::pow(b2, (float)(it + 1));
@@ -549,35 +804,103 @@ double surrogate_train(DevicePlan &dp, int H, int steps, int B, float lr, uint64
     return last / (double)tail;
 }
 
+namespace {
+__global__ void k_zero(double *__restrict__ a, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0.0;
+}
+}  // namespace
+
+void build_band_list(DevicePlan &dp, hipStream_t st)
+{
+    if (dp.band_built) return;
+    const HostPlan &hp = dp.hp;
+    const int nblk = dp.n_p2p_blk;
+    std::vector<int64_t> cnt((size_t)std::max(nblk, 1), 0), off((size_t)std::max(nblk, 1) + 1, 0);
+    int64_t *dcnt = nullptr;
+    hip_check(hipMalloc(&dcnt, sizeof(int64_t) * (cnt.size() + 1)), "hipMalloc band counts");
+    try {
+        if (nblk > 0) {
+            k_band_count<<<nblk, kBandThreads, 0, st>>>(dp.p2p_blk, nblk, hp.n_tets, dp.tet_xyz, dp.p2p_idx, dp.tgt_xyz,
+                                                        hp.n_targets, dcnt);
+            hip_check(hipGetLastError(), "k_band_count launch");
+            hip_check(hipMemcpyAsync(cnt.data(), dcnt, sizeof(int64_t) * nblk, hipMemcpyDeviceToHost, st),
+                      "hipMemcpy band counts");
+            hip_check(hipStreamSynchronize(st), "band counts");
+        }
+        for (int b = 0; b < nblk; ++b) off[b + 1] = off[b] + cnt[b];
+        const int64_t n = off[nblk > 0 ? nblk : 0];
+        int32_t *pairs = nullptr;
+        const hipError_t e = hipMalloc(&pairs, sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(n, 1));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw PlanError{TFMM_ENOMEM, "band pair list: device memory exhausted (" + std::to_string(n) + " pairs)"};
+        }
+        dp.band_pairs = pairs;
+        dp.n_band_pairs = n;
+        dp.device_bytes += (int64_t)(sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(n, 1));
+        if (nblk > 0 && n > 0) {
+            hip_check(hipMemcpyAsync(dcnt, off.data(), sizeof(int64_t) * nblk, hipMemcpyHostToDevice, st),
+                      "hipMemcpy band offsets");
+            k_band_fill<<<nblk, kBandThreads, 0, st>>>(dp.p2p_blk, nblk, hp.n_tets, dp.tet_xyz, dp.p2p_idx, dp.tgt_xyz,
+                                                       hp.n_targets, dcnt, dp.band_pairs);
+            hip_check(hipGetLastError(), "k_band_fill launch");
+        }
+        int nr = 0;
+        std::vector<double> rule = simplex_rule(5, &nr);  // the Gauss control: 27 points, degree 5
+        hip_check(hipMalloc(&dp.band_rule, sizeof(double) * rule.size()), "hipMalloc band rule");
+        hip_check(hipMemcpyAsync(dp.band_rule, rule.data(), sizeof(double) * rule.size(), hipMemcpyHostToDevice, st),
+                  "hipMemcpy band rule");
+        dp.n_band_rule = nr;
+        hip_check(hipStreamSynchronize(st), "band list");
+    } catch (...) {
+        (void)hipFree(dcnt);
+        throw;
+    }
+    (void)hipFree(dcnt);
+    dp.band_built = true;
+    ++dp.schedule_gen;
+}
+
+void run_band_pairs(DevicePlan &dp, int mode, const double *M, int32_t F, double *u, hipStream_t st)
+{
+    const HostPlan &hp = dp.hp;
+    if (!dp.band_built) throw DeviceError{"band pair list not built"};
+    const int64_t n = dp.n_band_pairs;
+    if (n == 0) return;
+    const unsigned grid = (unsigned)((n + 63) / 64);
+    const __bf16 *Wt = reinterpret_cast<const __bf16 *>(dp.sur_wb);
+#define TFMM_BAND(MODE, H)                                                                                          \
+    k_band_eval<MODE, H><<<grid, 64, 0, st>>>(dp.band_pairs, n, hp.n_tets, dp.tet_xyz, dp.tet_node, dp.tgt_xyz,     \
+                                             dp.tgt_perm, hp.n_targets, M, hp.n_nodes, F, Wt, dp.sur_w, dp.band_rule, \
+                                             dp.n_band_rule, u)
+    switch (mode) {
+    case kBandMLP:
+        if (!dp.sur_wb) throw DeviceError{"no surrogate attached"};
+        if (dp.sur_hidden == 32)
+            TFMM_BAND(kBandMLP, 32);
+        else if (dp.sur_hidden == 64)
+            TFMM_BAND(kBandMLP, 64);
+        else
+            TFMM_BAND(kBandMLP, 128);
+        break;
+    case kBandGauss: TFMM_BAND(kBandGauss, 32); break;
+    case kBandQuad: TFMM_BAND(kBandQuad, 32); break;
+    default: TFMM_BAND(kBandExact, 32); break;
+    }
+#undef TFMM_BAND
+    hip_check(hipGetLastError(), "k_band_eval launch");
+}
+
 void run_band(DevicePlan &dp, bool use_sur, const double *M, double *u, hipStream_t st)
 {
     const HostPlan &hp = dp.hp;
-    const unsigned n = (unsigned)dp.n_p2p_blk;
+    if (use_sur && !dp.sur_wb) throw DeviceError{"no surrogate attached"};
+    build_band_list(dp, st);
     k_zero<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>((hp.n_targets + 255) / 256, 65536)), 256, 0, st>>>(
         u, hp.n_targets);
-    if (n == 0) return;
-    if (!use_sur) {
-        k_band<false, 32><<<n, 64, 0, st>>>(dp.p2p_blk, (int)n, hp.n_tets, dp.tet_xyz, dp.tet_node, dp.p2p_idx,
-                                            dp.tgt_xyz, dp.tgt_perm, hp.n_targets, M, nullptr, nullptr, u);
-    } else {
-        if (!dp.sur_wb) throw DeviceError{"no surrogate loaded"};
-        const __bf16 *Wt = reinterpret_cast<const __bf16 *>(dp.sur_wb);
-        switch (dp.sur_hidden) {
-        case 32:
-            k_band<true, 32><<<n, 64, 0, st>>>(dp.p2p_blk, (int)n, hp.n_tets, dp.tet_xyz, dp.tet_node, dp.p2p_idx,
-                                               dp.tgt_xyz, dp.tgt_perm, hp.n_targets, M, Wt, dp.sur_w, u);
-            break;
-        case 64:
-            k_band<true, 64><<<n, 64, 0, st>>>(dp.p2p_blk, (int)n, hp.n_tets, dp.tet_xyz, dp.tet_node, dp.p2p_idx,
-                                               dp.tgt_xyz, dp.tgt_perm, hp.n_targets, M, Wt, dp.sur_w, u);
-            break;
-        default:
-            k_band<true, 128><<<n, 64, 0, st>>>(dp.p2p_blk, (int)n, hp.n_tets, dp.tet_xyz, dp.tet_node, dp.p2p_idx,
-                                                dp.tgt_xyz, dp.tgt_perm, hp.n_targets, M, Wt, dp.sur_w, u);
-            break;
-        }
-    }
-    hip_check(hipGetLastError(), "k_band launch");
+    run_band_pairs(dp, use_sur ? kBandMLP : kBandExact, M, 1, u, st);
 }
 
 }  // namespace tfmm

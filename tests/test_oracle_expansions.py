@@ -243,10 +243,10 @@ def test_reference_perceptron_gradient_by_finite_differences():
     from oracle import mlp
     H = 8
     _, n = mlp.layout(H)
-    assert n == 12 * H + H + 2 * (H * H + H) + H * 12 + 12
+    assert n == 16 * H + H + 2 * (H * H + H) + H * 12 + 12
     rng = np.random.default_rng(3)
     p = rng.standard_normal(n) * 0.5
-    X = rng.standard_normal((7, 12))
+    X = rng.standard_normal((7, 16))
     Tg = rng.standard_normal((7, 12))
     loss, g = mlp.loss_and_grad(p, H, X, Tg)
     eps = 1e-6
