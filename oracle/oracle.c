@@ -573,7 +573,8 @@ static void orc_m2m_acc(const orc_basis *B, const double *Qc, const double *delt
 }
 
 /* M2L: l_m(c_A) += 1/(4 pi) (-1)^|m| sum_{|n|>=1, |n|+|m|<=p} C(n+m,n) a_{n+m}(c_A - c_B) Q_n(c_B) */
-static void orc_m2l_acc(const orc_basis *B, const double *Qb, const double *R, double *La)
+/* (p = pt <= B->p: the order of the target cell's level)                   */
+static void orc_m2l_acc_p(const orc_basis *B, const double *Qb, const double *R, double *La, int pt)
 {
     double a[(ORC_MAXP + 1) * (ORC_MAXP + 2) * (ORC_MAXP + 3) / 6];
     orc_taylor(B, R, B->p, a);
@@ -584,12 +585,22 @@ static void orc_m2l_acc(const orc_basis *B, const double *Qb, const double *R, d
         for (int in = 1; in < B->ncoef; ++in) {
             const int *n = B->mi[in];
             int dn = n[0] + n[1] + n[2];
-            if (dn + dm > B->p) break; /* graded order: all later n are of higher degree */
+            if (dn + dm > pt) break; /* graded order: all later n are of higher degree */
             double c = B->binom[n[0] + m[0]][n[0]] * B->binom[n[1] + m[1]][n[1]] * B->binom[n[2] + m[2]][n[2]];
             s += c * a[B->idx[n[0] + m[0]][n[1] + m[1]][n[2] + m[2]]] * Qb[in];
         }
         La[im] += ORC_INV4PI * ((dm % 2) ? -s : s);
     }
+}
+static void orc_m2l_acc(const orc_basis *B, const double *Qb, const double *R, double *La)
+{
+    orc_m2l_acc_p(B, Qb, R, La, B->p);
+}
+
+/* Zero the coefficients of degree above q (graded order: a tail). */
+static void orc_truncate(const orc_basis *B, double *X, int q)
+{
+    for (int k = (q + 1) * (q + 2) * (q + 3) / 6; k < B->ncoef; ++k) X[k] = 0.0;
 }
 
 /* L2L: l_m(c_C) += sum_{k>=m, |k|<=p} C(k,m) (c_C - c_P)^{k-m} l_k(c_P) */
@@ -817,6 +828,7 @@ typedef struct {
     orc_rule R;
     double *Q, *L; /* [ncells][ncoef] for the last evaluated field */
     int points;    /* sources are point dipoles at the nodes (orc_fmm_build_points) */
+    int plev[ORC_MAXDEPTH + 1]; /* expansion order of each level (all p by default) */
 } orc_fmm;
 
 static uint32_t orc_key1(double xd, double o, double S)
@@ -1019,6 +1031,7 @@ void *orc_fmm_build(const double *nodes, int64_t n_nodes, const int32_t *tets, i
     T->n_nodes = n_nodes;
     T->n_tets = n_tets;
     T->p = p;
+    for (int l = 0; l <= ORC_MAXDEPTH; ++l) T->plev[l] = p;
     T->leaf = leaf;
     T->theta = theta;
     T->nodes = malloc(sizeof(double) * 3 * (size_t)n_nodes);
@@ -1221,14 +1234,18 @@ static void orc_upward(orc_fmm *T, const double *Mf)
             orc_p2m_tet_acc(&T->B, &T->R, v, m, C->c, T->Q + (size_t)ci * nc);
         }
     }
-    /* children always have larger indices than their parent: sweep backward */
+    /* children always have larger indices than their parent: sweep backward;
+       a cell's multipole is complete when the sweep reaches it and is kept to
+       the order of its level (per-level orders) before it is shifted up */
     for (int ci = T->ncells - 1; ci > 0; --ci) {
         orc_cell *C = &T->cells[ci];
         orc_cell *P = &T->cells[C->parent];
         double delta[3];
+        orc_truncate(&T->B, T->Q + (size_t)ci * nc, T->plev[C->level]);
         sub3(C->c, P->c, delta);
         orc_m2m_acc(&T->B, T->Q + (size_t)ci * nc, delta, T->Q + (size_t)C->parent * nc);
     }
+    if (T->ncells > 0) orc_truncate(&T->B, T->Q, T->plev[0]);
 }
 
 static void orc_cell_m2l(orc_fmm *T, int ci)
@@ -1239,7 +1256,7 @@ static void orc_cell_m2l(orc_fmm *T, int ci)
         const orc_cell *Bc = &T->cells[A->m2l[j]];
         double R[3];
         sub3(A->c, Bc->c, R);
-        orc_m2l_acc(&T->B, T->Q + (size_t)A->m2l[j] * nc, R, T->L + (size_t)ci * nc);
+        orc_m2l_acc_p(&T->B, T->Q + (size_t)A->m2l[j] * nc, R, T->L + (size_t)ci * nc, T->plev[A->level]);
     }
 }
 
@@ -1293,6 +1310,7 @@ int orc_fmm_evaluate(void *h, const double *M, int32_t F, double *u)
             double delta[3];
             sub3(C->c, P->c, delta);
             orc_l2l_acc(&T->B, T->L + (size_t)C->parent * nc, delta, T->L + (size_t)ci * nc);
+            orc_truncate(&T->B, T->L + (size_t)ci * nc, T->plev[C->level]);
         }
 #pragma omp parallel for schedule(dynamic, 4)
         for (int ci = 0; ci < T->ncells; ++ci) {
@@ -1353,6 +1371,7 @@ int orc_fmm_evaluate_sample(void *h, const double *M, int32_t F, const int64_t *
             double delta[3];
             sub3(C->c, T->cells[C->parent].c, delta);
             orc_l2l_acc(&T->B, T->L + (size_t)C->parent * nc, delta, T->L + (size_t)ci * nc);
+            orc_truncate(&T->B, T->L + (size_t)ci * nc, T->plev[C->level]);
         }
 #pragma omp parallel for schedule(dynamic, 1)
         for (int64_t s = 0; s < ns; ++s) {
@@ -1367,6 +1386,24 @@ int orc_fmm_evaluate_sample(void *h, const double *M, int32_t F, const int64_t *
     free(leaf_of);
     free(need);
     free(needlist);
+    return 0;
+}
+
+/* Per-level expansion orders (an accuracy knob beside theta and p): level   */
+/* l keeps multipole and local coefficients of degree <= q_l, with          */
+/* q_l = order[min(l, n - 1)] clamped to [1, p]; P2M and M2M results are     */
+/* truncated at their cell's level, M2L into a cell of level l keeps         */
+/* |n| + |m| <= q_l (its sources' multipoles already hold |n| <= q of their  */
+/* level), L2L results are truncated at the child's level.  Uniform orders   */
+/* (the default) are the method as before.  Returns 0, or -1 on bad input.   */
+int orc_fmm_set_level_orders(void *h, const int32_t *order, int32_t n)
+{
+    orc_fmm *T = h;
+    if (!T || !order || n < 1) return -1;
+    for (int l = 0; l <= ORC_MAXDEPTH; ++l) {
+        int q = order[l < n ? l : n - 1];
+        T->plev[l] = q < 1 ? 1 : (q > T->p ? T->p : q);
+    }
     return 0;
 }
 

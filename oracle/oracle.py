@@ -70,6 +70,8 @@ def _load():
     lib.orc_fmm_evaluate.argtypes = [C.c_void_p, _dp, C.c_int32, _dp]
     lib.orc_fmm_evaluate_sample.restype = C.c_int
     lib.orc_fmm_evaluate_sample.argtypes = [C.c_void_p, _dp, C.c_int32, _i64p, C.c_int64, _dp]
+    lib.orc_fmm_set_level_orders.restype = C.c_int
+    lib.orc_fmm_set_level_orders.argtypes = [C.c_void_p, _i32p, C.c_int32]
     lib.orc_fmm_expansions.restype = C.c_int
     lib.orc_fmm_expansions.argtypes = [C.c_void_p, C.c_int32, _dp]
     lib.orc_dipole_potential.restype = C.c_double
@@ -252,6 +254,13 @@ class FMM:
         if h is not None and _lib is not None:
             _lib.orc_fmm_free(h)
             self._h = None
+
+    def set_level_orders(self, orders):
+        """Expansion order per octree level (level l takes orders[min(l, len - 1)],
+        clamped to [1, p]); the default is p everywhere."""
+        o = np.ascontiguousarray(orders, dtype=np.int32)
+        if _load().orc_fmm_set_level_orders(self._h, _ptr(o, _i32p), o.size) != 0:
+            raise ValueError("bad level orders")
 
     def stats(self):
         out = np.zeros(8, dtype=np.int64)
