@@ -122,6 +122,7 @@ typedef struct {
     int64_t n_band_pairs; /* near pairs of the surrogate's band (0 until first used) */
     int32_t surrogate;    /* TFMM_SUR_* of the plan */
     int32_t surrogate_hidden; /* width of the attached network, 0 if none */
+    int32_t level_order[22];  /* expansion order of octree levels 0..21 (all p unless set) */
 } tfmm_stats;
 
 /*
@@ -237,6 +238,35 @@ int tfmm_tune_accuracy(const double *nodes, int64_t n_nodes, const int32_t *tets
 int tfmm_tune_accuracy_points(const double *points, int64_t n_points, const tfmm_params *base, const double *M,
                               double tol, int32_t n_sample, uint64_t seed, const int32_t *p_list, int32_t n_p,
                               const double *theta_list, int32_t n_theta, tfmm_tune_result *out, double *table);
+
+/*
+ * Per-level expansion orders (the accuracy knob beside theta and p that the
+ * paper names as the next performance lever, Sec. 4.1): level l of the octree
+ * keeps multipole and local coefficients of degree <= q_l, with
+ * q_l = orders[min(l, n - 1)], 1 <= q_l <= p (the plan's p is the largest
+ * order and fixes the storage).  P2M and M2M results are truncated to their
+ * cell's level, M2L into a cell of level l keeps |n| + |m| <= q_l and runs
+ * on matrix cores at that order, L2L results are truncated to the child's
+ * level.  All q_l = p is the method as built.  The first evaluation after a
+ * change builds per-level M2L tile lists (host work, synchronous).
+ * Errors: TFMM_EINVAL (NULL, n < 1, an order outside [1, p]).
+ */
+int tfmm_plan_set_level_orders(tfmm_plan plan, const int32_t *orders, int32_t n);
+
+/*
+ * Per-level orders for an accuracy target on an existing plan (targets = its
+ * nodes): candidate profiles are the uniform order p and every two-order
+ * step, the levels from a split level down (or up) at p - 1 or p - 2 and the
+ * others at p; each is evaluated for the probe field M (host [n_nodes][3])
+ * and its relative L2 error measured against the FP64 direct sum at n_sample
+ * nodes drawn with `seed`; profiles within tol / 2 are timed (best of 3) and
+ * the fastest is set on the plan.  orders [22] receives the chosen order of
+ * levels 0..21, *err the sampled error and *ms the time of one evaluation
+ * (both -1 and the plan's orders unchanged when no profile met the
+ * tolerance).  Synchronous.  Errors: TFMM_EINVAL, TFMM_EDEVICE.
+ */
+int tfmm_tune_level_orders(tfmm_plan plan, const double *M, double tol, int32_t n_sample, uint64_t seed,
+                           int32_t *orders, double *err, double *ms);
 
 /* Switch the near-field surrogate of an existing plan (one of TFMM_SUR_*;
  * TFMM_SUR_MLP needs an attached network by the next evaluation).  The first

@@ -17,7 +17,7 @@ __all__ = [
     "TetFMMError", "Plan", "tfmm_plan_create", "tfmm_evaluate", "tfmm_direct", "tfmm_evaluate_host",
     "tfmm_direct_host", "tfmm_plan_stats", "tfmm_plan_lists", "tfmm_plan_cells", "tfmm_plan_expansions",
     "tfmm_plan_destroy", "tfmm_last_error", "tfmm_simplex_rule", "tfmm_set_timing", "tfmm_kernel_times",
-    "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS", "tfmm_plan_set_m2l_precision", "tfmm_plan_set_surrogate", "SUR_OFF", "SUR_MLP", "SUR_GAUSS", "SUR_QUAD", "M2L_FP64", "M2L_FP32", "M2L_BF16X3", "M2L_BF16X6",
+    "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS", "tfmm_plan_set_m2l_precision", "tfmm_plan_set_surrogate", "tfmm_plan_set_level_orders", "tfmm_tune_level_orders", "SUR_OFF", "SUR_MLP", "SUR_GAUSS", "SUR_QUAD", "M2L_FP64", "M2L_FP32", "M2L_BF16X3", "M2L_BF16X6",
     "tfmm_plan_autotune", "tfmm_plan_set_schedule", "tfmm_elementary", "ELEMENTARY", "tfmm_batch_create", "tfmm_batch_evaluate", "tfmm_batch_autotune", "tfmm_batch_plan",
     "tfmm_batch_destroy", "Batch", "tfmm_surrogate_param_count", "tfmm_surrogate_train", "tfmm_surrogate_load",
     "tfmm_surrogate_samples", "tfmm_surrogate_grad", "tfmm_band_potential", "tfmm_demag_energy", "tfmm_demag_energy_noalloc", "NOALLOC_MAX_TETS", "tfmm_demag_field_nodes",
@@ -68,7 +68,8 @@ class _Stats(C.Structure):
         ("near_nnz", C.c_int64), ("near_bytes", C.c_int64),
         ("m2l_keys_per_item", C.c_int32), ("p2p_wide", C.c_int32),
         ("p2p_node_evals", C.c_int64), ("p2p_edge_evals", C.c_int64), ("p2p_face_evals", C.c_int64),
-        ("n_band_pairs", C.c_int64), ("surrogate", C.c_int32), ("surrogate_hidden", C.c_int32)]
+        ("n_band_pairs", C.c_int64), ("surrogate", C.c_int32), ("surrogate_hidden", C.c_int32),
+        ("level_order", C.c_int32 * 22)]
 
 
 class TetFMMError(RuntimeError):
@@ -103,6 +104,8 @@ def _load():
         "tfmm_plan_destroy": (C.c_int, [C.c_void_p]),
         "tfmm_plan_set_m2l_precision": (C.c_int, [C.c_void_p, C.c_int32]),
         "tfmm_plan_set_surrogate": (C.c_int, [C.c_void_p, C.c_int32]),
+        "tfmm_plan_set_level_orders": (C.c_int, [C.c_void_p, _i32p, C.c_int32]),
+        "tfmm_tune_level_orders": (C.c_int, [C.c_void_p, _dp, C.c_double, C.c_int32, C.c_uint64, _i32p, _dp, _dp]),
         "tfmm_plan_store_near": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
         "tfmm_plan_create_points": (C.c_int, [_dp, C.c_int64, _dp, C.c_int64, C.c_void_p, C.POINTER(C.c_void_p)]),
         "tfmm_tune_accuracy": (C.c_int, [_dp, C.c_int64, _i32p, C.c_int64, C.c_void_p, _dp, C.c_double, C.c_int32,
@@ -498,7 +501,9 @@ def tfmm_band_potential(plan, M, use_surrogate, u=None, stream=None):
 def tfmm_plan_stats(plan):
     st = _Stats()
     _check(_load().tfmm_plan_stats(plan.handle, C.byref(st)))
-    return {n: getattr(st, n) for n, _ in _Stats._fields_}
+    out = {n: getattr(st, n) for n, _ in _Stats._fields_}
+    out["level_order"] = list(out["level_order"])
+    return out
 
 
 def tfmm_plan_lists(plan, kind):
@@ -525,6 +530,27 @@ def tfmm_plan_expansions(plan, which):
     out = np.zeros((st["n_cells"], st["ncoef"]))
     _check(_load().tfmm_plan_expansions(plan.handle, {"Q": 0, "L": 1}[which], _ptr(out, _dp)))
     return out
+
+
+def tfmm_plan_set_level_orders(plan, orders):
+    """Expansion order per octree level (level l takes orders[min(l, len - 1)],
+    each in [1, p] of the plan)."""
+    o = np.ascontiguousarray(orders, dtype=np.int32)
+    _check(_load().tfmm_plan_set_level_orders(plan.handle, _ptr(o, _i32p), o.size))
+
+
+def tfmm_tune_level_orders(plan, M, tol, n_sample=512, seed=1):
+    """Fastest per-level order profile whose sampled error against the FP64
+    direct sum is within tol / 2 (set on the plan).  M: host [n_nodes, 3].
+    Returns dict(orders [22], err, ms, met)."""
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    if M.shape != (plan.n_nodes, 3):
+        raise ValueError("M must be [n_nodes, 3]")
+    orders = np.zeros(22, dtype=np.int32)
+    err, ms = C.c_double(0.0), C.c_double(0.0)
+    _check(_load().tfmm_tune_level_orders(plan.handle, _ptr(M, _dp), float(tol), int(n_sample), int(seed),
+                                          _ptr(orders, _i32p), C.byref(err), C.byref(ms)))
+    return dict(orders=orders.tolist(), err=err.value, ms=ms.value, met=ms.value >= 0.0)
 
 
 def tfmm_plan_set_surrogate(plan, mode):

@@ -308,6 +308,11 @@ void free_plan(DevicePlan &dp)
         for (void *p : tp)
             if (p) (void)hipFree(p);
     }
+    for (auto &t : dp.lvl_tiles) {
+        void *tp[] = {t.tile_tgt, t.tile_rng, t.ent_key, t.ent_src};
+        for (void *p : tp)
+            if (p) (void)hipFree(p);
+    }
 }
 
 }  // namespace tfmm
@@ -348,6 +353,7 @@ static int plan_create(const double *nodes, int64_t n_nodes, const int32_t *tets
         P->dp.ncoef = (prm->p + 1) * (prm->p + 2) * (prm->p + 3) / 6;
         P->dp.m2l_precision = prm->m2l_precision;
         P->dp.sur_mode = prm->surrogate;
+        for (int l = 0; l < tfmm::kMaxLevels; ++l) P->dp.lo.q[l] = (int8_t)prm->p;
         if (prm->device >= 0) {
             int ndev = 0;
             if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
@@ -476,6 +482,7 @@ int tfmm_plan_stats(tfmm_plan plan, tfmm_stats *out)
     out->n_band_pairs = plan->dp.n_band_pairs;
     out->surrogate = plan->dp.sur_mode;
     out->surrogate_hidden = plan->dp.sur_hidden;
+    for (int l = 0; l < 22; ++l) out->level_order[l] = plan->dp.lo.q[l];
     return TFMM_OK;
 }
 
@@ -564,6 +571,30 @@ int tfmm_plan_expansions(tfmm_plan plan, int32_t which, double *out)
         const size_t per = (size_t)plan->dp.hp.cells.size() * plan->dp.ncoef;
         const double *src = (which == 0 ? plan->dp.Q : plan->dp.L) + per * (size_t)(plan->dp.last_F - 1);
         tfmm::hip_check(hipMemcpy(out, src, per * sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy expansions");
+        return TFMM_OK;
+    });
+}
+
+int tfmm_plan_set_level_orders(tfmm_plan plan, const int32_t *orders, int32_t n)
+{
+    if (!plan || !orders || n < 1) return set_error(TFMM_EINVAL, "NULL plan or orders, or n < 1");
+    const int p = plan->dp.hp.p;
+    for (int32_t i = 0; i < n; ++i)
+        if (orders[i] < 1 || orders[i] > p)
+            return set_error(TFMM_EINVAL, "level orders must lie in [1, p] of the plan");
+    return guarded([&]() -> int {
+        tfmm::DevicePlan &dp = plan->dp;
+        bool differ = false;
+        for (int l = 0; l < tfmm::kMaxLevels; ++l) {
+            dp.lo.q[l] = (int8_t)orders[l < n ? l : n - 1];
+            differ = differ || dp.lo.q[l] != p;
+        }
+        if (plan->on_device) {
+            DeviceScope ds(dp.device);
+            if (!differ) tfmm::drop_m2l_level_tiles(dp);
+        }
+        dp.level_orders = differ;
+        ++dp.schedule_gen;
         return TFMM_OK;
     });
 }
@@ -734,6 +765,122 @@ static std::vector<int64_t> tune_sample(int64_t n, int64_t k, uint64_t seed)
     idx.resize((size_t)k);
     std::sort(idx.begin(), idx.end());
     return idx;
+}
+
+int tfmm_tune_level_orders(tfmm_plan plan, const double *M, double tol, int32_t n_sample, uint64_t seed,
+                           int32_t *orders, double *err_out, double *ms_out)
+{
+    if (!plan || !M || !orders || !err_out || !ms_out) return set_error(TFMM_EINVAL, "NULL argument");
+    if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan");
+    if (plan->dp.hp.points || !plan->dp.hp.targets_are_nodes)
+        return set_error(TFMM_EINVAL, "the plan's sources must be tets and its targets its nodes");
+    if (!(tol > 0.0) || n_sample < 1) return set_error(TFMM_EINVAL, "tol > 0 and n_sample >= 1 required");
+    tfmm::DevicePlan &dp = plan->dp;
+    const tfmm::HostPlan &hp = dp.hp;
+    const int64_t n_nodes = hp.n_nodes;
+    const int p = hp.p, depth = (int)hp.depth;
+    const int64_t ns = std::min<int64_t>(n_sample, n_nodes);
+    const std::vector<int64_t> sample = tune_sample(n_nodes, ns, seed);
+    std::vector<double> xs(3 * (size_t)ns);
+    for (int64_t i = 0; i < ns; ++i)
+        for (int k = 0; k < 3; ++k) xs[3 * (size_t)i + k] = hp.nodes[3 * sample[(size_t)i] + k];
+    const tfmm::LevelOrders lo0 = dp.lo;
+    const bool lv0 = dp.level_orders;
+    double *dM = nullptr, *du = nullptr, *dref = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    tfmm_plan ref = nullptr;
+    auto cleanup = [&]() {
+        if (ref) tfmm_plan_destroy(ref);
+        if (st) (void)hipStreamSynchronize(st);
+        if (dM) (void)hipFree(dM);
+        if (du) (void)hipFree(du);
+        if (dref) (void)hipFree(dref);
+        if (ea) (void)hipEventDestroy(ea);
+        if (eb) (void)hipEventDestroy(eb);
+        if (st) (void)hipStreamDestroy(st);
+    };
+    int rc = guarded([&]() -> int {
+        DeviceScope ds(dp.device);
+        tfmm::hip_check(hipStreamCreate(&st), "hipStreamCreate");
+        tfmm::hip_check(hipEventCreate(&ea), "hipEventCreate");
+        tfmm::hip_check(hipEventCreate(&eb), "hipEventCreate");
+        tfmm::hip_check(hipMalloc(&dM, sizeof(double) * 3 * (size_t)n_nodes), "hipMalloc M");
+        tfmm::hip_check(hipMalloc(&du, sizeof(double) * (size_t)n_nodes), "hipMalloc u");
+        tfmm::hip_check(hipMalloc(&dref, sizeof(double) * (size_t)ns), "hipMalloc reference");
+        tfmm::hip_check(hipMemcpy(dM, M, sizeof(double) * 3 * (size_t)n_nodes, hipMemcpyHostToDevice), "hipMemcpy M");
+        // reference: the FP64 direct sum at the sampled nodes
+        const tfmm_params rp{2, 64, 0.5, TFMM_M2L_FP64, TFMM_SUR_OFF, dp.device};
+        int r = tfmm_plan_create(hp.nodes.data(), n_nodes, hp.tet_nodes.data(), hp.n_tets, xs.data(), ns, &rp, &ref);
+        if (r) return r;
+        if ((r = tfmm_direct(ref, dM, 1, dref, st))) return r;
+        std::vector<double> uref((size_t)ns), u((size_t)n_nodes);
+        tfmm::hip_check(hipMemcpyAsync(uref.data(), dref, sizeof(double) * (size_t)ns, hipMemcpyDeviceToHost, st),
+                        "hipMemcpy reference");
+        tfmm::hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        double nref = 0.0;
+        for (double v : uref) nref += v * v;
+        nref = std::sqrt(nref);
+        // candidate profiles: uniform p, then two orders split at a level (the
+        // finest levels lowered, or the coarsest), lower order p - 1 or p - 2
+        std::vector<std::vector<int32_t>> cand;
+        cand.push_back(std::vector<int32_t>((size_t)depth + 1, p));
+        for (int q = p - 1; q >= std::max(1, p - 2); --q)
+            for (int s = depth; s >= 1; --s) {
+                std::vector<int32_t> fine((size_t)depth + 1, p), coarse((size_t)depth + 1, q);
+                for (int l = s; l <= depth; ++l) fine[(size_t)l] = q;
+                for (int l = s; l <= depth; ++l) coarse[(size_t)l] = p;
+                cand.push_back(fine);
+                cand.push_back(coarse);
+            }
+        double best_ms = -1.0, best_err = -1.0;
+        std::vector<int32_t> best;
+        for (const auto &o : cand) {
+            if ((r = tfmm_plan_set_level_orders(plan, o.data(), (int32_t)o.size()))) return r;
+            if ((r = tfmm_evaluate(plan, dM, 1, du, st))) return r;
+            tfmm::hip_check(hipMemcpyAsync(u.data(), du, sizeof(double) * (size_t)n_nodes, hipMemcpyDeviceToHost, st),
+                            "hipMemcpy u");
+            tfmm::hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            double e2 = 0.0;
+            for (int64_t i = 0; i < ns; ++i) {
+                const double d = u[(size_t)sample[(size_t)i]] - uref[(size_t)i];
+                e2 += d * d;
+            }
+            const double err = nref > 0.0 ? std::sqrt(e2) / nref : std::sqrt(e2);
+            if (err > 0.5 * tol) continue;  // a margin for the sampling, as tfmm_tune_accuracy
+            float ms = -1.f;
+            for (int rep = 0; rep < 3; ++rep) {
+                tfmm::hip_check(hipEventRecord(ea, st), "hipEventRecord");
+                if ((r = tfmm_evaluate(plan, dM, 1, du, st))) return r;
+                tfmm::hip_check(hipEventRecord(eb, st), "hipEventRecord");
+                tfmm::hip_check(hipEventSynchronize(eb), "hipEventSynchronize");
+                float t = 0.f;
+                tfmm::hip_check(hipEventElapsedTime(&t, ea, eb), "hipEventElapsedTime");
+                if (ms < 0.f || t < ms) ms = t;
+            }
+            if (best_ms < 0.0 || ms < best_ms) {
+                best_ms = ms;
+                best_err = err;
+                best = o;
+            }
+        }
+        if (best.empty()) {  // nothing met the tolerance: keep the plan's own orders
+            dp.lo = lo0;
+            dp.level_orders = lv0;
+            ++dp.schedule_gen;
+            for (int l = 0; l < 22; ++l) orders[l] = dp.lo.q[l];
+            *err_out = -1.0;
+            *ms_out = -1.0;
+            return TFMM_OK;
+        }
+        if ((r = tfmm_plan_set_level_orders(plan, best.data(), (int32_t)best.size()))) return r;
+        for (int l = 0; l < 22; ++l) orders[l] = dp.lo.q[l];
+        *err_out = best_err;
+        *ms_out = best_ms;
+        return TFMM_OK;
+    });
+    cleanup();
+    return rc;
 }
 
 // The (p, theta) search of tfmm_tune_accuracy for tets (tets != NULL) or for

@@ -26,6 +26,13 @@ constexpr int kFarDeg[kFarBands] = {13, 11, 9, 7};
 constexpr int kFarOff[kFarBands + 1] = {0, 343, 559, 684, 748};
 constexpr double kFarRatio[kFarBands] = {3.0, 6.0, 12.0, 24.0};
 
+// Expansion order of every octree level (levels beyond the tree unused),
+// passed to kernels by value.
+constexpr int kMaxLevels = 32;
+struct LevelOrders {
+    int8_t q[kMaxLevels];
+};
+
 // Thrown by launchers on HIP failures (converted to TFMM_EDEVICE at the ABI).
 struct DeviceError {
     std::string msg;
@@ -72,8 +79,14 @@ struct DevicePlan {
         int32_t *tile_tgt = nullptr, *tile_rng = nullptr, *ent_key = nullptr, *ent_src = nullptr;
         int32_t ntiles = 0;
         int64_t nent = 0;
+        int64_t bytes = 0;  // device bytes of the four lists
     };
     Tiles m2l_tiles[5];
+    // per-level expansion orders (tfmm_plan_set_level_orders): all hp.p
+    // unless level_orders; then M2L runs per target level on its own tiles
+    LevelOrders lo{};
+    bool level_orders = false;
+    std::vector<Tiles> lvl_tiles;
     int m2l_precision = 0;  // TFMM_M2L_*
     // schedule knobs (tfmm_plan_autotune): keys per M2L work item, and four
     // wavefronts per P2P workgroup also for one or two fields
@@ -185,6 +198,9 @@ void build_tet_moments(DevicePlan &dp);
 void build_m2l_table(DevicePlan &dp);
 // Tiles of tpt target cells (16, 8, 4, 2 or 1), built and uploaded once.
 DevicePlan::Tiles &ensure_m2l_tiles(DevicePlan &dp, int tpt);
+// The same per target level (for per-level orders), and their release.
+const std::vector<DevicePlan::Tiles> &ensure_m2l_level_tiles(DevicePlan &dp, int tpt);
+void drop_m2l_level_tiles(DevicePlan &dp);
 
 // Allocate everything an evaluation of F fields needs (expansions, M2L tiles
 // and operand buffers), so that a later run_evaluate allocates nothing.

@@ -282,7 +282,7 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m(const int32_t *__restrict__
                                                      const double *__restrict__ tet_xyz, const int32_t *__restrict__ tet_node,
                                                      int64_t T, const double *__restrict__ mom,
                                                      const double *__restrict__ M, int64_t n_nodes, int F, int p,
-                                                     int ncells, int points, double *__restrict__ Q)
+                                                     int ncells, int points, LevelOrders lo, double *__restrict__ Q)
 {
     extern __shared__ double s_dyn[];
     const int ncoef = ncoef_of(p);
@@ -353,13 +353,15 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m(const int32_t *__restrict__
             }
         }
     }
+    // kept to the order of the leaf's level (the rest stays zero)
+    const int nkeep = ncoef_of(lo.q[cell_i[CI_N * cell + CI_LEVEL]]);
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         const int n = tid + r * kP2MThreads;
         if (n >= ncoef) continue;
 #pragma unroll
         for (int j = 0; j < FC; ++j)
-            if (f0 + j < F) Q[((int64_t)(f0 + j) * C + cell) * ncoef + n] = acc[r][j];
+            if (f0 + j < F) Q[((int64_t)(f0 + j) * C + cell) * ncoef + n] = n < nkeep ? acc[r][j] : 0.0;
     }
 }
 
@@ -402,11 +404,11 @@ __device__ __forceinline__ void shift_pass(const double *__restrict__ in, double
 // M2M: one workgroup per parent of a level; child g of the parent is item g.
 //   Q_n(P) = sum_children sum_{k <= n} C(n,k) (c_C - c_P)^{n-k} Q_k(C)
 __global__ __launch_bounds__(kShiftThreads) void k_m2m(const int32_t *__restrict__ cells, const int32_t *__restrict__ cell_i,
-                                                       const double *__restrict__ cell_c, int64_t C, int p,
+                                                       const double *__restrict__ cell_c, int64_t C, int p, int pout,
                                                        double *__restrict__ Q)
 {
     extern __shared__ double s_dyn[];
-    const int ncoef = ncoef_of(p);
+    const int ncoef = ncoef_of(p), nkeep = ncoef_of(pout);
     double *s_a = s_dyn, *s_b = s_dyn + kShiftItems * ncoef;
     const int cell = cells[blockIdx.x];
     const int f = blockIdx.y;
@@ -431,7 +433,7 @@ __global__ __launch_bounds__(kShiftThreads) void k_m2m(const int32_t *__restrict
         double q = 0.0;
         for (int c = 0; c < nch && c < kShiftItems; ++c)
             if (cell_i[CI_N * (cbeg + c) + CI_TEND] > cell_i[CI_N * (cbeg + c) + CI_TBEG]) q += s_b[c * ncoef + n];
-        Q[((int64_t)f * C + cell) * ncoef + n] = q;
+        Q[((int64_t)f * C + cell) * ncoef + n] = n < nkeep ? q : 0.0;  // kept to the parent level's order
     }
 }
 
@@ -440,11 +442,11 @@ __global__ __launch_bounds__(kShiftThreads) void k_m2m(const int32_t *__restrict
 //   l_m(C) += sum_{k >= m, |k| <= p} C(k,m) (c_C - c_P)^{k-m} l_k(P)
 __global__ __launch_bounds__(kShiftThreads) void k_l2l(const int32_t *__restrict__ cells, int ncells,
                                                        const int32_t *__restrict__ cell_i,
-                                                       const double *__restrict__ cell_c, int64_t C, int p,
+                                                       const double *__restrict__ cell_c, int64_t C, int p, int pout,
                                                        double *__restrict__ L)
 {
     extern __shared__ double s_dyn[];
-    const int ncoef = ncoef_of(p);
+    const int ncoef = ncoef_of(p), nkeep = ncoef_of(pout);
     double *s_a = s_dyn, *s_b = s_dyn + kShiftItems * ncoef;
     const int f = blockIdx.y;
     const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
@@ -467,7 +469,7 @@ __global__ __launch_bounds__(kShiftThreads) void k_l2l(const int32_t *__restrict
     if (act) {
         shift_pass<false>(s_a + g * ncoef, s_b + g * ncoef, ncoef, p, 2, t[2], lane);
         // the lanes that wrote out[n] add it (no barrier needed)
-        for (int n = lane; n < ncoef; n += 32) L[((int64_t)f * C + cell) * ncoef + n] += s_b[g * ncoef + n];
+        for (int n = lane; n < nkeep; n += 32) L[((int64_t)f * C + cell) * ncoef + n] += s_b[g * ncoef + n];
     }
 }
 
@@ -713,6 +715,7 @@ __device__ __forceinline__ void m2l_wave_mfma(typename Mfma<T>::v4 (&acc)[m2l_nr
 // column c = t * FPT + g (target slot t, field f0 + g).
 struct M2LCols {
     int tpt, fpt, f0, F;
+    int dstr;  // row stride of the derivative tables (the plan's order; P may be lower)
 };
 
 // One workgroup of kM2LWaves wavefronts per target tile (see k_m2l_mfma).
@@ -780,7 +783,7 @@ __device__ __forceinline__ void m2l_tile(const int32_t *__restrict__ tile_rng, c
 #pragma unroll
         for (int j = 0; j < DREG; ++j) {
             const int k = tid + NT * j;
-            o.d[j] = Dtab[(int64_t)key * ND + (k < ND ? k : ND - 1)];
+            o.d[j] = Dtab[(int64_t)key * cols.dstr + (k < ND ? k : ND - 1)];
         }
         o.ok = active && src >= 0;
         const T *q = qf + (int64_t)(o.ok ? src : 0) * qpad;
@@ -861,7 +864,7 @@ __global__ __launch_bounds__(64 * kM2LWaves, 2) void k_m2l_mfma(
     const int32_t *__restrict__ tile_tgt, const int32_t *__restrict__ tile_rng, const int32_t *__restrict__ ent_key,
     const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys, const T *__restrict__ Dtab,
     const T *__restrict__ Qr, int qpad, const int32_t *__restrict__ cell_i, double side, int64_t C, int tpt, int fpt,
-    int F, int ntiles, double *__restrict__ L)
+    int F, int ntiles, int dstr, int lstr, double *__restrict__ L)
 {
     using v4 = typename Mfma<T>::v4;
     constexpr int NC = ncoef_of(P), NROW = m2l_nrows(P), ND = nd_of(P), NRT = m2l_nrt(P), KSTR = m2l_kstr(P);
@@ -874,7 +877,7 @@ __global__ __launch_bounds__(64 * kM2LWaves, 2) void k_m2l_mfma(
     const int tile = blockIdx.x;
     if (tile >= ntiles) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const M2LCols cols{tpt, fpt, (int)blockIdx.y * fpt, F};
+    const M2LCols cols{tpt, fpt, (int)blockIdx.y * fpt, F, dstr};
     for (int i = tid; i < 2 * 16 * KSTR; i += blockDim.x) s_Q[i] = (T)0;  // column padding stays zero
     for (int i = tid; i < 2 * (ND + 1); i += blockDim.x) s_D[i] = (T)0;   // zero slot ND of each buffer
     __syncthreads();
@@ -916,7 +919,7 @@ __global__ __launch_bounds__(64 * kM2LWaves, 2) void k_m2l_mfma(
         const double is = 1.0 / ldexp(side, -cell_i[CI_N * A + CI_LEVEL]);
         double sp = is;
         for (int k = 0; k < dm; ++k) sp *= is;
-        atomicAdd(&L[((int64_t)field * C + A) * NC + m],
+        atomicAdd(&L[((int64_t)field * C + A) * lstr + m],
                   lt * kInv4Pi * sp * c_bin.invfact[mx] * c_bin.invfact[my] * c_bin.invfact[mz]);
     }
 }
@@ -1039,7 +1042,7 @@ __device__ __forceinline__ void m2lb_tile(const int32_t *__restrict__ tile_rng, 
 #pragma unroll
         for (int j = 0; j < DREG; ++j) {
             const int k = tid + NT * j;
-            pd[j] = Dtab[(int64_t)key * ND + (k < ND ? k : ND - 1)];
+            pd[j] = Dtab[(int64_t)key * cols.dstr + (k < ND ? k : ND - 1)];
         }
         qok = active && src >= 0;
         const float *q = qf + (int64_t)(qok ? src : 0) * qpad;
@@ -1111,7 +1114,7 @@ __global__ __launch_bounds__(64 * kM2LBWaves, 2) void k_m2l_bf16(
     const int32_t *__restrict__ tile_tgt, const int32_t *__restrict__ tile_rng, const int32_t *__restrict__ ent_key,
     const int32_t *__restrict__ ent_src, const int32_t *__restrict__ keys, const float *__restrict__ Dtab,
     const float *__restrict__ Qr, int qpad, const int32_t *__restrict__ cell_i, double side, int64_t C, int tpt, int fpt,
-    int F, int ntiles, double *__restrict__ L)
+    int F, int ntiles, int dstr, int lstr, double *__restrict__ L)
 {
     using v4 = Mfma<float>::v4;
     constexpr int NC = ncoef_of(P), NROW = m2l_nrows(P), ND = nd_of(P), NRT = m2l_nrt(P), KSTR = m2lb_kstr(P);
@@ -1124,7 +1127,7 @@ __global__ __launch_bounds__(64 * kM2LBWaves, 2) void k_m2l_bf16(
     const int tile = blockIdx.x;
     if (tile >= ntiles) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const M2LCols cols{tpt, fpt, (int)blockIdx.y * fpt, F};
+    const M2LCols cols{tpt, fpt, (int)blockIdx.y * fpt, F, dstr};
     for (int i = tid; i < 2 * 3 * 16 * KSTR; i += blockDim.x) s_Q[i] = (__bf16)0.0f;  // padding stays zero
     for (int i = tid; i < 2 * 3 * (ND + 1); i += blockDim.x) s_D[i] = (__bf16)0.0f;   // zero slots
     __syncthreads();
@@ -1164,7 +1167,7 @@ __global__ __launch_bounds__(64 * kM2LBWaves, 2) void k_m2l_bf16(
         const double is = 1.0 / ldexp(side, -cell_i[CI_N * A + CI_LEVEL]);
         double sp = is;
         for (int k = 0; k < dm; ++k) sp *= is;
-        atomicAdd(&L[((int64_t)field * C + A) * NC + m],
+        atomicAdd(&L[((int64_t)field * C + A) * lstr + m],
                   lt * kInv4Pi * sp * c_bin.invfact[mx] * c_bin.invfact[my] * c_bin.invfact[mz]);
     }
 }
@@ -2216,7 +2219,7 @@ void launch_m2l_p(DevicePlan &dp, const DevicePlan::Tiles &tl, const T *D, const
     const unsigned groups = (unsigned)((F + fpt - 1) / fpt);
     k_m2l_mfma<T, P><<<dim3(tl.ntiles, groups), dim3(64 * kM2LWaves), 0, st>>>(
         tl.tile_tgt, tl.tile_rng, tl.ent_key, tl.ent_src, dp.m2l_keys, D, Qt, dp.qpad, dp.cell_i, hp.side,
-        (int64_t)hp.cells.size(), tl.tpt, fpt, F, tl.ntiles, dp.L);
+        (int64_t)hp.cells.size(), tl.tpt, fpt, F, tl.ntiles, m2l_table_width(hp.p), dp.ncoef, dp.L);
     hip_check(hipGetLastError(), "k_m2l_mfma launch");
 }
 
@@ -2228,15 +2231,16 @@ void launch_m2lb_p(DevicePlan &dp, const DevicePlan::Tiles &tl, const float *D, 
     const unsigned groups = (unsigned)((F + fpt - 1) / fpt);
     k_m2l_bf16<P, NP><<<dim3(tl.ntiles, groups), dim3(64 * kM2LBWaves), 0, st>>>(
         tl.tile_tgt, tl.tile_rng, tl.ent_key, tl.ent_src, dp.m2l_keys, D, Qt, dp.qpad, dp.cell_i, hp.side,
-        (int64_t)hp.cells.size(), tl.tpt, fpt, F, tl.ntiles, dp.L);
+        (int64_t)hp.cells.size(), tl.tpt, fpt, F, tl.ntiles, m2l_table_width(hp.p), dp.ncoef, dp.L);
     hip_check(hipGetLastError(), "k_m2l_bf16 launch");
 }
 
+// (p: the order of the translation, the plan's or a level's)
 template <int NP>
 void launch_m2lb_t(DevicePlan &dp, const DevicePlan::Tiles &tl, const float *D, const float *Qt, int fpt, int32_t F,
-                   hipStream_t st)
+                   hipStream_t st, int p)
 {
-    switch (dp.hp.p) {
+    switch (p) {
     case 1: launch_m2lb_p<1, NP>(dp, tl, D, Qt, fpt, F, st); break;
     case 2: launch_m2lb_p<2, NP>(dp, tl, D, Qt, fpt, F, st); break;
     case 3: launch_m2lb_p<3, NP>(dp, tl, D, Qt, fpt, F, st); break;
@@ -2253,9 +2257,9 @@ void launch_m2lb_t(DevicePlan &dp, const DevicePlan::Tiles &tl, const float *D, 
 
 template <typename T>
 void launch_m2l_t(DevicePlan &dp, const DevicePlan::Tiles &tl, const T *D, const T *Qt, int fpt, int32_t F,
-                  hipStream_t st)
+                  hipStream_t st, int p)
 {
-    switch (dp.hp.p) {
+    switch (p) {
     case 1: launch_m2l_p<T, 1>(dp, tl, D, Qt, fpt, F, st); break;
     case 2: launch_m2l_p<T, 2>(dp, tl, D, Qt, fpt, F, st); break;
     case 3: launch_m2l_p<T, 3>(dp, tl, D, Qt, fpt, F, st); break;
@@ -2279,6 +2283,20 @@ int m2l_fpt(int32_t F)
     return fpt;
 }
 
+// The translations of one tile list at order p in the plan's M2L precision.
+void launch_m2l_tiles(DevicePlan &dp, const DevicePlan::Tiles &tl, int fpt, int32_t F, hipStream_t st, int p)
+{
+    if (tl.ntiles == 0) return;
+    if (dp.m2l_precision == TFMM_M2L_BF16X3)
+        launch_m2lb_t<2>(dp, tl, dp.m2l_Df, dp.Qtf, fpt, F, st, p);
+    else if (dp.m2l_precision == TFMM_M2L_BF16X6)
+        launch_m2lb_t<3>(dp, tl, dp.m2l_Df, dp.Qtf, fpt, F, st, p);
+    else if (dp.m2l_precision == TFMM_M2L_FP32)
+        launch_m2l_t<float>(dp, tl, dp.m2l_Df, dp.Qtf, fpt, F, st, p);
+    else
+        launch_m2l_t<double>(dp, tl, dp.m2l_D, dp.Qt, fpt, F, st, p);
+}
+
 void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
 {
     const HostPlan &hp = dp.hp;
@@ -2291,19 +2309,19 @@ void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
     if (dp.m2l_precision != TFMM_M2L_FP64) {  // FP32 operands (FP32, BF16x3, BF16x6)
         if (!dp.m2l_Df || dp.qtf_cap < F) throw DeviceError{"M2L buffers not prepared"};
         k_qreduce<float><<<qgrid, dim3(256), 0, st>>>(dp.Q, dp.cell_i, C, hp.side, hp.p, dp.qpad, dp.Qtf);
-        hip_check(hipGetLastError(), "k_qreduce launch");
-        if (dp.m2l_precision == TFMM_M2L_BF16X3)
-            launch_m2lb_t<2>(dp, tl, dp.m2l_Df, dp.Qtf, fpt, F, st);
-        else if (dp.m2l_precision == TFMM_M2L_BF16X6)
-            launch_m2lb_t<3>(dp, tl, dp.m2l_Df, dp.Qtf, fpt, F, st);
-        else
-            launch_m2l_t<float>(dp, tl, dp.m2l_Df, dp.Qtf, fpt, F, st);
     } else {
         if (dp.qt_cap < F) throw DeviceError{"M2L buffers not prepared"};
         k_qreduce<double><<<qgrid, dim3(256), 0, st>>>(dp.Q, dp.cell_i, C, hp.side, hp.p, dp.qpad, dp.Qt);
-        hip_check(hipGetLastError(), "k_qreduce launch");
-        launch_m2l_t<double>(dp, tl, dp.m2l_D, dp.Qt, fpt, F, st);
     }
+    hip_check(hipGetLastError(), "k_qreduce launch");
+    if (!dp.level_orders) {
+        launch_m2l_tiles(dp, tl, fpt, F, st, hp.p);
+        return;
+    }
+    // per-level orders: one launch per target level at that level's order
+    // (the source multipoles already hold no terms above their own level's)
+    const std::vector<DevicePlan::Tiles> &lt = ensure_m2l_level_tiles(dp, 16 / fpt);
+    for (size_t lv = 0; lv < lt.size(); ++lv) launch_m2l_tiles(dp, lt[lv], fpt, F, st, dp.lo.q[lv]);
 }
 
 }  // namespace
@@ -2418,25 +2436,23 @@ void build_m2l_table(DevicePlan &dp)
     hip_check(hipDeviceSynchronize(), "k_m2l_table");
 }
 
-DevicePlan::Tiles &ensure_m2l_tiles(DevicePlan &dp, int tpt)
+static void free_tiles(DevicePlan &dp, DevicePlan::Tiles &t)
 {
-    int slot = 0;
-    while ((16 >> slot) != tpt && slot < 4) ++slot;
-    if ((16 >> slot) != tpt) throw DeviceError{"bad M2L tile width"};
-    DevicePlan::Tiles &t = dp.m2l_tiles[slot];
-    if (t.tpt == tpt && t.max_ent == dp.m2l_max_ent) return t;
-    // a captured graph may hold the old tile pointers
-    ++dp.schedule_gen;
     for (int32_t *q : {t.tile_tgt, t.tile_rng, t.ent_key, t.ent_src})
         if (q) (void)hipFree(q);
+    dp.device_bytes -= t.bytes;
     t = DevicePlan::Tiles{};
-    M2LTiles h;
-    build_m2l_tiles(dp.hp, tpt, dp.m2l_max_ent, h);
+}
+
+static void upload_tiles(DevicePlan &dp, const M2LTiles &h, int tpt, DevicePlan::Tiles &t)
+{
     auto up = [&](const std::vector<int32_t> &v, int32_t *&d) {
-        hip_check(hipMalloc(&d, sizeof(int32_t) * std::max<size_t>(v.size(), 1)), "hipMalloc M2L tiles");
+        const size_t b = sizeof(int32_t) * std::max<size_t>(v.size(), 1);
+        hip_check(hipMalloc(&d, b), "hipMalloc M2L tiles");
+        t.bytes += (int64_t)b;
+        dp.device_bytes += (int64_t)b;
         if (!v.empty())
             hip_check(hipMemcpy(d, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice), "hipMemcpy M2L tiles");
-        dp.device_bytes += (int64_t)(sizeof(int32_t) * std::max<size_t>(v.size(), 1));
     };
     up(h.tile_tgt, t.tile_tgt);
     up(h.tile_rng, t.tile_rng);
@@ -2446,7 +2462,44 @@ DevicePlan::Tiles &ensure_m2l_tiles(DevicePlan &dp, int tpt)
     t.nent = (int64_t)h.ent_key.size();
     t.tpt = tpt;
     t.max_ent = dp.m2l_max_ent;
+}
+
+DevicePlan::Tiles &ensure_m2l_tiles(DevicePlan &dp, int tpt)
+{
+    int slot = 0;
+    while ((16 >> slot) != tpt && slot < 4) ++slot;
+    if ((16 >> slot) != tpt) throw DeviceError{"bad M2L tile width"};
+    DevicePlan::Tiles &t = dp.m2l_tiles[slot];
+    if (t.tpt == tpt && t.max_ent == dp.m2l_max_ent) return t;
+    // a captured graph may hold the old tile pointers
+    ++dp.schedule_gen;
+    free_tiles(dp, t);
+    M2LTiles h;
+    build_m2l_tiles(dp.hp, tpt, dp.m2l_max_ent, h);
+    upload_tiles(dp, h, tpt, t);
     return t;
+}
+
+void drop_m2l_level_tiles(DevicePlan &dp)
+{
+    if (!dp.lvl_tiles.empty()) ++dp.schedule_gen;  // a captured graph may hold them
+    for (auto &t : dp.lvl_tiles) free_tiles(dp, t);
+    dp.lvl_tiles.clear();
+}
+
+const std::vector<DevicePlan::Tiles> &ensure_m2l_level_tiles(DevicePlan &dp, int tpt)
+{
+    if (!dp.lvl_tiles.empty() && dp.lvl_tiles[0].tpt == tpt && dp.lvl_tiles[0].max_ent == dp.m2l_max_ent)
+        return dp.lvl_tiles;
+    drop_m2l_level_tiles(dp);
+    ++dp.schedule_gen;
+    dp.lvl_tiles.resize((size_t)dp.hp.depth + 1);
+    for (int lv = 0; lv <= dp.hp.depth; ++lv) {
+        M2LTiles h;
+        build_m2l_tiles(dp.hp, tpt, dp.m2l_max_ent, h, lv);
+        upload_tiles(dp, h, tpt, dp.lvl_tiles[lv]);
+    }
+    return dp.lvl_tiles;
 }
 
 void collect_timing(DevicePlan &dp)
@@ -2501,6 +2554,7 @@ void prepare_evaluate(DevicePlan &dp, int32_t F)
     }
     ensure_expansions(dp, F);
     ensure_m2l_tiles(dp, 16 / m2l_fpt(F));
+    if (dp.level_orders) ensure_m2l_level_tiles(dp, 16 / m2l_fpt(F));
     if (dp.m2l_precision != TFMM_M2L_FP64) {
         if (!dp.m2l_Df) {
             ++dp.schedule_gen;
@@ -2632,7 +2686,7 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
             const size_t lds = sizeof(double) * (size_t)kP2MStage * (dp.ncoef + 12 * FC);
             k_p2m<FC><<<dim3(xcd_grid(dp.n_p2m_cells), (F + FC - 1) / FC), dim3(kP2MThreads), lds, st>>>(
                 dp.p2m_cells, dp.cell_i, dp.cell_c, C, dp.tet_xyz, dp.tet_node, hp.n_tets, dp.tet_mom, M, hp.n_nodes, F,
-                p, dp.n_p2m_cells, hp.points ? 1 : 0, dp.Q);
+                p, dp.n_p2m_cells, hp.points ? 1 : 0, dp.lo, dp.Q);
             hip_check(hipGetLastError(), "k_p2m launch");
         });
     }
@@ -2642,7 +2696,7 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
             int b = dp.m2m_level_ptr[Lv], e = dp.m2m_level_ptr[Lv + 1];
             if (e > b) {
                 k_m2m<<<dim3(e - b, F), dim3(kShiftThreads), shift_lds, st>>>(dp.m2m_cells + b, dp.cell_i, dp.cell_c,
-                                                                                  C, p, dp.Q);
+                                                                                  C, p, dp.lo.q[Lv], dp.Q);
                 hip_check(hipGetLastError(), "k_m2m launch");
             }
         }
@@ -2657,7 +2711,7 @@ void run_evaluate(DevicePlan &dp, const double *M, int32_t F, double *u, hipStre
             int b = dp.l2l_level_ptr[Lv], e = dp.l2l_level_ptr[Lv + 1];
             if (e > b) {
                 k_l2l<<<dim3((e - b + kShiftItems - 1) / kShiftItems, F), dim3(kShiftThreads), shift_lds, st>>>(
-                    dp.l2l_cells + b, e - b, dp.cell_i, dp.cell_c, C, p, dp.L);
+                    dp.l2l_cells + b, e - b, dp.cell_i, dp.cell_c, C, p, dp.lo.q[Lv], dp.L);
                 hip_check(hipGetLastError(), "k_l2l launch");
             }
         }

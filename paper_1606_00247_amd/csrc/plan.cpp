@@ -353,7 +353,7 @@ void build_m2l_keys(HostPlan &hp)
 
 }  // namespace
 
-void build_m2l_tiles(const HostPlan &hp, int tpt, int max_ent, M2LTiles &out)
+void build_m2l_tiles(const HostPlan &hp, int tpt, int max_ent, M2LTiles &out, int only_level)
 {
     out.tpt = tpt;
     out.tile_tgt.clear();
@@ -408,6 +408,7 @@ void build_m2l_tiles(const HostPlan &hp, int tpt, int max_ent, M2LTiles &out)
     for (int64_t a = 0; a < nc; ++a) {
         if (hp.m2l_ptr[a + 1] == hp.m2l_ptr[a]) continue;
         const Cell &c = hp.cells[a];
+        if (only_level >= 0 && c.level != only_level) continue;
         const uint64_t mp = morton((uint32_t)c.ix >> 1, (uint32_t)c.iy >> 1, (uint32_t)c.iz >> 1);
         const uint64_t oct = (uint64_t)((c.ix & 1) | (c.iy & 1) << 1 | (c.iz & 1) << 2);
         lvl[c.level].push_back({((mp >> tbits) << (3 + tbits)) | (oct << tbits) | (mp & ((1u << tbits) - 1)), (int32_t)a});

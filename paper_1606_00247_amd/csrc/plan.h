@@ -128,8 +128,9 @@ struct PlanError {
 };
 
 // Groups the M2L pairs of a built plan into target tiles of tpt cells and
-// work items of at most max_ent entries.
-void build_m2l_tiles(const HostPlan &hp, int tpt, int max_ent, M2LTiles &out);
+// work items of at most max_ent entries (only target cells of level
+// only_level when it is >= 0).
+void build_m2l_tiles(const HostPlan &hp, int tpt, int max_ent, M2LTiles &out, int only_level = -1);
 
 // Builds the plan.  Throws PlanError on invalid input.  With points = true
 // the sources are the n_nodes points `nodes` (tets is ignored).
