@@ -123,6 +123,9 @@ typedef struct {
     int32_t surrogate;    /* TFMM_SUR_* of the plan */
     int32_t surrogate_hidden; /* width of the attached network, 0 if none */
     int32_t level_order[22];  /* expansion order of octree levels 0..21 (all p unless set) */
+    int32_t m2l_packed;         /* schedule: 1 if M2L of fewer than 16 fields runs packed by key */
+    int32_t m2l_groups_per_item; /* schedule: key groups per packed M2L workgroup item */
+    int64_t m2l_groups;         /* packed M2L: groups of 16 matrix-core columns of one key (one field; 0 until built) */
 } tfmm_stats;
 
 /*
@@ -287,8 +290,9 @@ int tfmm_plan_stats(tfmm_plan plan, tfmm_stats *out);
 /*
  * Interaction lists as integer cell coordinates, for verification.
  *  kind 0 = M2L pairs, 1 = P2P pairs, 2 = the M2L pairs in the order the
- *  matrix-core tiles (16 target cells) schedule them: the same set as
- *  kind 0, each pair once.
+ *  matrix-core tiles (16 target cells) schedule them, 3 = the M2L pairs in
+ *  the order the key-packed groups of one field schedule them: kinds 2 and
+ *  3 are the same set as kind 0, each pair once.
  *  out  host, [n][8] int32: levelA, ixA, iyA, izA, levelB, ixB, iyB, izB
  *       (A target cell, B source cell; a cell at level L covers
  *       [origin + i s, origin + (i+1) s) per axis with s = side / 2^L), or
@@ -401,14 +405,20 @@ int tfmm_plan_autotune(tfmm_plan plan, void *hip_stream);
 
 /*
  * Set the schedule knobs that tfmm_plan_autotune picks: M2L keys per
- * workgroup item (16..4096) and the P2P workgroup shape for one or two fields
- * (p2p_wide 1: four wavefronts per block; 0: one).  Every choice computes the
- * same arithmetic; the point is to run a given schedule (for instance the one
- * a benchmark timed) under test.  Builds the M2L tiles of the new item size
+ * workgroup item of the tiled form (16..4096), the P2P workgroup shape for
+ * one or two fields (p2p_wide 1: four wavefronts per block; 0: one), and
+ * the M2L form for fewer than 16 fields with FP64 or FP32 translations
+ * (m2l_packed 1: the translations of each key are packed 16 columns at a
+ * time inside blocks of target cells, m2l_groups_per_item (16..4096) such
+ * groups per workgroup item; 0: target tiles run through their keys).
+ * Every choice computes the same contraction (sums in another order); the
+ * point is to run a given schedule (for instance the one a benchmark timed)
+ * under test.  Builds the M2L work lists of the new schedule for one field
  * (synchronous).  Errors: TFMM_EINVAL (NULL or host-only plan, values out of
  * range), TFMM_EDEVICE.
  */
-int tfmm_plan_set_schedule(tfmm_plan plan, int32_t m2l_keys_per_item, int32_t p2p_wide);
+int tfmm_plan_set_schedule(tfmm_plan plan, int32_t m2l_keys_per_item, int32_t p2p_wide, int32_t m2l_packed,
+                           int32_t m2l_groups_per_item);
 
 /*
  * The elementary functions of the exact near-field integral (Sec. 2.1: its

@@ -69,7 +69,8 @@ class _Stats(C.Structure):
         ("m2l_keys_per_item", C.c_int32), ("p2p_wide", C.c_int32),
         ("p2p_node_evals", C.c_int64), ("p2p_edge_evals", C.c_int64), ("p2p_face_evals", C.c_int64),
         ("n_band_pairs", C.c_int64), ("surrogate", C.c_int32), ("surrogate_hidden", C.c_int32),
-        ("level_order", C.c_int32 * 22)]
+        ("level_order", C.c_int32 * 22), ("m2l_packed", C.c_int32), ("m2l_groups_per_item", C.c_int32),
+        ("m2l_groups", C.c_int64)]
 
 
 class TetFMMError(RuntimeError):
@@ -117,7 +118,7 @@ def _load():
         "tfmm_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
         "tfmm_kernel_times": (C.c_int, [C.c_void_p, _dp, _i64p]),
         "tfmm_plan_autotune": (C.c_int, [C.c_void_p, C.c_void_p]),
-        "tfmm_plan_set_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+        "tfmm_plan_set_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
         "tfmm_elementary": (C.c_int, [C.c_int32, _dp, _dp, _dp, C.c_int64, C.c_int32]),
         "tfmm_demag_field_nodes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
         "tfmm_demag_energy_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -288,9 +289,10 @@ def tfmm_plan_autotune(plan, stream=None):
     _check(_load().tfmm_plan_autotune(plan.handle, _stream_handle(stream, dev)))
 
 
-def tfmm_plan_set_schedule(plan, m2l_keys_per_item, p2p_wide):
+def tfmm_plan_set_schedule(plan, m2l_keys_per_item, p2p_wide, m2l_packed=1, m2l_groups_per_item=256):
     """Set the schedule knobs tfmm_plan_autotune picks (same results, other launch shapes)."""
-    _check(_load().tfmm_plan_set_schedule(plan.handle, int(m2l_keys_per_item), int(p2p_wide)))
+    _check(_load().tfmm_plan_set_schedule(plan.handle, int(m2l_keys_per_item), int(p2p_wide), int(m2l_packed),
+                                          int(m2l_groups_per_item)))
 
 
 ELEMENTARY = {"log_ratio": 0, "atan2": 1, "div": 2, "rsqrt": 3}
@@ -507,9 +509,10 @@ def tfmm_plan_stats(plan):
 
 
 def tfmm_plan_lists(plan, kind):
-    """kind 'm2l', 'p2p' or 'm2l_tiles' (the M2L pairs as the matrix-core
-    tiles schedule them) -> int32 [n, 8] (levA, ixA, iyA, izA, levB, ixB, iyB, izB)."""
-    k = {"m2l": 0, "p2p": 1, "m2l_tiles": 2}[kind]
+    """kind 'm2l', 'p2p', 'm2l_tiles' or 'm2l_packs' (the M2L pairs as the
+    matrix-core tiles or the key-packed groups schedule them) -> int32 [n, 8]
+    (levA, ixA, iyA, izA, levB, ixB, iyB, izB)."""
+    k = {"m2l": 0, "p2p": 1, "m2l_tiles": 2, "m2l_packs": 3}[kind]
     n = _check(_load().tfmm_plan_lists(plan.handle, k, None))
     out = np.zeros((n, 8), dtype=np.int32)
     _check(_load().tfmm_plan_lists(plan.handle, k, _ptr(out, _i32p)))

@@ -313,6 +313,8 @@ void free_plan(DevicePlan &dp)
         for (void *p : tp)
             if (p) (void)hipFree(p);
     }
+    tfmm::free_m2l_packs(dp);
+    if (dp.Lr) (void)hipFree(dp.Lr);
 }
 
 }  // namespace tfmm
@@ -483,13 +485,17 @@ int tfmm_plan_stats(tfmm_plan plan, tfmm_stats *out)
     out->surrogate = plan->dp.sur_mode;
     out->surrogate_hidden = plan->dp.sur_hidden;
     for (int l = 0; l < 22; ++l) out->level_order[l] = plan->dp.lo.q[l];
+    out->m2l_packed = plan->dp.m2l_pack ? 1 : 0;
+    out->m2l_groups_per_item = plan->dp.m2l_max_grp;
+    out->m2l_groups = plan->dp.m2l_packs[0].ngrp;
     return TFMM_OK;
 }
 
 int64_t tfmm_plan_lists(tfmm_plan plan, int32_t kind, int32_t *out)
 {
     if (!plan) return set_error(TFMM_EINVAL, "NULL plan");
-    if (kind < 0 || kind > 2) return set_error(TFMM_EINVAL, "kind must be 0 (M2L), 1 (P2P) or 2 (M2L tile schedule)");
+    if (kind < 0 || kind > 3)
+        return set_error(TFMM_EINVAL, "kind must be 0 (M2L), 1 (P2P), 2 (M2L tile schedule) or 3 (M2L packed schedule)");
     const tfmm::HostPlan &hp = plan->dp.hp;
     auto put = [&](int64_t k, int32_t a, int32_t b) {
         const tfmm::Cell &A = hp.cells[a], &B = hp.cells[b];
@@ -528,6 +534,27 @@ int64_t tfmm_plan_lists(tfmm_plan plan, int32_t kind, int32_t *out)
                     if (out) put(k, a, b);
                     ++k;
                 }
+        return k;
+    }
+    if (kind == 3) {  // the pairs as the packed form (one field, the plan's order) schedules them
+        tfmm::M2LPacks pk;
+        try {
+            tfmm::build_m2l_packs(hp, hp.p <= 8 ? 128 : 64, 16, plan->dp.m2l_max_grp, pk);
+        } catch (const tfmm::PlanError &e) {
+            return set_error(e.code, e.msg);
+        }
+        int64_t k = 0;
+        for (size_t i = 0; 3 * i < pk.item.size(); ++i) {
+            const int32_t blk = pk.item[3 * i];
+            for (int32_t g = pk.item[3 * i + 1]; g < pk.item[3 * i + 2]; ++g)
+                for (int s = 0; s < pk.tpg; ++s) {
+                    const int32_t b = pk.grp_src[(size_t)g * pk.tpg + s];
+                    if (b < 0) continue;
+                    const int32_t a = pk.blk_cells[(size_t)blk * pk.nb + pk.grp_slot[(size_t)g * pk.tpg + s]];
+                    if (out) put(k, a, b);
+                    ++k;
+                }
+        }
         return k;
     }
     int64_t n = (int64_t)hp.p2p_a.size();
@@ -591,7 +618,10 @@ int tfmm_plan_set_level_orders(tfmm_plan plan, const int32_t *orders, int32_t n)
         }
         if (plan->on_device) {
             DeviceScope ds(dp.device);
-            if (!differ) tfmm::drop_m2l_level_tiles(dp);
+            if (!differ) {
+                tfmm::drop_m2l_level_tiles(dp);
+                tfmm::free_m2l_packs(dp);
+            }
         }
         dp.level_orders = differ;
         ++dp.schedule_gen;
@@ -714,16 +744,21 @@ int tfmm_elementary(int32_t fn, const double *a, const double *b, double *out, i
     });
 }
 
-int tfmm_plan_set_schedule(tfmm_plan plan, int32_t m2l_keys_per_item, int32_t p2p_wide)
+int tfmm_plan_set_schedule(tfmm_plan plan, int32_t m2l_keys_per_item, int32_t p2p_wide, int32_t m2l_packed,
+                           int32_t m2l_groups_per_item)
 {
     if (!plan) return set_error(TFMM_EINVAL, "NULL plan");
     if (!plan->on_device) return set_error(TFMM_EINVAL, "host-only plan");
-    if (m2l_keys_per_item < 16 || m2l_keys_per_item > 4096 || (p2p_wide != 0 && p2p_wide != 1))
-        return set_error(TFMM_EINVAL, "m2l_keys_per_item must be in [16, 4096] and p2p_wide 0 or 1");
+    if (m2l_keys_per_item < 16 || m2l_keys_per_item > 4096 || (p2p_wide != 0 && p2p_wide != 1) ||
+        (m2l_packed != 0 && m2l_packed != 1) || m2l_groups_per_item < 16 || m2l_groups_per_item > 4096)
+        return set_error(TFMM_EINVAL, "m2l_keys_per_item and m2l_groups_per_item must be in [16, 4096], "
+                                      "p2p_wide and m2l_packed 0 or 1");
     return guarded([&]() -> int {
         DeviceScope ds(plan->dp.device);
         plan->dp.m2l_max_ent = m2l_keys_per_item;
         plan->dp.p2p_wide = p2p_wide != 0;
+        plan->dp.m2l_pack = m2l_packed != 0;
+        plan->dp.m2l_max_grp = m2l_groups_per_item;
         ++plan->dp.schedule_gen;
         tfmm::prepare_evaluate(plan->dp, 1);  // the tiles of the new work item size
         return TFMM_OK;

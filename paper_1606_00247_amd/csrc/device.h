@@ -87,6 +87,24 @@ struct DevicePlan {
     LevelOrders lo{};
     bool level_orders = false;
     std::vector<Tiles> lvl_tiles;
+    // M2L packed by key in blocks of target cells (fewer than 16 fields, FP64
+    // and FP32 translations): per field width fpt = 1, 2, 4, 8 (built on
+    // demand), and per level when the levels have their own orders; the
+    // reduced locals Lr [F][C][lrs] they accumulate into
+    struct Packs {
+        int nb = 0, tpg = 0, max_grp = 0, p = 0;
+        int32_t *blk_cells = nullptr, *item = nullptr, *grp_key = nullptr, *grp_src = nullptr;
+        uint8_t *grp_slot = nullptr;
+        int32_t nitems = 0;
+        int64_t ngrp = 0, npairs = 0;
+        int64_t bytes = 0;
+    };
+    Packs m2l_packs[4];
+    std::vector<Packs> lvl_packs;
+    bool m2l_pack = true;  // schedule knob: the packed form where it applies
+    int m2l_max_grp = 256;  // groups per packed work item
+    double *Lr = nullptr;
+    int32_t lr_cap = 0;
     int m2l_precision = 0;  // TFMM_M2L_*
     // schedule knobs (tfmm_plan_autotune): keys per M2L work item, and four
     // wavefronts per P2P workgroup also for one or two fields
@@ -200,6 +218,7 @@ void build_m2l_table(DevicePlan &dp);
 DevicePlan::Tiles &ensure_m2l_tiles(DevicePlan &dp, int tpt);
 // The same per target level (for per-level orders), and their release.
 const std::vector<DevicePlan::Tiles> &ensure_m2l_level_tiles(DevicePlan &dp, int tpt);
+void free_m2l_packs(DevicePlan &dp);
 void drop_m2l_level_tiles(DevicePlan &dp);
 
 // Allocate everything an evaluation of F fields needs (expansions, M2L tiles

@@ -925,6 +925,194 @@ __global__ __launch_bounds__(64 * kM2LWaves, 2) void k_m2l_mfma(
 }
 
 // ---------------------------------------------------------------------------
+// M2L packed by key (fewer than 16 fields).
+//
+// The contraction is that of k_m2l_mfma (scaled, harmonically reduced
+// multipoles; Hankel operand H[m][n] = D_{n+m} of the key; outputs Lr with
+// m_z <= 1), but the 16 matrix-core columns of a step are 16 / fpt
+// translations of one key x fpt fields, taken from a block of up to
+// nb = slots / fpt target cells: every column carries a translation except
+// in the last group of each key.  The reduced locals of the block's
+// (cell, field) slots are summed in LDS (FP64) and added to Lr once per
+// work item; k_lr_expand then expands Lr to all m and adds it to L.
+//
+// Each wavefront takes a contiguous run of the item's groups (consecutive
+// groups mostly share the key).  The key's derivative row is staged in the
+// wavefront's own LDS row when the key changes; the multipoles of the next
+// group are loaded into registers while the matrix cores work on the
+// current one (two register sets, loop unrolled by two).
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int m2l_all_steps(int P)
+{
+    int s = 0;
+    for (int rt = 0; rt < m2l_nrt(P); ++rt) s += m2l_ks(P, rt);
+    return s;
+}
+// LDS accumulator slots (target cell x field) of one packed block
+__host__ __device__ constexpr int m2lp_slots(int P) { return P <= 8 ? 128 : 64; }
+constexpr int kM2LPWaves = 4;
+
+template <typename T, int P>
+__global__ __launch_bounds__(64 * kM2LPWaves, P <= 8 ? 2 : 1) void k_m2l_pack(
+    const int32_t *__restrict__ item, int nitems, const int32_t *__restrict__ blk_cells, int nb, int tpg,
+    const int32_t *__restrict__ grp_key, const int32_t *__restrict__ grp_src, const uint8_t *__restrict__ grp_slot,
+    const int32_t *__restrict__ keys, const T *__restrict__ Dtab, int dstr, const T *__restrict__ Qr, int qpad,
+    int64_t C, int fpt, int F, double *__restrict__ Lr, int lrs)
+{
+    using v4 = typename Mfma<T>::v4;
+    constexpr int NR = nr_of(P), ND = nd_of(P), NROW = m2l_nrows(P), NRT = m2l_nrt(P), KS0 = m2l_ks(P, 0);
+    constexpr int NS = m2l_all_steps(P), NSLOT = m2lp_slots(P), DSTR = ND + 1;
+    __shared__ double s_L[NSLOT * NROW];
+    __shared__ T s_D[kM2LPWaves][2][DSTR];
+    const int it = blockIdx.x;
+    if (it >= nitems) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int col = lane & 15, pair = col / fpt, fsub = col % fpt, field = (int)blockIdx.y * fpt + fsub;
+    const bool fok = field < F;
+    for (int i = tid; i < NSLOT * NROW; i += blockDim.x) s_L[i] = 0.0;
+    if (lane < 2) s_D[w][lane][ND] = (T)0;  // the zero slot of each row
+    // this lane's table index of the A operand of every step (ks-major,
+    // row tiles inner; the zero slot outside |n| + |m| <= P), and the
+    // degree of its B-operand coefficient n = 4 ks + lane / 16 + 1
+    int didx[NS], qdeg[KS0];
+    {
+        int s = 0;
+#pragma unroll
+        for (int ks = 0; ks < KS0; ++ks) {
+            const int n = 1 + 4 * ks + (lane >> 4);
+            qdeg[ks] = n < NR ? c_red.r[n][3] : 0;
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+                if (ks < m2l_ks(P, rt)) {
+                    const int m = 16 * rt + (lane & 15);
+                    int di = ND;
+                    if (m < NROW && n < NR && c_red.r[m][3] + c_red.r[n][3] <= P)
+                        di = didx_of(c_red.r[m][0] + c_red.r[n][0], c_red.r[m][1] + c_red.r[n][1],
+                                     c_red.r[m][2] + c_red.r[n][2]);
+                    didx[s++] = di;
+                }
+        }
+    }
+    __syncthreads();
+    const int blk = item[3 * it], g0 = item[3 * it + 1], g1 = item[3 * it + 2];
+    const int wg0 = g0 + (int)((int64_t)(g1 - g0) * w / kM2LPWaves);
+    const int wg1 = g0 + (int)((int64_t)(g1 - g0) * (w + 1) / kM2LPWaves);
+    const T *qf = Qr + (int64_t)(fok ? field : 0) * C * qpad;
+    struct Ops {
+        T b[KS0];
+        int slot;
+        bool ok;
+    };
+    // loads of group g: clamped addresses, masked when used
+    auto fetch = [&](Ops &o, int g) {
+        const int src = grp_src[(int64_t)g * tpg + pair];
+        o.slot = grp_slot[(int64_t)g * tpg + pair];
+        o.ok = fok && src >= 0;
+        const T *q = qf + (int64_t)(o.ok ? src : 0) * qpad;
+#pragma unroll
+        for (int ks = 0; ks < KS0; ++ks) {
+            const int n = 1 + 4 * ks + (lane >> 4);
+            o.b[ks] = q[n < NR ? n : NR - 1];
+        }
+    };
+    int prev = -1, buf = 0, dl = 0;
+    auto run = [&](const Ops &o, int g) {
+        const int key = grp_key[g];
+        if (key != prev) {  // uniform over the wavefront
+            buf ^= 1;
+            T *D = s_D[w][buf];
+            for (int j = lane; j < ND; j += 64) D[j] = Dtab[(int64_t)key * dstr + j];
+            dl = keys[4 * key];
+            prev = key;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        const T *D = s_D[w][buf];
+        T b[KS0];
+#pragma unroll
+        for (int ks = 0; ks < KS0; ++ks) {
+            const int n = 1 + 4 * ks + (lane >> 4);
+            b[ks] = (o.ok && n < NR) ? (T)ldexp(o.b[ks], -dl * qdeg[ks]) : (T)0;  // 2^(-dl |n|), exact
+        }
+        v4 acc[NRT], acc0[2] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
+#pragma unroll
+        for (int rt = 0; rt < NRT; ++rt) acc[rt] = v4{0, 0, 0, 0};
+        int s = 0, r0 = 0;
+#pragma unroll
+        for (int ks = 0; ks < KS0; ++ks)
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+                if (ks < m2l_ks(P, rt)) {
+                    const T a = D[didx[s++]];
+                    if (rt == 0) {
+                        acc0[r0 & 1] = Mfma<T>::mma(a, b[ks], acc0[r0 & 1]);
+                        ++r0;
+                    } else {
+                        acc[rt] = Mfma<T>::mma(a, b[ks], acc[rt]);
+                    }
+                }
+        acc[0] = acc0[0] + acc0[1];
+        if (o.ok) {
+            double *Ls = s_L + (o.slot * fpt + fsub) * NROW;
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = 16 * rt + Mfma<T>::row(lane, r);
+                    if (m < NROW) atomicAdd(&Ls[m], (double)acc[rt][r]);
+                }
+        }
+    };
+    if (wg0 < wg1) {
+        Ops oa, ob;
+        fetch(oa, wg0);
+        for (int g = wg0; g < wg1; g += 2) {
+            if (g + 1 < wg1) fetch(ob, g + 1);
+            run(oa, g);
+            if (g + 1 < wg1) {
+                if (g + 2 < wg1) fetch(oa, g + 2);
+                run(ob, g + 1);
+            }
+        }
+    }
+    __syncthreads();
+    // add the block's reduced locals to Lr
+    for (int i = tid; i < NSLOT * NROW; i += blockDim.x) {
+        const double v = s_L[i];
+        if (v == 0.0) continue;
+        const int c = i / NROW, m = i - c * NROW;
+        const int fld = (int)blockIdx.y * fpt + c % fpt, cell = c / fpt < nb ? blk_cells[(int64_t)blk * nb + c / fpt] : -1;
+        if (cell >= 0 && fld < F) atomicAdd(&Lr[((int64_t)fld * C + cell) * lrs + m], v);
+    }
+}
+
+// L_m(A) += Lt_m(A) / (4 pi m! s_A^(|m|+1)), Lt expanded from the reduced
+// locals Lr (see k_m2l_mfma), for |m| < the order of A's level; one thread
+// per (cell, m), fields in blockIdx.y.
+__global__ void k_lr_expand(const double *__restrict__ Lr, int lrs, const int32_t *__restrict__ cell_i, double side,
+                            int64_t C, int ncoef, LevelOrders lo, double *__restrict__ L)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C * ncoef) return;
+    const int64_t A = i / ncoef;
+    const int m = (int)(i - A * ncoef), f = blockIdx.y;
+    const int lev = cell_i[CI_N * A + CI_LEVEL];
+    const int mx = c_mi.v[m][0], my = c_mi.v[m][1], mz = c_mi.v[m][2], dm = c_mi.v[m][3];
+    if (dm >= lo.q[lev]) return;
+    const double *red = Lr + ((int64_t)f * C + A) * lrs;
+    const int j = mz >> 1, cz = mz & 1;
+    double lt = 0.0;
+    for (int k = 0; k <= j; ++k) lt += c_bin.c[j][k] * red[ridx(mx + 2 * k, my + 2 * (j - k), cz)];
+    if (lt == 0.0) return;
+    if (j & 1) lt = -lt;
+    const double is = 1.0 / ldexp(side, -lev);
+    double sp = is;
+    for (int k = 0; k < dm; ++k) sp *= is;
+    L[((int64_t)f * C + A) * ncoef + m] += lt * kInv4Pi * sp * c_bin.invfact[mx] * c_bin.invfact[my] * c_bin.invfact[mz];
+}
+
+// ---------------------------------------------------------------------------
 // M2L with split BF16 operands on matrix cores (v_mfma_f32_16x16x32_bf16).
 //
 // The FP32 operands of the FP32 form (derivative rows and reduced multipoles,
@@ -2274,6 +2462,40 @@ void launch_m2l_t(DevicePlan &dp, const DevicePlan::Tiles &tl, const T *D, const
     }
 }
 
+template <typename T, int P>
+void launch_m2l_pack_p(DevicePlan &dp, const DevicePlan::Packs &k, const T *D, const T *Qt, int fpt, int32_t F,
+                       hipStream_t st)
+{
+    const HostPlan &hp = dp.hp;
+    if (k.nitems == 0) return;
+    if (k.nb * fpt != m2lp_slots(P) || k.tpg * fpt != 16 || k.p != P)
+        throw DeviceError{"M2L packs do not match the translation order"};
+    const unsigned groups = (unsigned)((F + fpt - 1) / fpt);
+    k_m2l_pack<T, P><<<dim3((unsigned)k.nitems, groups), dim3(64 * kM2LPWaves), 0, st>>>(
+        k.item, k.nitems, k.blk_cells, k.nb, k.tpg, k.grp_key, k.grp_src, k.grp_slot, dp.m2l_keys, D,
+        m2l_table_width(hp.p), Qt, dp.qpad, (int64_t)hp.cells.size(), fpt, F, dp.Lr, m2l_nrows(hp.p));
+    hip_check(hipGetLastError(), "k_m2l_pack launch");
+}
+
+template <typename T>
+void launch_m2l_pack_t(DevicePlan &dp, const DevicePlan::Packs &k, const T *D, const T *Qt, int fpt, int32_t F,
+                       hipStream_t st, int p)
+{
+    switch (p) {
+    case 1: launch_m2l_pack_p<T, 1>(dp, k, D, Qt, fpt, F, st); break;
+    case 2: launch_m2l_pack_p<T, 2>(dp, k, D, Qt, fpt, F, st); break;
+    case 3: launch_m2l_pack_p<T, 3>(dp, k, D, Qt, fpt, F, st); break;
+    case 4: launch_m2l_pack_p<T, 4>(dp, k, D, Qt, fpt, F, st); break;
+    case 5: launch_m2l_pack_p<T, 5>(dp, k, D, Qt, fpt, F, st); break;
+    case 6: launch_m2l_pack_p<T, 6>(dp, k, D, Qt, fpt, F, st); break;
+    case 7: launch_m2l_pack_p<T, 7>(dp, k, D, Qt, fpt, F, st); break;
+    case 8: launch_m2l_pack_p<T, 8>(dp, k, D, Qt, fpt, F, st); break;
+    case 9: launch_m2l_pack_p<T, 9>(dp, k, D, Qt, fpt, F, st); break;
+    case 10: launch_m2l_pack_p<T, 10>(dp, k, D, Qt, fpt, F, st); break;
+    default: throw DeviceError{"unsupported expansion order"};
+    }
+}
+
 // Scaled multipoles, then the translations, in the plan's M2L precision.
 // Field tile width of M2L for F fields: FPT fields x 16/FPT target cells.
 int m2l_fpt(int32_t F)
@@ -2281,6 +2503,21 @@ int m2l_fpt(int32_t F)
     int fpt = 1;
     while (fpt * 2 <= std::min<int32_t>(F, 16)) fpt *= 2;
     return fpt;
+}
+
+// Whether M2L runs in the packed form: fewer than 16 fields (the tiles of 16
+// or more fields carry one target cell x 16 fields, every column used) and
+// FP64 or FP32 translations.
+bool m2l_packed(const DevicePlan &dp, int32_t F)
+{
+    return dp.m2l_pack && m2l_fpt(F) < 16 &&
+           (dp.m2l_precision == TFMM_M2L_FP64 || dp.m2l_precision == TFMM_M2L_FP32);
+}
+int m2l_pack_slot(int fpt)
+{
+    int s = 0;
+    while ((1 << s) < fpt) ++s;
+    return s;
 }
 
 // The translations of one tile list at order p in the plan's M2L precision.
@@ -2302,8 +2539,7 @@ void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
     const HostPlan &hp = dp.hp;
     const int64_t C = (int64_t)hp.cells.size();
     const int fpt = m2l_fpt(F);
-    const DevicePlan::Tiles &tl = ensure_m2l_tiles(dp, 16 / fpt);
-    if (tl.ntiles == 0) return;
+    if (hp.m2l_src.empty()) return;
     const int64_t nq = C * dp.qpad;
     const dim3 qgrid((unsigned)((nq + 255) / 256), F);
     if (dp.m2l_precision != TFMM_M2L_FP64) {  // FP32 operands (FP32, BF16x3, BF16x6)
@@ -2314,8 +2550,30 @@ void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
         k_qreduce<double><<<qgrid, dim3(256), 0, st>>>(dp.Q, dp.cell_i, C, hp.side, hp.p, dp.qpad, dp.Qt);
     }
     hip_check(hipGetLastError(), "k_qreduce launch");
+    if (m2l_packed(dp, F)) {
+        if (dp.lr_cap < F) throw DeviceError{"M2L buffers not prepared"};
+        const int lrs = m2l_nrows(hp.p);
+        fill(dp.Lr, (int64_t)F * C * lrs, 0.0, st);
+        const bool f32 = dp.m2l_precision == TFMM_M2L_FP32;
+        auto go = [&](const DevicePlan::Packs &k, int p) {
+            if (f32)
+                launch_m2l_pack_t<float>(dp, k, dp.m2l_Df, dp.Qtf, fpt, F, st, p);
+            else
+                launch_m2l_pack_t<double>(dp, k, dp.m2l_D, dp.Qt, fpt, F, st, p);
+        };
+        if (!dp.level_orders) {
+            go(dp.m2l_packs[m2l_pack_slot(fpt)], hp.p);
+        } else {
+            for (size_t lv = 0; lv < dp.lvl_packs.size(); ++lv) go(dp.lvl_packs[lv], dp.lo.q[lv]);
+        }
+        const int64_t n = C * dp.ncoef;
+        k_lr_expand<<<dim3((unsigned)((n + 255) / 256), (unsigned)F), dim3(256), 0, st>>>(
+            dp.Lr, lrs, dp.cell_i, hp.side, C, dp.ncoef, dp.lo, dp.L);
+        hip_check(hipGetLastError(), "k_lr_expand launch");
+        return;
+    }
     if (!dp.level_orders) {
-        launch_m2l_tiles(dp, tl, fpt, F, st, hp.p);
+        launch_m2l_tiles(dp, ensure_m2l_tiles(dp, 16 / fpt), fpt, F, st, hp.p);
         return;
     }
     // per-level orders: one launch per target level at that level's order
@@ -2502,6 +2760,91 @@ const std::vector<DevicePlan::Tiles> &ensure_m2l_level_tiles(DevicePlan &dp, int
     return dp.lvl_tiles;
 }
 
+static void free_packs(DevicePlan &dp, DevicePlan::Packs &k)
+{
+    void *q[] = {k.blk_cells, k.item, k.grp_key, k.grp_src, k.grp_slot};
+    for (void *x : q)
+        if (x) (void)hipFree(x);
+    dp.device_bytes -= k.bytes;
+    k = DevicePlan::Packs{};
+}
+
+void free_m2l_packs(DevicePlan &dp)
+{
+    bool any = !dp.lvl_packs.empty();
+    for (auto &k : dp.m2l_packs) {
+        any = any || k.nb != 0;
+        free_packs(dp, k);
+    }
+    for (auto &k : dp.lvl_packs) free_packs(dp, k);
+    dp.lvl_packs.clear();
+    if (any) ++dp.schedule_gen;  // a captured graph may hold them
+}
+
+// Packs of fpt fields for translations of order p (all levels, or one).
+static void build_packs(DevicePlan &dp, int fpt, int p, int only_level, DevicePlan::Packs &k)
+{
+    M2LPacks h;
+    build_m2l_packs(dp.hp, m2lp_slots(p) / fpt, 16 / fpt, dp.m2l_max_grp, h, only_level);
+    auto up = [&](const auto &v, auto *&d) {
+        using E = typename std::decay_t<decltype(v)>::value_type;
+        const size_t b = sizeof(E) * std::max<size_t>(v.size(), 1);
+        hip_check(hipMalloc(&d, b), "hipMalloc M2L packs");
+        k.bytes += (int64_t)b;
+        dp.device_bytes += (int64_t)b;
+        if (!v.empty())
+            hip_check(hipMemcpy(d, v.data(), sizeof(E) * v.size(), hipMemcpyHostToDevice), "hipMemcpy M2L packs");
+    };
+    up(h.blk_cells, k.blk_cells);
+    up(h.item, k.item);
+    up(h.grp_key, k.grp_key);
+    up(h.grp_src, k.grp_src);
+    up(h.grp_slot, k.grp_slot);
+    k.nb = h.nb;
+    k.tpg = h.tpg;
+    k.max_grp = dp.m2l_max_grp;
+    k.p = p;
+    k.nitems = (int32_t)(h.item.size() / 3);
+    k.ngrp = (int64_t)h.grp_key.size();
+    k.npairs = 0;
+    for (int32_t s : h.grp_src) k.npairs += s >= 0;
+}
+
+static void ensure_m2l_packs(DevicePlan &dp, int32_t F)
+{
+    if (!m2l_packed(dp, F)) return;
+    const HostPlan &hp = dp.hp;
+    const int fpt = m2l_fpt(F);
+    if (!dp.level_orders) {
+        DevicePlan::Packs &k = dp.m2l_packs[m2l_pack_slot(fpt)];
+        if (k.nb == 0 || k.max_grp != dp.m2l_max_grp || k.p != hp.p) {
+            ++dp.schedule_gen;
+            free_packs(dp, k);
+            build_packs(dp, fpt, hp.p, -1, k);
+        }
+    } else {
+        bool ok = dp.lvl_packs.size() == (size_t)hp.depth + 1;
+        for (size_t lv = 0; ok && lv < dp.lvl_packs.size(); ++lv) {
+            const DevicePlan::Packs &k = dp.lvl_packs[lv];
+            ok = k.tpg * fpt == 16 && k.max_grp == dp.m2l_max_grp && k.p == dp.lo.q[lv];
+        }
+        if (!ok) {
+            ++dp.schedule_gen;
+            for (auto &k : dp.lvl_packs) free_packs(dp, k);
+            dp.lvl_packs.assign((size_t)hp.depth + 1, DevicePlan::Packs{});
+            for (int lv = 0; lv <= hp.depth; ++lv) build_packs(dp, fpt, dp.lo.q[lv], lv, dp.lvl_packs[lv]);
+        }
+    }
+    if (dp.lr_cap < F) {
+        ++dp.schedule_gen;
+        if (dp.Lr) (void)hipFree(dp.Lr);
+        dp.Lr = nullptr;
+        dp.lr_cap = 0;
+        hip_check(hipMalloc(&dp.Lr, sizeof(double) * (size_t)F * hp.cells.size() * m2l_nrows(hp.p)), "hipMalloc Lr");
+        dp.lr_cap = F;
+    }
+}
+
 void collect_timing(DevicePlan &dp)
 {
     for (const auto &sp : dp.spans) {
@@ -2553,8 +2896,12 @@ void prepare_evaluate(DevicePlan &dp, int32_t F)
         hip_check(hipEventCreateWithFlags(&dp.ev_join, hipEventDisableTiming), "hipEventCreate");
     }
     ensure_expansions(dp, F);
-    ensure_m2l_tiles(dp, 16 / m2l_fpt(F));
-    if (dp.level_orders) ensure_m2l_level_tiles(dp, 16 / m2l_fpt(F));
+    if (m2l_packed(dp, F)) {
+        ensure_m2l_packs(dp, F);
+    } else {
+        ensure_m2l_tiles(dp, 16 / m2l_fpt(F));
+        if (dp.level_orders) ensure_m2l_level_tiles(dp, 16 / m2l_fpt(F));
+    }
     if (dp.m2l_precision != TFMM_M2L_FP64) {
         if (!dp.m2l_Df) {
             ++dp.schedule_gen;
@@ -2619,16 +2966,33 @@ void autotune(DevicePlan &dp, hipStream_t st)
     dp.timing = false;
     try {
         fill(M, 3 * hp.n_nodes, 1.0, st);
-        // M2L work item size, then the P2P workgroup shape; the arithmetic of
-        // every candidate is the same, only the schedule differs
-        int best_ent = dp.m2l_max_ent;
+        // M2L form and work item size, then the P2P workgroup shape; every
+        // candidate computes the same contraction, only the schedule differs
+        int best_ent = dp.m2l_max_ent, best_grp = dp.m2l_max_grp;
+        bool best_pack = false;
         float best = -1.f;
+        dp.m2l_pack = false;
         for (int ent : {128, 256, 512, 1024}) {
             dp.m2l_max_ent = ent;
             const float t = time_config(dp, M, u, st);
             if (best < 0.f || t < best) best = t, best_ent = ent;
         }
         dp.m2l_max_ent = best_ent;
+        dp.m2l_pack = true;
+        if (m2l_packed(dp, 1)) {
+            for (int grp : {256, 512}) {
+                dp.m2l_max_grp = grp;
+                const float t = time_config(dp, M, u, st);
+                if (t < best) best = t, best_grp = grp, best_pack = true;
+            }
+        }
+        dp.m2l_pack = best_pack;
+        dp.m2l_max_grp = best_grp;
+        // the work lists of the form not taken are rebuilt if it is set later
+        if (best_pack)
+            free_tiles(dp, dp.m2l_tiles[0]);
+        else
+            free_m2l_packs(dp);
         bool best_wide = false;
         for (bool wide : {false, true}) {
             dp.p2p_wide = wide;

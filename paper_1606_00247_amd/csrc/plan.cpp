@@ -353,6 +353,45 @@ void build_m2l_keys(HostPlan &hp)
 
 }  // namespace
 
+// Dispatch order of M2L work items.  Workgroup w runs on XCD w % kM2LXcds
+// (round-robin), each XCD with its own L2.  The items of every level (in
+// octree order) are cut into kM2LXcds runs of about equal weight (range
+// length), run x going to XCD x, so that the items of one XCD are neighbours
+// in space and find their source multipoles in its L2; an XCD runs its items
+// longest first (stable).  Returns item ids per dispatch slot, -1 where an
+// XCD has no item left; slots that are empty on every XCD at the end are
+// dropped.
+static std::vector<int32_t> xcd_dispatch_order(const std::vector<std::array<int32_t, 2>> &rng,
+                                               const std::vector<int32_t> &lev)
+{
+    std::map<int, std::vector<int32_t>> by_level;
+    for (size_t i = 0; i < rng.size(); ++i) by_level[lev[i]].push_back((int32_t)i);
+    std::vector<std::vector<int32_t>> per(kM2LXcds);
+    for (const auto &kv : by_level) {
+        int64_t W = 0, acc = 0;
+        for (int32_t i : kv.second) W += rng[i][1] - rng[i][0];
+        for (int32_t i : kv.second) {
+            const int64_t w = rng[i][1] - rng[i][0];
+            const int x = (int)std::min<int64_t>(kM2LXcds - 1, (2 * acc + w) * kM2LXcds / std::max<int64_t>(2 * W, 1));
+            per[x].push_back(i);
+            acc += w;
+        }
+    }
+    size_t kmax = 0;
+    for (auto &v : per) {
+        std::stable_sort(v.begin(), v.end(), [&](int32_t x, int32_t y) {
+            return rng[x][1] - rng[x][0] > rng[y][1] - rng[y][0];
+        });
+        kmax = std::max(kmax, v.size());
+    }
+    std::vector<int32_t> slots;
+    slots.reserve(kmax * kM2LXcds);
+    for (size_t k = 0; k < kmax; ++k)
+        for (int x = 0; x < kM2LXcds; ++x) slots.push_back(k < per[x].size() ? per[x][k] : -1);
+    while (!slots.empty() && slots.back() < 0) slots.pop_back();
+    return slots;
+}
+
 void build_m2l_tiles(const HostPlan &hp, int tpt, int max_ent, M2LTiles &out, int only_level)
 {
     out.tpt = tpt;
@@ -423,52 +462,85 @@ void build_m2l_tiles(const HostPlan &hp, int tpt, int max_ent, M2LTiles &out, in
         }
         flush();
     }
-    // Dispatch order.  Workgroup w runs on XCD w % kM2LXcds (round-robin),
-    // each XCD with its own L2.  The items of every level (octree order) are
-    // cut into kM2LXcds runs of about equal entry count, run x going to XCD
-    // x, so that the tiles of one XCD are neighbours in space and find their
-    // source multipoles in its L2; an XCD runs its items longest first
-    // (stable).  Slots past the end of an XCD's list are empty items.
-    std::map<int, std::vector<int32_t>> by_level;
-    for (size_t i = 0; i < rng.size(); ++i) by_level[lev[i]].push_back((int32_t)i);
-    std::vector<std::vector<int32_t>> per(kM2LXcds);
-    for (const auto &kv : by_level) {
-        int64_t W = 0, acc = 0;
-        for (int32_t i : kv.second) W += rng[i][1] - rng[i][0];
-        for (int32_t i : kv.second) {
-            const int64_t w = rng[i][1] - rng[i][0];
-            const int x = (int)std::min<int64_t>(kM2LXcds - 1, (2 * acc + w) * kM2LXcds / std::max<int64_t>(2 * W, 1));
-            per[x].push_back(i);
-            acc += w;
+    const std::vector<int32_t> slots = xcd_dispatch_order(rng, lev);
+    out.tile_tgt.reserve(slots.size() * tpt);
+    out.tile_rng.reserve(2 * slots.size());
+    for (int32_t i : slots) {
+        if (i >= 0) {
+            out.tile_tgt.insert(out.tile_tgt.end(), tgt.begin() + (size_t)i * tpt, tgt.begin() + (size_t)(i + 1) * tpt);
+            out.tile_rng.push_back(rng[i][0]);
+            out.tile_rng.push_back(rng[i][1]);
+        } else {
+            out.tile_tgt.insert(out.tile_tgt.end(), (size_t)tpt, -1);
+            out.tile_rng.push_back(0);
+            out.tile_rng.push_back(0);
         }
     }
-    size_t kmax = 0;
-    for (auto &v : per) {
-        std::stable_sort(v.begin(), v.end(), [&](int32_t x, int32_t y) {
-            return rng[x][1] - rng[x][0] > rng[y][1] - rng[y][0];
-        });
-        kmax = std::max(kmax, v.size());
+}
+
+void build_m2l_packs(const HostPlan &hp, int nb, int tpg, int max_grp, M2LPacks &out, int only_level)
+{
+    if (nb < 1 || nb > 256 || tpg < 1 || max_grp < 1) throw PlanError{TFMM_EINVAL, "bad M2L pack shape"};
+    out = M2LPacks{};
+    out.nb = nb;
+    out.tpg = tpg;
+    const int64_t nc = (int64_t)hp.cells.size();
+    // target cells with translations, per level in Morton order
+    std::map<int, std::vector<std::pair<uint64_t, int32_t>>> lvl;
+    for (int64_t a = 0; a < nc; ++a) {
+        if (hp.m2l_ptr[a + 1] == hp.m2l_ptr[a]) continue;
+        const Cell &c = hp.cells[a];
+        if (only_level >= 0 && c.level != only_level) continue;
+        lvl[c.level].push_back({morton((uint32_t)c.ix, (uint32_t)c.iy, (uint32_t)c.iz), (int32_t)a});
     }
-    out.tile_tgt.reserve(kmax * kM2LXcds * tpt);
-    out.tile_rng.reserve(2 * kmax * kM2LXcds);
-    for (size_t k = 0; k < kmax; ++k)
-        for (int x = 0; x < kM2LXcds; ++x) {
-            if (k < per[x].size()) {
-                const int32_t i = per[x][k];
-                out.tile_tgt.insert(out.tile_tgt.end(), tgt.begin() + (size_t)i * tpt, tgt.begin() + (size_t)(i + 1) * tpt);
-                out.tile_rng.push_back(rng[i][0]);
-                out.tile_rng.push_back(rng[i][1]);
-            } else {
-                out.tile_tgt.insert(out.tile_tgt.end(), (size_t)tpt, -1);
-                out.tile_rng.push_back(0);
-                out.tile_rng.push_back(0);
+    std::vector<std::array<int32_t, 2>> rng;  // items: group range
+    std::vector<int32_t> iblk, lev;
+    std::vector<std::array<int32_t, 3>> trip;  // key, slot, source
+    for (auto &kv : lvl) {
+        std::sort(kv.second.begin(), kv.second.end());
+        const auto &v = kv.second;
+        for (size_t b0 = 0; b0 < v.size(); b0 += (size_t)nb) {
+            const int32_t blk = (int32_t)(out.blk_cells.size() / nb);
+            const size_t b1 = std::min(v.size(), b0 + (size_t)nb);
+            trip.clear();
+            for (size_t i = b0; i < b0 + (size_t)nb; ++i) {
+                const int32_t a = i < b1 ? v[i].second : -1;
+                out.blk_cells.push_back(a);
+                if (a < 0) continue;
+                for (int32_t j = hp.m2l_ptr[a]; j < hp.m2l_ptr[a + 1]; ++j)
+                    trip.push_back({hp.m2l_pair_key[j], (int32_t)(i - b0), hp.m2l_src[j]});
+            }
+            std::sort(trip.begin(), trip.end());
+            const int32_t g0 = (int32_t)out.grp_key.size();
+            for (size_t i = 0; i < trip.size();) {
+                const int32_t k = trip[i][0];
+                size_t j = i;
+                while (j < trip.size() && trip[j][0] == k) ++j;
+                for (size_t s = i; s < j; s += (size_t)tpg) {
+                    out.grp_key.push_back(k);
+                    for (int q = 0; q < tpg; ++q) {
+                        const bool ok = s + q < j;
+                        out.grp_src.push_back(ok ? trip[s + q][2] : -1);
+                        out.grp_slot.push_back(ok ? (uint8_t)trip[s + q][1] : (uint8_t)0);
+                    }
+                }
+                i = j;
+            }
+            const int32_t g1 = (int32_t)out.grp_key.size();
+            if (out.grp_key.size() > (size_t)INT32_MAX / 16) throw PlanError{TFMM_ENOTSUP, "too many M2L groups"};
+            // runs of about equal size, none above max_grp
+            const int32_t n = g1 - g0, parts = (n + max_grp - 1) / std::max(max_grp, 1);
+            for (int32_t p = 0; p < parts; ++p) {
+                rng.push_back({g0 + (int32_t)((int64_t)n * p / parts), g0 + (int32_t)((int64_t)n * (p + 1) / parts)});
+                iblk.push_back(blk);
+                lev.push_back(kv.first);
             }
         }
-    // trailing slots that are empty on every XCD are dropped
-    while (!out.tile_rng.empty() && out.tile_rng[out.tile_rng.size() - 1] == 0 &&
-           out.tile_rng[out.tile_rng.size() - 2] == 0) {
-        out.tile_rng.resize(out.tile_rng.size() - 2);
-        out.tile_tgt.resize(out.tile_tgt.size() - tpt);
+    }
+    for (int32_t i : xcd_dispatch_order(rng, lev)) {
+        out.item.push_back(i >= 0 ? iblk[i] : 0);
+        out.item.push_back(i >= 0 ? rng[i][0] : 0);
+        out.item.push_back(i >= 0 ? rng[i][1] : 0);
     }
 }
 

@@ -80,6 +80,23 @@ struct M2LTiles {
     std::vector<int32_t> ent_src;   // [nent][tpt]
 };
 
+// M2L grouped by key inside blocks of target cells (the form for fewer than
+// 16 fields).  A block holds up to nb target cells of one level, consecutive
+// in Morton order; its translations are sorted by key, and the pairs of one
+// key are packed into groups of tpg = 16 / fpt (target slot, source cell)
+// pairs, so that every matrix-core column of a group carries a translation
+// except in the last group of each key.  A work item is a run of at most
+// max_grp groups of one block; items are ordered for the XCDs as the tiles.
+struct M2LPacks {
+    int nb = 0, tpg = 0;
+    std::vector<int32_t> blk_cells;  // [nblk][nb] target cells (-1: empty slot)
+    std::vector<int32_t> item;       // [nitems][3] block, group begin, group end
+    std::vector<int32_t> grp_key;    // [ngrp]
+    std::vector<int32_t> grp_src;    // [ngrp][tpg] source cell (-1: empty)
+    std::vector<uint8_t> grp_slot;   // [ngrp][tpg] target slot in the block
+};
+void build_m2l_packs(const HostPlan &hp, int nb, int tpg, int max_grp, M2LPacks &out, int only_level = -1);
+
 // Mesh entities of the near-field source blocks.  Each P2P block (<= 64 tets
 // of one leaf, [tbeg, tend) in octree order) is cut into chunks of at most
 // kTopoTets tets with at most kTopoNodes distinct nodes, kTopoEdges edges and

@@ -54,18 +54,34 @@ def test_plan_matches_oracle_exactly(orc, n, p, leaf, theta):
 
 
 @pytest.mark.parametrize("n,leaf,theta", [(10, 8, 0.5), ((14, 6, 9), 16, 0.4), (6, 2, 0.6)])
-def test_m2l_tile_schedule_covers_every_pair_once(orc, n, leaf, theta):
-    """The matrix-core schedule (tiles of 16 target cells, entries per key,
-    work items spread over the XCDs) translates every M2L pair of the
-    oracle's list exactly once."""
+def test_m2l_schedules_cover_every_pair_once(orc, n, leaf, theta):
+    """Both matrix-core schedules translate every M2L pair of the oracle's
+    list exactly once: the tiles (16 target cells, entries per key, work
+    items spread over the XCDs) and the key-packed groups (blocks of target
+    cells, the pairs of each key in groups of 16).  In the packed order a
+    block's pairs come key by key: the translation vector (level difference,
+    centre offset) changes only between keys."""
     nodes, tets = meshgen.box_mesh(n, jitter=0.15, seed=3)
     P = T.tfmm_plan_create(nodes, tets, p=4, leaf_size=leaf, theta=theta, device=-1)
-    sched = T.tfmm_plan_lists(P, "m2l_tiles")
     ref = orc.FMM(nodes, tets, 4, leaf, theta).lists("m2l")
-    assert sched.shape == ref.shape
-    a = np.unique(sched, axis=0, return_counts=True)
-    assert a[1].max() == 1 and a[0].shape[0] == ref.shape[0]
-    assert {tuple(r) for r in a[0]} == {tuple(r) for r in ref}
+    for kind in ("m2l_tiles", "m2l_packs"):
+        sched = T.tfmm_plan_lists(P, kind)
+        assert sched.shape == ref.shape, kind
+        a = np.unique(sched, axis=0, return_counts=True)
+        assert a[1].max() == 1 and a[0].shape[0] == ref.shape[0], kind
+        assert {tuple(r) for r in a[0]} == {tuple(r) for r in ref}, kind
+    # translation vector of each pair in units of the finer cell's half side
+    sched = T.tfmm_plan_lists(P, "m2l_packs").astype(np.int64)
+    la, lb = sched[:, 0], sched[:, 4]
+    fine = np.maximum(la, lb)
+    ca = (2 * sched[:, 1:4] + 1) << (fine - la)[:, None]
+    cb = (2 * sched[:, 5:8] + 1) << (fine - lb)[:, None]
+    key = np.concatenate([(lb - la)[:, None], ca - cb], axis=1)
+    runs = 1 + int(np.any(key[1:] != key[:-1], axis=1).sum())
+    assert runs <= sched.shape[0] and runs >= np.unique(key, axis=0).shape[0]
+    # each (block, key) is one run: far fewer runs than pairs in a dense tree
+    if sched.shape[0] > 2000:
+        assert runs < sched.shape[0] / 2
 
 
 def test_plan_explicit_targets_and_unjittered(orc):

@@ -60,9 +60,11 @@ def _sample(n, k, seed):
     return np.sort(np.random.default_rng(seed).choice(n, k, replace=False))
 
 
-# the schedules the plan's autotune chooses between (M2L keys per work item,
-# four-wavefront one-field P2P blocks); the benchmark times the tuned one
-SCHEDULES = [(k, w) for k in (128, 256, 512, 1024) for w in (0, 1)]
+# the schedules the plan's autotune chooses between (M2L keys per work item of
+# the tiled form, four-wavefront one-field P2P blocks, M2L packed by key and
+# its groups per work item); the benchmark times the tuned one
+SCHEDULES = ([(k, w, 0, 256) for k in (128, 256, 512, 1024) for w in (0, 1)]
+             + [(512, w, 1, g) for g in (256, 512) for w in (0, 1)])
 
 
 def test_cube40_fp64_vs_oracle_all_targets_every_schedule(torch_dev, orc):
@@ -75,14 +77,14 @@ def test_cube40_fp64_vs_oracle_all_targets_every_schedule(torch_dev, orc):
     _say("cube40 oracle FMM on all targets")
     uo = orc.FMM(nodes, tets, 8, 64, 0.5).evaluate(M)
     scale = np.abs(uo).max()
-    for keys, wide in SCHEDULES:
-        _say("cube40 fp64 schedule", keys, wide)
-        T.tfmm_plan_set_schedule(P, keys, wide)
+    for sch in SCHEDULES:
+        _say("cube40 fp64 schedule", sch)
+        T.tfmm_plan_set_schedule(P, *sch)
         st = T.tfmm_plan_stats(P)
-        assert (st["m2l_keys_per_item"], st["p2p_wide"]) == (keys, wide)
+        assert (st["m2l_keys_per_item"], st["p2p_wide"], st["m2l_packed"], st["m2l_groups_per_item"]) == sch
         u = _eval(torch_dev, P, M)
-        assert _rel(u, uo) <= FMM_TOL, (keys, wide)
-        assert np.abs(u - uo).max() <= 1e-11 * scale, (keys, wide)
+        assert _rel(u, uo) <= FMM_TOL, sch
+        assert np.abs(u - uo).max() <= 1e-11 * scale, sch
     _say("cube40 autotuned schedule")
     T.tfmm_plan_autotune(P)
     u = _eval(torch_dev, P, M)
