@@ -87,8 +87,8 @@ struct DevicePlan {
     LevelOrders lo{};
     bool level_orders = false;
     std::vector<Tiles> lvl_tiles;
-    // M2L packed by key in blocks of target cells (fewer than 16 fields, FP64
-    // and FP32 translations): per field width fpt = 1, 2, 4, 8 (built on
+    // M2L packed by key in blocks of target cells (FP64 translations of fewer
+    // than 16 fields): per field width fpt = 1, 2, 4, 8 (built on
     // demand), and per level when the levels have their own orders; the
     // reduced locals Lr [F][C][lrs] they accumulate into
     struct Packs {
@@ -99,7 +99,7 @@ struct DevicePlan {
         int64_t ngrp = 0, npairs = 0;
         int64_t bytes = 0;
     };
-    Packs m2l_packs[4];
+    Packs m2l_packs[4];  // fpt = 1, 2, 4, 8
     std::vector<Packs> lvl_packs;
     bool m2l_pack = true;  // schedule knob: the packed form where it applies
     int m2l_max_grp = 256;  // groups per packed work item

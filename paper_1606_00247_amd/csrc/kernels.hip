@@ -925,7 +925,7 @@ __global__ __launch_bounds__(64 * kM2LWaves, 2) void k_m2l_mfma(
 }
 
 // ---------------------------------------------------------------------------
-// M2L packed by key (fewer than 16 fields).
+// M2L packed by key (FP64, fewer than 16 fields).
 //
 // The contraction is that of k_m2l_mfma (scaled, harmonically reduced
 // multipoles; Hankel operand H[m][n] = D_{n+m} of the key; outputs Lr with
@@ -962,25 +962,27 @@ __global__ __launch_bounds__(64 * kM2LPWaves, P <= 8 ? 2 : 1) void k_m2l_pack(
     using v4 = typename Mfma<T>::v4;
     constexpr int NR = nr_of(P), ND = nd_of(P), NROW = m2l_nrows(P), NRT = m2l_nrt(P), KS0 = m2l_ks(P, 0);
     constexpr int NS = m2l_all_steps(P), NSLOT = m2lp_slots(P), DSTR = ND + 1;
-    __shared__ double s_L[NSLOT * NROW];
+    // odd row stride of the accumulators: the 16 columns of an output
+    // register (the same row of 16 slots) fall in 16 different bank pairs
+    // when their slots differ mod 16, as the packer arranges
+    constexpr int LSTR = NROW | 1;
+    __shared__ double s_L[NSLOT * LSTR];
     __shared__ T s_D[kM2LPWaves][2][DSTR];
     const int it = blockIdx.x;
     if (it >= nitems) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int col = lane & 15, pair = col / fpt, fsub = col % fpt, field = (int)blockIdx.y * fpt + fsub;
     const bool fok = field < F;
-    for (int i = tid; i < NSLOT * NROW; i += blockDim.x) s_L[i] = 0.0;
+    for (int i = tid; i < NSLOT * LSTR; i += blockDim.x) s_L[i] = 0.0;
     if (lane < 2) s_D[w][lane][ND] = (T)0;  // the zero slot of each row
     // this lane's table index of the A operand of every step (ks-major,
-    // row tiles inner; the zero slot outside |n| + |m| <= P), and the
-    // degree of its B-operand coefficient n = 4 ks + lane / 16 + 1
-    int didx[NS], qdeg[KS0];
+    // row tiles inner; the zero slot outside |n| + |m| <= P)
+    int didx[NS];
     {
         int s = 0;
 #pragma unroll
         for (int ks = 0; ks < KS0; ++ks) {
             const int n = 1 + 4 * ks + (lane >> 4);
-            qdeg[ks] = n < NR ? c_red.r[n][3] : 0;
 #pragma unroll
             for (int rt = 0; rt < NRT; ++rt)
                 if (ks < m2l_ks(P, rt)) {
@@ -998,12 +1000,14 @@ __global__ __launch_bounds__(64 * kM2LPWaves, P <= 8 ? 2 : 1) void k_m2l_pack(
     const int wg0 = g0 + (int)((int64_t)(g1 - g0) * w / kM2LPWaves);
     const int wg1 = g0 + (int)((int64_t)(g1 - g0) * (w + 1) / kM2LPWaves);
     const T *qf = Qr + (int64_t)(fok ? field : 0) * C * qpad;
+    constexpr int DREG = (ND + 63) / 64;
     struct Ops {
-        T b[KS0];
-        int slot;
-        bool ok;
+        T b[KS0], d[DREG];
+        int slot, key, dl;
+        bool ok, newkey;
     };
-    // loads of group g: clamped addresses, masked when used
+    // loads of group g (the derivative row too when its key differs from
+    // the previous group's): clamped addresses, masked when used
     auto fetch = [&](Ops &o, int g) {
         const int src = grp_src[(int64_t)g * tpg + pair];
         o.slot = grp_slot[(int64_t)g * tpg + pair];
@@ -1014,26 +1018,47 @@ __global__ __launch_bounds__(64 * kM2LPWaves, P <= 8 ? 2 : 1) void k_m2l_pack(
             const int n = 1 + 4 * ks + (lane >> 4);
             o.b[ks] = q[n < NR ? n : NR - 1];
         }
+        o.key = grp_key[g];
+        o.newkey = g == wg0 || grp_key[g - 1] != o.key;  // uniform over the wavefront
+        if (o.newkey) {
+            o.dl = keys[4 * o.key];
+#pragma unroll
+            for (int j = 0; j < DREG; ++j) {
+                const int k = lane + 64 * j;
+                o.d[j] = Dtab[(int64_t)o.key * dstr + (k < ND ? k : ND - 1)];
+            }
+        }
     };
-    int prev = -1, buf = 0, dl = 0;
+    int buf = 0, dl = 0;
     auto run = [&](const Ops &o, int g) {
-        const int key = grp_key[g];
-        if (key != prev) {  // uniform over the wavefront
+        if (o.newkey) {
             buf ^= 1;
             T *D = s_D[w][buf];
-            for (int j = lane; j < ND; j += 64) D[j] = Dtab[(int64_t)key * dstr + j];
-            dl = keys[4 * key];
-            prev = key;
+#pragma unroll
+            for (int j = 0; j < DREG; ++j) {
+                const int k = lane + 64 * j;
+                if (k < ND) D[k] = o.d[j];
+            }
+            dl = o.dl;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         const T *D = s_D[w][buf];
+        // B operand: the multipoles times 2^(-dl |n|) (exact).  Columns of
+        // empty slots and rows n >= NR hold finite values that meet zero A
+        // entries or are never added out, so they need no masking.
         T b[KS0];
+        if (dl == 0) {  // uniform over the wavefront
 #pragma unroll
-        for (int ks = 0; ks < KS0; ++ks) {
-            const int n = 1 + 4 * ks + (lane >> 4);
-            b[ks] = (o.ok && n < NR) ? (T)ldexp(o.b[ks], -dl * qdeg[ks]) : (T)0;  // 2^(-dl |n|), exact
+            for (int ks = 0; ks < KS0; ++ks) b[ks] = o.b[ks];
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < KS0; ++ks) {
+                const int n = 1 + 4 * ks + (lane >> 4);
+                const int deg = (int)sqrtf((float)n);  // exact: the degree block of n starts at deg^2
+                b[ks] = (T)ldexp(o.b[ks], -dl * deg);
+            }
         }
         v4 acc[NRT], acc0[2] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
 #pragma unroll
@@ -1054,7 +1079,7 @@ __global__ __launch_bounds__(64 * kM2LPWaves, P <= 8 ? 2 : 1) void k_m2l_pack(
                 }
         acc[0] = acc0[0] + acc0[1];
         if (o.ok) {
-            double *Ls = s_L + (o.slot * fpt + fsub) * NROW;
+            double *Ls = s_L + (o.slot * fpt + fsub) * LSTR;
 #pragma unroll
             for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
@@ -1079,9 +1104,9 @@ __global__ __launch_bounds__(64 * kM2LPWaves, P <= 8 ? 2 : 1) void k_m2l_pack(
     __syncthreads();
     // add the block's reduced locals to Lr
     for (int i = tid; i < NSLOT * NROW; i += blockDim.x) {
-        const double v = s_L[i];
-        if (v == 0.0) continue;
         const int c = i / NROW, m = i - c * NROW;
+        const double v = s_L[c * LSTR + m];
+        if (v == 0.0) continue;
         const int fld = (int)blockIdx.y * fpt + c % fpt, cell = c / fpt < nb ? blk_cells[(int64_t)blk * nb + c / fpt] : -1;
         if (cell >= 0 && fld < F) atomicAdd(&Lr[((int64_t)fld * C + cell) * lrs + m], v);
     }
@@ -2505,13 +2530,14 @@ int m2l_fpt(int32_t F)
     return fpt;
 }
 
-// Whether M2L runs in the packed form: fewer than 16 fields (the tiles of 16
-// or more fields carry one target cell x 16 fields, every column used) and
-// FP64 or FP32 translations.
+// Whether M2L runs in the packed form: FP64 translations of fewer than 16
+// fields (the tiles of 16 or more fields carry one target cell x 16 fields,
+// every column used; the FP32 and split-BF16 tiles are faster than their
+// packed forms, whose few matrix-core cycles per group leave the LDS
+// accumulation as the bound).
 bool m2l_packed(const DevicePlan &dp, int32_t F)
 {
-    return dp.m2l_pack && m2l_fpt(F) < 16 &&
-           (dp.m2l_precision == TFMM_M2L_FP64 || dp.m2l_precision == TFMM_M2L_FP32);
+    return dp.m2l_pack && m2l_fpt(F) < 16 && dp.m2l_precision == TFMM_M2L_FP64;
 }
 int m2l_pack_slot(int fpt)
 {
@@ -2554,12 +2580,8 @@ void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
         if (dp.lr_cap < F) throw DeviceError{"M2L buffers not prepared"};
         const int lrs = m2l_nrows(hp.p);
         fill(dp.Lr, (int64_t)F * C * lrs, 0.0, st);
-        const bool f32 = dp.m2l_precision == TFMM_M2L_FP32;
         auto go = [&](const DevicePlan::Packs &k, int p) {
-            if (f32)
-                launch_m2l_pack_t<float>(dp, k, dp.m2l_Df, dp.Qtf, fpt, F, st, p);
-            else
-                launch_m2l_pack_t<double>(dp, k, dp.m2l_D, dp.Qt, fpt, F, st, p);
+            launch_m2l_pack_t<double>(dp, k, dp.m2l_D, dp.Qt, fpt, F, st, p);
         };
         if (!dp.level_orders) {
             go(dp.m2l_packs[m2l_pack_slot(fpt)], hp.p);

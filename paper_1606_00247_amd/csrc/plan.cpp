@@ -510,18 +510,28 @@ void build_m2l_packs(const HostPlan &hp, int nb, int tpg, int max_grp, M2LPacks 
                 for (int32_t j = hp.m2l_ptr[a]; j < hp.m2l_ptr[a + 1]; ++j)
                     trip.push_back({hp.m2l_pair_key[j], (int32_t)(i - b0), hp.m2l_src[j]});
             }
-            std::sort(trip.begin(), trip.end());
+            // by key, then by slot class (slot mod tpg), then slot: the pairs
+            // of a key are dealt round-robin over its ceil(n / tpg) groups, so
+            // that a group's slots differ mod tpg wherever the class counts
+            // allow (its accumulator rows then fall in different LDS banks)
+            std::sort(trip.begin(), trip.end(), [tpg](const std::array<int32_t, 3> &x, const std::array<int32_t, 3> &y) {
+                if (x[0] != y[0]) return x[0] < y[0];
+                if (x[1] % tpg != y[1] % tpg) return x[1] % tpg < y[1] % tpg;
+                return x[1] < y[1];
+            });
             const int32_t g0 = (int32_t)out.grp_key.size();
             for (size_t i = 0; i < trip.size();) {
                 const int32_t k = trip[i][0];
                 size_t j = i;
                 while (j < trip.size() && trip[j][0] == k) ++j;
-                for (size_t s = i; s < j; s += (size_t)tpg) {
+                const size_t n = j - i, G = (n + (size_t)tpg - 1) / (size_t)tpg;
+                for (size_t g = 0; g < G; ++g) {
                     out.grp_key.push_back(k);
                     for (int q = 0; q < tpg; ++q) {
-                        const bool ok = s + q < j;
-                        out.grp_src.push_back(ok ? trip[s + q][2] : -1);
-                        out.grp_slot.push_back(ok ? (uint8_t)trip[s + q][1] : (uint8_t)0);
+                        const size_t e = g + (size_t)q * G;  // round-robin deal
+                        const bool ok = e < n;
+                        out.grp_src.push_back(ok ? trip[i + e][2] : -1);
+                        out.grp_slot.push_back(ok ? (uint8_t)trip[i + e][1] : (uint8_t)0);
                     }
                 }
                 i = j;
