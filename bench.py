@@ -154,9 +154,11 @@ def kernel_breakdown(T, torch, plan, M, u, steps):
 
 def ragged_batch(T, torch, steps):
     """32 jittered cubes with 2k-200k tets (log-uniform), one field each, p=8,
-    leaf 64, theta 0.5, FP64: one eager evaluation per mesh vs the batch's
-    captured graph, before and after schedule tuning; then the tuned graph
-    with split-BF16 and FP32 translations and with the stored near field."""
+    leaf 64, theta 0.5, FP64: one eager evaluation per mesh, the per-mesh
+    plans as one captured graph (4 branches), and the merged plan (every mesh
+    in one launch per phase) as one graph, before and after schedule tuning;
+    then the tuned merged graph with split-BF16 and FP32 translations and
+    with the stored near field."""
     import meshgen
     ns = meshgen.ragged_sizes(32)
     meshes = [meshgen.box_mesh(int(n), seed=i) for i, n in enumerate(ns)]
@@ -165,6 +167,7 @@ def ragged_batch(T, torch, steps):
          for i, m in enumerate(meshes)]
     u = [torch.empty(m[0].shape[0], dtype=torch.float64, device="cuda:0") for m in meshes]
     plans = [T.tfmm_batch_plan(B, i) for i in range(len(meshes))]
+    merged = T.tfmm_batch_merged_plan(B)
     evals = sum(m[0].shape[0] for m in meshes)
 
     def timed(fn):
@@ -177,7 +180,10 @@ def ragged_batch(T, torch, steps):
         return (time.perf_counter() - t0) / steps
 
     t_eager = timed(lambda: [T.tfmm_evaluate(p, m, x) for p, m, x in zip(plans, M, u)])
+    T.tfmm_batch_set_merged(B, 0)
     t_graph = timed(lambda: T.tfmm_batch_evaluate(B, M, u))
+    T.tfmm_batch_set_merged(B, 1)
+    t_merged = timed(lambda: T.tfmm_batch_evaluate(B, M, u))
     T.tfmm_batch_autotune(B)
     t_tuned = timed(lambda: T.tfmm_batch_evaluate(B, M, u))
     uds = [T.tfmm_direct(p, m) for p, m in zip(plans, M)]
@@ -191,17 +197,17 @@ def ragged_batch(T, torch, steps):
     forms = {}
     for name, prec, store in (("bf16x3", T.M2L_BF16X3, False), ("fp32", T.M2L_FP32, False),
                               ("fp32_near_stored", T.M2L_FP32, True)):
-        for pl in plans:
-            T.tfmm_plan_set_m2l_precision(pl, prec)
-            if store:
-                T.tfmm_plan_store_near(pl)
+        T.tfmm_plan_set_m2l_precision(merged, prec)
+        if store:
+            T.tfmm_plan_store_near(merged)
         t = timed(lambda: T.tfmm_batch_evaluate(B, M, u))
         forms[name] = {"value": evals / t, "ms_per_step": t * 1e3, "rel_l2_vs_direct_max_over_meshes": max_err(),
                        "speedup_vs_fp64_graph": t_tuned / t}
     T.tfmm_batch_destroy(B)
     return {"meshes": len(meshes), "tets": int(sum(m[1].shape[0] for m in meshes)), "targets": int(evals),
             "value": evals / t_tuned, "unit": "evals/s", "ms_per_step": t_tuned * 1e3,
-            "ms_eager_per_mesh_launches": t_eager * 1e3, "ms_graph": t_graph * 1e3, "ms_graph_tuned": t_tuned * 1e3,
+            "ms_eager_per_mesh_launches": t_eager * 1e3, "ms_graph_per_mesh_plans": t_graph * 1e3,
+            "ms_graph_merged_plan": t_merged * 1e3, "ms_graph_merged_tuned": t_tuned * 1e3,
             "m2l": "fp64", "rel_l2_vs_direct_max_over_meshes": err, "forms": forms}
 
 
@@ -471,8 +477,9 @@ def main():
                                f"random unit nodal M",
                    "n_tets": int(tets.shape[0]), "n_targets": int(nodes.shape[0]), "fields": W["F"],
                    "p": W["p"], "leaf": W["leaf"], "theta": W["theta"], "m2l": "fp64",
-                   "schedule": {"autotuned": True, "m2l_keys_per_item": st["m2l_keys_per_item"],
-                                "p2p_wide": bool(st["p2p_wide"])}},
+                   "schedule": {"autotuned": True, "m2l_packed": bool(st["m2l_packed"]),
+                                "m2l_groups_per_item": st["m2l_groups_per_item"],
+                                "m2l_keys_per_item": st["m2l_keys_per_item"], "p2p_wide": bool(st["p2p_wide"])}},
         "rel_l2_vs_direct": err,
         "setup_s": setup_s,
         "setup_includes": "plan build and schedule autotune",

@@ -435,10 +435,14 @@ int tfmm_plan_set_schedule(tfmm_plan plan, int32_t m2l_keys_per_item, int32_t p2
 int tfmm_elementary(int32_t fn, const double *a, const double *b, double *out, int64_t n, int32_t device);
 
 /*
- * Ragged batches of meshes (one field each).  tfmm_batch_create builds one
- * plan per mesh i from nodes[i] ([n_nodes[i]][3], host) and tets[i]
- * ([n_tets[i]][4], host), targets = the nodes, all with the parameters prm
- * (prm->device >= 0).  The caller may free its arrays on return.
+ * Ragged batches of meshes (one field each; the FMM of Secs. 2-3 on every
+ * mesh).  tfmm_batch_create builds one plan per mesh i from nodes[i]
+ * ([n_nodes[i]][3], host) and tets[i] ([n_tets[i]][4], host), targets = the
+ * nodes, all with the parameters prm (prm->device >= 0), and one merged plan
+ * over all meshes: each mesh's tree and lists normalised to its own root
+ * cube (the potential scales with the cube side at fixed M) and
+ * concatenated, so that one launch per phase serves every mesh and no mesh
+ * interacts with another.  The caller may free its arrays on return.
  * Errors: as tfmm_plan_create (the message names the mesh), TFMM_EINVAL for
  * n_meshes < 1, NULL arrays or a host-only device.
  */
@@ -448,22 +452,35 @@ int tfmm_batch_create(int32_t n_meshes, const double *const *nodes, const int64_
 /*
  * Evaluate every mesh of the batch: M[i] device [n_nodes_i][3] FP64 nodal
  * magnetisation, u[i] device [n_nodes_i] FP64 output (written, not added
- * to).  The whole sequence of launches is captured once into a HIP graph
- * (on internal streams; the meshes are spread over 4 branches that run
- * concurrently, balanced by the plans' P2P and M2L counts) and replayed on
- * hip_stream while the M and u
- * pointers and the plans' precision and schedule stay the same; a change
- * re-captures.  Asynchronous like tfmm_evaluate.  With kernel timing enabled
- * on any plan the launches run eagerly instead.
+ * to).  By default the merged plan runs: M is gathered into it (scaled by
+ * each mesh's root side), evaluated, and u scattered back.  With
+ * tfmm_batch_set_merged(batch, 0) the per-mesh plans run instead, spread
+ * over 4 concurrent branches balanced by their P2P and M2L counts.  Either
+ * sequence of launches is captured once into a HIP graph on internal
+ * streams and replayed on hip_stream while the M and u pointers and the
+ * plans' precision and schedule stay the same; a change re-captures.
+ * Asynchronous like tfmm_evaluate.  With kernel timing enabled on the plans
+ * that run, the launches run eagerly instead.
  * Errors: TFMM_EINVAL (NULL arguments), TFMM_EDEVICE.
  */
 int tfmm_batch_evaluate(tfmm_batch batch, const double *const *M, double *const *u, void *hip_stream);
 
-/* Tune every plan of the batch (tfmm_plan_autotune) and drop its graph. */
+/* Tune the plans that evaluate the batch (tfmm_plan_autotune: the merged
+ * plan, or every mesh's plan) and drop its graph. */
 int tfmm_batch_autotune(tfmm_batch batch, void *hip_stream);
 
 /* Plan of mesh i (owned by the batch: do not destroy it). */
 int tfmm_batch_plan(tfmm_batch batch, int32_t i, tfmm_plan *out);
+
+/* The merged plan over all meshes (owned by the batch: do not destroy it).
+ * Its precision, stored near field and schedule are set with the plan
+ * calls; its nodes are the meshes' nodes, mesh after mesh, in the frame of
+ * each mesh's root cube, so it is not meant for tfmm_evaluate by itself. */
+int tfmm_batch_merged_plan(tfmm_batch batch, tfmm_plan *out);
+
+/* on = 1 (default): tfmm_batch_evaluate runs the merged plan; 0: the
+ * per-mesh plans.  Errors: TFMM_EINVAL. */
+int tfmm_batch_set_merged(tfmm_batch batch, int32_t on);
 
 /* Destroy the batch, its plans and its graph.  NULL is accepted. */
 int tfmm_batch_destroy(tfmm_batch batch);

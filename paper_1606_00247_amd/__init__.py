@@ -18,7 +18,7 @@ __all__ = [
     "tfmm_direct_host", "tfmm_plan_stats", "tfmm_plan_lists", "tfmm_plan_cells", "tfmm_plan_expansions",
     "tfmm_plan_destroy", "tfmm_last_error", "tfmm_simplex_rule", "tfmm_set_timing", "tfmm_kernel_times",
     "library_path", "TFMM_PMAX", "KERNEL_NAMES", "ERRORS", "tfmm_plan_set_m2l_precision", "tfmm_plan_set_surrogate", "tfmm_plan_set_level_orders", "tfmm_tune_level_orders", "SUR_OFF", "SUR_MLP", "SUR_GAUSS", "SUR_QUAD", "M2L_FP64", "M2L_FP32", "M2L_BF16X3", "M2L_BF16X6",
-    "tfmm_plan_autotune", "tfmm_plan_set_schedule", "tfmm_elementary", "ELEMENTARY", "tfmm_batch_create", "tfmm_batch_evaluate", "tfmm_batch_autotune", "tfmm_batch_plan",
+    "tfmm_plan_autotune", "tfmm_plan_set_schedule", "tfmm_elementary", "ELEMENTARY", "tfmm_batch_create", "tfmm_batch_evaluate", "tfmm_batch_autotune", "tfmm_batch_plan", "tfmm_batch_merged_plan", "tfmm_batch_set_merged",
     "tfmm_batch_destroy", "Batch", "tfmm_surrogate_param_count", "tfmm_surrogate_train", "tfmm_surrogate_load",
     "tfmm_surrogate_samples", "tfmm_surrogate_grad", "tfmm_band_potential", "tfmm_demag_energy", "tfmm_demag_energy_noalloc", "NOALLOC_MAX_TETS", "tfmm_demag_field_nodes",
     "tfmm_plan_store_near", "tfmm_tune_accuracy", "tfmm_plan_create_points",
@@ -128,6 +128,8 @@ def _load():
         "tfmm_batch_evaluate": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
         "tfmm_batch_autotune": (C.c_int, [C.c_void_p, C.c_void_p]),
         "tfmm_batch_plan": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+        "tfmm_batch_merged_plan": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+        "tfmm_batch_set_merged": (C.c_int, [C.c_void_p, C.c_int32]),
         "tfmm_batch_destroy": (C.c_int, [C.c_void_p]),
         "tfmm_surrogate_param_count": (C.c_int, [C.c_int32]),
         "tfmm_demag_energy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, _dp, C.c_void_p]),
@@ -389,6 +391,20 @@ def tfmm_batch_plan(batch, i):
     _check(_load().tfmm_batch_plan(batch.handle, int(i), C.byref(h)))
     n_nodes = batch.sizes[i][0]
     return _BorrowedPlan(h.value, batch.device, n_nodes, n_nodes, dict(batch.params))
+
+
+def tfmm_batch_merged_plan(batch):
+    """The merged plan over all meshes (owned by the batch): set its precision,
+    stored near field or schedule with the plan calls."""
+    h = C.c_void_p()
+    _check(_load().tfmm_batch_merged_plan(batch.handle, C.byref(h)))
+    n = int(sum(s[0] for s in batch.sizes))
+    return _BorrowedPlan(h.value, batch.device, n, n, dict(batch.params))
+
+
+def tfmm_batch_set_merged(batch, on):
+    """1 (default): evaluate the batch as its merged plan; 0: per-mesh plans."""
+    _check(_load().tfmm_batch_set_merged(batch.handle, int(on)))
 
 
 def tfmm_batch_destroy(batch):

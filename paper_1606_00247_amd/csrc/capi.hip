@@ -31,6 +31,18 @@ constexpr int kBatchBranches = 4;  // concurrent branches of a batch graph
 
 struct tfmm_batch_s {
     std::vector<tfmm_plan> plans;
+    // all meshes as one plan (tfmm::merge_host_plans): one launch per phase
+    // over every mesh; M is gathered into it scaled by each mesh's root side
+    // and u scattered back
+    tfmm_plan merged = nullptr;
+    bool use_merged = true;
+    std::vector<double> scale;
+    std::vector<int64_t> off;
+    double *mM = nullptr, *mU = nullptr, *d_scale = nullptr;
+    int64_t *d_off = nullptr;
+    const double **dM = nullptr;
+    double **dU = nullptr;
+    bool key_merged = false;
     int device = 0;
     hipStream_t capture = nullptr;
     hipStream_t branch[kBatchBranches] = {};
@@ -1086,6 +1098,7 @@ static void batch_drop_graph(tfmm_batch b)
     b->keyM.clear();
     b->keyU.clear();
     b->keyGen.clear();
+    b->key_merged = false;
 }
 
 int tfmm_batch_destroy(tfmm_batch batch)
@@ -1101,8 +1114,12 @@ int tfmm_batch_destroy(tfmm_batch batch)
                 if (batch->join[k]) (void)hipEventDestroy(batch->join[k]);
             }
             if (batch->fork) (void)hipEventDestroy(batch->fork);
+            void *bufs[] = {batch->mM, batch->mU, batch->d_scale, batch->d_off, batch->dM, batch->dU};
+            for (void *q : bufs)
+                if (q) (void)hipFree(q);
         }
         int rc = TFMM_OK;
+        if (batch->merged) rc = tfmm_plan_destroy(batch->merged);
         for (tfmm_plan p : batch->plans) {
             const int r = tfmm_plan_destroy(p);
             if (r && !rc) rc = r;
@@ -1144,6 +1161,34 @@ int tfmm_batch_create(int32_t n_meshes, const double *const *nodes, const int64_
             tfmm::hip_check(hipStreamCreateWithFlags(&b->branch[k], hipStreamNonBlocking), "hipStreamCreate");
             tfmm::hip_check(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming), "hipEventCreate");
         }
+        // the merged plan over all meshes
+        std::vector<const tfmm::HostPlan *> hps;
+        for (tfmm_plan p : b->plans) hps.push_back(&p->dp.hp);
+        std::unique_ptr<tfmm_plan_s> P(new tfmm_plan_s());
+        tfmm::merge_host_plans(hps, P->dp.hp, b->scale, b->off);
+        P->dp.ncoef = (prm->p + 1) * (prm->p + 2) * (prm->p + 3) / 6;
+        P->dp.m2l_precision = prm->m2l_precision;
+        P->dp.sur_mode = TFMM_SUR_OFF;
+        for (int l = 0; l < tfmm::kMaxLevels; ++l) P->dp.lo.q[l] = (int8_t)prm->p;
+        P->dp.device = b->device;
+        try {
+            tfmm::upload_plan(P->dp);
+        } catch (...) {
+            tfmm::free_plan(P->dp);
+            throw;
+        }
+        P->on_device = true;
+        b->merged = P.release();
+        const size_t n = b->plans.size();
+        const int64_t N = b->off[n];
+        tfmm::hip_check(hipMalloc(&b->mM, sizeof(double) * 3 * (size_t)std::max<int64_t>(N, 1)), "hipMalloc batch M");
+        tfmm::hip_check(hipMalloc(&b->mU, sizeof(double) * (size_t)std::max<int64_t>(N, 1)), "hipMalloc batch u");
+        tfmm::hip_check(hipMalloc(&b->d_scale, sizeof(double) * n), "hipMalloc batch scale");
+        tfmm::hip_check(hipMalloc(&b->d_off, sizeof(int64_t) * (n + 1)), "hipMalloc batch offsets");
+        tfmm::hip_check(hipMalloc(&b->dM, sizeof(double *) * n), "hipMalloc batch M pointers");
+        tfmm::hip_check(hipMalloc(&b->dU, sizeof(double *) * n), "hipMalloc batch u pointers");
+        tfmm::hip_check(hipMemcpy(b->d_scale, b->scale.data(), sizeof(double) * n, hipMemcpyHostToDevice), "hipMemcpy");
+        tfmm::hip_check(hipMemcpy(b->d_off, b->off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice), "hipMemcpy");
         return TFMM_OK;
     });
     if (rc) {
@@ -1163,6 +1208,53 @@ int tfmm_batch_evaluate(tfmm_batch batch, const double *const *M, double *const 
     return guarded([&]() -> int {
         DeviceScope ds(batch->device);
         hipStream_t st = (hipStream_t)hip_stream;
+        if (batch->use_merged && batch->merged) {
+            tfmm::DevicePlan &dp = batch->merged->dp;
+            const int nm = (int)n;
+            const int64_t N = batch->off[n];
+            auto put_pointers = [&]() {
+                tfmm::hip_check(hipMemcpy(batch->dM, M, sizeof(double *) * n, hipMemcpyHostToDevice), "hipMemcpy");
+                tfmm::hip_check(hipMemcpy(batch->dU, u, sizeof(double *) * n, hipMemcpyHostToDevice), "hipMemcpy");
+            };
+            if (dp.timing) {  // per-phase events cannot live in a graph: run eagerly
+                batch_drop_graph(batch);
+                put_pointers();
+                tfmm::batch_gather(batch->dM, batch->d_off, batch->d_scale, nm, N, batch->mM, st);
+                tfmm::run_evaluate(dp, batch->mM, 1, batch->mU, st);
+                tfmm::batch_scatter(batch->mU, batch->d_off, nm, N, batch->dU, st);
+                return TFMM_OK;
+            }
+            const bool same = batch->exec && batch->key_merged && std::equal(batch->keyM.begin(), batch->keyM.end(), M) &&
+                              std::equal(batch->keyU.begin(), batch->keyU.end(), u) && batch->keyGen.size() == 1 &&
+                              batch->keyGen[0] == dp.schedule_gen;
+            if (!same) {
+                batch_drop_graph(batch);
+                tfmm::prepare_evaluate(dp, 1);
+                put_pointers();
+                tfmm::hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+                tfmm::hip_check(hipStreamBeginCapture(batch->capture, hipStreamCaptureModeThreadLocal),
+                                "hipStreamBeginCapture");
+                try {
+                    tfmm::batch_gather(batch->dM, batch->d_off, batch->d_scale, nm, N, batch->mM, batch->capture);
+                    tfmm::run_evaluate(dp, batch->mM, 1, batch->mU, batch->capture);
+                    tfmm::batch_scatter(batch->mU, batch->d_off, nm, N, batch->dU, batch->capture);
+                } catch (...) {
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(batch->capture, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                tfmm::hip_check(hipStreamEndCapture(batch->capture, &batch->graph), "hipStreamEndCapture");
+                tfmm::hip_check(hipGraphInstantiate(&batch->exec, batch->graph, nullptr, nullptr, 0),
+                                "hipGraphInstantiate");
+                batch->keyM.assign(M, M + n);
+                batch->keyU.assign(u, u + n);
+                batch->keyGen.assign(1, dp.schedule_gen);
+                batch->key_merged = true;
+            }
+            tfmm::hip_check(hipGraphLaunch(batch->exec, st), "hipGraphLaunch");
+            return TFMM_OK;
+        }
         bool timing = false;
         for (tfmm_plan p : batch->plans) timing = timing || p->dp.timing;
         if (timing) {  // per-phase events cannot live in a graph: run eagerly
@@ -1171,7 +1263,7 @@ int tfmm_batch_evaluate(tfmm_batch batch, const double *const *M, double *const 
         }
         std::vector<uint64_t> gen(n);
         for (size_t i = 0; i < n; ++i) gen[i] = batch->plans[i]->dp.schedule_gen;
-        const bool same = batch->exec && std::equal(batch->keyM.begin(), batch->keyM.end(), M) &&
+        const bool same = batch->exec && !batch->key_merged && std::equal(batch->keyM.begin(), batch->keyM.end(), M) &&
                           std::equal(batch->keyU.begin(), batch->keyU.end(), u) && gen == batch->keyGen;
         if (!same) {
             batch_drop_graph(batch);
@@ -1225,6 +1317,7 @@ int tfmm_batch_evaluate(tfmm_batch batch, const double *const *M, double *const 
 int tfmm_batch_autotune(tfmm_batch batch, void *hip_stream)
 {
     if (!batch) return set_error(TFMM_EINVAL, "NULL batch");
+    if (batch->use_merged && batch->merged) return tfmm_plan_autotune(batch->merged, hip_stream);
     for (tfmm_plan p : batch->plans) {
         const int rc = tfmm_plan_autotune(p, hip_stream);
         if (rc) return rc;
@@ -1241,6 +1334,24 @@ int tfmm_batch_plan(tfmm_batch batch, int32_t i, tfmm_plan *out)
     if (!batch || !out || i < 0 || (size_t)i >= batch->plans.size()) return set_error(TFMM_EINVAL, "bad batch index");
     *out = batch->plans[i];
     return TFMM_OK;
+}
+
+int tfmm_batch_merged_plan(tfmm_batch batch, tfmm_plan *out)
+{
+    if (!batch || !out) return set_error(TFMM_EINVAL, "NULL argument");
+    *out = batch->merged;
+    return TFMM_OK;
+}
+
+int tfmm_batch_set_merged(tfmm_batch batch, int32_t on)
+{
+    if (!batch || (on != 0 && on != 1)) return set_error(TFMM_EINVAL, "NULL batch or on not 0/1");
+    return guarded([&]() -> int {
+        DeviceScope ds(batch->device);
+        if (batch->use_merged != (on != 0)) batch_drop_graph(batch);
+        batch->use_merged = on != 0;
+        return TFMM_OK;
+    });
 }
 
 int tfmm_demag_energy(tfmm_plan plan, const double *M, const double *u, double *H_tet, double *energy,

@@ -219,6 +219,10 @@ DevicePlan::Tiles &ensure_m2l_tiles(DevicePlan &dp, int tpt);
 // The same per target level (for per-level orders), and their release.
 const std::vector<DevicePlan::Tiles> &ensure_m2l_level_tiles(DevicePlan &dp, int tpt);
 void free_m2l_packs(DevicePlan &dp);
+// merged-batch input and output (see k_batch_gather)
+void batch_gather(const double *const *M, const int64_t *off, const double *scale, int n, int64_t N, double *out,
+                  hipStream_t st);
+void batch_scatter(const double *u, const int64_t *off, int n, int64_t N, double *const *U, hipStream_t st);
 void drop_m2l_level_tiles(DevicePlan &dp);
 
 // Allocate everything an evaluation of F fields needs (expansions, M2L tiles

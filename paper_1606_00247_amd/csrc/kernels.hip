@@ -2270,6 +2270,40 @@ struct KTimer {
     }
 };
 
+// Ragged batches evaluated as one merged plan: mesh i's nodal M (device
+// [n_i][3]) times scale[i] into rows off[i] .. off[i+1] of the merged M, and
+// the merged u back into each mesh's u (device [n_i]).
+__device__ __forceinline__ int batch_mesh(const int64_t *__restrict__ off, int n, int64_t j)
+{
+    int lo = 0, hi = n;  // last i with off[i] <= j
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= j) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+__global__ void k_batch_gather(const double *const *__restrict__ M, const int64_t *__restrict__ off,
+                               const double *__restrict__ scale, int n, double *__restrict__ out)
+{
+    const int64_t N = off[n];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < N; j += (int64_t)gridDim.x * blockDim.x) {
+        const int i = batch_mesh(off, n, j);
+        const double *m = M[i] + 3 * (j - off[i]);
+        const double s = scale[i];
+        out[3 * j] = s * m[0];
+        out[3 * j + 1] = s * m[1];
+        out[3 * j + 2] = s * m[2];
+    }
+}
+__global__ void k_batch_scatter(const double *__restrict__ u, const int64_t *__restrict__ off, int n,
+                                double *const *__restrict__ U)
+{
+    const int64_t N = off[n];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < N; j += (int64_t)gridDim.x * blockDim.x) {
+        const int i = batch_mesh(off, n, j);
+        U[i][j - off[i]] = u[j];
+    }
+}
 void fill(double *a, int64_t n, double v, hipStream_t st)
 {
     if (n <= 0) return;
@@ -2605,6 +2639,22 @@ void run_m2l(DevicePlan &dp, int32_t F, hipStream_t st)
 }
 
 }  // namespace
+
+void batch_gather(const double *const *M, const int64_t *off, const double *scale, int n, int64_t N, double *out,
+                  hipStream_t st)
+{
+    if (N <= 0) return;
+    k_batch_gather<<<dim3((unsigned)std::min<int64_t>((N + 255) / 256, 65536)), dim3(256), 0, st>>>(M, off, scale, n,
+                                                                                                   out);
+    hip_check(hipGetLastError(), "k_batch_gather launch");
+}
+void batch_scatter(const double *u, const int64_t *off, int n, int64_t N, double *const *U, hipStream_t st)
+{
+    if (N <= 0) return;
+    k_batch_scatter<<<dim3((unsigned)std::min<int64_t>((N + 255) / 256, 65536)), dim3(256), 0, st>>>(u, off, n, U);
+    hip_check(hipGetLastError(), "k_batch_scatter launch");
+}
+
 
 void store_near(DevicePlan &dp, hipStream_t st)
 {

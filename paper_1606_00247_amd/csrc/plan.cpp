@@ -555,6 +555,135 @@ void build_m2l_packs(const HostPlan &hp, int nb, int tpg, int max_grp, M2LPacks 
 }
 
 
+void merge_host_plans(const std::vector<const HostPlan *> &in, HostPlan &out, std::vector<double> &scale,
+                      std::vector<int64_t> &node_off)
+{
+    if (in.empty()) throw PlanError{TFMM_EINVAL, "no plans to merge"};
+    const HostPlan &h0 = *in[0];
+    for (const HostPlan *h : in)
+        if (h->p != h0.p || h->leaf != h0.leaf || h->theta != h0.theta || h->points || !h->targets_are_nodes)
+            throw PlanError{TFMM_EINVAL, "merged plans need tet sources at the nodes and one p, leaf and theta"};
+    out = HostPlan{};
+    out.p = h0.p;
+    out.leaf = h0.leaf;
+    out.theta = h0.theta;
+    out.targets_are_nodes = true;
+    out.side = 1.0;
+    const size_t n = in.size();
+    scale.assign(n, 1.0);
+    node_off.assign(n + 1, 0);
+    std::vector<int64_t> tet_off(n + 1, 0);
+    int depth = 0;
+    for (size_t i = 0; i < n; ++i) {
+        node_off[i + 1] = node_off[i] + in[i]->n_nodes;
+        tet_off[i + 1] = tet_off[i] + in[i]->n_tets;
+        depth = std::max(depth, in[i]->depth);
+        scale[i] = in[i]->side;
+    }
+    if (node_off[n] > INT32_MAX || tet_off[n] > INT32_MAX) throw PlanError{TFMM_ENOTSUP, "merged batch too large"};
+    out.n_nodes = node_off[n];
+    out.n_tets = tet_off[n];
+    out.n_targets = node_off[n];
+    out.depth = depth;
+    out.nodes.resize(3 * (size_t)out.n_nodes);
+    out.tgt_xyz.resize(3 * (size_t)out.n_targets);
+    out.tet_perm.resize((size_t)out.n_tets);
+    out.tet_nodes.resize(4 * (size_t)out.n_tets);
+    out.tgt_perm.resize((size_t)out.n_targets);
+    for (size_t i = 0; i < n; ++i) {
+        const HostPlan &h = *in[i];
+        const double k = 1.0 / h.side;
+        for (int64_t j = 0; j < h.n_nodes; ++j)
+            for (int d = 0; d < 3; ++d) {
+                out.nodes[3 * (node_off[i] + j) + d] = (h.nodes[3 * j + d] - h.origin[d]) * k;
+                out.tgt_xyz[3 * (node_off[i] + j) + d] = (h.tgt_xyz[3 * j + d] - h.origin[d]) * k;
+            }
+        for (int64_t s = 0; s < h.n_tets; ++s) {
+            out.tet_perm[tet_off[i] + s] = (int32_t)(tet_off[i] + h.tet_perm[s]);
+            for (int c = 0; c < 4; ++c) out.tet_nodes[4 * (tet_off[i] + s) + c] = (int32_t)(node_off[i] + h.tet_nodes[4 * s + c]);
+        }
+        for (int64_t s = 0; s < h.n_targets; ++s) out.tgt_perm[node_off[i] + s] = (int32_t)(node_off[i] + h.tgt_perm[s]);
+        out.n_p2p_pairs += h.n_p2p_pairs;
+        out.setup_seconds += h.setup_seconds;
+    }
+    // cells by level, mesh by mesh
+    std::vector<std::vector<int32_t>> remap(n);
+    for (size_t i = 0; i < n; ++i) remap[i].assign(in[i]->cells.size(), -1);
+    out.level_begin.assign(1, 0);
+    std::vector<std::pair<int32_t, int32_t>> order;  // (mesh, old cell) in new order
+    for (int L = 0; L <= depth; ++L) {
+        for (size_t i = 0; i < n; ++i) {
+            const HostPlan &h = *in[i];
+            if (L > h.depth) continue;
+            for (int32_t c = h.level_begin[L]; c < h.level_begin[L + 1]; ++c) {
+                remap[i][c] = (int32_t)order.size();
+                order.push_back({(int32_t)i, c});
+            }
+        }
+        out.level_begin.push_back((int32_t)order.size());
+    }
+    out.cells.resize(order.size());
+    for (size_t nc = 0; nc < order.size(); ++nc) {
+        const size_t i = (size_t)order[nc].first;
+        const HostPlan &h = *in[i];
+        const Cell &C = h.cells[order[nc].second];
+        Cell K = C;
+        const double s = std::ldexp(1.0, -C.level);
+        K.c[0] = ((double)C.ix + 0.5) * s;
+        K.c[1] = ((double)C.iy + 0.5) * s;
+        K.c[2] = ((double)C.iz + 0.5) * s;
+        K.tbeg = (int32_t)(tet_off[i] + C.tbeg);
+        K.tend = (int32_t)(tet_off[i] + C.tend);
+        K.xbeg = (int32_t)(node_off[i] + C.xbeg);
+        K.xend = (int32_t)(node_off[i] + C.xend);
+        K.cbeg = C.nchild > 0 ? remap[i][C.cbeg] : (int32_t)out.cells.size();
+        K.parent = C.parent >= 0 ? remap[i][C.parent] : -1;
+        K.rsrc = C.rsrc / h.side;
+        K.rtgt = C.rtgt / h.side;
+        out.cells[nc] = K;
+    }
+    // children stay contiguous: a parent's children are consecutive cells of
+    // one level of one mesh, which keep their order
+    for (const Cell &K : out.cells)
+        for (int32_t k = 1; k < K.nchild; ++k)
+            if (out.cells[K.cbeg + k].parent != out.cells[K.cbeg].parent) throw PlanError{TFMM_ENOTSUP, "merge broke a sibling run"};
+    // lists
+    const int64_t nc = (int64_t)out.cells.size();
+    std::map<std::array<int32_t, 4>, int32_t> kid;
+    out.m2l_ptr.assign(nc + 1, 0);
+    for (int64_t c = 0; c < nc; ++c) {
+        const HostPlan &h = *in[order[c].first];
+        const int32_t oc = order[c].second;
+        out.m2l_ptr[c + 1] = out.m2l_ptr[c] + (h.m2l_ptr[oc + 1] - h.m2l_ptr[oc]);
+    }
+    out.m2l_src.resize((size_t)out.m2l_ptr[nc]);
+    out.m2l_pair_key.resize((size_t)out.m2l_ptr[nc]);
+    for (int64_t c = 0; c < nc; ++c) {
+        const size_t i = (size_t)order[c].first;
+        const HostPlan &h = *in[i];
+        const int32_t oc = order[c].second;
+        int32_t w = out.m2l_ptr[c];
+        for (int32_t j = h.m2l_ptr[oc]; j < h.m2l_ptr[oc + 1]; ++j, ++w) {
+            out.m2l_src[w] = remap[i][h.m2l_src[j]];
+            const int32_t *kk = &h.m2l_keys[4 * (size_t)h.m2l_pair_key[j]];
+            const std::array<int32_t, 4> key{kk[0], kk[1], kk[2], kk[3]};
+            auto it = kid.find(key);
+            if (it == kid.end()) {
+                it = kid.emplace(key, (int32_t)(out.m2l_keys.size() / 4)).first;
+                out.m2l_keys.insert(out.m2l_keys.end(), key.begin(), key.end());
+            }
+            out.m2l_pair_key[w] = it->second;
+        }
+    }
+    for (size_t i = 0; i < n; ++i) {
+        const HostPlan &h = *in[i];
+        for (size_t k = 0; k < h.p2p_a.size(); ++k) {
+            out.p2p_a.push_back(remap[i][h.p2p_a[k]]);
+            out.p2p_b.push_back(remap[i][h.p2p_b[k]]);
+        }
+    }
+}
+
 void build_near_operator_layout(const HostPlan &hp, NearOpLayout &out)
 {
     const int64_t C = (int64_t)hp.cells.size();

@@ -149,6 +149,19 @@ struct PlanError {
 // only_level when it is >= 0).
 void build_m2l_tiles(const HostPlan &hp, int tpt, int max_ent, M2LTiles &out, int only_level = -1);
 
+// One plan over several meshes (a ragged batch): the plans `in` (same p,
+// leaf and theta, tet sources, targets = nodes) are normalised to their own
+// root cube (origin 0, side 1: coordinates x' = (x - origin) / side) and
+// concatenated: nodes, tets and targets in mesh order, cells grouped by
+// level (mesh by mesh within a level, each mesh's order kept), lists with
+// their cell indices remapped, keys unified.  Trees, radii and lists are
+// those of the meshes, so no mesh interacts with another.  The potential of
+// a mesh in its normalised frame is its true potential divided by its root
+// side (u scales with length at fixed M): scale[i] = side_i; node_off[i] is
+// the first node (and target) of mesh i (node_off.back() = total).
+void merge_host_plans(const std::vector<const HostPlan *> &in, HostPlan &out, std::vector<double> &scale,
+                      std::vector<int64_t> &node_off);
+
 // Builds the plan.  Throws PlanError on invalid input.  With points = true
 // the sources are the n_nodes points `nodes` (tets is ignored).
 void build_host_plan(HostPlan &hp, const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,

@@ -1,8 +1,11 @@
 """GPU tests of ragged batches (one HIP graph per batch) and schedule tuning.
 
-Graph replays are checked against eager evaluations of the same plans, with
-the program's own eager work (new fields written by torch) and
-synchronisations between the replays, and against the oracle FMM.
+A batch evaluates either as one merged plan over all meshes (each mesh
+normalised to its own root cube, one launch per phase) or as the per-mesh
+plans on four graph branches; both are tested.  Graph replays are checked
+against eager evaluations of the per-mesh plans, with the program's own
+eager work (new fields written by torch) and synchronisations between the
+replays, and against the oracle FMM.
 """
 import sys
 
@@ -40,14 +43,19 @@ def _ragged(count, seed):
     return [meshgen.box_mesh(n, seed=seed + i) for i, n in enumerate(sizes)]
 
 
-def test_batch_graph_replays_match_eager_and_oracle(torch_dev, orc):
+@pytest.mark.parametrize("merged", [1, 0])
+def test_batch_graph_replays_match_eager_and_oracle(torch_dev, orc, merged):
     torch = torch_dev
     meshes = _ragged(6, 21)
-    _say("batch of", len(meshes), [m[1].shape[0] for m in meshes])
+    _say("batch of", len(meshes), [m[1].shape[0] for m in meshes], "merged", merged)
     B = T.tfmm_batch_create(meshes, p=6, leaf_size=16, theta=0.5)
+    T.tfmm_batch_set_merged(B, merged)
     M = [torch.empty((m[0].shape[0], 3), dtype=torch.float64, device="cuda:0") for m in meshes]
     u = [torch.empty(m[0].shape[0], dtype=torch.float64, device="cuda:0") for m in meshes]
     plans = [T.tfmm_batch_plan(B, i) for i in range(len(meshes))]
+    # the merged plan works in each mesh's normalised frame: rounding-level
+    # differences from the per-mesh plans
+    tol_eager = 1e-12 if merged else 1e-13
     for r in range(3):
         for i, m in enumerate(meshes):  # eager work between replays: new fields
             M[i].copy_(torch.from_numpy(meshgen.random_fields(m[0].shape[0], F=1, seed=100 * r + i)[0]))
@@ -57,7 +65,7 @@ def test_batch_graph_replays_match_eager_and_oracle(torch_dev, orc):
         for i, m in enumerate(meshes):
             ue = T.tfmm_evaluate(plans[i], M[i])
             torch.cuda.synchronize()
-            assert _rel(u[i].cpu().numpy(), ue.cpu().numpy()) <= 1e-13, (r, i)
+            assert _rel(u[i].cpu().numpy(), ue.cpu().numpy()) <= tol_eager, (r, i)
             if r == 1:
                 uo = orc.FMM(m[0], m[1], 6, 16, 0.5).evaluate(M[i].cpu().numpy())
                 assert _rel(u[i].cpu().numpy(), uo) <= TOL, i
@@ -67,11 +75,40 @@ def test_batch_graph_replays_match_eager_and_oracle(torch_dev, orc):
     torch.cuda.synchronize()
     for a, b in zip(u, u2):
         assert _rel(b.cpu().numpy(), a.cpu().numpy()) <= 1e-13
-    # a precision change of one plan re-captures too
-    T.tfmm_plan_set_m2l_precision(plans[2], T.M2L_FP32)
+    # a precision change re-captures too (of one plan, or of the merged plan)
+    T.tfmm_plan_set_m2l_precision(T.tfmm_batch_merged_plan(B) if merged else plans[2], T.M2L_FP32)
     T.tfmm_batch_evaluate(B, M, u2)
     torch.cuda.synchronize()
     assert 0.0 < _rel(u2[2].cpu().numpy(), u[2].cpu().numpy()) <= 1e-6
+    T.tfmm_batch_destroy(B)
+
+
+def test_merged_batch_equals_per_mesh_batch(torch_dev, orc):
+    """The merged plan and the per-mesh plans of one batch (meshes of very
+    different sizes and root cubes: a film, a stretched box, cubes) give the
+    oracle's potentials; switching between them re-captures."""
+    torch = torch_dev
+    meshes = _ragged(5, 81) + [meshgen.box_mesh((12, 12, 1), lo=(-6, -6, 0), hi=(6, 6, 0.5), jitter=0.0),
+                               meshgen.box_mesh((3, 9, 4), lo=(0, 0, 0), hi=(0.01, 0.03, 0.013), seed=3)]
+    _say("merged vs per mesh", [m[1].shape[0] for m in meshes])
+    B = T.tfmm_batch_create(meshes, p=7, leaf_size=8, theta=0.5)
+    M = [torch.from_numpy(meshgen.random_fields(m[0].shape[0], F=1, seed=90 + i)[0]).to("cuda:0")
+         for i, m in enumerate(meshes)]
+    st = T.tfmm_plan_stats(T.tfmm_batch_merged_plan(B))
+    assert st["n_nodes"] == sum(m[0].shape[0] for m in meshes)
+    assert st["n_tets"] == sum(m[1].shape[0] for m in meshes)
+    assert st["n_m2l"] == sum(T.tfmm_plan_stats(T.tfmm_batch_plan(B, i))["n_m2l"] for i in range(len(meshes)))
+    um = [x.cpu().numpy() for x in T.tfmm_batch_evaluate(B, M)]
+    T.tfmm_batch_set_merged(B, 0)
+    up = [x.cpu().numpy() for x in T.tfmm_batch_evaluate(B, M)]
+    T.tfmm_batch_set_merged(B, 1)
+    um2 = [x.cpu().numpy() for x in T.tfmm_batch_evaluate(B, M)]
+    torch.cuda.synchronize()
+    for i, m in enumerate(meshes):
+        uo = orc.FMM(m[0], m[1], 7, 8, 0.5).evaluate(M[i].cpu().numpy())
+        assert _rel(um[i], uo) <= TOL, i
+        assert _rel(up[i], uo) <= TOL, i
+        assert _rel(um2[i], um[i]) <= 1e-14, i
     T.tfmm_batch_destroy(B)
 
 
@@ -122,18 +159,21 @@ def test_ragged32_batch_accuracy(torch_dev):
     assert worst <= 1e-5, worst
 
 
-def test_batch_with_stored_near(torch_dev, orc):
-    """A plan of the batch switched to its stored near-field operator: the graph
-    is captured again and replays match the oracle."""
+@pytest.mark.parametrize("merged", [1, 0])
+def test_batch_with_stored_near(torch_dev, orc, merged):
+    """The batch's plan (the merged one, or one mesh's) switched to its stored
+    near-field operator: the graph is captured again and replays match the
+    oracle."""
     torch = torch_dev
     meshes = _ragged(4, 31)
-    _say("batch with stored near", [m[1].shape[0] for m in meshes])
+    _say("batch with stored near", [m[1].shape[0] for m in meshes], "merged", merged)
     B = T.tfmm_batch_create(meshes, p=6, leaf_size=16, theta=0.5)
+    T.tfmm_batch_set_merged(B, merged)
     M = [torch.from_numpy(meshgen.random_fields(m[0].shape[0], F=1, seed=40 + i)[0]).to("cuda:0")
          for i, m in enumerate(meshes)]
     u0 = T.tfmm_batch_evaluate(B, M)
     torch.cuda.synchronize()
-    T.tfmm_plan_store_near(T.tfmm_batch_plan(B, 1))
+    T.tfmm_plan_store_near(T.tfmm_batch_merged_plan(B) if merged else T.tfmm_batch_plan(B, 1))
     for r in range(2):
         u = T.tfmm_batch_evaluate(B, M, u0 if r else None)
         torch.cuda.synchronize()
@@ -143,25 +183,34 @@ def test_batch_with_stored_near(torch_dev, orc):
     T.tfmm_batch_destroy(B)
 
 
-def test_batch_graph_after_plan_buffers_regrow(torch_dev, orc):
-    """A batch plan evaluated on its own with 4 fields regrows its expansion
-    and scaled-multipole buffers; the next batch evaluation must capture a new
-    graph on the new buffers (not replay the old one on freed memory)."""
+@pytest.mark.parametrize("merged", [1, 0])
+def test_batch_graph_after_plan_buffers_regrow(torch_dev, orc, merged):
+    """The batch's plan (the merged one, or one mesh's) evaluated on its own
+    with 4 fields regrows its expansion and scaled-multipole buffers; the
+    next batch evaluation must capture a new graph on the new buffers (not
+    replay the old one on freed memory)."""
     torch = torch_dev
     meshes = _ragged(3, 51)
-    _say("batch regrow", [m[1].shape[0] for m in meshes])
+    _say("batch regrow", [m[1].shape[0] for m in meshes], "merged", merged)
     B = T.tfmm_batch_create(meshes, p=6, leaf_size=16, theta=0.5)
+    T.tfmm_batch_set_merged(B, merged)
     M = [torch.from_numpy(meshgen.random_fields(m[0].shape[0], F=1, seed=60 + i)[0]).to("cuda:0")
          for i, m in enumerate(meshes)]
     u = T.tfmm_batch_evaluate(B, M)
     torch.cuda.synchronize()
-    P1 = T.tfmm_batch_plan(B, 1)
-    M4 = torch.from_numpy(meshgen.random_fields(meshes[1][0].shape[0], F=4, seed=70)).to("cuda:0")
-    u4 = T.tfmm_evaluate(P1, M4)
+    if merged:
+        P = T.tfmm_batch_merged_plan(B)
+        M4 = torch.zeros((4, P.n_nodes, 3), dtype=torch.float64, device="cuda:0")
+        T.tfmm_evaluate(P, M4)
+    else:
+        P1 = T.tfmm_batch_plan(B, 1)
+        M4 = torch.from_numpy(meshgen.random_fields(meshes[1][0].shape[0], F=4, seed=70)).to("cuda:0")
+        u4 = T.tfmm_evaluate(P1, M4)
+        torch.cuda.synchronize()
+        u4o = orc.FMM(meshes[1][0], meshes[1][1], 6, 16, 0.5).evaluate(M4.cpu().numpy())
+        for f in range(4):
+            assert _rel(u4[f].cpu().numpy(), u4o[f]) <= TOL, f
     torch.cuda.synchronize()
-    u4o = orc.FMM(meshes[1][0], meshes[1][1], 6, 16, 0.5).evaluate(M4.cpu().numpy())
-    for f in range(4):
-        assert _rel(u4[f].cpu().numpy(), u4o[f]) <= TOL, f
     for r in range(2):
         T.tfmm_batch_evaluate(B, M, u)
         torch.cuda.synchronize()
