@@ -1805,7 +1805,7 @@ __global__ __launch_bounds__(NT, NT == 64 ? 2 : 4) void k_p2p_topo(const int32_t
                                                     const int32_t *__restrict__ tgt_perm, int64_t N,
                                                     double *__restrict__ u)
 {
-    __shared__ double s_w[kTopoNodes][3];
+    __shared__ double s_w[kTopoNodes][4];  // rows of 4: node offsets are shifts, not multiplies
     __shared__ double s_R[kTopoNodes][NT];
     __shared__ int s_ea[kTopoEdges], s_eb[kTopoEdges];
     __shared__ double s_il[kTopoEdges], s_B[kTopoEdges][11];
@@ -1820,7 +1820,7 @@ __global__ __launch_bounds__(NT, NT == 64 ? 2 : 4) void k_p2p_topo(const int32_t
                   foff = ch_i[8 * ch + 6], nf = ch_i[8 * ch + 7];
         const double c[3] = {ch_c[3 * ch], ch_c[3 * ch + 1], ch_c[3 * ch + 2]};
         __syncthreads();
-        for (int i = lane; i < nn * 3; i += NT) (&s_w[0][0])[i] = nw[(int64_t)noff * 3 + i];
+        for (int i = lane; i < nn * 3; i += NT) s_w[i / 3][i % 3] = nw[(int64_t)noff * 3 + i];
         for (int i = lane; i < ne; i += NT) {
             s_ea[i] = eab[2 * ((int64_t)eoff + i)];
             s_eb[i] = eab[2 * ((int64_t)eoff + i) + 1];
@@ -1860,12 +1860,12 @@ __global__ __launch_bounds__(NT, NT == 64 ? 2 : 4) void k_p2p_topo(const int32_t
                 const double cx0 = da[1] * db[2] - da[2] * db[1], cx1 = da[2] * db[0] - da[0] * db[2],
                              cx2 = da[0] * db[1] - da[1] * db[0];
                 const double r0sq = (cx0 * cx0 + cx1 * cx1 + cx2 * cx2) * (il * il);
-                const double f = edge_log(Ra, Rb, la, lb, r0sq);
+                const double f = edge_log<false>(Ra, Rb, la, lb, r0sq);
                 const double g = r0sq * f + lb * Rb - la * Ra;
                 const double *Be = s_B[e];
-                double bq = 0.0;
+                double bq = Be[0];
 #pragma unroll
-                for (int q = 0; q < 10; ++q) bq = fma(Be[q], m[q], bq);
+                for (int q = 1; q < 10; ++q) bq = fma(Be[q], m[q], bq);
                 acc = fma(f * il, bq, fma(Be[10], g, acc));
             }
 #pragma unroll 1
