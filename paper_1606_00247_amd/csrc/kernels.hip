@@ -970,7 +970,10 @@ __global__ __launch_bounds__(64 * kM2LPWaves, P <= 8 ? 2 : 1) void k_m2l_pack(
     __shared__ T s_D[kM2LPWaves][2][DSTR];
     const int it = blockIdx.x;
     if (it >= nitems) return;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // the wavefront index made visibly uniform: the group bounds, keys and
+    // the key-change branch then live in scalar registers, and reading a key
+    // does not wait for the vector loads of the prefetched multipoles
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int col = lane & 15, pair = col / fpt, fsub = col % fpt, field = (int)blockIdx.y * fpt + fsub;
     const bool fok = field < F;
     for (int i = tid; i < NSLOT * LSTR; i += blockDim.x) s_L[i] = 0.0;
@@ -1993,7 +1996,9 @@ __global__ __launch_bounds__(64 * kNearItemsPerBlock) void k_near_apply(
     const int blk = xcd_item((nitems + kNearItemsPerBlock - 1) / kNearItemsPerBlock);
     if (blk < 0) return;
     const int lane = threadIdx.x & 63;
-    const int it = blk * kNearItemsPerBlock + (threadIdx.x >> 6);
+    // one item per wavefront, its index made visibly uniform (the item's
+    // bounds, column list and rows are then read on the scalar path)
+    const int it = blk * kNearItemsPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (it >= nitems) return;
     const int32_t a = items[2 * it], r0 = items[2 * it + 1];
     const int xb = cell_i[8 * a + 2];
