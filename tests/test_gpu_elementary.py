@@ -63,6 +63,29 @@ def test_log_ratio(gpu):
     assert u.max() <= 4.0
 
 
+def test_log_ratio_is_odd(gpu):
+    """ln(a/b) = -ln(b/a) bit for bit: the edge logarithm of the shared-entity
+    near field takes ln((R_a - l_a)/(R_b - l_b)) as -ln((R_b - l_b)/(R_a - l_a)),
+    which is the same value only if the reduction (the factor 2 on one
+    argument, the exponent difference) and the odd series flip sign exactly.
+    Random ratios across binades and ratios at the reduction thresholds
+    sqrt2 and 1/sqrt2 (where the factor 2 moves from one argument to the
+    other)."""
+    rng = np.random.default_rng(5)
+    n = 4000
+    a = 10.0 ** rng.uniform(-30, 30, n)
+    b = a * 10.0 ** rng.uniform(-8, 8, n)
+    s2 = np.sqrt(2.0)
+    m = rng.uniform(0.5, 1.0, 400)
+    edge = np.concatenate([m * s2 * (1.0 + k * 2.0 ** -52) for k in range(-3, 4)])
+    a = np.concatenate([a, np.tile(m, 7), edge])
+    b = np.concatenate([b, edge, np.tile(m, 7)])
+    _say("log_ratio oddness", a.size)
+    f = T.tfmm_elementary("log_ratio", a, b)
+    g = T.tfmm_elementary("log_ratio", b, a)
+    assert np.array_equal(f, -g)
+
+
 def test_atan2(gpu):
     rng = np.random.default_rng(2)
     n = 6000
