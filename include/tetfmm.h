@@ -139,9 +139,10 @@ typedef struct {
  *  targets  host, [n_targets][3] double, or NULL to use the nodes as targets
  *  prm      parameters (see tfmm_params)
  *  out      receives the plan; NULL on failure
- * Errors: TFMM_EINVAL (sizes, p, leaf_size, theta), TFMM_EINDEX,
- *         TFMM_EDEGEN (|det| <= 1e-12 * mean edge^3 for some tet),
- *         TFMM_ENONFINITE, TFMM_ENOMEM, TFMM_EDEVICE.
+ * Errors: TFMM_EINVAL (sizes: fewer than 4 nodes or no tet, explicit
+ *         targets with n_targets < 1, NULL arrays; p, leaf_size, theta),
+ *         TFMM_EINDEX, TFMM_EDEGEN (|det| <= 1e-12 * mean edge^3 for some
+ *         tet), TFMM_ENONFINITE, TFMM_ENOMEM, TFMM_EDEVICE.
  */
 int tfmm_plan_create(const double *nodes, int64_t n_nodes, const int32_t *tets, int64_t n_tets,
                      const double *targets, int64_t n_targets, const tfmm_params *prm, tfmm_plan *out);

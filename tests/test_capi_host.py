@@ -141,6 +141,12 @@ def test_errors():
     with pytest.raises(T.TetFMMError) as e:
         T.tfmm_plan_create(nan_nodes, tets, device=-1)
     assert e.value.code == -4
+    # empty inputs: no tet, fewer than 4 nodes, an empty explicit target list
+    for nd, tt, tg in ((nodes, tets[:0], None), (nodes[:3], np.zeros((0, 4), np.int32), None),
+                       (nodes, tets, np.zeros((0, 3)))):
+        with pytest.raises(T.TetFMMError) as e:
+            T.tfmm_plan_create(nd, tt, targets=tg, device=-1)
+        assert e.value.code == -1
     P = T.tfmm_plan_create(nodes, tets, p=4, leaf_size=8, theta=0.5, device=-1)
     M = np.zeros((nodes.shape[0], 3))
     with pytest.raises(T.TetFMMError) as e:
