@@ -144,32 +144,67 @@ def test_film_oracle_parity_and_full_film_accuracy(torch_dev, orc):
     assert _rel(u64[idx], ud) <= ACC_TOL
     assert _rel(u32[idx], ud) <= ACC_TOL
     assert _rel(u32, u64) <= 1e-6
+    # the full film in FP64 against the oracle FMM on sampled targets
+    _say("film 512 fp64 vs oracle FMM (128 sampled targets)")
+    idx = _sample(nodes.shape[0], 128, 8)
+    uo = orc.FMM(nodes, tets, 8, 64, FILM_THETA).evaluate_sample(M, idx)
+    assert _rel(u64[idx], uo) <= FMM_TOL
+    assert np.abs(u64[idx] - uo).max() <= 1e-11 * np.abs(uo).max()
 
 
-def test_cube64_64_fields_bf16x3(torch_dev):
+# FP64 parity with random unit nodal fields on the 64^3 cube.  Independent
+# unit vectors at neighbouring nodes give every tet large surface and volume
+# charges that cancel, so |u| is 20-35x smaller than for a smooth field of
+# the same size, and the rounding of two correct FP64 FMMs summed in
+# different orders grows, relative to |u|, with the mesh: 3.5e-13 on the
+# 40^3 cube, 1.6e-12 on the 64^3 cube at theta 0.45, while a uniform and a
+# vortex field on the same plan agree to 4e-15 and 7e-15.
+RANDOM_FIELD_TOL_64 = 5e-12
+
+
+def test_cube64_64_fields_bf16x3(torch_dev, orc):
+    """The 64^3 cube (1.57M tets) with 64 fields and split-BF16 M2L against
+    the direct sum (max over fields); the same plan in FP64 against the
+    oracle FMM on sampled targets for two of the random fields and a uniform
+    field."""
     nodes, tets = meshgen.box_mesh(64, seed=0)
     F = 64
     M = meshgen.random_fields(nodes.shape[0], F=F, seed=1)
     _say("cube64 x 64 fields bf16x3 m2l vs direct (sampled)", tets.shape)
     P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=64, theta=CUBE64_THETA, m2l_precision=T.M2L_BF16X3)
     u = _eval(torch_dev, P, M)
+    T.tfmm_plan_set_m2l_precision(P, T.M2L_FP64)
+    M3 = np.concatenate([M[:2], meshgen.uniform_field(nodes.shape[0], (1.0, 0.0, 0.0))[None]])
+    u64 = _eval(torch_dev, P, M3)
     del P
+    _say("cube64 fp64 vs oracle FMM (2 random + 1 uniform field, 128 sampled targets)")
+    io = _sample(nodes.shape[0], 128, 9)
+    uo = orc.FMM(nodes, tets, 8, 64, CUBE64_THETA).evaluate_sample(M3, io)
+    for f, tol in ((0, RANDOM_FIELD_TOL_64), (1, RANDOM_FIELD_TOL_64), (2, FMM_TOL)):
+        assert _rel(u64[f, io], uo[f]) <= tol, f
+        assert np.abs(u64[f, io] - uo[f]).max() <= 10 * tol * np.abs(uo[f]).max(), f
     idx = _sample(nodes.shape[0], 256, 5)
     ud = _direct_at(torch_dev, nodes, tets, M, idx)
     errs = [_rel(u[f, idx], ud[f]) for f in range(F)]
     assert max(errs) <= ACC_TOL, max(errs)
 
 
-def test_sphere_uniform_field(torch_dev):
+def test_sphere_uniform_field(torch_dev, orc):
     """Sphere of radius 1 (96^3 grid, ~2.78M tets), M = (0, 0, 1): the FMM
-    agrees with the direct sum, and inside (|r| < 0.8) both approach the
-    exact u = M.r/3 of the true sphere up to the staircase boundary."""
+    agrees with the oracle FMM on sampled targets and with the direct sum,
+    and inside (|r| < 0.8) both approach the exact u = M.r/3 of the true
+    sphere up to the staircase boundary."""
     nodes, tets = meshgen.sphere_mesh(96)
     M = meshgen.uniform_field(nodes.shape[0], (0.0, 0.0, 1.0))
     _say("sphere 96 fp64", tets.shape)
     P = T.tfmm_plan_create(nodes, tets, p=8, leaf_size=64, theta=0.5)
     u = _eval(torch_dev, P, M)
     del P
+    _say("sphere fp64 vs oracle FMM (256 sampled targets)")
+    io = _sample(nodes.shape[0], 256, 10)
+    uo = orc.FMM(nodes, tets, 8, 64, 0.5).evaluate_sample(M, io)
+    assert _rel(u[io], uo) <= FMM_TOL
+    assert np.abs(u[io] - uo).max() <= 1e-11 * np.abs(uo).max()
     inner = np.flatnonzero(np.linalg.norm(nodes, axis=1) < 0.8)
     idx = inner[_sample(inner.size, 512, 6)]
     ud = _direct_at(torch_dev, nodes, tets, M, idx)
