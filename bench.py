@@ -466,6 +466,19 @@ def main():
         hw = measured_counters("p2p")
         if hw is not None:
             roof["hw_counters"] = hw
+    # the second phase: M2L on the FP64 matrix cores (the phase time holds the
+    # multipole reduction, the translations and the expansion of the reduced
+    # locals)
+    t_m2l = ktimes["m2l"][0] * 1e-3
+    am = st["n_m2l"] * W["F"] * 2 * m2l_terms(W["p"]) / t_m2l / 1e12
+    m2l_roof = {"kernel": "m2l", "bound": "mfma", "achieved": round(am, 3), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(am / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic("m2l"),
+                "algorithmic_unit": f"translations x fields x 2 x {m2l_terms(W['p'])} multiply-adds of the "
+                                    "harmonically reduced contraction",
+                "launch_ms": round(t_m2l * 1e3, 4)}
+    hw = measured_counters("m2l")
+    if hw is not None:
+        m2l_roof["hw_counters"] = hw
 
     out = {
         "metric": METRIC,
@@ -495,6 +508,7 @@ def main():
                    "p2p_node_evals": st["p2p_node_evals"], "p2p_edge_evals": st["p2p_edge_evals"],
                    "p2p_face_evals": st["p2p_face_evals"]},
         "roofline": roof,
+        "m2l_roofline": m2l_roof,
         "path_roofline": path_roofline(st, W["p"], W["F"], dt * 1e3, nodes.shape[0]),
     }
 
