@@ -1795,7 +1795,11 @@ __global__ __launch_bounds__(64) void k_topo_coef(const int32_t *__restrict__ ch
 }
 
 // NT = 64: one wavefront per workgroup; NT = 256: four wavefronts share the
-// staged chunk (less LDS per wavefront: 4 waves per SIMD instead of 3).
+// staged chunk (less LDS per wavefront).  The 256-thread form asks for 4
+// workgroups per CU but its 41 KB of LDS admits 3 (3 waves per SIMD); the
+// register allocation under that request gives the tightest entity loops
+// (asking for 3 lets it take 144 VGPRs, and the edge and face loops grow by
+// 7 and 9 instructions).
 template <int NT>
 __global__ __launch_bounds__(NT, NT == 64 ? 2 : 4) void k_p2p_topo(const int32_t *__restrict__ blk, int nblk,
                                                     const int32_t *__restrict__ ch_i, const double *__restrict__ ch_c,
