@@ -383,8 +383,8 @@ def main():
                     help="run a study instead of the benchmark and print its JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                          "(multi-GPU sharding is a design note, not implemented)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 "
+                          "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
 
     import torch

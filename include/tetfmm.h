@@ -44,7 +44,7 @@ extern "C" {
 #define TFMM_ENONFINITE (-4) /* NaN or Inf in the inputs */
 #define TFMM_ENOMEM (-5)     /* host or device allocation failed */
 #define TFMM_EDEVICE (-6)    /* HIP error, or no usable device */
-#define TFMM_ENOTSUP (-7)    /* valid request this build does not support */
+#define TFMM_ENOTSUP (-7)    /* valid request the library does not support */
 
 /* largest expansion order p accepted */
 #define TFMM_PMAX 10
