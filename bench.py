@@ -676,6 +676,14 @@ def main():
         t1 = time.perf_counter()
         oracle.direct(n8, t8, M8)
         t_d8 = time.perf_counter() - t1
+        # the oracle's direct sum at 32 of the benchmark's own targets, beside
+        # the GPU direct sum there
+        sd = sample[:32]
+        t1 = time.perf_counter()
+        udc = oracle.direct(nodes, tets, M, targets=nodes[sd])
+        t_dc = time.perf_counter() - t1
+        udg = ud.cpu().numpy()[:, sd]
+        dcheck = float(np.linalg.norm(udg - udc) / np.linalg.norm(udc))
         out["cpu_baseline"] = {
             "value": evals / t_full, "unit": "evals/s", "cores": ncores, "kind": "oracle",
             "sample": f"oracle FMM on {len(sample)} seeded targets of {nodes.shape[0]} (full upward pass, "
@@ -685,6 +693,10 @@ def main():
             "direct_cube8": {"value": n8.shape[0] / t_d8, "unit": "evals/s", "cores": ncores,
                              "sample": f"oracle direct sum on the 8^3 cube (3,072 tets, all {n8.shape[0]} nodes): "
                                        f"{t_d8:.2f}s"},
+            "direct_sample": {"value": len(sd) * W["F"] / t_dc, "unit": "evals/s", "cores": ncores,
+                              "sample": f"oracle direct sum at {len(sd)} seeded targets of the benchmark mesh "
+                                        f"({tets.shape[0]} tets): {t_dc:.1f}s",
+                              "gpu_direct_vs_oracle_direct_rel_l2": dcheck},
             "single_core": {"value": evals / t_full1, "cores": 1,
                             "sample": f"64 targets (upward pass {t_up1:.1f}s, {per1 * 1e3:.2f} ms per target), "
                                       f"extrapolated: {t_full1:.1f}s per evaluation"},
