@@ -1721,6 +1721,10 @@ __global__ __launch_bounds__(kPtThreads) void k_p2p_points(const int32_t *__rest
 // k_p2p_topo then evaluates one square root per node, one log per edge and
 // one solid angle per face of the chunk for every target.
 // ---------------------------------------------------------------------------
+// One wavefront takes kTopoChunksPerWave chunks, 16 lanes (one per tet) each.
+constexpr int kTopoChunksPerWave = 4;
+static_assert(kTopoTets <= 64 / kTopoChunksPerWave, "one lane per tet of a chunk");
+
 __global__ __launch_bounds__(64) void k_topo_coef(const int32_t *__restrict__ ch_i, const double *__restrict__ ch_c,
                                                   int nch, const int32_t *__restrict__ inc,
                                                   const double *__restrict__ tet_xyz,
@@ -1728,18 +1732,23 @@ __global__ __launch_bounds__(64) void k_topo_coef(const int32_t *__restrict__ ch
                                                   const double *__restrict__ M, double *__restrict__ A,
                                                   double *__restrict__ Bc)
 {
-    __shared__ double s_A[kTopoFaces][4];
-    __shared__ double s_B[kTopoEdges][11];
-    const int ch = blockIdx.x;
-    if (ch >= nch) return;
-    const int tb = ch_i[8 * ch], nt = ch_i[8 * ch + 1], eoff = ch_i[8 * ch + 4], ne = ch_i[8 * ch + 5],
-              foff = ch_i[8 * ch + 6], nf = ch_i[8 * ch + 7];
-    const double c[3] = {ch_c[3 * ch], ch_c[3 * ch + 1], ch_c[3 * ch + 2]};
-    for (int i = threadIdx.x; i < kTopoFaces * 4; i += blockDim.x) (&s_A[0][0])[i] = 0.0;
-    for (int i = threadIdx.x; i < kTopoEdges * 11; i += blockDim.x) (&s_B[0][0])[i] = 0.0;
+    constexpr int LPC = 64 / kTopoChunksPerWave;  // lanes per chunk
+    __shared__ double s_Aw[kTopoChunksPerWave][kTopoFaces][4];
+    __shared__ double s_Bw[kTopoChunksPerWave][kTopoEdges][11];
+    const int sub = (int)threadIdx.x / LPC, tl = (int)threadIdx.x % LPC;
+    const int ch = (int)blockIdx.x * kTopoChunksPerWave + sub;
+    const bool live = ch < nch;
+    const int chl = live ? ch : nch - 1;  // clamped: reads stay in bounds, nothing is written
+    const int tb = ch_i[8 * chl], nt = live ? ch_i[8 * chl + 1] : 0, eoff = ch_i[8 * chl + 4],
+              ne = ch_i[8 * chl + 5], foff = ch_i[8 * chl + 6], nf = ch_i[8 * chl + 7];
+    const double c[3] = {ch_c[3 * chl], ch_c[3 * chl + 1], ch_c[3 * chl + 2]};
+    double (*s_A)[4] = s_Aw[sub];
+    double (*s_B)[11] = s_Bw[sub];
+    for (int i = threadIdx.x; i < kTopoChunksPerWave * kTopoFaces * 4; i += blockDim.x) (&s_Aw[0][0][0])[i] = 0.0;
+    for (int i = threadIdx.x; i < kTopoChunksPerWave * kTopoEdges * 11; i += blockDim.x) (&s_Bw[0][0][0])[i] = 0.0;
     __syncthreads();
-    if ((int)threadIdx.x < nt) {
-        const int64_t t = tb + threadIdx.x;
+    if (tl < nt) {
+        const int64_t t = tb + tl;
         TetGeom G;
         TetField Fd;
         tet_prepare(tet_xyz, tet_node, T, t, M, &G, Fd);
@@ -1790,8 +1799,9 @@ __global__ __launch_bounds__(64) void k_topo_coef(const int32_t *__restrict__ ch
         for (int e = 0; e < 6; ++e) atomicAdd(&s_B[ti[e]][10], Fd.g[e]);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nf * 4; i += blockDim.x) A[(int64_t)foff * 4 + i] = (&s_A[0][0])[i];
-    for (int i = threadIdx.x; i < ne * 11; i += blockDim.x) Bc[(int64_t)eoff * 11 + i] = (&s_B[0][0])[i];
+    if (!live) return;
+    for (int i = tl; i < nf * 4; i += LPC) A[(int64_t)foff * 4 + i] = (&s_A[0][0])[i];
+    for (int i = tl; i < ne * 11; i += LPC) Bc[(int64_t)eoff * 11 + i] = (&s_B[0][0])[i];
 }
 
 // NT = 64: one wavefront per workgroup; NT = 256: four wavefronts share the
@@ -2386,7 +2396,7 @@ void run_p2p(DevicePlan &dp, bool direct, const double *M, int32_t F, double *u,
     if (direct) throw DeviceError{"the tet direct sum runs in k_direct"};
     if (!band_skip && F == 1 && dp.p2p_topo && dp.n_topo_ch > 0) {
         const HostPlan &hp = dp.hp;
-        k_topo_coef<<<dim3(dp.n_topo_ch), dim3(64), 0, st>>>(dp.topo_ch_i, dp.topo_ch_c, dp.n_topo_ch, dp.topo_inc,
+        k_topo_coef<<<dim3((unsigned)((dp.n_topo_ch + kTopoChunksPerWave - 1) / kTopoChunksPerWave)), dim3(64), 0, st>>>(dp.topo_ch_i, dp.topo_ch_c, dp.n_topo_ch, dp.topo_inc,
                                                              dp.tet_xyz, dp.tet_node, hp.n_tets, M, dp.topo_A,
                                                              dp.topo_B);
         hip_check(hipGetLastError(), "k_topo_coef launch");
